@@ -1,0 +1,127 @@
+"""CPU oracle for exact angular pair counting -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package.  The product library never imports, links or calls it.  See
+pc_oracle.c for the definition it implements and the readings it takes.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+_lib = None
+
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dp = ctypes.POINTER(ctypes.c_double)
+_up = ctypes.POINTER(ctypes.c_uint64)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        L.oracle_sincosd.argtypes = [ctypes.c_double, _dp, _dp]
+        L.oracle_sincosd.restype = None
+        L.oracle_unit_vectors.argtypes = [_i64, _dp, _dp, _dp]
+        L.oracle_unit_vectors.restype = None
+        L.oracle_chord2_edges.argtypes = [_i32, _dp, _dp]
+        L.oracle_chord2_edges.restype = None
+        L.oracle_count_xyz.argtypes = [_i64, _dp, _i64, _dp, _i32, _i32, _dp, _i64, _i64, _up]
+        L.oracle_count_xyz.restype = None
+        L.oracle_count.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i32, _i32, _dp, _i64, _i64, _up]
+        L.oracle_count.restype = ctypes.c_int
+        L.oracle_wtheta.argtypes = [_up, _up, _up, _i32, _i64, _i64, _dp]
+        L.oracle_wtheta.restype = None
+        L.oracle_num_threads.argtypes = []
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _u(a):
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return a, a.ctypes.data_as(_up)
+
+
+def sincosd(x: float):
+    s = ctypes.c_double()
+    c = ctypes.c_double()
+    lib().oracle_sincosd(float(x), ctypes.byref(s), ctypes.byref(c))
+    return s.value, c.value
+
+
+def unit_vectors(ra, dec) -> np.ndarray:
+    ra, pr = _d(ra)
+    dec, pd = _d(dec)
+    out = np.empty((ra.size, 3), dtype=np.float64)
+    lib().oracle_unit_vectors(ra.size, pr, pd, out.ctypes.data_as(_dp))
+    return out
+
+
+def chord2_edges(theta_deg) -> np.ndarray:
+    t, pt = _d(theta_deg)
+    out = np.empty(t.size, dtype=np.float64)
+    lib().oracle_chord2_edges(t.size, pt, out.ctypes.data_as(_dp))
+    return out
+
+
+def count_xyz(xyzA, e, xyzB=None, auto=True, rows=None) -> np.ndarray:
+    xa, pa = _d(xyzA)
+    nA = xa.size // 3
+    if auto:
+        xb, pb, nB = None, None, 0
+    else:
+        xb, pb = _d(xyzB)
+        nB = xb.size // 3
+    e, pe = _d(e)
+    r0, r1 = (0, nA) if rows is None else rows
+    out = np.zeros(e.size + 1, dtype=np.uint64)
+    lib().oracle_count_xyz(nA, pa, nB, pb, 1 if auto else 0, e.size, pe, r0, r1,
+                           out.ctypes.data_as(_up))
+    return out
+
+
+def count(A, theta_edges, B=None, auto=True, rows=None) -> np.ndarray:
+    """Pair counts [under, bin 0..B-1, over] for catalogue A = (ra, dec) (auto
+    pairs i<j) or A x B (cross).  rows = (r0, r1) restricts i to [r0, r1)."""
+    ra, pra = _d(A[0])
+    da, pda = _d(A[1])
+    if auto:
+        rb = db = None
+        prb = pdb = None
+        nB = 0
+    else:
+        rb, prb = _d(B[0])
+        db, pdb = _d(B[1])
+        nB = rb.size
+    t, pt = _d(theta_edges)
+    r0, r1 = (0, ra.size) if rows is None else rows
+    out = np.zeros(t.size + 1, dtype=np.uint64)
+    rc = lib().oracle_count(ra.size, pra, pda, nB, prb, pdb, 1 if auto else 0, t.size, pt,
+                            int(r0), int(r1), out.ctypes.data_as(_up))
+    if rc != 0:
+        raise MemoryError("oracle_count: out of memory")
+    return out
+
+
+def wtheta(DD, DR, RR, nD: int, nR: int) -> np.ndarray:
+    DD, p1 = _u(DD)
+    DR, p2 = _u(DR)
+    RR, p3 = _u(RR)
+    out = np.empty(DD.size, dtype=np.float64)
+    lib().oracle_wtheta(p1, p2, p3, DD.size, int(nD), int(nR), out.ctypes.data_as(_dp))
+    return out
+
+
+def num_threads() -> int:
+    return lib().oracle_num_threads()
