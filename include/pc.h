@@ -1,0 +1,240 @@
+/*
+ * pc.h -- exact angular pair counting on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libpc.so.  Plain pointers and sizes only.
+ *
+ * The problem (Bard et al., "Cosmological calculations on the GPU", Sec. 2):
+ * given catalogues of sky positions (RA, Dec), count pairs of points by their
+ * great-circle separation theta (Appendix A) in user-chosen bins (Sec. 2.1,
+ * binning presets): DD and RR over the n(n-1)/2 unordered pairs of one
+ * catalogue (no self-pairs, no double counting), DR over all n*n_r pairs of
+ * two catalogues; then form the Landy-Szalay estimate w(theta) (Eq. 2).
+ *
+ * Counts are exact: every pair is binned as the binary64 reference
+ * definition bins it (unit vectors from RA/Dec by an exactly specified
+ * degree sine/cosine, squared chord c = (dx*dx + dy*dy) + dz*dz with no fused
+ * multiply-add, compared with edges 4*sin^2(theta_k/2)).  The fast path
+ * computes c in binary32 and re-computes in binary64 only the pairs that fall
+ * inside a proven error band around an edge.
+ *
+ * Conventions for every call:
+ *  - Return value: PC_OK (0) or a pc_status error code.  On error the
+ *    outputs are left untouched and pc_last_error() describes the cause.
+ *  - Ownership: the caller owns every buffer it passes in; the library never
+ *    frees caller memory.  Catalogue handles own only library allocations.
+ *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Device
+ *    inputs must be ready on that stream; calls return when their host
+ *    outputs are written.
+ *  - Threads: calls are thread-safe; concurrent calls should use distinct
+ *    streams.
+ */
+#ifndef PC_H
+#define PC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum pc_status {
+    PC_OK = 0,
+    PC_ERR_INVALID = 1,   /* bad argument: NaN/Inf, |Dec| > 90, n < 0, bad edges, ... */
+    PC_ERR_NOMEM = 2,     /* device or host allocation failed, or admission refused   */
+    PC_ERR_DEVICE = 3,    /* HIP runtime error or no usable gfx950 device               */
+    PC_ERR_BUSY = 4,      /* server queue full                                          */
+    PC_ERR_CANCELLED = 5  /* job cancelled                                              */
+};
+
+enum pc_mode {
+    PC_MIXED = 0,      /* binary32 chord^2 + binary64 re-check in the guard band (default) */
+    PC_FP64_PLAIN = 1  /* binary64 chord^2 for every pair (baseline kernel)                */
+};
+
+/* A catalogue of n points: RA and Dec in degrees, binary64.  Paper Sec. 2.2
+ * (input is a list of RA, Dec per galaxy).  RA: any finite value.  Dec: finite
+ * and in [-90, 90].  on_device = 1: ra_deg/dec_deg are device pointers (e.g.
+ * torch data_ptr() of float64 CUDA tensors); 0: host pointers. */
+typedef struct {
+    const double *ra_deg;
+    const double *dec_deg;
+    int64_t n;
+    int32_t on_device;
+    int32_t reserved;
+} pc_catalog;
+
+/*
+ * pc_count -- pair counts of one catalogue (auto) or of two (cross).
+ * Paper Sec. 2: DD/RR count the n(n-1)/2 pairs i<j of one catalogue; DR counts
+ * all n_A*n_B pairs.  Sec. 2.1: histogram of separations over user edges.
+ *
+ *   A, B            catalogues; B is ignored (may be NULL) when auto_flag = 1.
+ *   theta_edges_deg n_edges >= 2 host binary64 values, strictly increasing,
+ *                   in [0, 180] degrees.
+ *   auto_flag       1: unordered pairs of A; 0: all pairs of A x B.
+ *   counts          host array of n_edges + 1 uint64, written on success:
+ *                   counts[0]         pairs with theta <  edges[0] (underflow)
+ *                   counts[k], 1<=k<n_edges: edges[k-1] <= theta < edges[k]
+ *                   counts[n_edges]   pairs with theta >= edges[n_edges-1]
+ *                   (theta compared through the binary64 squared chord).
+ *                   The entries sum to n(n-1)/2 (auto) or n_A*n_B (cross).
+ *   stream          hipStream_t or NULL.
+ * n = 0 or 1 (auto) gives all-zero counts.  Mode PC_MIXED.
+ */
+int pc_count(const pc_catalog *A, const pc_catalog *B, const double *theta_edges_deg,
+             int32_t n_edges, int32_t auto_flag, uint64_t *counts, void *stream);
+
+/*
+ * pc_count_ex -- pc_count with an explicit mode and a row range.
+ *   mode            PC_MIXED or PC_FP64_PLAIN (identical counts, different kernels).
+ *   row_begin/end   count only pairs whose A-side index i is in [row_begin,
+ *                   row_end) (auto: pairs i<j with i in range; cross: (i, j) for
+ *                   all j).  row_end = -1 means n_A.  Rows outside [0, n_A] are
+ *                   PC_ERR_INVALID.  Disjoint row ranges add up to the full count
+ *                   (the paper's submatrix decomposition, Sec. 2.1).
+ */
+int pc_count_ex(const pc_catalog *A, const pc_catalog *B, const double *theta_edges_deg,
+                int32_t n_edges, int32_t auto_flag, int32_t mode, int64_t row_begin,
+                int64_t row_end, uint64_t *counts, void *stream);
+
+/* One counting job inside a batch; fields as in pc_count_ex.  counts is a host
+ * array of n_edges + 1 uint64 owned by the caller. */
+typedef struct {
+    const pc_catalog *A;
+    const pc_catalog *B;
+    const double *theta_edges_deg;
+    int32_t n_edges;
+    int32_t auto_flag;
+    int64_t row_begin;
+    int64_t row_end;
+    uint64_t *counts;
+} pc_job;
+
+/*
+ * pc_count_batch -- many counting jobs in one persistent kernel launch (the
+ * paper's DD, DR and RR of one estimate; or many mock catalogues against a
+ * shared random catalogue for Monte Carlo errors, Sec. 4).  Catalogues passed
+ * with identical (ra_deg, dec_deg, n) pointers are converted once.  Jobs may use
+ * different edge sets.  All jobs use `mode`.  Results are the same as running
+ * each job alone.  n_jobs >= 1.
+ */
+int pc_count_batch(const pc_job *jobs, int32_t n_jobs, int32_t mode, void *stream);
+
+/*
+ * pc_wtheta -- Landy-Szalay estimator (Eq. 2) from in-range bin counts.
+ *   DD, DR, RR   host arrays of n_bins uint64 (pass counts + 1 of pc_count).
+ *   nD, nR       catalogue sizes, each >= 2.
+ *   w            host array of n_bins binary64, written:
+ *                w[k] = ((dd - 2 dr) + rr) / rr with dd = DD[k]/(nD(nD-1)/2),
+ *                dr = DR[k]/(nD nR), rr = RR[k]/(nR(nR-1)/2)  (binary64, this
+ *                order, no fused multiply-add).  RR[k] = 0 gives NaN.
+ * Host computation; no device needed.
+ */
+int pc_wtheta(const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_t n_bins,
+              int64_t nD, int64_t nR, double *w);
+
+/* Thread-local description of the last error on this thread ("" if none).
+ * Valid until the next pc_* call on the same thread. */
+const char *pc_last_error(void);
+
+/* Library version string, e.g. "pc 0.1 gfx950". */
+const char *pc_version(void);
+
+/* ------------------------------------------------------------ residency */
+
+/*
+ * pc_catalog_upload -- convert a catalogue once (RA/Dec -> binary64 and
+ * binary32 unit vectors, 48 bytes per point) and keep it resident on the
+ * current device.  *handle receives a nonzero id.  Paper Sec. 2.1: positions
+ * are copied to GPU global memory once and reused for every submatrix.
+ */
+int pc_catalog_upload(const pc_catalog *c, void *stream, uint64_t *handle);
+
+/* Release a resident catalogue (waits for work on the device to finish). */
+int pc_catalog_release(uint64_t handle);
+
+/* pc_count_ex on resident catalogues (hB ignored when auto_flag = 1). */
+int pc_count_h(uint64_t hA, uint64_t hB, const double *theta_edges_deg, int32_t n_edges,
+               int32_t auto_flag, int32_t mode, int64_t row_begin, int64_t row_end,
+               uint64_t *counts, void *stream);
+
+/*
+ * pc_unit_vectors -- the conversion step alone, for verification.
+ *   c        catalogue (host or device).
+ *   xyz64    host array of 3n binary64 (x, y, z per point), written;
+ *   xyz32    host array of 3n binary32 (round-to-nearest of xyz64), written;
+ *            either may be NULL.
+ * x = cos(dec) cos(ra), y = cos(dec) sin(ra), z = sin(dec) (Appendix A
+ * coordinates), computed on the device.
+ */
+int pc_unit_vectors(const pc_catalog *c, double *xyz64, float *xyz32, void *stream);
+
+/* ------------------------------------------------------------- tables */
+
+/*
+ * pc_chord2_edges -- e[k] = 4 sin^2(theta_k/2) in binary64 (host), the squared
+ * chord of each edge separation; n_edges values.  Appendix A separation
+ * expressed through the chord.  No device needed.
+ */
+int pc_chord2_edges(const double *theta_edges_deg, int32_t n_edges, double *e);
+
+/*
+ * pc_guard_band -- the binary32 band around each squared-chord edge inside
+ * which the mixed kernel re-checks a pair in binary64.  Host, no device.
+ *   lo[k], hi[k]  written (n_edges floats): a binary32 chord^2 above hi[k]
+ *                 proves the binary64 chord^2 is >= e[k]; one below lo[k]
+ *                 proves it is < e[k].
+ */
+int pc_guard_band(const double *theta_edges_deg, int32_t n_edges, float *lo, float *hi);
+
+/* ------------------------------------------------------------- serving */
+
+/*
+ * A w(theta) server: requests (a data catalogue on one of the caller's sky
+ * patches, plus theta edges) are admitted while free device memory minus a
+ * budget allows, their DD/DR/RR work is packed into persistent launches on
+ * several streams so that new requests overlap running ones, random catalogues
+ * are resident per patch and RR counts are cached per (patch, edges).
+ *
+ * pc_server_create: json_cfg (may be NULL) keys:
+ *   "hbm_budget_bytes"  bytes of device memory to leave free (default 4 GiB)
+ *   "max_inflight"      requests on the device at once (default 64)
+ *   "streams"           number of streams (default 2)
+ *   "max_batch_pairs"   pairs packed into one launch (default 2e12)
+ *   "mode"              0 mixed, 1 fp64 plain
+ */
+int pc_server_create(const char *json_cfg, void **server);
+
+/* Register the random catalogue of sky patch `patch_id` (converted and kept
+ * resident; copied, so the caller may free its arrays afterwards). */
+int pc_server_set_random(void *server, int32_t patch_id, const pc_catalog *randoms);
+
+/* Submit a request.  The data arrays are copied before return.  *job_id
+ * receives the request id.  PC_ERR_BUSY when the queue is full. */
+int pc_server_submit(void *server, const pc_catalog *data, int32_t patch_id,
+                     const double *theta_edges_deg, int32_t n_edges, uint64_t *job_id);
+
+/*
+ * Poll a request.  *done = 1 when finished (then DD, DR, RR (n_edges+1 uint64
+ * each, any may be NULL) and w (n_edges-1 binary64, may be NULL) are written and
+ * the request is forgotten), 0 while queued or running, -1 if it failed (the
+ * status is returned and the request forgotten).  latency_s (may be NULL)
+ * receives submit-to-completion seconds.
+ */
+int pc_server_poll(void *server, uint64_t job_id, int32_t *done, uint64_t *DD, uint64_t *DR,
+                   uint64_t *RR, double *w, double *latency_s);
+
+/* Block until every submitted request has finished. */
+int pc_server_drain(void *server);
+
+/* Server statistics as a JSON string (thread-local buffer, valid until the
+ * next call on this thread). */
+const char *pc_server_stats(void *server);
+
+int pc_server_destroy(void *server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PC_H */

@@ -1,0 +1,342 @@
+"""Python binding of libpc.so: exact angular pair counting on AMD MI355X.
+
+Argument marshalling only -- every step runs in the HIP library.  Functions
+carry the C names of include/pc.h.  Catalogues are (ra_deg, dec_deg) pairs of
+float64 arrays: torch CUDA tensors are passed as device pointers, numpy arrays
+(or CPU tensors) as host pointers.  Counts come back as numpy uint64 arrays of
+n_edges + 1 entries [underflow, bins..., overflow].
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpc.so")
+
+PC_OK, PC_ERR_INVALID, PC_ERR_NOMEM, PC_ERR_DEVICE, PC_ERR_BUSY, PC_ERR_CANCELLED = range(6)
+PC_MIXED, PC_FP64_PLAIN = 0, 1
+
+
+class PcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libpc error {code}: {msg}")
+        self.code = code
+
+
+class pc_catalog(ctypes.Structure):
+    _fields_ = [("ra_deg", ctypes.c_void_p), ("dec_deg", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("on_device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pc_job(ctypes.Structure):
+    _fields_ = [("A", ctypes.POINTER(pc_catalog)), ("B", ctypes.POINTER(pc_catalog)),
+                ("theta_edges_deg", ctypes.c_void_p), ("n_edges", ctypes.c_int32),
+                ("auto_flag", ctypes.c_int32), ("row_begin", ctypes.c_int64),
+                ("row_end", ctypes.c_int64), ("counts", ctypes.c_void_p)]
+
+
+_lib = None
+
+_i32, _i64, _u64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
+_PCAT = ctypes.POINTER(pc_catalog)
+
+_SIGNATURES = {
+    "pc_count": ([_PCAT, _PCAT, _vp, _i32, _i32, _vp, _vp], ctypes.c_int),
+    "pc_count_ex": ([_PCAT, _PCAT, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp], ctypes.c_int),
+    "pc_count_batch": ([ctypes.POINTER(pc_job), _i32, _i32, _vp], ctypes.c_int),
+    "pc_wtheta": ([_vp, _vp, _vp, _i32, _i64, _i64, _vp], ctypes.c_int),
+    "pc_last_error": ([], ctypes.c_char_p),
+    "pc_version": ([], ctypes.c_char_p),
+    "pc_catalog_upload": ([_PCAT, _vp, ctypes.POINTER(_u64)], ctypes.c_int),
+    "pc_catalog_release": ([_u64], ctypes.c_int),
+    "pc_count_h": ([_u64, _u64, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp], ctypes.c_int),
+    "pc_unit_vectors": ([_PCAT, _vp, _vp, _vp], ctypes.c_int),
+    "pc_chord2_edges": ([_vp, _i32, _vp], ctypes.c_int),
+    "pc_guard_band": ([_vp, _i32, _vp, _vp], ctypes.c_int),
+    "pc_debug_lut32": ([_vp, _i32, _vp, _vp, _i64], ctypes.c_int),
+    "pc_debug_set_timing": ([_i32], ctypes.c_int),
+    "pc_debug_last_launch": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "pc_server_create": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
+    "pc_server_set_random": ([_vp, _i32, _PCAT], ctypes.c_int),
+    "pc_server_submit": ([_vp, _PCAT, _i32, _vp, _i32, ctypes.POINTER(_u64)], ctypes.c_int),
+    "pc_server_poll": ([_vp, _u64, ctypes.POINTER(_i32), _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "pc_server_drain": ([_vp], ctypes.c_int),
+    "pc_server_stats": ([_vp], ctypes.c_char_p),
+    "pc_server_destroy": ([_vp], ctypes.c_int),
+}
+
+
+def lib():
+    """The loaded libpc.so.  Raises ImportError when it has not been built:
+    there is no fallback implementation."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1208_3658_amd.build` "
+                              "(or __graft_entry__.build()); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (argt, rest) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = argt
+            f.restype = rest
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PC_OK:
+        raise PcError(rc, lib().pc_last_error().decode())
+
+
+def pc_last_error() -> str:
+    return lib().pc_last_error().decode()
+
+
+def pc_version() -> str:
+    return lib().pc_version().decode()
+
+
+# ---------------------------------------------------------------- marshalling
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+class Catalog:
+    """Holds a pc_catalog and keeps its arrays alive."""
+
+    def __init__(self, ra, dec):
+        if _is_torch(ra):
+            if ra.dtype != dec.dtype or str(ra.dtype) != "torch.float64":
+                raise TypeError("catalogue tensors must be float64")
+            if ra.device != dec.device:
+                raise ValueError("ra and dec on different devices")
+            if ra.is_cuda:
+                ra, dec = ra.contiguous(), dec.contiguous()
+                self.keep = (ra, dec)
+                self.c = pc_catalog(ra.data_ptr(), dec.data_ptr(), ra.numel(), 1, 0)
+                if ra.numel() != dec.numel():
+                    raise ValueError("ra and dec differ in length")
+                return
+            ra, dec = ra.numpy(), dec.numpy()
+        ra = np.ascontiguousarray(ra, dtype=np.float64)
+        dec = np.ascontiguousarray(dec, dtype=np.float64)
+        if ra.shape != dec.shape or ra.ndim != 1:
+            raise ValueError("ra and dec must be 1-D arrays of equal length")
+        self.keep = (ra, dec)
+        self.c = pc_catalog(ra.ctypes.data, dec.ctypes.data, ra.size, 0, 0)
+
+    @property
+    def n(self) -> int:
+        return int(self.c.n)
+
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def as_catalog(x) -> Catalog:
+    if isinstance(x, Catalog):
+        return x
+    ra, dec = x
+    return Catalog(ra, dec)
+
+
+def _edges(theta):
+    t = np.ascontiguousarray(theta, dtype=np.float64)
+    return t, t.ctypes.data
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+# --------------------------------------------------------------------- API
+
+def pc_count(A, theta_edges, B=None, auto: bool = True, stream=None) -> np.ndarray:
+    """Pair counts [under, bins, over] (uint64, len(theta_edges)+1)."""
+    return pc_count_ex(A, theta_edges, B=B, auto=auto, mode=PC_MIXED, stream=stream)
+
+
+def pc_count_ex(A, theta_edges, B=None, auto: bool = True, mode: int = PC_MIXED,
+                rows=(0, -1), stream=None) -> np.ndarray:
+    a = as_catalog(A)
+    b = None if auto else as_catalog(B)
+    t, tp = _edges(theta_edges)
+    out = np.zeros(t.size + 1, dtype=np.uint64)
+    _check(lib().pc_count_ex(a.ref(), None if b is None else b.ref(), tp, t.size, 1 if auto else 0,
+                             int(mode), int(rows[0]), int(rows[1]), out.ctypes.data, _stream(stream)))
+    return out
+
+
+def pc_count_batch(jobs, mode: int = PC_MIXED, stream=None):
+    """jobs: list of dicts {A, B (cross only), edges, auto, rows}.  Returns a
+    list of count arrays, one per job, from one launch."""
+    keep = []
+    cats = {}
+
+    def cat(x):
+        key = id(x)
+        if key not in cats:
+            cats[key] = as_catalog(x)
+        return cats[key]
+
+    arr = (pc_job * len(jobs))()
+    outs = []
+    for q, j in enumerate(jobs):
+        a = cat(j["A"])
+        auto = bool(j.get("auto", True))
+        b = None if auto else cat(j["B"])
+        t, tp = _edges(j["edges"])
+        out = np.zeros(t.size + 1, dtype=np.uint64)
+        r0, r1 = j.get("rows", (0, -1))
+        keep += [a, b, t, out]
+        arr[q] = pc_job(ctypes.pointer(a.c), None if b is None else ctypes.pointer(b.c), tp, t.size,
+                        1 if auto else 0, int(r0), int(r1), out.ctypes.data)
+        outs.append(out)
+    _check(lib().pc_count_batch(arr, len(jobs), int(mode), _stream(stream)))
+    return outs
+
+
+def pc_wtheta(DD, DR, RR, nD: int, nR: int) -> np.ndarray:
+    """Landy-Szalay w(theta) from in-range bin counts (pass counts[1:-1])."""
+    DD = np.ascontiguousarray(DD, dtype=np.uint64)
+    DR = np.ascontiguousarray(DR, dtype=np.uint64)
+    RR = np.ascontiguousarray(RR, dtype=np.uint64)
+    if not (DD.size == DR.size == RR.size):
+        raise ValueError("DD, DR, RR differ in length")
+    w = np.empty(DD.size, dtype=np.float64)
+    _check(lib().pc_wtheta(DD.ctypes.data, DR.ctypes.data, RR.ctypes.data, DD.size, int(nD), int(nR),
+                           w.ctypes.data))
+    return w
+
+
+def pc_catalog_upload(A, stream=None) -> int:
+    a = as_catalog(A)
+    h = _u64(0)
+    _check(lib().pc_catalog_upload(a.ref(), _stream(stream), ctypes.byref(h)))
+    return int(h.value)
+
+
+def pc_catalog_release(handle: int):
+    _check(lib().pc_catalog_release(int(handle)))
+
+
+def pc_count_h(hA: int, theta_edges, hB: int = 0, auto: bool = True, mode: int = PC_MIXED,
+               rows=(0, -1), stream=None) -> np.ndarray:
+    t, tp = _edges(theta_edges)
+    out = np.zeros(t.size + 1, dtype=np.uint64)
+    _check(lib().pc_count_h(int(hA), int(hB), tp, t.size, 1 if auto else 0, int(mode), int(rows[0]),
+                            int(rows[1]), out.ctypes.data, _stream(stream)))
+    return out
+
+
+def pc_unit_vectors(A, stream=None):
+    a = as_catalog(A)
+    x64 = np.empty((a.n, 3), dtype=np.float64)
+    x32 = np.empty((a.n, 3), dtype=np.float32)
+    _check(lib().pc_unit_vectors(a.ref(), x64.ctypes.data, x32.ctypes.data, _stream(stream)))
+    return x64, x32
+
+
+def pc_chord2_edges(theta_edges) -> np.ndarray:
+    t, tp = _edges(theta_edges)
+    e = np.empty(t.size, dtype=np.float64)
+    _check(lib().pc_chord2_edges(tp, t.size, e.ctypes.data))
+    return e
+
+
+def pc_guard_band(theta_edges):
+    t, tp = _edges(theta_edges)
+    lo = np.empty(t.size, dtype=np.float32)
+    hi = np.empty(t.size, dtype=np.float32)
+    _check(lib().pc_guard_band(tp, t.size, lo.ctypes.data, hi.ctypes.data))
+    return lo, hi
+
+
+def pc_debug_lut32(theta_edges):
+    t, tp = _edges(theta_edges)
+    info = np.zeros(8, dtype=np.int64)
+    _check(lib().pc_debug_lut32(tp, t.size, info.ctypes.data, None, 0))
+    ent = np.zeros((int(info[0]), 4), dtype=np.uint32)
+    _check(lib().pc_debug_lut32(tp, t.size, info.ctypes.data, ent.ctypes.data, int(info[0])))
+    keys = ["n_cells", "shift", "clamp_lo", "clamp_hi", "row_bytes", "cols", "multi", "_"]
+    return dict(zip(keys, (int(v) for v in info))), ent
+
+
+def pc_debug_set_timing(on: bool):
+    _check(lib().pc_debug_set_timing(1 if on else 0))
+
+
+def pc_debug_last_launch() -> dict:
+    ms = ctypes.c_double(0)
+    items = _u64(0)
+    grid = _i32(0)
+    lds = ctypes.c_uint32(0)
+    _check(lib().pc_debug_last_launch(ctypes.byref(ms), ctypes.byref(items), ctypes.byref(grid), ctypes.byref(lds)))
+    return {"kernel_ms": ms.value, "items": int(items.value), "grid": int(grid.value), "lds_bytes": int(lds.value)}
+
+
+# ------------------------------------------------------------------ serving
+
+class Server:
+    """w(theta) request server (pc_server_*)."""
+
+    def __init__(self, config: dict | None = None):
+        self._h = _vp()
+        cfg = None if config is None else json.dumps(config).encode()
+        _check(lib().pc_server_create(cfg, ctypes.byref(self._h)))
+        self._keep = {}
+
+    def set_random(self, patch_id: int, R):
+        r = as_catalog(R)
+        _check(lib().pc_server_set_random(self._h, int(patch_id), r.ref()))
+
+    def submit(self, D, patch_id: int, theta_edges) -> int:
+        d = as_catalog(D)
+        t, tp = _edges(theta_edges)
+        jid = _u64(0)
+        _check(lib().pc_server_submit(self._h, d.ref(), int(patch_id), tp, t.size, ctypes.byref(jid)))
+        self._keep[int(jid.value)] = t.size
+        return int(jid.value)
+
+    def poll(self, job_id: int):
+        """None while running; else dict with DD, DR, RR, w, latency_s."""
+        ne = self._keep[job_id]
+        DD = np.zeros(ne + 1, dtype=np.uint64)
+        DR = np.zeros(ne + 1, dtype=np.uint64)
+        RR = np.zeros(ne + 1, dtype=np.uint64)
+        w = np.zeros(max(ne - 1, 1), dtype=np.float64)
+        lat = ctypes.c_double(0.0)
+        done = _i32(0)
+        rc = lib().pc_server_poll(self._h, int(job_id), ctypes.byref(done), DD.ctypes.data, DR.ctypes.data,
+                                  RR.ctypes.data, w.ctypes.data, ctypes.byref(lat))
+        if done.value == 0:
+            return None
+        del self._keep[job_id]
+        _check(rc)
+        return {"DD": DD, "DR": DR, "RR": RR, "w": w[: ne - 1], "latency_s": lat.value}
+
+    def drain(self):
+        _check(lib().pc_server_drain(self._h))
+
+    def stats(self) -> dict:
+        return json.loads(lib().pc_server_stats(self._h).decode())
+
+    def close(self):
+        if self._h:
+            _check(lib().pc_server_destroy(self._h))
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

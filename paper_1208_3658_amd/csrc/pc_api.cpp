@@ -1,0 +1,781 @@
+// pc_api.cpp -- the C ABI of libpc.so: validation, device memory, edge-set
+// tables, catalogue conversion and residency, and the batched launch.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pc.h"
+#include "pc_internal.hpp"
+#include "pc_math.h"
+#include "pc_runtime.hpp"
+#include "../../include/pc_debug.h"
+
+namespace pc {
+
+hipError_t launch_convert(const double *ra, const double *dec, int64_t n, double4 *a64, float4 *a32,
+                          int *err, hipStream_t st);
+hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st);
+hipError_t launch_count(bool fp64, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
+                        uint64_t total_items, uint32_t lut_lds_off, uint32_t lds_bytes, int grid,
+                        hipStream_t st);
+hipError_t count_occupancy(bool fp64, uint32_t lds_bytes, int *blocks_per_cu);
+hipError_t set_max_lds(uint32_t bytes);
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string t_err;
+
+int fail(int code, const std::string &msg) {
+    t_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(PC_ERR_NOMEM, std::string(what) + ": " + hipGetErrorString(e));
+    return fail(PC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define PC_HIP(call, what)                                  \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, (what));  \
+    } while (0)
+
+void clear_error() { t_err.clear(); }
+
+// ------------------------------------------------------------------ device
+
+static std::mutex g_dev_mu;
+static std::map<int, DeviceInfo> g_dev;
+
+int device_info(DeviceInfo **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev.find(dev);
+    if (it == g_dev.end()) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        DeviceInfo d;
+        d.device = dev;
+        d.cus = prop.multiProcessorCount;
+        d.lds_per_block = static_cast<uint32_t>(prop.sharedMemPerBlock);
+        d.lds_per_cu = static_cast<uint32_t>(prop.maxSharedMemoryPerMultiProcessor);
+        d.arch = prop.gcnArchName;
+        d.ok = d.arch.rfind("gfx950", 0) == 0;
+        if (d.ok) {
+            const uint32_t want = std::max<uint32_t>(d.lds_per_block, 64u * 1024u);
+            if (set_max_lds(want) == hipSuccess) d.lds_per_block = want;
+        }
+        it = g_dev.emplace(dev, d).first;
+    }
+    if (!it->second.ok)
+        return fail(PC_ERR_DEVICE, "libpc needs an AMD gfx950 (MI355X) device; current device is " +
+                                       it->second.arch);
+    *out = &it->second;
+    return PC_OK;
+}
+
+// ------------------------------------------------------------------ tables
+
+struct TableKey {
+    int device;
+    std::vector<uint64_t> bits;
+    bool operator<(const TableKey &o) const {
+        if (device != o.device) return device < o.device;
+        return bits < o.bits;
+    }
+};
+
+static std::mutex g_tab_mu;
+static std::map<TableKey, std::shared_ptr<DevTable>> g_tabs;
+
+DevTable::~DevTable() {
+    if (d_mem) (void)hipFree(d_mem);
+}
+
+int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *out) {
+    if (!theta) return fail(PC_ERR_INVALID, "theta_edges_deg is NULL");
+    if (n_edges < 2) return fail(PC_ERR_INVALID, "n_edges must be >= 2");
+    DeviceInfo *di = nullptr;
+    int rc = device_info(&di);
+    if (rc) return rc;
+    TableKey key;
+    key.device = di->device;
+    key.bits.resize(static_cast<size_t>(n_edges));
+    memcpy(key.bits.data(), theta, sizeof(double) * static_cast<size_t>(n_edges));
+    {
+        std::lock_guard<std::mutex> lk(g_tab_mu);
+        auto it = g_tabs.find(key);
+        if (it != g_tabs.end()) {
+            *out = it->second;
+            return PC_OK;
+        }
+    }
+    auto t = std::make_shared<DevTable>();
+    std::string err;
+    if (!build_table(theta, n_edges, t->host, err)) return fail(PC_ERR_INVALID, err);
+    const HostTable &h = t->host;
+    // one device block: e64 | lut32 | lut64
+    const size_t b_e = sizeof(double) * h.e64.size();
+    const size_t o_l32 = (b_e + 255) & ~size_t(255);
+    const size_t b_l32 = sizeof(LutEntry32) * h.lut32.size();
+    const size_t o_l64 = (o_l32 + b_l32 + 255) & ~size_t(255);
+    const size_t b_l64 = sizeof(LutEntry64) * h.lut64.size();
+    const size_t total = o_l64 + b_l64 + 256;
+    std::vector<unsigned char> blob(total, 0);
+    memcpy(blob.data(), h.e64.data(), b_e);
+    if (b_l32) memcpy(blob.data() + o_l32, h.lut32.data(), b_l32);
+    if (b_l64) memcpy(blob.data() + o_l64, h.lut64.data(), b_l64);
+    void *d = nullptr;
+    PC_HIP(hipMalloc(&d, total), "hipMalloc(tables)");
+    t->d_mem = d;
+    PC_HIP(hipMemcpy(d, blob.data(), total, hipMemcpyHostToDevice), "hipMemcpy(tables)");
+    unsigned char *base = static_cast<unsigned char *>(d);
+    t->d_e64 = reinterpret_cast<const double *>(base);
+    t->d_lut32 = base + o_l32;
+    t->d_lut64 = base + o_l64;
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto it = g_tabs.find(key);
+    if (it != g_tabs.end()) {
+        *out = it->second;  // another thread won; ours is freed
+        return PC_OK;
+    }
+    g_tabs.emplace(key, t);
+    *out = t;
+    return PC_OK;
+}
+
+TableDesc table_desc(const DevTable &t, bool fp64) {
+    TableDesc d;
+    memset(&d, 0, sizeof(d));
+    const HostTable &h = t.host;
+    d.e64 = t.d_e64;
+    d.n_edges = static_cast<int32_t>(h.e64.size());
+    d.cols = h.cols;
+    if (fp64) {
+        d.lut = t.d_lut64;
+        d.clamp_lo = h.clamp_lo64;
+        d.clamp_hi = h.clamp_hi64;
+        d.shift = h.shift64;
+        d.key0 = h.clamp_lo64 >> h.shift64;
+        d.n_cells = static_cast<int32_t>(h.lut64.size());
+        d.search = h.search64 ? 1 : 0;
+    } else {
+        d.lut = t.d_lut32;
+        d.clamp_lo = h.clamp_lo32;
+        d.clamp_hi = h.clamp_hi32;
+        d.shift = h.shift32;
+        d.key0 = h.clamp_lo32 >> h.shift32;
+        d.n_cells = static_cast<int32_t>(h.lut32.size());
+        d.search = 0;
+    }
+    return d;
+}
+
+// LDS bytes a table needs: histogram rows, then the cell table (or edges)
+static void table_lds(const DevTable &t, bool fp64, uint32_t *hist, uint32_t *lut) {
+    const HostTable &h = t.host;
+    *hist = static_cast<uint32_t>(h.e64.size() + 2) * h.row_bytes;
+    if (fp64)
+        *lut = h.search64 ? static_cast<uint32_t>(8 * h.e64.size())
+                          : static_cast<uint32_t>(16 * h.lut64.size());
+    else
+        *lut = static_cast<uint32_t>(16 * h.lut32.size());
+}
+
+// ------------------------------------------------------------- catalogues
+
+static std::mutex g_cat_mu;
+static std::unordered_map<uint64_t, std::shared_ptr<Resident>> g_cats;
+static std::atomic<uint64_t> g_next_handle{1};
+
+Resident::~Resident() {
+    if (d_mem) (void)hipFree(d_mem);
+}
+
+int validate_catalog(const pc_catalog *c, const char *name) {
+    if (!c) return fail(PC_ERR_INVALID, std::string(name) + " is NULL");
+    if (c->n < 0) return fail(PC_ERR_INVALID, std::string(name) + ".n < 0");
+    if (c->n > 0 && (!c->ra_deg || !c->dec_deg))
+        return fail(PC_ERR_INVALID, std::string(name) + " has NULL coordinate pointers");
+    if (c->n > (int64_t(1) << 40)) return fail(PC_ERR_INVALID, std::string(name) + ".n too large");
+    if (!c->on_device) {
+        for (int64_t i = 0; i < c->n; ++i) {
+            const double r = c->ra_deg[i], d = c->dec_deg[i];
+            if (!std::isfinite(r) || !std::isfinite(d) || d < -90.0 || d > 90.0)
+                return fail(PC_ERR_INVALID, std::string(name) + ": RA must be finite and Dec in [-90, 90] (index " +
+                                                std::to_string(i) + ")");
+        }
+    }
+    return PC_OK;
+}
+
+static int get_resident(uint64_t h, std::shared_ptr<Resident> *out) {
+    std::lock_guard<std::mutex> lk(g_cat_mu);
+    auto it = g_cats.find(h);
+    if (it == g_cats.end()) return fail(PC_ERR_INVALID, "unknown catalogue handle");
+    *out = it->second;
+    return PC_OK;
+}
+
+// Workspace for one batch: converted copies of the non-resident catalogues,
+// staging for host inputs, error flags, counters and descriptors, in one
+// stream-ordered allocation.
+struct Workspace {
+    void *mem = nullptr;
+    hipStream_t st = nullptr;
+    ~Workspace() {
+        if (mem) (void)hipFreeAsync(mem, st);
+    }
+};
+
+struct Arena {
+    size_t size = 0;
+    size_t take(size_t bytes) {
+        const size_t o = (size_t(size) + 255) & ~size_t(255);
+        size = o + bytes;
+        return o;
+    }
+};
+
+// ------------------------------------------------------------------- batch
+
+// optional per-thread timing of the counting kernel (HIP events on its stream)
+static thread_local bool t_timing = false;
+static thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
+static thread_local BatchStats t_last;
+
+int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, BatchStats *stats) {
+    if (jobs.empty()) return fail(PC_ERR_INVALID, "no jobs");
+    if (mode != PC_MIXED && mode != PC_FP64_PLAIN) return fail(PC_ERR_INVALID, "unknown mode");
+    const bool fp64 = mode == PC_FP64_PLAIN;
+    // host-side validation first, so bad arguments are reported as such
+    for (const BatchJob &j : jobs) {
+        if (j.auto_flag != 0 && j.auto_flag != 1) return fail(PC_ERR_INVALID, "auto_flag must be 0 or 1");
+        std::string err;
+        if (!validate_edges(j.theta, j.n_edges, err)) return fail(PC_ERR_INVALID, err);
+        if (!j.counts) return fail(PC_ERR_INVALID, "counts is NULL");
+        int r = j.hA ? PC_OK : validate_catalog(j.A, "A");
+        if (r) return r;
+        if (!j.auto_flag) {
+            r = j.hB ? PC_OK : validate_catalog(j.B, "B");
+            if (r) return r;
+        }
+        if (!j.hA) {
+            const int64_t nA = j.A->n;
+            const int64_t r0 = j.row_begin, r1 = j.row_end < 0 ? nA : j.row_end;
+            if (r0 < 0 || r1 > nA || r0 > r1)
+                return fail(PC_ERR_INVALID, "row range [" + std::to_string(r0) + ", " + std::to_string(r1) +
+                                                ") outside [0, " + std::to_string(nA) + "]");
+        }
+    }
+    DeviceInfo *di = nullptr;
+    int rc = device_info(&di);
+    if (rc) return rc;
+
+    // ---- unique catalogues to convert
+    struct Conv {
+        const pc_catalog *c;
+        size_t o_a64, o_a32, o_ra, o_dec;
+    };
+    std::vector<Conv> convs;
+    std::map<std::tuple<const double *, const double *, int64_t>, int> conv_idx;
+    struct Side {
+        int conv = -1;                       // index into convs, or -1
+        std::shared_ptr<Resident> res;       // resident catalogue
+        int64_t n = 0;
+    };
+    std::vector<Side> sideA(jobs.size()), sideB(jobs.size());
+    Arena ar;
+    auto add_side = [&](const BatchJob &j, bool is_a, Side &sd) -> int {
+        if (is_a ? j.hA : j.hB) {
+            int r = get_resident(is_a ? j.hA : j.hB, &sd.res);
+            if (r) return r;
+            sd.n = sd.res->n;
+            return PC_OK;
+        }
+        const pc_catalog *c = is_a ? j.A : j.B;
+        sd.n = c->n;
+        auto key = std::make_tuple(c->ra_deg, c->dec_deg, c->n);
+        auto it = conv_idx.find(key);
+        if (it != conv_idx.end()) {
+            sd.conv = it->second;
+            return PC_OK;
+        }
+        Conv cv;
+        cv.c = c;
+        cv.o_a64 = ar.take(sizeof(double4) * static_cast<size_t>(std::max<int64_t>(c->n, 1)));
+        cv.o_a32 = ar.take(sizeof(float4) * static_cast<size_t>(std::max<int64_t>(c->n, 1)));
+        cv.o_ra = cv.o_dec = 0;
+        if (!c->on_device && c->n > 0) {
+            cv.o_ra = ar.take(sizeof(double) * static_cast<size_t>(c->n));
+            cv.o_dec = ar.take(sizeof(double) * static_cast<size_t>(c->n));
+        }
+        sd.conv = static_cast<int>(convs.size());
+        conv_idx.emplace(key, sd.conv);
+        convs.push_back(cv);
+        return PC_OK;
+    };
+
+    std::vector<std::shared_ptr<DevTable>> tabs;
+    std::map<const DevTable *, int> tab_idx;
+    std::vector<int> job_tab(jobs.size());
+    std::vector<size_t> job_counts_off(jobs.size());
+    for (size_t q = 0; q < jobs.size(); ++q) {
+        const BatchJob &j = jobs[q];
+        if (j.auto_flag != 0 && j.auto_flag != 1) return fail(PC_ERR_INVALID, "auto_flag must be 0 or 1");
+        rc = add_side(j, true, sideA[q]);
+        if (rc) return rc;
+        if (!j.auto_flag) {
+            rc = add_side(j, false, sideB[q]);
+            if (rc) return rc;
+        }
+        std::shared_ptr<DevTable> t;
+        rc = get_table(j.theta, j.n_edges, &t);
+        if (rc) return rc;
+        auto it = tab_idx.find(t.get());
+        if (it == tab_idx.end()) {
+            it = tab_idx.emplace(t.get(), static_cast<int>(tabs.size())).first;
+            tabs.push_back(t);
+        }
+        job_tab[q] = it->second;
+        const int64_t nA = sideA[q].n;
+        const int64_t r0 = j.row_begin, r1 = j.row_end < 0 ? nA : j.row_end;
+        if (r0 < 0 || r1 > nA || r0 > r1)
+            return fail(PC_ERR_INVALID, "row range [" + std::to_string(r0) + ", " + std::to_string(r1) +
+                                            ") outside [0, " + std::to_string(nA) + "]");
+        if (!j.counts) return fail(PC_ERR_INVALID, "counts is NULL");
+        job_counts_off[q] = ar.take(sizeof(unsigned long long) * static_cast<size_t>(j.n_edges + 1));
+    }
+    const size_t o_err = ar.take(sizeof(int) * std::max<size_t>(convs.size(), 1));
+
+    // ---- segments
+    std::vector<SegDesc> segs;
+    uint64_t items = 0;
+    auto tiles = [](int64_t n) { return (n + kTile - 1) / kTile; };
+    for (size_t q = 0; q < jobs.size(); ++q) {
+        const BatchJob &j = jobs[q];
+        const int64_t nA = sideA[q].n;
+        const int64_t r0 = j.row_begin, r1 = j.row_end < 0 ? nA : j.row_end;
+        auto add = [&](bool tri, int64_t i0, int64_t ni, int64_t j0, int64_t nj) {
+            if (ni <= 0 || nj <= 0) return;
+            SegDesc s;
+            memset(&s, 0, sizeof(s));
+            s.tri = tri ? 1 : 0;
+            s.i0 = i0;
+            s.ni = ni;
+            s.j0 = j0;
+            s.nj = nj;
+            s.tiles_i = tiles(ni);
+            s.tiles_j = tiles(nj);
+            s.n_items = tri ? static_cast<uint64_t>(s.tiles_i) * static_cast<uint64_t>(s.tiles_i + 1) / 2
+                            : static_cast<uint64_t>(s.tiles_i) * static_cast<uint64_t>(s.tiles_j);
+            s.item0 = items;
+            items += s.n_items;
+            s.tab = job_tab[q];
+            s.job = static_cast<int32_t>(q);
+            s.pad = j.auto_flag ? 1 : 0;  // side B of the segment is side A of the job
+            segs.push_back(s);
+        };
+        if (j.auto_flag) {
+            add(true, r0, r1 - r0, r0, r1 - r0);
+            add(false, r0, r1 - r0, r1, nA - r1);
+        } else {
+            add(false, r0, r1 - r0, 0, sideB[q].n);
+        }
+    }
+    const size_t o_segs = ar.take(sizeof(SegDesc) * std::max<size_t>(segs.size(), 1));
+    const size_t o_tabs = ar.take(sizeof(TableDesc) * tabs.size());
+
+    // ---- allocate the workspace
+    Workspace ws;
+    ws.st = st;
+    PC_HIP(hipMallocAsync(&ws.mem, ar.size, st), "hipMallocAsync(workspace)");
+    unsigned char *W = static_cast<unsigned char *>(ws.mem);
+
+    // ---- convert catalogues, check their validity flags
+    if (!convs.empty()) {
+        PC_HIP(hipMemsetAsync(W + o_err, 0, sizeof(int) * convs.size(), st), "hipMemsetAsync(err)");
+        bool any_device_input = false;
+        for (size_t k = 0; k < convs.size(); ++k) {
+            const pc_catalog *c = convs[k].c;
+            if (c->n <= 0) continue;
+            const double *ra = c->ra_deg, *dec = c->dec_deg;
+            if (!c->on_device) {
+                double *dra = reinterpret_cast<double *>(W + convs[k].o_ra);
+                double *ddec = reinterpret_cast<double *>(W + convs[k].o_dec);
+                PC_HIP(hipMemcpyAsync(dra, ra, sizeof(double) * c->n, hipMemcpyHostToDevice, st), "H2D ra");
+                PC_HIP(hipMemcpyAsync(ddec, dec, sizeof(double) * c->n, hipMemcpyHostToDevice, st), "H2D dec");
+                ra = dra;
+                dec = ddec;
+            } else {
+                any_device_input = true;
+            }
+            PC_HIP(launch_convert(ra, dec, c->n, reinterpret_cast<double4 *>(W + convs[k].o_a64),
+                                  reinterpret_cast<float4 *>(W + convs[k].o_a32),
+                                  reinterpret_cast<int *>(W + o_err) + k, st),
+                   "convert");
+        }
+        if (any_device_input) {
+            std::vector<int> flags(convs.size());
+            PC_HIP(hipMemcpyAsync(flags.data(), W + o_err, sizeof(int) * convs.size(), hipMemcpyDeviceToHost, st),
+                   "D2H flags");
+            PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+            for (size_t k = 0; k < convs.size(); ++k)
+                if (flags[k]) return fail(PC_ERR_INVALID, "catalogue has non-finite RA/Dec or |Dec| > 90");
+        }
+    }
+
+    // ---- descriptors
+    auto side_ptrs = [&](const Side &sd, const float4 **p32, const double4 **p64) {
+        if (sd.res) {
+            *p32 = sd.res->a32;
+            *p64 = sd.res->a64;
+        } else {
+            *p32 = reinterpret_cast<const float4 *>(W + convs[sd.conv].o_a32);
+            *p64 = reinterpret_cast<const double4 *>(W + convs[sd.conv].o_a64);
+        }
+    };
+    for (SegDesc &s : segs) {
+        const size_t q = static_cast<size_t>(s.job);
+        side_ptrs(sideA[q], &s.i32, &s.i64);
+        if (s.pad) side_ptrs(sideA[q], &s.j32, &s.j64);
+        else side_ptrs(sideB[q], &s.j32, &s.j64);
+        s.pad = 0;
+        s.counts = reinterpret_cast<unsigned long long *>(W + job_counts_off[q]);
+    }
+    std::vector<TableDesc> tds;
+    uint32_t hist_max = 0, lut_max = 0;
+    for (auto &t : tabs) {
+        tds.push_back(table_desc(*t, fp64));
+        uint32_t h, l;
+        table_lds(*t, fp64, &h, &l);
+        hist_max = std::max(hist_max, h);
+        lut_max = std::max(lut_max, l);
+    }
+    for (size_t k = 0; k < tds.size(); ++k) {
+        // nothing
+    }
+    const uint32_t lut_off = (hist_max + 15u) & ~15u;
+    const uint32_t lds_bytes = lut_off + std::max<uint32_t>(lut_max, 16u);
+    if (lds_bytes > di->lds_per_block)
+        return fail(PC_ERR_INVALID, "edge set needs " + std::to_string(lds_bytes) +
+                                        " bytes of LDS per wave; the device allows " +
+                                        std::to_string(di->lds_per_block));
+    if (!segs.empty())
+        PC_HIP(hipMemcpyAsync(W + o_segs, segs.data(), sizeof(SegDesc) * segs.size(), hipMemcpyHostToDevice, st),
+               "H2D segments");
+    PC_HIP(hipMemcpyAsync(W + o_tabs, tds.data(), sizeof(TableDesc) * tds.size(), hipMemcpyHostToDevice, st),
+           "H2D tables");
+    int64_t n_counts = 0;
+    for (auto &j : jobs) n_counts += j.n_edges + 1;
+    // counters are contiguous in job order (taken consecutively from the arena
+    // after each job's table lookup); zero each job's block
+    for (size_t q = 0; q < jobs.size(); ++q)
+        PC_HIP(launch_zero(reinterpret_cast<unsigned long long *>(W + job_counts_off[q]), jobs[q].n_edges + 1, st),
+               "zero counts");
+
+    // ---- launch
+    int grid = 0;
+    if (items > 0) {
+        int per_cu = 0;
+        PC_HIP(count_occupancy(fp64, lds_bytes, &per_cu), "occupancy");
+        per_cu = std::max(per_cu, 1);
+        int64_t g = static_cast<int64_t>(di->cus) * per_cu;
+        g = std::min<int64_t>(g, static_cast<int64_t>(items));
+        if (g >= 8) g -= g % 8;
+        grid = static_cast<int>(std::max<int64_t>(g, 1));
+        const bool timed = t_timing;
+        if (timed) {
+            if (!t_ev0) {
+                PC_HIP(hipEventCreate(&t_ev0), "hipEventCreate");
+                PC_HIP(hipEventCreate(&t_ev1), "hipEventCreate");
+            }
+            PC_HIP(hipEventRecord(t_ev0, st), "hipEventRecord");
+        }
+        PC_HIP(launch_count(fp64, reinterpret_cast<const SegDesc *>(W + o_segs), static_cast<int32_t>(segs.size()),
+                            reinterpret_cast<const TableDesc *>(W + o_tabs), items, lut_off, lds_bytes, grid, st),
+               "count kernel");
+        if (timed) PC_HIP(hipEventRecord(t_ev1, st), "hipEventRecord");
+    }
+
+    // ---- results
+    for (size_t q = 0; q < jobs.size(); ++q)
+        PC_HIP(hipMemcpyAsync(jobs[q].counts, W + job_counts_off[q], sizeof(uint64_t) * (jobs[q].n_edges + 1),
+                              hipMemcpyDeviceToHost, st),
+               "D2H counts");
+    PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    t_last = BatchStats();
+    t_last.items = items;
+    t_last.grid = grid;
+    t_last.lds_bytes = lds_bytes;
+    t_last.segments = static_cast<int>(segs.size());
+    t_last.kernel_ms = -1.0;
+    if (t_timing && items > 0) {
+        float ms = 0.0f;
+        PC_HIP(hipEventElapsedTime(&ms, t_ev0, t_ev1), "hipEventElapsedTime");
+        t_last.kernel_ms = ms;
+    }
+    if (stats) {
+        stats->items = items;
+        stats->grid = grid;
+        stats->lds_bytes = lds_bytes;
+        stats->segments = static_cast<int>(segs.size());
+    }
+    (void)n_counts;
+    return PC_OK;
+}
+
+int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
+    int rc = validate_catalog(c, "catalogue");
+    if (rc) return rc;
+    if (!handle) return fail(PC_ERR_INVALID, "handle is NULL");
+    DeviceInfo *di = nullptr;
+    rc = device_info(&di);
+    if (rc) return rc;
+    auto r = std::make_shared<Resident>();
+    r->n = c->n;
+    r->device = di->device;
+    const size_t n = static_cast<size_t>(std::max<int64_t>(c->n, 1));
+    Arena ar;
+    const size_t o64 = ar.take(sizeof(double4) * n);
+    const size_t o32 = ar.take(sizeof(float4) * n);
+    const size_t oerr = ar.take(sizeof(int));
+    size_t ora = 0, odec = 0;
+    if (!c->on_device) {
+        ora = ar.take(sizeof(double) * n);
+        odec = ar.take(sizeof(double) * n);
+    }
+    PC_HIP(hipMalloc(&r->d_mem, ar.size), "hipMalloc(catalogue)");
+    unsigned char *W = static_cast<unsigned char *>(r->d_mem);
+    r->a64 = reinterpret_cast<double4 *>(W + o64);
+    r->a32 = reinterpret_cast<float4 *>(W + o32);
+    PC_HIP(hipMemsetAsync(W + oerr, 0, sizeof(int), st), "hipMemsetAsync");
+    if (c->n > 0) {
+        const double *ra = c->ra_deg, *dec = c->dec_deg;
+        if (!c->on_device) {
+            PC_HIP(hipMemcpyAsync(W + ora, ra, sizeof(double) * c->n, hipMemcpyHostToDevice, st), "H2D ra");
+            PC_HIP(hipMemcpyAsync(W + odec, dec, sizeof(double) * c->n, hipMemcpyHostToDevice, st), "H2D dec");
+            ra = reinterpret_cast<const double *>(W + ora);
+            dec = reinterpret_cast<const double *>(W + odec);
+        }
+        PC_HIP(launch_convert(ra, dec, c->n, r->a64, r->a32, reinterpret_cast<int *>(W + oerr), st), "convert");
+    }
+    int flag = 0;
+    PC_HIP(hipMemcpyAsync(&flag, W + oerr, sizeof(int), hipMemcpyDeviceToHost, st), "D2H flag");
+    PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (flag) return fail(PC_ERR_INVALID, "catalogue has non-finite RA/Dec or |Dec| > 90");
+    const uint64_t h = g_next_handle.fetch_add(1);
+    {
+        std::lock_guard<std::mutex> lk(g_cat_mu);
+        g_cats.emplace(h, r);
+    }
+    *handle = h;
+    return PC_OK;
+}
+
+int release_catalog(uint64_t h) {
+    std::shared_ptr<Resident> r;
+    {
+        std::lock_guard<std::mutex> lk(g_cat_mu);
+        auto it = g_cats.find(h);
+        if (it == g_cats.end()) return fail(PC_ERR_INVALID, "unknown catalogue handle");
+        r = it->second;
+        g_cats.erase(it);
+    }
+    // the allocation goes when the last user (a running batch) drops it
+    return PC_OK;
+}
+
+int resident_catalog(uint64_t h, std::shared_ptr<Resident> *out) { return get_resident(h, out); }
+
+}  // namespace pc
+
+// ===================================================================== C ABI
+
+using namespace pc;
+
+extern "C" {
+
+const char *pc_last_error(void) { return t_err.c_str(); }
+
+const char *pc_version(void) { return "pc 0.1 gfx950"; }
+
+int pc_count_ex(const pc_catalog *A, const pc_catalog *B, const double *theta_edges_deg, int32_t n_edges,
+                int32_t auto_flag, int32_t mode, int64_t row_begin, int64_t row_end, uint64_t *counts,
+                void *stream) {
+    clear_error();
+    BatchJob j;
+    j.A = A;
+    j.B = B;
+    j.theta = theta_edges_deg;
+    j.n_edges = n_edges;
+    j.auto_flag = auto_flag;
+    j.row_begin = row_begin;
+    j.row_end = row_end;
+    j.counts = counts;
+    std::vector<BatchJob> v(1, j);
+    return run_batch(v, mode, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int pc_count(const pc_catalog *A, const pc_catalog *B, const double *theta_edges_deg, int32_t n_edges,
+             int32_t auto_flag, uint64_t *counts, void *stream) {
+    return pc_count_ex(A, B, theta_edges_deg, n_edges, auto_flag, PC_MIXED, 0, -1, counts, stream);
+}
+
+int pc_count_batch(const pc_job *jobs, int32_t n_jobs, int32_t mode, void *stream) {
+    clear_error();
+    if (!jobs || n_jobs < 1) return fail(PC_ERR_INVALID, "jobs is NULL or n_jobs < 1");
+    std::vector<BatchJob> v(static_cast<size_t>(n_jobs));
+    for (int32_t q = 0; q < n_jobs; ++q) {
+        v[q].A = jobs[q].A;
+        v[q].B = jobs[q].B;
+        v[q].theta = jobs[q].theta_edges_deg;
+        v[q].n_edges = jobs[q].n_edges;
+        v[q].auto_flag = jobs[q].auto_flag;
+        v[q].row_begin = jobs[q].row_begin;
+        v[q].row_end = jobs[q].row_end;
+        v[q].counts = jobs[q].counts;
+    }
+    return run_batch(v, mode, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int pc_wtheta(const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_t n_bins, int64_t nD, int64_t nR,
+              double *w) {
+    clear_error();
+    if (!DD || !DR || !RR || !w) return fail(PC_ERR_INVALID, "NULL argument");
+    if (n_bins < 1) return fail(PC_ERR_INVALID, "n_bins must be >= 1");
+    if (nD < 2 || nR < 2) return fail(PC_ERR_INVALID, "nD and nR must be >= 2");
+    landy_szalay(DD, DR, RR, n_bins, nD, nR, w);
+    return PC_OK;
+}
+
+int pc_catalog_upload(const pc_catalog *c, void *stream, uint64_t *handle) {
+    clear_error();
+    return upload_catalog(c, static_cast<hipStream_t>(stream), handle);
+}
+
+int pc_catalog_release(uint64_t handle) {
+    clear_error();
+    return release_catalog(handle);
+}
+
+int pc_count_h(uint64_t hA, uint64_t hB, const double *theta_edges_deg, int32_t n_edges, int32_t auto_flag,
+               int32_t mode, int64_t row_begin, int64_t row_end, uint64_t *counts, void *stream) {
+    clear_error();
+    if (!hA || (!auto_flag && !hB)) return fail(PC_ERR_INVALID, "catalogue handle is 0");
+    BatchJob j;
+    j.hA = hA;
+    j.hB = auto_flag ? 0 : hB;
+    j.theta = theta_edges_deg;
+    j.n_edges = n_edges;
+    j.auto_flag = auto_flag;
+    j.row_begin = row_begin;
+    j.row_end = row_end;
+    j.counts = counts;
+    std::vector<BatchJob> v(1, j);
+    return run_batch(v, mode, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int pc_unit_vectors(const pc_catalog *c, double *xyz64, float *xyz32, void *stream) {
+    clear_error();
+    uint64_t h = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = upload_catalog(c, st, &h);
+    if (rc) return rc;
+    std::shared_ptr<Resident> r;
+    get_resident(h, &r);
+    release_catalog(h);
+    const size_t n = static_cast<size_t>(c->n);
+    if (n > 0) {
+        std::vector<double4> v64(n);
+        std::vector<float4> v32(n);
+        PC_HIP(hipMemcpyAsync(v64.data(), r->a64, sizeof(double4) * n, hipMemcpyDeviceToHost, st), "D2H a64");
+        PC_HIP(hipMemcpyAsync(v32.data(), r->a32, sizeof(float4) * n, hipMemcpyDeviceToHost, st), "D2H a32");
+        PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+        for (size_t i = 0; i < n; ++i) {
+            if (xyz64) {
+                xyz64[3 * i + 0] = v64[i].x;
+                xyz64[3 * i + 1] = v64[i].y;
+                xyz64[3 * i + 2] = v64[i].z;
+            }
+            if (xyz32) {
+                xyz32[3 * i + 0] = v32[i].x;
+                xyz32[3 * i + 1] = v32[i].y;
+                xyz32[3 * i + 2] = v32[i].z;
+            }
+        }
+    }
+    return PC_OK;
+}
+
+int pc_chord2_edges(const double *theta_edges_deg, int32_t n_edges, double *e) {
+    clear_error();
+    if (!theta_edges_deg || !e) return fail(PC_ERR_INVALID, "NULL argument");
+    HostTable t;
+    std::string err;
+    if (!build_table(theta_edges_deg, n_edges, t, err)) return fail(PC_ERR_INVALID, err);
+    memcpy(e, t.e64.data(), sizeof(double) * static_cast<size_t>(n_edges));
+    return PC_OK;
+}
+
+int pc_guard_band(const double *theta_edges_deg, int32_t n_edges, float *lo, float *hi) {
+    clear_error();
+    if (!theta_edges_deg || !lo || !hi) return fail(PC_ERR_INVALID, "NULL argument");
+    HostTable t;
+    std::string err;
+    if (!build_table(theta_edges_deg, n_edges, t, err)) return fail(PC_ERR_INVALID, err);
+    memcpy(lo, t.lo.data(), sizeof(float) * static_cast<size_t>(n_edges));
+    memcpy(hi, t.hi.data(), sizeof(float) * static_cast<size_t>(n_edges));
+    return PC_OK;
+}
+
+}  // extern "C"
+
+extern "C" int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, int64_t *info, uint32_t *entries,
+                              int64_t max_cells) {
+    clear_error();
+    if (!theta_edges_deg || !info) return fail(PC_ERR_INVALID, "NULL argument");
+    HostTable t;
+    std::string err;
+    if (!build_table(theta_edges_deg, n_edges, t, err)) return fail(PC_ERR_INVALID, err);
+    info[0] = static_cast<int64_t>(t.lut32.size());
+    info[1] = t.shift32;
+    info[2] = t.clamp_lo32;
+    info[3] = t.clamp_hi32;
+    info[4] = t.row_bytes;
+    info[5] = t.cols;
+    info[6] = t.multi32;
+    info[7] = 0;
+    if (entries && static_cast<int64_t>(t.lut32.size()) <= max_cells)
+        memcpy(entries, t.lut32.data(), sizeof(LutEntry32) * t.lut32.size());
+    return PC_OK;
+}
+
+extern "C" int pc_debug_set_timing(int32_t on) {
+    clear_error();
+    t_timing = on != 0;
+    return PC_OK;
+}
+
+extern "C" int pc_debug_last_launch(double *kernel_ms, uint64_t *items, int32_t *grid, uint32_t *lds_bytes) {
+    clear_error();
+    if (kernel_ms) *kernel_ms = t_last.kernel_ms;
+    if (items) *items = t_last.items;
+    if (grid) *grid = t_last.grid;
+    if (lds_bytes) *lds_bytes = t_last.lds_bytes;
+    return PC_OK;
+}

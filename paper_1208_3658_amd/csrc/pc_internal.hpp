@@ -1,0 +1,92 @@
+// pc_internal.hpp -- descriptors shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace pc {
+
+constexpr int kWave = 64;                 // gfx950 wavefront
+constexpr int kR = 4;                     // i-points held per lane
+constexpr int kTile = kWave * kR;         // points per tile, both axes (square tiles)
+constexpr int kMaxLutCells = 1024;        // per table, 16 bytes each
+constexpr uint32_t kLdsTarget = 24 * 1024;  // per-wave LDS aimed for (>= 6 waves per CU)
+
+// Histogram layout in LDS: n_edges + 2 rows (under/overflow bins and one
+// discard row for masked pairs) of `cols` lane columns, padded by one word so
+// that a row-wise sweep is free of bank conflicts.  Lane l adds to column
+// l & (cols - 1): with cols = 64 no two lanes of a wave share a word.
+inline uint32_t row_bytes_for(int cols) { return static_cast<uint32_t>(cols + 1) * 4u; }
+
+// Cell lookup entry of the mixed (binary32) kernel.  For a squared chord c in
+// the cell: c > hi -> histogram row offset off_hi, else off_lo; lo <= c <= hi
+// -> re-check in binary64.  Offsets are byte offsets of histogram rows.
+struct LutEntry32 {
+    uint32_t off_lo, off_hi;
+    float lo, hi;
+};
+
+// Cell lookup entry of the binary64 kernel: c >= e -> off_hi, else off_lo.
+struct LutEntry64 {
+    uint32_t off_lo, off_hi;
+    double e;
+};
+
+// One edge set as the kernels see it.
+struct TableDesc {
+    const void *lut;        // LutEntry32[] (mixed) or LutEntry64[] (fp64); device
+    const double *e64;      // n_edges binary64 squared-chord edges; device
+    uint32_t clamp_lo;      // cell key clamp (binary32 bits, or high word of binary64)
+    uint32_t clamp_hi;
+    uint32_t shift;         // cell = clamped key >> shift
+    uint32_t key0;          // first cell = clamp_lo >> shift
+    int32_t n_cells;
+    int32_t n_edges;
+    int32_t search;         // fp64 only: 1 = no exact cell table, binary search per pair
+    int32_t cols;           // histogram lane columns (power of two <= 64)
+};
+
+// A block of tile pairs of one job: a triangle (unordered pairs i<j inside
+// one index range of one catalogue) or a rectangle (all pairs of two ranges).
+struct SegDesc {
+    uint64_t item0;         // first global work item of the segment
+    uint64_t n_items;
+    const float4 *i32, *j32;
+    const double4 *i64, *j64;
+    int64_t i0, ni, j0, nj;
+    int64_t tiles_i, tiles_j;
+    int32_t tri, tab, job, pad;
+    unsigned long long *counts;  // the job's n_edges+1 device counters
+};
+
+// Host-side form of an edge set.
+struct HostTable {
+    int cols = 64;
+    uint32_t row_bytes = 260;
+    std::vector<double> theta;
+    std::vector<double> e64;
+    std::vector<float> lo, hi;
+    // mixed kernel
+    uint32_t clamp_lo32 = 0, clamp_hi32 = 0, shift32 = 0;
+    std::vector<LutEntry32> lut32;
+    int multi32 = 0;  // cells that always re-check (bands closer than the cell width)
+    // fp64 kernel
+    uint32_t clamp_lo64 = 0, clamp_hi64 = 0, shift64 = 0;
+    std::vector<LutEntry64> lut64;
+    bool search64 = false;
+};
+
+// Checks theta edges: 2..1024 values, finite, in [0, 180], strictly increasing.
+bool validate_edges(const double *theta_deg, int n_edges, std::string &err);
+
+// Validates theta edges; fills e64, the guard band and both cell tables.
+bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string &err);
+
+// The guard band of one squared-chord edge e (binary64): binary32 lo, hi with
+//   c32 > hi  =>  c64 >= e,     c32 < lo  =>  c64 < e.
+void guard_band(double e, float *lo, float *hi);
+
+}  // namespace pc

@@ -1,0 +1,84 @@
+// pc_runtime.hpp -- host runtime internals shared by the C ABI and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/pc.h"
+#include "pc_internal.hpp"
+
+namespace pc {
+
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+struct DeviceInfo {
+    int device = 0;
+    int cus = 0;
+    uint32_t lds_per_block = 0;
+    uint32_t lds_per_cu = 0;
+    std::string arch;
+    bool ok = false;
+};
+int device_info(DeviceInfo **out);
+
+// An edge set uploaded to one device.
+struct DevTable {
+    HostTable host;
+    void *d_mem = nullptr;
+    const double *d_e64 = nullptr;
+    const void *d_lut32 = nullptr;
+    const void *d_lut64 = nullptr;
+    ~DevTable();
+};
+int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *out);
+
+// A converted catalogue kept on the device.
+struct Resident {
+    void *d_mem = nullptr;
+    double4 *a64 = nullptr;
+    float4 *a32 = nullptr;
+    int64_t n = 0;
+    int device = 0;
+    ~Resident();
+};
+int validate_catalog(const pc_catalog *c, const char *name);
+int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle);
+int release_catalog(uint64_t h);
+int resident_catalog(uint64_t h, std::shared_ptr<Resident> *out);
+
+// One counting job: catalogues by pointer (A/B) or by resident handle (hA/hB).
+struct BatchJob {
+    const pc_catalog *A = nullptr;
+    const pc_catalog *B = nullptr;
+    uint64_t hA = 0, hB = 0;
+    const double *theta = nullptr;
+    int32_t n_edges = 0;
+    int32_t auto_flag = 1;
+    int64_t row_begin = 0;
+    int64_t row_end = -1;
+    uint64_t *counts = nullptr;  // host, n_edges + 1
+};
+
+struct BatchStats {
+    uint64_t items = 0;
+    int grid = 0;
+    uint32_t lds_bytes = 0;
+    int segments = 0;
+    double kernel_ms = -1.0;
+};
+
+// Runs the jobs in one persistent launch on `st` and blocks until the host
+// counts are written.
+int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, BatchStats *stats);
+
+// Landy-Szalay in binary64, fixed operation order, no contraction.
+void landy_szalay(const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_t n_bins, int64_t nD,
+                  int64_t nR, double *w);
+
+}  // namespace pc

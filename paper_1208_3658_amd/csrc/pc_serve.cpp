@@ -1,0 +1,518 @@
+// pc_serve.cpp -- w(theta) request server with continuous batching.
+//
+// Each request is a data catalogue on one registered sky patch plus theta
+// edges; its answer is DD, DR (against the patch's resident random
+// catalogue), RR and the Landy-Szalay w(theta) (paper Sec. 2, Eq. 2).
+//
+//  * Admission: a request enters the device only while the memory it needs
+//    (48 bytes per point for its converted catalogue plus 16 bytes of staging)
+//    fits in the free device memory minus a configured budget, and while fewer
+//    than max_inflight requests are on the device.  A request that can never
+//    fit fails with PC_ERR_NOMEM.
+//  * Continuous batching: one worker thread per stream.  A worker takes every
+//    admitted request waiting at that moment (up to max_batch_pairs), packs
+//    their DD, DR and missing RR jobs into one persistent launch on its own
+//    stream, and returns for more.  Requests that arrive while a batch runs are
+//    picked up by an idle worker, so their work overlaps the running batch on
+//    the device.
+//  * Random catalogues are converted once per patch and stay resident; RR is
+//    cached per (patch, edge set), so a patch's RR is counted once.
+//  * Latency = submit -> answer ready, per request; the stats report p50/p99.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "pc_runtime.hpp"
+
+namespace pc {
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct ServerCfg {
+    uint64_t hbm_budget = 4ull << 30;
+    int max_inflight = 64;
+    int streams = 2;
+    double max_batch_pairs = 2e12;
+    int mode = PC_MIXED;
+    int max_queue = 1 << 20;
+};
+
+// minimal reader for flat {"key": number, ...} objects
+bool parse_cfg(const char *s, ServerCfg &c, std::string &err) {
+    if (!s) return true;
+    std::string j(s);
+    size_t p = 0;
+    auto skip = [&]() { while (p < j.size() && isspace(static_cast<unsigned char>(j[p]))) ++p; };
+    skip();
+    if (p >= j.size() || j[p] != '{') { err = "config must be a JSON object"; return false; }
+    ++p;
+    while (true) {
+        skip();
+        if (p < j.size() && j[p] == '}') break;
+        if (p >= j.size() || j[p] != '"') { err = "config: expected a key"; return false; }
+        const size_t q = j.find('"', p + 1);
+        if (q == std::string::npos) { err = "config: bad key"; return false; }
+        const std::string key = j.substr(p + 1, q - p - 1);
+        p = q + 1;
+        skip();
+        if (p >= j.size() || j[p] != ':') { err = "config: expected ':'"; return false; }
+        ++p;
+        skip();
+        char *end = nullptr;
+        const double v = strtod(j.c_str() + p, &end);
+        if (end == j.c_str() + p) { err = "config: value of " + key + " must be a number"; return false; }
+        p = static_cast<size_t>(end - j.c_str());
+        if (key == "hbm_budget_bytes") c.hbm_budget = static_cast<uint64_t>(std::max(0.0, v));
+        else if (key == "max_inflight") c.max_inflight = std::max(1, static_cast<int>(v));
+        else if (key == "streams") c.streams = std::min(8, std::max(1, static_cast<int>(v)));
+        else if (key == "max_batch_pairs") c.max_batch_pairs = std::max(1.0, v);
+        else if (key == "mode") c.mode = static_cast<int>(v);
+        else if (key == "max_queue") c.max_queue = std::max(1, static_cast<int>(v));
+        else { err = "config: unknown key " + key; return false; }
+        skip();
+        if (p < j.size() && j[p] == ',') { ++p; continue; }
+        skip();
+        if (p < j.size() && j[p] == '}') break;
+        err = "config: expected ',' or '}'";
+        return false;
+    }
+    if (c.mode != PC_MIXED && c.mode != PC_FP64_PLAIN) { err = "config: mode must be 0 or 1"; return false; }
+    return true;
+}
+
+struct Request {
+    uint64_t id = 0;
+    int32_t patch = 0;
+    std::vector<double> ra, dec;
+    std::vector<double> edges;
+    Clock::time_point t_submit;
+    uint64_t need_bytes = 0;
+    double pairs = 0;
+    // results
+    int status = PC_OK;
+    std::string error;
+    std::vector<uint64_t> DD, DR, RR;
+    std::vector<double> w;
+    double latency = 0;
+    bool done = false;
+};
+
+struct Patch {
+    uint64_t handle = 0;
+    int64_t n = 0;
+};
+
+std::string edge_key(int32_t patch, const std::vector<double> &e) {
+    std::string k(reinterpret_cast<const char *>(&patch), sizeof(patch));
+    k.append(reinterpret_cast<const char *>(e.data()), sizeof(double) * e.size());
+    return k;
+}
+
+}  // namespace
+
+struct Server {
+    ServerCfg cfg;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Request>> queue;
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> jobs;  // submitted, not yet polled
+    std::map<int32_t, Patch> patches;
+    std::map<std::string, std::vector<uint64_t>> rr_cache;
+    uint64_t next_id = 1;
+    int inflight = 0;
+    uint64_t reserved = 0;
+    bool stop = false;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;
+    // stats
+    uint64_t n_submitted = 0, n_done = 0, n_failed = 0, n_batches = 0, n_admit_waits = 0;
+    double pairs_done = 0, busy_s = 0;
+    std::vector<double> latencies;
+    Clock::time_point t0 = Clock::now();
+    std::string stats_buf;
+
+    void worker(int k);
+    int take_batch(std::vector<std::shared_ptr<Request>> &out, uint64_t &bytes);
+};
+
+int Server::take_batch(std::vector<std::shared_ptr<Request>> &out, uint64_t &bytes) {
+    // called with mu held; admits from the front of the queue
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    double pairs = 0;
+    bytes = 0;
+    while (!queue.empty() && inflight < cfg.max_inflight) {
+        auto &r = queue.front();
+        if (r->need_bytes + cfg.hbm_budget > total_b) {
+            // can never fit
+            r->status = PC_ERR_NOMEM;
+            r->error = "request needs " + std::to_string(r->need_bytes) + " bytes; device has " +
+                       std::to_string(total_b) + " with a budget of " + std::to_string(cfg.hbm_budget);
+            r->latency = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
+            r->done = true;
+            ++n_failed;
+            queue.pop_front();
+            cv_done.notify_all();
+            continue;
+        }
+        const uint64_t avail = free_b > cfg.hbm_budget + reserved ? free_b - cfg.hbm_budget - reserved : 0;
+        if (r->need_bytes + bytes > avail) {
+            ++n_admit_waits;
+            break;
+        }
+        if (!out.empty() && pairs + r->pairs > cfg.max_batch_pairs) break;
+        pairs += r->pairs;
+        bytes += r->need_bytes;
+        ++inflight;
+        out.push_back(r);
+        queue.pop_front();
+    }
+    reserved += bytes;
+    return static_cast<int>(out.size());
+}
+
+void Server::worker(int k) {
+    (void)hipSetDevice(device);
+    hipStream_t st = streams[k];
+    while (true) {
+        std::vector<std::shared_ptr<Request>> batch;
+        uint64_t bytes = 0;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] {
+                if (stop) return true;
+                if (queue.empty()) return false;
+                return true;
+            });
+            if (stop && queue.empty()) return;
+            take_batch(batch, bytes);
+            if (batch.empty()) {
+                // nothing admissible now: wait for memory to free up
+                cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+        }
+        // build the jobs: DD, DR, and RR where not cached
+        std::vector<pc_catalog> cats(batch.size());
+        std::vector<BatchJob> jobs;
+        std::vector<std::string> rr_keys;
+        std::vector<int> rr_job(batch.size(), -1);
+        std::map<std::string, int> rr_new;
+        std::vector<std::vector<uint64_t>> rr_store;
+        std::vector<Patch> pinfo(batch.size());
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (size_t q = 0; q < batch.size(); ++q) pinfo[q] = patches[batch[q]->patch];
+        }
+        for (size_t q = 0; q < batch.size(); ++q) {
+            Request &r = *batch[q];
+            const int32_t ne = static_cast<int32_t>(r.edges.size());
+            r.DD.assign(ne + 1, 0);
+            r.DR.assign(ne + 1, 0);
+            cats[q].ra_deg = r.ra.data();
+            cats[q].dec_deg = r.dec.data();
+            cats[q].n = static_cast<int64_t>(r.ra.size());
+            cats[q].on_device = 0;
+            cats[q].reserved = 0;
+            BatchJob dd;
+            dd.A = &cats[q];
+            dd.theta = r.edges.data();
+            dd.n_edges = ne;
+            dd.auto_flag = 1;
+            dd.counts = r.DD.data();
+            jobs.push_back(dd);
+            BatchJob dr;
+            dr.A = &cats[q];
+            dr.hB = pinfo[q].handle;
+            dr.theta = r.edges.data();
+            dr.n_edges = ne;
+            dr.auto_flag = 0;
+            dr.counts = r.DR.data();
+            jobs.push_back(dr);
+            const std::string key = edge_key(r.patch, r.edges);
+            bool cached;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                auto it = rr_cache.find(key);
+                cached = it != rr_cache.end();
+                if (cached) r.RR = it->second;
+            }
+            if (!cached) {
+                auto it = rr_new.find(key);
+                if (it == rr_new.end()) {
+                    it = rr_new.emplace(key, static_cast<int>(rr_store.size())).first;
+                    rr_store.emplace_back(ne + 1, 0);
+                    rr_keys.push_back(key);
+                    BatchJob rr;
+                    rr.hA = pinfo[q].handle;
+                    rr.theta = r.edges.data();
+                    rr.n_edges = ne;
+                    rr.auto_flag = 1;
+                    rr.counts = nullptr;  // set below, after rr_store stops growing
+                    jobs.push_back(rr);
+                }
+                rr_job[q] = it->second;
+            }
+        }
+        // RR jobs are the ones with hA set and auto; point them at rr_store
+        {
+            size_t s = 0;
+            for (auto &j : jobs)
+                if (j.hA && j.auto_flag) j.counts = rr_store[s++].data();
+        }
+        const auto t_start = Clock::now();
+        const int rc = run_batch(jobs, cfg.mode, st, nullptr);
+        const std::string err = rc ? std::string(pc_last_error()) : std::string();
+        const double dt = std::chrono::duration<double>(Clock::now() - t_start).count();
+        double pairs = 0;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (rc == PC_OK)
+                for (size_t s = 0; s < rr_keys.size(); ++s) rr_cache.emplace(rr_keys[s], rr_store[s]);
+            for (size_t q = 0; q < batch.size(); ++q) {
+                Request &r = *batch[q];
+                if (rc == PC_OK) {
+                    if (rr_job[q] >= 0) r.RR = rr_store[rr_job[q]];
+                    const int32_t nb = static_cast<int32_t>(r.edges.size()) - 1;
+                    r.w.assign(nb, 0.0);
+                    if (r.ra.size() >= 2 && pinfo[q].n >= 2)
+                        landy_szalay(r.DD.data() + 1, r.DR.data() + 1, r.RR.data() + 1, nb,
+                                     static_cast<int64_t>(r.ra.size()), pinfo[q].n, r.w.data());
+                    else
+                        std::fill(r.w.begin(), r.w.end(), std::nan(""));
+                    pairs += r.pairs;
+                    ++n_done;
+                } else {
+                    r.status = rc;
+                    r.error = err;
+                    ++n_failed;
+                }
+                r.latency = std::chrono::duration<double>(Clock::now() - r.t_submit).count();
+                if (rc == PC_OK) latencies.push_back(r.latency);
+                r.done = true;
+                std::vector<double>().swap(r.ra);
+                std::vector<double>().swap(r.dec);
+                --inflight;
+            }
+            reserved -= bytes;
+            ++n_batches;
+            pairs_done += pairs;
+            busy_s += dt;
+        }
+        cv_done.notify_all();
+        cv_work.notify_all();
+    }
+}
+
+}  // namespace pc
+
+using namespace pc;
+
+extern "C" {
+
+int pc_server_create(const char *json_cfg, void **server) {
+    clear_error();
+    if (!server) return fail(PC_ERR_INVALID, "server is NULL");
+    ServerCfg cfg;
+    std::string err;
+    if (!parse_cfg(json_cfg, cfg, err)) return fail(PC_ERR_INVALID, err);
+    DeviceInfo *di = nullptr;
+    int rc = device_info(&di);
+    if (rc) return rc;
+    auto *s = new Server();
+    s->cfg = cfg;
+    s->device = di->device;
+    for (int k = 0; k < cfg.streams; ++k) {
+        hipStream_t st = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            for (auto x : s->streams) (void)hipStreamDestroy(x);
+            delete s;
+            return hip_fail(e, "hipStreamCreate");
+        }
+        s->streams.push_back(st);
+    }
+    for (int k = 0; k < cfg.streams; ++k) s->workers.emplace_back(&Server::worker, s, k);
+    *server = s;
+    return PC_OK;
+}
+
+int pc_server_set_random(void *server, int32_t patch_id, const pc_catalog *randoms) {
+    clear_error();
+    auto *s = static_cast<Server *>(server);
+    if (!s) return fail(PC_ERR_INVALID, "server is NULL");
+    (void)hipSetDevice(s->device);
+    uint64_t h = 0;
+    int rc = upload_catalog(randoms, s->streams[0], &h);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->patches.find(patch_id);
+    if (it != s->patches.end()) {
+        release_catalog(it->second.handle);
+        // drop cached RR of this patch
+        for (auto c = s->rr_cache.begin(); c != s->rr_cache.end();) {
+            int32_t p;
+            memcpy(&p, c->first.data(), sizeof(p));
+            if (p == patch_id) c = s->rr_cache.erase(c);
+            else ++c;
+        }
+    }
+    Patch p;
+    p.handle = h;
+    p.n = randoms->n;
+    s->patches[patch_id] = p;
+    return PC_OK;
+}
+
+int pc_server_submit(void *server, const pc_catalog *data, int32_t patch_id, const double *theta_edges_deg,
+                     int32_t n_edges, uint64_t *job_id) {
+    clear_error();
+    auto *s = static_cast<Server *>(server);
+    if (!s || !job_id) return fail(PC_ERR_INVALID, "NULL argument");
+    int rc = validate_catalog(data, "data");
+    if (rc) return rc;
+    HostTable t;
+    std::string err;
+    if (!theta_edges_deg || !build_table(theta_edges_deg, n_edges, t, err))
+        return fail(PC_ERR_INVALID, theta_edges_deg ? err : "theta_edges_deg is NULL");
+    auto r = std::make_shared<Request>();
+    r->patch = patch_id;
+    r->edges.assign(theta_edges_deg, theta_edges_deg + n_edges);
+    const size_t n = static_cast<size_t>(data->n);
+    r->ra.resize(n);
+    r->dec.resize(n);
+    if (n) {
+        if (data->on_device) {
+            (void)hipSetDevice(s->device);
+            hipError_t e = hipMemcpy(r->ra.data(), data->ra_deg, sizeof(double) * n, hipMemcpyDeviceToHost);
+            if (e == hipSuccess)
+                e = hipMemcpy(r->dec.data(), data->dec_deg, sizeof(double) * n, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "copy request catalogue");
+            for (size_t i = 0; i < n; ++i)
+                if (!std::isfinite(r->ra[i]) || !std::isfinite(r->dec[i]) || r->dec[i] < -90.0 || r->dec[i] > 90.0)
+                    return fail(PC_ERR_INVALID, "data: RA must be finite and Dec in [-90, 90]");
+        } else {
+            memcpy(r->ra.data(), data->ra_deg, sizeof(double) * n);
+            memcpy(r->dec.data(), data->dec_deg, sizeof(double) * n);
+        }
+    }
+    r->need_bytes = 64ull * std::max<size_t>(n, 1) + (1u << 20);
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto pit = s->patches.find(patch_id);
+    if (pit == s->patches.end()) return fail(PC_ERR_INVALID, "no random catalogue registered for this patch");
+    const double nn = static_cast<double>(n), nr = static_cast<double>(pit->second.n);
+    r->pairs = 0.5 * nn * (nn - 1.0) + nn * nr;
+    if (static_cast<int>(s->queue.size()) >= s->cfg.max_queue) return fail(PC_ERR_BUSY, "server queue is full");
+    r->id = s->next_id++;
+    r->t_submit = Clock::now();
+    s->jobs.emplace(r->id, r);
+    s->queue.push_back(r);
+    ++s->n_submitted;
+    *job_id = r->id;
+    s->cv_work.notify_one();
+    return PC_OK;
+}
+
+int pc_server_poll(void *server, uint64_t job_id, int32_t *done, uint64_t *DD, uint64_t *DR, uint64_t *RR,
+                   double *w, double *latency_s) {
+    clear_error();
+    auto *s = static_cast<Server *>(server);
+    if (!s || !done) return fail(PC_ERR_INVALID, "NULL argument");
+    std::shared_ptr<Request> r;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->jobs.find(job_id);
+        if (it == s->jobs.end()) return fail(PC_ERR_INVALID, "unknown job id");
+        if (!it->second->done) {
+            *done = 0;
+            return PC_OK;
+        }
+        r = it->second;
+        s->jobs.erase(it);
+    }
+    if (latency_s) *latency_s = r->latency;
+    if (r->status != PC_OK) {
+        *done = -1;
+        return fail(r->status, r->error);
+    }
+    *done = 1;
+    const size_t ne = r->edges.size();
+    if (DD) memcpy(DD, r->DD.data(), sizeof(uint64_t) * (ne + 1));
+    if (DR) memcpy(DR, r->DR.data(), sizeof(uint64_t) * (ne + 1));
+    if (RR) memcpy(RR, r->RR.data(), sizeof(uint64_t) * (ne + 1));
+    if (w) memcpy(w, r->w.data(), sizeof(double) * (ne - 1));
+    return PC_OK;
+}
+
+int pc_server_drain(void *server) {
+    clear_error();
+    auto *s = static_cast<Server *>(server);
+    if (!s) return fail(PC_ERR_INVALID, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->queue.empty() && s->inflight == 0; });
+    return PC_OK;
+}
+
+const char *pc_server_stats(void *server) {
+    clear_error();
+    auto *s = static_cast<Server *>(server);
+    static thread_local std::string buf;
+    if (!s) {
+        buf = "{}";
+        return buf.c_str();
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<double> l = s->latencies;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double p) {
+        if (l.empty()) return 0.0;
+        const size_t i = std::min(l.size() - 1, static_cast<size_t>(std::ceil(p * l.size())) - (p > 0 ? 1 : 0));
+        return l[i];
+    };
+    std::ostringstream o;
+    o.precision(9);
+    const double wall = std::chrono::duration<double>(Clock::now() - s->t0).count();
+    o << "{\"submitted\": " << s->n_submitted << ", \"completed\": " << s->n_done << ", \"failed\": " << s->n_failed
+      << ", \"queued\": " << s->queue.size() << ", \"inflight\": " << s->inflight << ", \"batches\": " << s->n_batches
+      << ", \"admission_waits\": " << s->n_admit_waits << ", \"pairs\": " << s->pairs_done
+      << ", \"busy_s\": " << s->busy_s << ", \"wall_s\": " << wall << ", \"p50_s\": " << pct(0.50)
+      << ", \"p99_s\": " << pct(0.99) << ", \"max_s\": " << (l.empty() ? 0.0 : l.back())
+      << ", \"rr_cached\": " << s->rr_cache.size() << ", \"streams\": " << s->cfg.streams << "}";
+    buf = o.str();
+    return buf.c_str();
+}
+
+int pc_server_destroy(void *server) {
+    clear_error();
+    auto *s = static_cast<Server *>(server);
+    if (!s) return PC_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    for (auto &t : s->workers) t.join();
+    (void)hipSetDevice(s->device);
+    for (auto &p : s->patches) release_catalog(p.second.handle);
+    for (auto st : s->streams) (void)hipStreamDestroy(st);
+    delete s;
+    return PC_OK;
+}
+
+}  // extern "C"

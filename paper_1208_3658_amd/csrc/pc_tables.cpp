@@ -1,0 +1,291 @@
+// pc_tables.cpp -- host construction of the per-edge-set tables.
+//
+// Binning is done on the squared chord c = |a - b|^2 = 4 sin^2(theta/2) of the
+// unit vectors a, b (the separation of Appendix A, through a monotone map), so
+// an edge theta_k becomes e_k = 4 sin^2(theta_k/2).
+//
+// The mixed kernel computes c in binary32 (c32) and must still bin every pair
+// exactly as the binary64 definition (c64) does.  guard_band() gives, for each
+// edge, binary32 limits lo <= hi such that c32 > hi proves c64 >= e and c32 < lo
+// proves c64 < e; only pairs with lo <= c32 <= hi are re-computed in binary64.
+//
+// Error bound (u = 2^-24, v = 2^-53, t = 2^-126 for underflow or flush-to-zero,
+// c = |a-b|^2 exactly for the binary64 unit vectors a, b, |a|, |b| <= 1 + 2^-40):
+//   * rounding a, b to binary32 moves each component by <= u|a_i| + t, and the
+//     binary32 difference adds <= u|d_i| + t, so the computed difference vector
+//     s satisfies |s - d| <= d0 + u sqrt(c),  d0 = 2u(1+u)^2(1+2^-40) + 6t;
+//   * |(|s|^2) - c| <= D (2 sqrt(c) + D) with D = d0 + u sqrt(c);
+//   * the sum of three squares, with or without fused multiply-add, has
+//     relative error <= g3 = 3u/(1-3u), plus <= 5t absolute from underflow;
+//   => |c32 - c| <= E(c) = D(2 sqrt c + D) + g3 (sqrt c + D)^2 + 5t.
+//   * the binary64 chord (3 subtractions, 3 products, 2 sums) has
+//     |c64 - c| <= g5 c + 5*2^-1074, g5 = 5v/(1-5v).
+// If c64 < e then c < e+ = (e + 5*2^-1074)/(1 - g5) and c32 <= e+ + E(e+) since E
+// is increasing: hi = RU32(e+ + K E(e+)).  If c64 >= e then c >= e- =
+// (e - 5*2^-1074)/(1 + g5) and c32 >= e- - E(e-) because c - E(c) increases for
+// sqrt(c) beyond ~d0: lo = RD32(e- - K E(e-)) when sqrt(e-) >= 4 K d0, else
+// -inf (every c32 <= hi is re-checked).  K = 2 is a safety factor that also
+// covers the binary64 rounding of these host formulas.  e = 0 needs no band
+// (c64 >= 0 always): lo = hi = -inf.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+#include "pc_internal.hpp"
+#include "pc_math.h"
+
+namespace pc {
+
+namespace {
+
+constexpr double kU = 0x1p-24;
+constexpr double kV = 0x1p-53;
+constexpr double kTau = 0x1p-126;
+constexpr double kK = 2.0;
+
+inline uint32_t f2u(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+inline float u2f(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
+inline uint64_t d2u(double d) { uint64_t u; memcpy(&u, &d, 8); return u; }
+inline double u2d(uint64_t u) { double d; memcpy(&d, &u, 8); return d; }
+
+double delta0() { return 2.0 * kU * (1.0 + kU) * (1.0 + kU) * (1.0 + 0x1p-40) + 6.0 * kTau; }
+
+// |c32 - c| <= E(c)
+double err32(double c) {
+    const double r = std::sqrt(c);
+    const double D = delta0() + kU * r;
+    const double g3 = 3.0 * kU / (1.0 - 3.0 * kU);
+    return D * (2.0 * r + D) + g3 * (r + D) * (r + D) + 5.0 * kTau;
+}
+
+float round_up32(double x) {
+    float f = static_cast<float>(x);
+    if (static_cast<double>(f) < x) f = std::nextafter(f, std::numeric_limits<float>::infinity());
+    return f;
+}
+
+float round_down32(double x) {
+    float f = static_cast<float>(x);
+    if (static_cast<double>(f) > x) f = std::nextafter(f, -std::numeric_limits<float>::infinity());
+    return f;
+}
+
+}  // namespace
+
+void guard_band(double e, float *lo, float *hi) {
+    const float ninf = -std::numeric_limits<float>::infinity();
+    if (e <= 0.0) {
+        *lo = ninf;
+        *hi = ninf;
+        return;
+    }
+    const double g5 = 5.0 * kV / (1.0 - 5.0 * kV);
+    // outward by a further 8v for the rounding of these expressions
+    const double ep = (e + 5.0 * 0x1p-1074) / (1.0 - g5) * (1.0 + 8.0 * kV);
+    const double em = (e - 5.0 * 0x1p-1074) / (1.0 + g5) * (1.0 - 8.0 * kV);
+    *hi = round_up32(ep + kK * err32(ep));
+    if (em > 0.0 && std::sqrt(em) >= 4.0 * kK * delta0()) {
+        const double l = em - kK * err32(em);
+        *lo = l > 0.0 ? round_down32(l) : ninf;
+    } else {
+        *lo = ninf;
+    }
+}
+
+namespace {
+
+// ---- binary32 cell table ------------------------------------------------
+//
+// Cell key = bits of c32 clamped to [clamp_lo, clamp_hi]; cell = key >> S.
+// For a cell with value range [mn, mx]: k_base = #bands wholly below (hi < mn);
+// if exactly one band meets the cell, entry = (k_base, k_base+1, lo, hi);
+// none: (k_base, k_base, +inf, +inf); several: (k_base, k_base, -inf, +inf),
+// i.e. always re-check.  Bands are sorted (lo and hi non-decreasing in e).
+
+void build_lut32(HostTable &t) {
+    const int n = static_cast<int>(t.e64.size());
+    const float inf = std::numeric_limits<float>::infinity();
+    float lo_min = inf, hi_max = -inf;
+    bool any_neg_lo = false;
+    for (int k = 0; k < n; ++k) {
+        if (t.hi[k] < 0.0f) continue;  // zero edge: always below every c32
+        if (t.lo[k] <= 0.0f) any_neg_lo = true;
+        lo_min = std::min(lo_min, t.lo[k]);
+        hi_max = std::max(hi_max, t.hi[k]);
+    }
+    const uint32_t clo = any_neg_lo ? 0u : f2u(lo_min);
+    const uint32_t chi = f2u(hi_max);
+    // band cell-key intervals (lo clipped at +0)
+    auto key_lo = [&](int k) { return t.lo[k] <= 0.0f ? 0u : f2u(t.lo[k]); };
+    int best_s = -1, best_multi = 1 << 30;
+    for (int s = 23; s >= 4; --s) {
+        const uint64_t cells = static_cast<uint64_t>(chi >> s) - (clo >> s) + 1;
+        if (cells > static_cast<uint64_t>(kMaxLutCells)) break;
+        int multi = 0;
+        int prev = -1;
+        for (int k = 0; k < n; ++k) {
+            if (t.hi[k] < 0.0f) continue;
+            if (prev >= 0 && (f2u(t.hi[prev]) >> s) >= (key_lo(k) >> s)) ++multi;
+            prev = k;
+        }
+        if (multi < best_multi) {
+            best_multi = multi;
+            best_s = s;
+        }
+        if (multi == 0) break;
+    }
+    if (best_s < 0) best_s = 23;  // cannot happen: S = 23 needs < 300 cells
+    const uint32_t s = static_cast<uint32_t>(best_s);
+    t.shift32 = s;
+    t.clamp_lo32 = clo;
+    t.clamp_hi32 = chi;
+    const uint32_t c0 = clo >> s, c1 = chi >> s;
+    t.lut32.clear();
+    t.multi32 = 0;
+    for (uint32_t c = c0; c <= c1; ++c) {
+        const float mn = u2f(c << s);
+        const float mx = u2f(static_cast<uint32_t>(((static_cast<uint64_t>(c) + 1) << s) - 1));
+        uint32_t k_base = 0;
+        int n_in = 0, k_in = -1;
+        for (int k = 0; k < n; ++k) {
+            if (t.hi[k] < mn) ++k_base;
+            else if (t.lo[k] <= mx) { ++n_in; k_in = k; }
+        }
+        LutEntry32 e;
+        e.off_lo = k_base * t.row_bytes;
+        if (n_in == 0) {
+            e.off_hi = e.off_lo;
+            e.lo = inf;
+            e.hi = inf;
+        } else if (n_in == 1) {
+            e.off_hi = (k_base + 1) * t.row_bytes;
+            e.lo = t.lo[k_in];
+            e.hi = t.hi[k_in];
+        } else {
+            e.off_hi = e.off_lo;
+            e.lo = -inf;
+            e.hi = inf;
+            ++t.multi32;
+        }
+        t.lut32.push_back(e);
+    }
+}
+
+// ---- binary64 cell table ------------------------------------------------
+//
+// Cell key = high 32 bits of c64 clamped; cell = key >> S.  For a cell with
+// value range [mn, mx]: k_base = #edges <= mn; at most one edge may lie in
+// (mn, mx]; entry = (k_base, k_base+1, that edge) or (k_base, k_base, +inf).
+// When no S within the size budget isolates every edge, the kernel falls back
+// to a binary search over the edges for every pair.
+
+void build_lut64(HostTable &t) {
+    const int n = static_cast<int>(t.e64.size());
+    double e_pos = 0.0;
+    for (int k = 0; k < n; ++k)
+        if (t.e64[k] > 0.0) { e_pos = t.e64[k]; break; }
+    const double below = std::nextafter(e_pos, 0.0);
+    const uint32_t clo = static_cast<uint32_t>(d2u(below) >> 32);
+    const uint32_t chi = static_cast<uint32_t>(d2u(t.e64[n - 1]) >> 32);
+    auto count_le = [&](double x) {
+        return static_cast<uint32_t>(std::upper_bound(t.e64.begin(), t.e64.end(), x) - t.e64.begin());
+    };
+    int chosen = -1;
+    for (int s = 20; s >= 0; --s) {
+        const uint64_t cells = static_cast<uint64_t>(chi >> s) - (clo >> s) + 1;
+        if (cells > static_cast<uint64_t>(kMaxLutCells)) break;
+        bool ok = true;
+        for (uint32_t c = clo >> s; c <= (chi >> s) && ok; ++c) {
+            const double mn = u2d(static_cast<uint64_t>(c << s) << 32);
+            const double mx = u2d((static_cast<uint64_t>((static_cast<uint64_t>(c) + 1) << s) << 32) - 1);
+            if (count_le(mx) - count_le(mn) > 1) ok = false;
+        }
+        if (ok) { chosen = s; break; }
+    }
+    t.lut64.clear();
+    if (chosen < 0) {
+        t.search64 = true;
+        t.shift64 = 0;
+        t.clamp_lo64 = clo;
+        t.clamp_hi64 = clo;
+        return;
+    }
+    t.search64 = false;
+    const uint32_t s = static_cast<uint32_t>(chosen);
+    t.shift64 = s;
+    t.clamp_lo64 = clo;
+    t.clamp_hi64 = chi;
+    for (uint32_t c = clo >> s; c <= (chi >> s); ++c) {
+        const double mn = u2d(static_cast<uint64_t>(c << s) << 32);
+        const double mx = u2d((static_cast<uint64_t>((static_cast<uint64_t>(c) + 1) << s) << 32) - 1);
+        const uint32_t kb = count_le(mn), kt = count_le(mx);
+        LutEntry64 e;
+        e.off_lo = kb * t.row_bytes;
+        if (kt == kb) {
+            e.off_hi = e.off_lo;
+            e.e = std::numeric_limits<double>::infinity();
+        } else {
+            e.off_hi = (kb + 1) * t.row_bytes;
+            e.e = t.e64[kb];
+        }
+        t.lut64.push_back(e);
+    }
+}
+
+}  // namespace
+
+bool validate_edges(const double *theta_deg, int n_edges, std::string &err) {
+    if (!theta_deg) {
+        err = "theta_edges_deg is NULL";
+        return false;
+    }
+    if (n_edges < 2) {
+        err = "n_edges must be >= 2";
+        return false;
+    }
+    if (n_edges > 1024) {
+        err = "n_edges must be <= 1024";
+        return false;
+    }
+    for (int k = 0; k < n_edges; ++k) {
+        const double x = theta_deg[k];
+        if (!std::isfinite(x) || x < 0.0 || x > 180.0) {
+            err = "theta edges must be finite and in [0, 180] degrees";
+            return false;
+        }
+        if (k > 0 && !(x > theta_deg[k - 1])) {
+            err = "theta edges must be strictly increasing";
+            return false;
+        }
+    }
+    return true;
+}
+
+bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string &err) {
+    if (!validate_edges(theta_deg, n_edges, err)) return false;
+    t.theta.assign(theta_deg, theta_deg + n_edges);
+    t.e64.resize(n_edges);
+    t.lo.resize(n_edges);
+    t.hi.resize(n_edges);
+    for (int k = 0; k < n_edges; ++k) {
+        t.e64[k] = chord2_of_theta(theta_deg[k]);
+        guard_band(t.e64[k], &t.lo[k], &t.hi[k]);
+    }
+    // widest histogram that keeps the per-wave LDS near the target
+    t.cols = 8;
+    for (int c = 64; c >= 8; c >>= 1) {
+        if (static_cast<uint64_t>(n_edges + 2) * row_bytes_for(c) + 16u * kMaxLutCells / 4 <= kLdsTarget) {
+            t.cols = c;
+            break;
+        }
+    }
+    t.row_bytes = row_bytes_for(t.cols);
+    build_lut32(t);
+    build_lut64(t);
+    return true;
+}
+
+}  // namespace pc

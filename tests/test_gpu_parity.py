@@ -1,0 +1,208 @@
+"""GPU parity: libpc.so on gfx950 against the CPU oracle, through the C ABI.
+
+Counts must be bit-exact (integers); unit vectors bit-exact; w(theta) within
+1e-12 relative.  Both kernels (mixed binary32 + binary64 re-check, and plain
+binary64) are checked."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_1208_3658_amd as pc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+MODES = [pc.PC_MIXED, pc.PC_FP64_PLAIN]
+
+
+def dev(cat):
+    return tuple(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in cat)
+
+
+def test_unit_vectors_bitwise():
+    rng = np.random.default_rng(8)
+    ra = np.concatenate([[0, 90, 180, 270, 360, -90, -720.5, 1e6 + 0.25, 45, 12.3456789, 359.999999999],
+                         rng.uniform(-1000, 1000, 3000)])
+    dec = np.concatenate([[0, 90, -90, 45, -45, 0, 89.9999999, -89.9999999, 30, 0.001, -0.001],
+                          rng.uniform(-90, 90, 3000)])
+    want = oracle.unit_vectors(ra, dec)
+    for cat in [(ra, dec), dev((ra, dec))]:
+        x64, x32 = pc.pc_unit_vectors(cat)
+        assert np.array_equal(x64.view(np.uint64), want.view(np.uint64))
+        assert np.array_equal(x32.view(np.uint32), want.astype(np.float32).view(np.uint32))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_small_config_dd_dr_rr_and_wtheta(mode):
+    c = synth.config_small(scale=0.3)                  # 3,000 clustered + 3,000 random
+    D, R, e = c["D"], c["R"], c["edges"]
+    dd, dr, rr = pc.pc_count_batch([{"A": dev(D), "edges": e}, {"A": dev(D), "B": dev(R), "edges": e, "auto": False},
+                                    {"A": dev(R), "edges": e}], mode=mode)
+    odd, odr, orr = oracle.count(D, e), oracle.count(D, e, B=R, auto=False), oracle.count(R, e)
+    assert dd.tolist() == odd.tolist()
+    assert dr.tolist() == odr.tolist()
+    assert rr.tolist() == orr.tolist()
+    nD, nR = D[0].size, R[0].size
+    w = pc.pc_wtheta(dd[1:-1], dr[1:-1], rr[1:-1], nD, nR)
+    ow = oracle.wtheta(odd[1:-1], odr[1:-1], orr[1:-1], nD, nR)
+    f = ~np.isnan(ow)
+    assert np.array_equal(np.isnan(w), np.isnan(ow))
+    assert np.all(np.abs(w[f] - ow[f]) <= 1e-12 * np.maximum(1.0, np.abs(ow[f])))
+
+
+SIZES = [0, 1, 2, 3, 63, 64, 65, 255, 256, 257, 511, 513, 1000, 2049]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_ragged_sizes_auto_and_cross(mode):
+    rng = np.random.default_rng(5)
+    e = synth.log_edges(0.05, 8.0, 12)
+    patch = synth.centred_patch(12.0)
+    for n in SIZES:
+        A = synth.uniform_patch(n, patch, rng) if n else (np.zeros(0), np.zeros(0))
+        got = pc.pc_count_ex(dev(A) if n else A, e, mode=mode)
+        assert got.tolist() == oracle.count(A, e).tolist(), n
+        assert int(got.sum()) == n * (n - 1) // 2
+        nb = (n * 7) % 300 + 1
+        B = synth.uniform_patch(nb, patch, rng)
+        got = pc.pc_count_ex(A, e, B=dev(B), auto=False, mode=mode)
+        assert got.tolist() == oracle.count(A, e, B=B, auto=False).tolist(), (n, nb)
+        assert int(got.sum()) == n * nb
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_row_ranges(mode):
+    c = synth.config_small(scale=0.2)
+    D, R, e = c["D"], c["R"], c["edges"]
+    n = D[0].size
+    Dd, Rd = dev(D), dev(R)
+    cuts = [0, 1, 300, 301, 1777, n]
+    tot_a = np.zeros(e.size + 1, dtype=np.uint64)
+    tot_c = np.zeros(e.size + 1, dtype=np.uint64)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        ga = pc.pc_count_ex(Dd, e, rows=(a, b), mode=mode)
+        assert ga.tolist() == oracle.count(D, e, rows=(a, b)).tolist(), (a, b)
+        gc = pc.pc_count_ex(Dd, e, B=Rd, auto=False, rows=(a, b), mode=mode)
+        assert gc.tolist() == oracle.count(D, e, B=R, auto=False, rows=(a, b)).tolist(), (a, b)
+        tot_a += ga
+        tot_c += gc
+    assert tot_a.tolist() == pc.pc_count_ex(Dd, e, mode=mode).tolist()
+    assert tot_c.tolist() == pc.pc_count_ex(Dd, e, B=Rd, auto=False, mode=mode).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_with_mixed_edge_sets_equals_single_jobs(mode):
+    rng = np.random.default_rng(12)
+    A = synth.neyman_scott(150, 20, 0.2, synth.Patch(0, 90, 0, 90), rng)
+    B = synth.uniform_patch(2500, synth.Patch(0, 90, 0, 90), rng)
+    S = synth.uniform_patch(1200, synth.FULL_SKY, rng)
+    sets = [synth.log_edges(0.001, 90.0, 254), synth.linear_edges(0.0, 30.0, 50), synth.log_edges(0.01, 10, 30),
+            synth.linear_edges(0.0, 180.0, 36)]
+    jobs = [{"A": dev(A), "edges": sets[0]},
+            {"A": dev(A), "B": dev(B), "edges": sets[1], "auto": False},
+            {"A": dev(B), "edges": sets[2], "rows": (100, 2000)},
+            {"A": dev(S), "edges": sets[3]},
+            {"A": dev(A), "edges": sets[1]}]
+    got = pc.pc_count_batch(jobs, mode=mode)
+    want = [oracle.count(A, sets[0]), oracle.count(A, sets[1], B=B, auto=False),
+            oracle.count(B, sets[2], rows=(100, 2000)), oracle.count(S, sets[3]), oracle.count(A, sets[1])]
+    for g, w in zip(got, want):
+        assert g.tolist() == w.tolist()
+    single = pc.pc_count_ex(dev(A), sets[0], mode=mode)
+    assert single.tolist() == got[0].tolist()
+
+
+def _near_edge_catalogue(theta, per_edge=24, seed=3):
+    """Points placed so that many pairs sit within a few binary32 ulps of
+    the edges: pairs on a meridian separated by theta_k (1 + eps)."""
+    rng = np.random.default_rng(seed)
+    ra, dec = [], []
+    for t in theta:
+        if not (0 < t < 150):
+            continue
+        for s in range(per_edge):
+            r0 = rng.uniform(0, 360)
+            d0 = rng.uniform(-60, 60 - t)
+            eps = rng.choice([0.0, 1e-12, -1e-12, 1e-9, -1e-9, 3e-8, -3e-8, 1e-7, -1e-7, 1e-6, -1e-6, 1e-4])
+            ra += [r0, r0]
+            dec += [d0, d0 + t * (1 + eps)]
+    return np.array(ra), np.array(dec)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_adversarial_near_edge_pairs_exact(mode):
+    for theta in [synth.log_edges(0.01, 20.0, 40), synth.linear_edges(0.0, 60.0, 30)]:
+        A = _near_edge_catalogue(theta)
+        got = pc.pc_count_ex(dev(A), theta, mode=mode)
+        assert got.tolist() == oracle.count(A, theta).tolist()
+
+
+def test_antipodes_poles_duplicates_full_sky():
+    e = synth.linear_edges(0.0, 180.0, 18)
+    ra = np.array([0, 180, 0, 0, 33, 33, 90, 270, 10, 10] * 20, dtype=np.float64)
+    dec = np.array([0, 0, 90, -90, 45, 45, 0, 0, -30, 30] * 20, dtype=np.float64)
+    for mode in MODES:
+        got = pc.pc_count_ex(dev((ra, dec)), e, mode=mode)
+        assert got.tolist() == oracle.count((ra, dec), e).tolist()
+
+
+def test_resident_handles_and_host_inputs():
+    c = synth.config_small(scale=0.1)
+    D, R, e = c["D"], c["R"], c["edges"]
+    hD = pc.pc_catalog_upload(dev(D))
+    hR = pc.pc_catalog_upload(R)                      # host arrays
+    try:
+        assert pc.pc_count_h(hD, e).tolist() == oracle.count(D, e).tolist()
+        assert pc.pc_count_h(hD, e, hB=hR, auto=False).tolist() == oracle.count(D, e, B=R, auto=False).tolist()
+        assert pc.pc_count_h(hR, e, mode=pc.PC_FP64_PLAIN).tolist() == oracle.count(R, e).tolist()
+    finally:
+        pc.pc_catalog_release(hD)
+        pc.pc_catalog_release(hR)
+    with pytest.raises(pc.PcError):
+        pc.pc_count_h(hD, e)
+
+
+def test_invalid_device_input_reported():
+    ra = torch.zeros(100, dtype=torch.float64, device="cuda")
+    dec = torch.zeros(100, dtype=torch.float64, device="cuda")
+    dec[17] = 95.0
+    with pytest.raises(pc.PcError) as ex:
+        pc.pc_count((ra, dec), [1.0, 2.0])
+    assert ex.value.code == pc.PC_ERR_INVALID
+    dec[17] = float("nan")
+    with pytest.raises(pc.PcError):
+        pc.pc_count((ra, dec), [1.0, 2.0])
+
+
+def test_repeatable_counts():
+    c = synth.config_small(scale=0.5)
+    D, e = dev(c["D"]), c["edges"]
+    first = pc.pc_count(D, e)
+    for _ in range(5):
+        assert pc.pc_count(D, e).tolist() == first.tolist()
+
+
+def test_1m_config_sampled_rows_and_decompositions():
+    """The 1M-point configuration at full size, in the launch bench.py times:
+    exact totals, both kernels identical, sampled rows against the oracle,
+    and a row decomposition that must add up to the full count."""
+    c = synth.config_1m()
+    D, R, e = c["D"], c["R"], c["edges"]
+    n = D[0].size
+    Dd, Rd = dev(D), dev(R)
+    jobs = [{"A": Dd, "edges": e}, {"A": Dd, "B": Rd, "edges": e, "auto": False}, {"A": Rd, "edges": e}]
+    mixed = pc.pc_count_batch(jobs, mode=pc.PC_MIXED)
+    plain = pc.pc_count_batch(jobs, mode=pc.PC_FP64_PLAIN)
+    for m, p in zip(mixed, plain):
+        assert m.tolist() == p.tolist()
+    assert int(mixed[0].sum()) == n * (n - 1) // 2
+    assert int(mixed[1].sum()) == n * R[0].size
+    assert int(mixed[2].sum()) == R[0].size * (R[0].size - 1) // 2
+    rows = [(0, 64), (437_000, 437_100), (n - 80, n)]
+    for r in rows:
+        assert pc.pc_count_ex(Dd, e, rows=r).tolist() == oracle.count(D, e, rows=r).tolist(), r
+        assert pc.pc_count_ex(Dd, e, B=Rd, auto=False, rows=r).tolist() == \
+            oracle.count(D, e, B=R, auto=False, rows=r).tolist(), r
+    parts = [pc.pc_count_ex(Dd, e, rows=r) for r in [(0, 333_333), (333_333, 777_777), (777_777, n)]]
+    assert np.sum(parts, axis=0).tolist() == mixed[0].tolist()

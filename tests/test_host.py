@@ -1,0 +1,202 @@
+"""Host-side checks of libpc.so that need no GPU: the exported ABI, the host
+tables (edges, guard band, cell table) and argument validation."""
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_1208_3658_amd as pc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        names |= set(re.findall(r"\b(pc_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_loads_and_exports_every_declared_function():
+    L = pc.lib()
+    names = _declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert pc.pc_version().startswith("pc ")
+
+
+EDGE_SETS = {
+    "log_30": synth.log_edges(0.01, 10.0, 30),
+    "log_40": synth.log_edges(0.01, 20.0, 40),
+    "log_50": synth.log_edges(0.005, 30.0, 50),
+    "paper_254": synth.log_edges(0.001, 90.0, 254),
+    "linear_zero_180": synth.linear_edges(0.0, 180.0, 36),
+    "linear_fine": synth.linear_edges(0.0, 10.0, 50),
+    "tiny": np.array([1e-5, 2e-5, 1e-3, 0.5]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE_SETS))
+def test_chord2_edges_match_oracle_bitwise(name):
+    e = EDGE_SETS[name]
+    got = pc.pc_chord2_edges(e)
+    want = oracle.chord2_edges(e)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def _c32_variants(a64, b64):
+    """binary32 squared chords as the kernel may form them: plain products and
+    sums, and fused multiply-adds (exact product + sum, rounded once)."""
+    a32 = a64.astype(np.float32)
+    b32 = b64.astype(np.float32)
+    d = (a32 - b32).astype(np.float32)
+    plain = (d[:, 0] * d[:, 0]).astype(np.float32)
+    plain = (plain + (d[:, 1] * d[:, 1]).astype(np.float32)).astype(np.float32)
+    plain = (plain + (d[:, 2] * d[:, 2]).astype(np.float32)).astype(np.float32)
+    dd = d.astype(np.float64)
+    f = (dd[:, 0] * dd[:, 0]).astype(np.float32).astype(np.float64)
+    f = (dd[:, 1] * dd[:, 1] + f).astype(np.float32).astype(np.float64)
+    f = (dd[:, 2] * dd[:, 2] + f).astype(np.float32)
+    return plain, f
+
+
+def _c64(a, b):
+    d = a - b
+    c = d[:, 0] * d[:, 0]
+    c = c + d[:, 1] * d[:, 1]
+    c = c + d[:, 2] * d[:, 2]
+    return c
+
+
+def _pairs_near_edges(theta, per_edge=400, seed=1):
+    """Point pairs whose separation is theta_k (1 + eps) for tiny eps, in
+    random places and orientations on the sphere."""
+    rng = np.random.default_rng(seed)
+    ra1, dec1, ra2, dec2 = [], [], [], []
+    for t in theta:
+        if t <= 0 or t >= 179:
+            continue
+        eps = np.concatenate([rng.uniform(-1e-3, 1e-3, per_edge // 2),
+                              rng.uniform(-1e-6, 1e-6, per_edge // 4),
+                              rng.uniform(-1e-9, 1e-9, per_edge // 4)])
+        r0 = rng.uniform(0, 360, eps.size)
+        d0 = rng.uniform(-60, 60, eps.size)
+        sep = t * (1.0 + eps)
+        horiz = rng.random(eps.size) < 0.5
+        ra1.append(r0)
+        dec1.append(d0)
+        # meridian offsets: exact separation; equatorial offsets: approximately
+        ra2.append(np.where(horiz, r0 + sep, r0))
+        dec2.append(np.where(horiz, 0.0 * d0, np.clip(d0 + sep, -90, 90)))
+        dec1[-1] = np.where(horiz, 0.0 * d0, d0)
+    return (np.concatenate(ra1), np.concatenate(dec1), np.concatenate(ra2), np.concatenate(dec2))
+
+
+@pytest.mark.parametrize("name", sorted(EDGE_SETS))
+def test_guard_band_separates_binary32_from_binary64_decisions(name):
+    theta = EDGE_SETS[name]
+    e = oracle.chord2_edges(theta)
+    lo, hi = pc.pc_guard_band(theta)
+    ra1, dec1, ra2, dec2 = _pairs_near_edges(theta)
+    a = oracle.unit_vectors(ra1, dec1)
+    b = oracle.unit_vectors(ra2, dec2)
+    c64 = _c64(a, b)
+    for c32 in _c32_variants(a, b):
+        for k in range(e.size):
+            above = c32 > hi[k]
+            below = c32 < lo[k]
+            assert np.all(c64[above] >= e[k]), (name, k)
+            assert np.all(c64[below] < e[k]), (name, k)
+    # the band is narrow: relative width at most ~0.6% for edges >= 0.001 deg
+    pos = e > 1e-12
+    assert np.all((hi[pos].astype(np.float64) - lo[pos]) / e[pos] < 0.2)
+    assert np.all(hi >= lo)
+
+
+def _emulate_kernel(theta, A, B=None):
+    """Bin all pairs as the mixed kernel does (cell table + guard band +
+    binary64 re-check), with emulated binary32 chords; returns counts."""
+    info, ent = pc.pc_debug_lut32(theta)
+    e64 = oracle.chord2_edges(theta)
+    xa = oracle.unit_vectors(*A)
+    if B is None:
+        i, j = np.triu_indices(xa.shape[0], 1)
+        a, b = xa[i], xa[j]
+    else:
+        xb = oracle.unit_vectors(*B)
+        i, j = np.meshgrid(np.arange(xa.shape[0]), np.arange(xb.shape[0]), indexing="ij")
+        a, b = xa[i.ravel()], xb[j.ravel()]
+    c64 = _c64(a, b)
+    counts = []
+    for c32 in _c32_variants(a, b):
+        key = np.clip(c32.view(np.uint32), info["clamp_lo"], info["clamp_hi"])
+        cell = (key >> info["shift"]) - (info["clamp_lo"] >> info["shift"])
+        E = ent[cell]
+        lo = E[:, 2].view(np.float32)
+        hi = E[:, 3].view(np.float32)
+        row = np.where(c32 > hi, E[:, 1], E[:, 0]) // info["row_bytes"]
+        band = (c32 >= lo) & ~(c32 > hi)
+        row = row.astype(np.int64)
+        row[band] = np.searchsorted(e64, c64[band], side="right")
+        counts.append(np.bincount(row, minlength=theta.size + 1).astype(np.uint64))
+    return counts
+
+
+@pytest.mark.parametrize("name", ["log_30", "paper_254", "linear_zero_180", "linear_fine", "tiny"])
+def test_cell_table_logic_reproduces_oracle(name):
+    theta = EDGE_SETS[name]
+    c = synth.config_small(scale=0.06)                  # 600 clustered + 600 random
+    A = c["D"]
+    if name in ("linear_zero_180",):
+        A = synth.uniform_patch(700, synth.FULL_SKY, np.random.default_rng(4))
+    want = oracle.count(A, theta)
+    for got in _emulate_kernel(theta, A):
+        assert got.tolist() == want.tolist()
+    want = oracle.count(A, theta, B=c["R"], auto=False)
+    for got in _emulate_kernel(theta, A, c["R"]):
+        assert got.tolist() == want.tolist()
+
+
+def test_wtheta_matches_oracle_bitwise():
+    rng = np.random.default_rng(2)
+    DD = rng.integers(0, 10**12, 50).astype(np.uint64)
+    DR = rng.integers(0, 10**12, 50).astype(np.uint64)
+    RR = rng.integers(1, 10**12, 50).astype(np.uint64)
+    RR[3] = 0
+    got = pc.pc_wtheta(DD, DR, RR, 1_000_003, 2_000_001)
+    want = oracle.wtheta(DD, DR, RR, 1_000_003, 2_000_001)
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    f = ~np.isnan(want)
+    assert np.array_equal(got[f].view(np.uint64), want[f].view(np.uint64))
+
+
+@pytest.mark.parametrize("args,fragment", [
+    (((np.zeros(3), np.array([0.0, 91.0, 0.0])), [1.0, 2.0]), "Dec"),
+    (((np.array([0.0, np.nan]), np.zeros(2)), [1.0, 2.0]), "finite"),
+    (((np.zeros(3), np.zeros(3)), [2.0, 1.0]), "increasing"),
+    (((np.zeros(3), np.zeros(3)), [1.0]), ">= 2"),
+    (((np.zeros(3), np.zeros(3)), [1.0, 181.0]), "[0, 180]"),
+    (((np.zeros(3), np.zeros(3)), [-1.0, 1.0]), "[0, 180]"),
+])
+def test_invalid_arguments_rejected_before_any_device_work(args, fragment):
+    with pytest.raises(pc.PcError) as ex:
+        pc.pc_count(*args)
+    assert ex.value.code == pc.PC_ERR_INVALID
+    assert fragment in str(ex.value)
+
+
+def test_invalid_row_range_and_wtheta_arguments():
+    A = (np.zeros(5), np.zeros(5))
+    with pytest.raises(pc.PcError) as ex:
+        pc.pc_count_ex(A, [1.0, 2.0], rows=(3, 9))
+    assert ex.value.code == pc.PC_ERR_INVALID
+    with pytest.raises(pc.PcError):
+        pc.pc_wtheta([1], [1], [1], 1, 5)
