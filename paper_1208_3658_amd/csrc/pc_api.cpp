@@ -164,8 +164,8 @@ TableDesc table_desc(const DevTable &t, bool fp64) {
     const HostTable &h = t.host;
     d.e64 = t.d_e64;
     d.n_edges = static_cast<int32_t>(h.e64.size());
-    d.cols = h.cols;
     if (fp64) {
+        d.cols = h.cols64;
         d.lut = t.d_lut64;
         d.clamp_lo = h.clamp_lo64;
         d.clamp_hi = h.clamp_hi64;
@@ -174,6 +174,7 @@ TableDesc table_desc(const DevTable &t, bool fp64) {
         d.n_cells = static_cast<int32_t>(h.lut64.size());
         d.search = h.search64 ? 1 : 0;
     } else {
+        d.cols = h.cols32;
         d.lut = t.d_lut32;
         d.clamp_lo = h.clamp_lo32;
         d.clamp_hi = h.clamp_hi32;
@@ -188,7 +189,7 @@ TableDesc table_desc(const DevTable &t, bool fp64) {
 // LDS bytes a table needs: histogram rows, then the cell table (or edges)
 static void table_lds(const DevTable &t, bool fp64, uint32_t *hist, uint32_t *lut) {
     const HostTable &h = t.host;
-    *hist = static_cast<uint32_t>(h.e64.size() + 2) * h.row_bytes;
+    *hist = static_cast<uint32_t>(h.e64.size() + 2) * (fp64 ? h.row_bytes64 : h.row_bytes32);
     if (fp64)
         *lut = h.search64 ? static_cast<uint32_t>(8 * h.e64.size())
                           : static_cast<uint32_t>(16 * h.lut64.size());
@@ -756,8 +757,8 @@ extern "C" int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, in
     info[1] = t.shift32;
     info[2] = t.clamp_lo32;
     info[3] = t.clamp_hi32;
-    info[4] = t.row_bytes;
-    info[5] = t.cols;
+    info[4] = t.row_bytes32;
+    info[5] = t.cols32;
     info[6] = t.multi32;
     info[7] = 0;
     if (entries && static_cast<int64_t>(t.lut32.size()) <= max_cells)

@@ -9,17 +9,28 @@
 
 namespace pc {
 
+#ifndef PC_R
+#define PC_R 4              // i-points held per lane
+#endif
+#ifndef PC_COLS32
+#define PC_COLS32 32        // widest histogram of the mixed kernel (lane columns)
+#endif
+#ifndef PC_COLS64
+#define PC_COLS64 16        // widest histogram of the binary64 kernel
+#endif
+
 constexpr int kWave = 64;                 // gfx950 wavefront
-constexpr int kR = 4;                     // i-points held per lane
+constexpr int kR = PC_R;                  // i-points held per lane
 constexpr int kTile = kWave * kR;         // points per tile, both axes (square tiles)
 constexpr int kMaxLutCells = 1024;        // per table, 16 bytes each
-constexpr uint32_t kLdsTarget = 24 * 1024;  // per-wave LDS aimed for (>= 6 waves per CU)
+constexpr uint32_t kLdsTarget = 16 * 1024;  // per-wave histogram bytes aimed for at most
 
 // Histogram layout in LDS: n_edges + 2 rows (under/overflow bins and one
-// discard row for masked pairs) of `cols` lane columns, padded by one word so
-// that a row-wise sweep is free of bank conflicts.  Lane l adds to column
-// l & (cols - 1): with cols = 64 no two lanes of a wave share a word.
-inline uint32_t row_bytes_for(int cols) { return static_cast<uint32_t>(cols + 1) * 4u; }
+// discard row for masked pairs) of `cols` lane columns.  Lane l adds to column
+// l & (cols - 1), so with cols = 64 no two lanes of a wave share a word, and
+// since a row is exactly `cols` words the word of lane l sits in bank l (mod
+// the bank count) whatever its row: the adds are free of bank conflicts.
+inline uint32_t row_bytes_for(int cols) { return static_cast<uint32_t>(cols) * 4u; }
 
 // Cell lookup entry of the mixed (binary32) kernel.  For a squared chord c in
 // the cell: c > hi -> histogram row offset off_hi, else off_lo; lo <= c <= hi
@@ -64,8 +75,10 @@ struct SegDesc {
 
 // Host-side form of an edge set.
 struct HostTable {
-    int cols = 64;
-    uint32_t row_bytes = 260;
+    // histogram columns and row size of each kernel's layout (the cell tables
+    // hold byte offsets of rows, so each kernel has its own)
+    int cols32 = 32, cols64 = 16;
+    uint32_t row_bytes32 = 128, row_bytes64 = 64;
     std::vector<double> theta;
     std::vector<double> e64;
     std::vector<float> lo, hi;

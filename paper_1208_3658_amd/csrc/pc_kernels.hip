@@ -81,6 +81,20 @@ __device__ __forceinline__ double4 ld_const(const double4 *p) {
     return make_double4(q[0], q[1], q[2], q[3]);
 }
 
+// A descriptor read through the constant address space (scalar loads), so
+// its fields live in scalar registers.
+template <typename T>
+__device__ __forceinline__ T ld_const_struct(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor size");
+    using CU = const __attribute__((address_space(4))) uint32_t;
+    CU *q = (CU *)(p);
+    T out;
+    uint32_t *o = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int i = 0; i < static_cast<int>(sizeof(T) / 4); ++i) o[i] = q[i];
+    return out;
+}
+
 __device__ __forceinline__ double chord2_64(double ax, double ay, double az, double bx, double by,
                                             double bz) {
 #pragma clang fp contract(off)
@@ -131,8 +145,9 @@ __device__ __forceinline__ uint32_t umed3(uint32_t x, uint32_t lo, uint32_t hi) 
 }
 
 // Sum the histogram rows [0, n_rows) over the lane columns into the job's
-// 64-bit counters, then clear every row (including the discard row).
-// (rows are `cols` words wide plus one pad word)
+// 64-bit counters, then clear every row (including the discard row).  Lane r
+// sums row r, visiting the columns in a lane-rotated order so that the lanes
+// of one read touch distinct banks.
 __device__ void flush_hist(unsigned char *lds, int32_t n_rows, int32_t cols, int32_t clear_words,
                            unsigned long long *counts) {
     __syncthreads();
@@ -140,8 +155,8 @@ __device__ void flush_hist(unsigned char *lds, int32_t n_rows, int32_t cols, int
     uint32_t *h = reinterpret_cast<uint32_t *>(lds);
     for (int32_t r = lane; r < n_rows; r += kWave) {
         unsigned long long s = 0;
-        const uint32_t *row = h + r * (cols + 1);
-        for (int c = 0; c < cols; ++c) s += row[c];
+        const uint32_t *row = h + r * cols;
+        for (int c = 0; c < cols; ++c) s += row[(c + r) & (cols - 1)];
         if (s) atomicAdd(counts + r, s);
     }
     __syncthreads();
@@ -218,55 +233,79 @@ struct TileCtx {
     const double *e64;
 };
 
-// One tile pair in binary32 with binary64 re-check of in-band pairs.
-// MASKED: some i slots are past the end of the range, or this is a diagonal
-// tile (only i < j counts); masked-out pairs go to the discard row.
-template <bool MASKED>
-__device__ __forceinline__ void tile32(unsigned char *lds, const float4 *__restrict__ Jt,
-                                       const double4 *__restrict__ J64t, int64_t jbeg, int32_t jn,
+#ifndef PC_JUNROLL
+#define PC_JUNROLL 2        // j-points per inner iteration
+#endif
+
+// NJ consecutive j-points against the lane's kR i-points: all chords first,
+// then all cell-table reads, then all histogram adds, so the LDS latency of
+// NJ * kR lookups overlaps.  Slot r of lane l holds i = ibeg + r*64 + l.
+template <bool MASKED, int NJ>
+__device__ __forceinline__ void step32(unsigned char *lds, const float4 *__restrict__ Jt,
+                                       const double4 *__restrict__ J64t, int32_t jj,
                                        const float (&ax)[kR], const float (&ay)[kR],
                                        const float (&az)[kR], const double4 *__restrict__ I64,
-                                       const int64_t (&gi)[kR], const bool (&iv)[kR], bool diag,
+                                       int64_t ibeg, int32_t i_lim, int32_t j_rel, bool diag,
                                        const TileCtx &k) {
-    for (int32_t jj = 0; jj < jn; ++jj) {
-        const float4 b = ld_const(Jt + jj);
-        float c2[kR];
-        uint32_t a[kR];
+    const int32_t lane = static_cast<int32_t>(threadIdx.x);
+    float4 b[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) b[q] = ld_const(Jt + jj + q);
+    float c2[NJ][kR];
+    uint32_t a[NJ][kR];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q)
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
-            c2[r] = chord2_32(ax[r], ay[r], az[r], b);
-            a[r] = cell_addr(key32(c2[r], k.klo, k.khi), k.shift, k.lut_base);
+            c2[q][r] = chord2_32(ax[r], ay[r], az[r], b[q]);
+            a[q][r] = cell_addr(key32(c2[q][r], k.klo, k.khi), k.shift, k.lut_base);
         }
-        uint4 e[kR];
+    uint4 e[NJ][kR];
 #pragma unroll
-        for (int r = 0; r < kR; ++r) e[r] = lds_read4(a[r]);
-        uint32_t flags = 0;
+    for (int q = 0; q < NJ; ++q)
+#pragma unroll
+        for (int r = 0; r < kR; ++r) e[q][r] = lds_read4(a[q][r]);
+    bool any_band = false;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q)
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
-            const bool gt = c2[r] > __uint_as_float(e[r].w);
-            const bool band = !gt & (c2[r] >= __uint_as_float(e[r].z));
-            uint32_t off = (gt ? e[r].y : e[r].x) + k.lane_off;
+            const bool gt = c2[q][r] > __uint_as_float(e[q][r].w);
+            const bool band = !gt & (c2[q][r] >= __uint_as_float(e[q][r].z));
+            uint32_t off = (gt ? e[q][r].y : e[q][r].x) + k.lane_off;
             if (MASKED) {
-                const bool ok = iv[r] && (!diag || gi[r] < jbeg + jj);
+                // i slot valid, and on a diagonal tile i < j (positions
+                // relative to the tile start: i = r*64 + lane, j = j_rel + jj + q)
+                const int32_t ir = r * kWave + lane;
+                const bool ok = ir < i_lim && (!diag || ir < j_rel + jj + q);
                 off = ok ? off : k.trash_off;
-                flags |= (ok && band) ? (1u << r) : 0u;
+                any_band |= ok & band;
             } else {
-                flags |= band ? (1u << r) : 0u;
+                any_band |= band;
             }
             lds_add(lds, off, 1u);
         }
-        if (__builtin_expect(flags != 0u, 0)) {
-            // rare: the binary32 chord is within the error band of an edge;
-            // recompute in binary64 exactly as the reference does and move
-            // the count from the provisional row to the exact one.
-            const double4 b64 = ld_const(J64t + jj);
+    if (__builtin_expect(any_band, 0)) {
+        // rare: a binary32 chord is within the error band of an edge;
+        // recompute such pairs in binary64 exactly as the reference does and
+        // move their count from the provisional row to the exact one
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) {
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
-                if (flags & (1u << r)) {
-                    const double4 a64 = I64[gi[r]];
+                const float c = chord2_32(ax[r], ay[r], az[r], b[q]);
+                const uint4 en = lds_read4(cell_addr(key32(c, k.klo, k.khi), k.shift, k.lut_base));
+                bool band = !(c > __uint_as_float(en.w)) & (c >= __uint_as_float(en.z));
+                if (MASKED) {
+                    const int32_t ir = r * kWave + lane;
+                    band &= ir < i_lim && (!diag || ir < j_rel + jj + q);
+                }
+                if (band) {
+                    const double4 b64 = J64t[jj + q];
+                    const double4 a64 = I64[ibeg + r * kWave + lane];
                     const double c64 = chord2_64(a64.x, a64.y, a64.z, b64.x, b64.y, b64.z);
                     const uint32_t exact = bin_search(k.e64, k.n_edges, c64) * k.row_bytes + k.lane_off;
-                    const uint32_t prov = e[r].x + k.lane_off;
+                    const uint32_t prov = en.x + k.lane_off;
                     if (exact != prov) {
                         lds_add(lds, exact, 1u);
                         lds_add(lds, prov, 0xFFFFFFFFu);
@@ -277,14 +316,32 @@ __device__ __forceinline__ void tile32(unsigned char *lds, const float4 *__restr
     }
 }
 
+// One tile pair in binary32 with binary64 re-check of in-band pairs.
+// MASKED: some i slots are past the end of the range (i_lim < kTile), or this
+// is a diagonal tile (only i < j counts); masked-out pairs go to the discard
+// row.  j_rel = first j of the tile minus first i of the tile.
+template <bool MASKED>
+__device__ __forceinline__ void tile32(unsigned char *lds, const float4 *__restrict__ Jt,
+                                       const double4 *__restrict__ J64t, int32_t jn,
+                                       const float (&ax)[kR], const float (&ay)[kR],
+                                       const float (&az)[kR], const double4 *__restrict__ I64,
+                                       int64_t ibeg, int32_t i_lim, int32_t j_rel, bool diag,
+                                       const TileCtx &k) {
+    int32_t jj = 0;
+    for (; jj + PC_JUNROLL <= jn; jj += PC_JUNROLL)
+        step32<MASKED, PC_JUNROLL>(lds, Jt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+    for (; jj < jn; ++jj)
+        step32<MASKED, 1>(lds, Jt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+}
+
 // ------------------------------------------------------------------ fp64
 
 template <bool MASKED, bool SEARCH>
-__device__ __forceinline__ void tile64(unsigned char *lds, const double4 *__restrict__ J64t,
-                                       int64_t jbeg, int32_t jn, const double (&ax)[kR],
-                                       const double (&ay)[kR], const double (&az)[kR],
-                                       const int64_t (&gi)[kR], const bool (&iv)[kR], bool diag,
+__device__ __forceinline__ void tile64(unsigned char *lds, const double4 *__restrict__ J64t, int32_t jn,
+                                       const double (&ax)[kR], const double (&ay)[kR],
+                                       const double (&az)[kR], int32_t i_lim, int32_t j_rel, bool diag,
                                        uint32_t kclo, uint32_t kchi, const TileCtx &k) {
+    const int32_t lane = static_cast<int32_t>(threadIdx.x);
     for (int32_t jj = 0; jj < jn; ++jj) {
         const double4 b = ld_const(J64t + jj);
         double c[kR];
@@ -318,7 +375,8 @@ __device__ __forceinline__ void tile64(unsigned char *lds, const double4 *__rest
         for (int r = 0; r < kR; ++r) {
             uint32_t o = off[r];
             if (MASKED) {
-                const bool ok = iv[r] && (!diag || gi[r] < jbeg + jj);
+                const int32_t ir = r * kWave + lane;
+                const bool ok = ir < i_lim && (!diag || ir < j_rel + jj);
                 o = ok ? o : k.trash_off;
             }
             lds_add(lds, o, 1u);
@@ -328,8 +386,14 @@ __device__ __forceinline__ void tile64(unsigned char *lds, const double4 *__rest
 
 // ------------------------------------------------------- persistent kernel
 
+#ifdef PC_WAVES_PER_EU
+#define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PC_WAVES_PER_EU)))
+#else
+#define PC_OCCUPANCY
+#endif
+
 template <bool FP64>
-__global__ void __launch_bounds__(kWave) k_count(KParams p) {
+__global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t lds0 = lds_addr(lds);
     const uint32_t lane = threadIdx.x;
@@ -344,7 +408,7 @@ __global__ void __launch_bounds__(kWave) k_count(KParams p) {
     if (beg >= end) return;
 
     int s = find_seg(p.segs, p.n_segs, beg);
-    SegDesc sd = p.segs[s];
+    SegDesc sd = ld_const_struct(p.segs + s);
     int cur_tab = -1, cur_job = -1;
     int32_t n_edges = 0, cols = 64, clear_words = 0;
     uint32_t row_bytes = 0, lane_off = 0;
@@ -358,19 +422,16 @@ __global__ void __launch_bounds__(kWave) k_count(KParams p) {
     int cur_t_seg = -1;
     float fx[kR], fy[kR], fz[kR];
     double dx[kR], dy[kR], dz[kR];
-    int64_t gi[kR];
-    bool iv[kR];
-    bool i_full = false;
 
     for (uint64_t it = beg; it < end; ++it) {
         while (it >= sd.item0 + sd.n_items) {
             ++s;
-            sd = p.segs[s];
+            sd = ld_const_struct(p.segs + s);
         }
         if (sd.tab != cur_tab || sd.job != cur_job || since_flush >= (1ull << 21)) {
             if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);
             if (sd.tab != cur_tab) {
-                const TableDesc td = p.tabs[sd.tab];
+                const TableDesc td = ld_const_struct(p.tabs + sd.tab);
                 n_edges = td.n_edges;
                 clo = td.clamp_lo;
                 chi = td.clamp_hi;
@@ -378,7 +439,7 @@ __global__ void __launch_bounds__(kWave) k_count(KParams p) {
                 search = td.search != 0;
                 e64 = td.e64;
                 cols = td.cols;
-                row_bytes = static_cast<uint32_t>(cols + 1) * 4u;
+                row_bytes = static_cast<uint32_t>(cols) * 4u;
                 // absolute LDS addresses: histogram at lds0, cell table at lds0 + lut_lds_off
                 lane_off = lds0 + (lane & static_cast<uint32_t>(cols - 1)) * 4u;
                 trash_off = static_cast<uint32_t>(n_edges + 1) * row_bytes + lane_off;
@@ -395,7 +456,7 @@ __global__ void __launch_bounds__(kWave) k_count(KParams p) {
                 }
                 // histogram words this table uses; anything beyond what was
                 // cleared before is cleared now
-                const int32_t words = (n_edges + 2) * (cols + 1);
+                const int32_t words = (n_edges + 2) * cols;
                 uint32_t *h = reinterpret_cast<uint32_t *>(lds);
                 for (int32_t x = lane + (cur_job < 0 ? 0 : clear_words); x < words; x += kWave) h[x] = 0u;
                 clear_words = max(clear_words, words);
@@ -411,14 +472,13 @@ __global__ void __launch_bounds__(kWave) k_count(KParams p) {
         int64_t t, u;
         map_item(sd, it - sd.item0, t, u);
         const int64_t iend = sd.i0 + sd.ni;
+        const int64_t ibeg = sd.i0 + t * kTile;
+        const int32_t i_lim = static_cast<int32_t>(uniform(static_cast<uint32_t>(min<int64_t>(kTile, iend - ibeg))));
         if (t != cur_t || s != cur_t_seg) {
-            const int64_t ibeg = sd.i0 + t * kTile;
-            i_full = ibeg + kTile <= iend;
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
-                gi[r] = ibeg + r * kWave + lane;
-                iv[r] = gi[r] < iend;
-                const int64_t g = iv[r] ? gi[r] : ibeg;
+                const int32_t ir = r * kWave + static_cast<int32_t>(lane);
+                const int64_t g = ibeg + (ir < i_lim ? ir : 0);
                 if (FP64) {
                     const double4 v = sd.i64[g];
                     dx[r] = v.x;
@@ -437,7 +497,8 @@ __global__ void __launch_bounds__(kWave) k_count(KParams p) {
         const int64_t jbeg = sd.j0 + u * kTile;
         const int32_t jn = static_cast<int32_t>(uniform(static_cast<uint32_t>(min<int64_t>(kTile, sd.j0 + sd.nj - jbeg))));
         const bool diag = uniform((sd.tri && t == u) ? 1u : 0u) != 0u;
-        const bool masked = diag || uniform(i_full ? 0u : 1u) != 0u;
+        const bool masked = diag || i_lim < kTile;
+        const int32_t j_rel = static_cast<int32_t>(uniform(static_cast<uint32_t>(jbeg - ibeg)));
         const double4 *J64t = uniform_ptr(sd.j64 + jbeg);
         TileCtx k;
         k.shift = shift;
@@ -452,21 +513,21 @@ __global__ void __launch_bounds__(kWave) k_count(KParams p) {
         if (FP64) {
             if (search) {
                 if (masked)
-                    tile64<true, true>(lds, J64t, jbeg, jn, dx, dy, dz, gi, iv, diag, clo, chi, k);
+                    tile64<true, true>(lds, J64t, jn, dx, dy, dz, i_lim, j_rel, diag, clo, chi, k);
                 else
-                    tile64<false, true>(lds, J64t, jbeg, jn, dx, dy, dz, gi, iv, diag, clo, chi, k);
+                    tile64<false, true>(lds, J64t, jn, dx, dy, dz, i_lim, j_rel, diag, clo, chi, k);
             } else {
                 if (masked)
-                    tile64<true, false>(lds, J64t, jbeg, jn, dx, dy, dz, gi, iv, diag, clo, chi, k);
+                    tile64<true, false>(lds, J64t, jn, dx, dy, dz, i_lim, j_rel, diag, clo, chi, k);
                 else
-                    tile64<false, false>(lds, J64t, jbeg, jn, dx, dy, dz, gi, iv, diag, clo, chi, k);
+                    tile64<false, false>(lds, J64t, jn, dx, dy, dz, i_lim, j_rel, diag, clo, chi, k);
             }
         } else {
             const float4 *Jt = uniform_ptr(sd.j32 + jbeg);
             if (masked)
-                tile32<true>(lds, Jt, J64t, jbeg, jn, fx, fy, fz, sd.i64, gi, iv, diag, k);
+                tile32<true>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
             else
-                tile32<false>(lds, Jt, J64t, jbeg, jn, fx, fy, fz, sd.i64, gi, iv, diag, k);
+                tile32<false>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
         }
     }
     flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);

@@ -155,13 +155,13 @@ void build_lut32(HostTable &t) {
             else if (t.lo[k] <= mx) { ++n_in; k_in = k; }
         }
         LutEntry32 e;
-        e.off_lo = k_base * t.row_bytes;
+        e.off_lo = k_base * t.row_bytes32;
         if (n_in == 0) {
             e.off_hi = e.off_lo;
             e.lo = inf;
             e.hi = inf;
         } else if (n_in == 1) {
-            e.off_hi = (k_base + 1) * t.row_bytes;
+            e.off_hi = (k_base + 1) * t.row_bytes32;
             e.lo = t.lo[k_in];
             e.hi = t.hi[k_in];
         } else {
@@ -223,12 +223,12 @@ void build_lut64(HostTable &t) {
         const double mx = u2d((static_cast<uint64_t>((static_cast<uint64_t>(c) + 1) << s) << 32) - 1);
         const uint32_t kb = count_le(mn), kt = count_le(mx);
         LutEntry64 e;
-        e.off_lo = kb * t.row_bytes;
+        e.off_lo = kb * t.row_bytes64;
         if (kt == kb) {
             e.off_hi = e.off_lo;
             e.e = std::numeric_limits<double>::infinity();
         } else {
-            e.off_hi = (kb + 1) * t.row_bytes;
+            e.off_hi = (kb + 1) * t.row_bytes64;
             e.e = t.e64[kb];
         }
         t.lut64.push_back(e);
@@ -274,15 +274,18 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
         t.e64[k] = chord2_of_theta(theta_deg[k]);
         guard_band(t.e64[k], &t.lo[k], &t.hi[k]);
     }
-    // widest histogram that keeps the per-wave LDS near the target
-    t.cols = 8;
-    for (int c = 64; c >= 8; c >>= 1) {
-        if (static_cast<uint64_t>(n_edges + 2) * row_bytes_for(c) + 16u * kMaxLutCells / 4 <= kLdsTarget) {
-            t.cols = c;
-            break;
-        }
-    }
-    t.row_bytes = row_bytes_for(t.cols);
+    // widest histogram (up to the kernel's preferred width) that keeps the
+    // per-wave histogram within the LDS target; narrower histograms let more
+    // waves share a CU
+    auto pick = [&](int widest) {
+        for (int c = widest; c > 8; c >>= 1)
+            if (static_cast<uint64_t>(n_edges + 2) * row_bytes_for(c) <= kLdsTarget) return c;
+        return 8;
+    };
+    t.cols32 = pick(PC_COLS32);
+    t.cols64 = pick(PC_COLS64);
+    t.row_bytes32 = row_bytes_for(t.cols32);
+    t.row_bytes64 = row_bytes_for(t.cols64);
     build_lut32(t);
     build_lut64(t);
     return true;
