@@ -33,6 +33,21 @@ def work_per_pair(n_bins: int) -> int:
     return 8 + math.ceil(math.log2(n_bins + 2))
 
 
+def recorded_traffic(mode: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    record, if it was taken on the kernel source as it is now; else None."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", "k_count_mixed_1M_traffic.json")
+    src = os.path.join(ROOT, "paper_1208_3658_amd", "csrc", "pc_kernels.hip")
+    if mode != "mixed" or not os.path.exists(rec):
+        return None
+    with open(rec) as f:
+        r = json.load(f)
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return r["traffic_bytes_per_launch"] if r.get("kernel_source_sha256") == sha else None
+
+
 def cpu_baseline(c, target_s: float):
     """The CPU oracle as it stands on a bounded row sample of the same
     workload: DD, DR and RR restricted to their first r rows."""
@@ -185,7 +200,7 @@ def main():
         "config": {"workload": c["name"], "n_data": nD, "n_random": nR, "bins": n_bins,
                    "theta_deg": [float(e[0]), float(e[-1])], "pairs_per_step": pairs, "mode": args.mode},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": recorded_traffic(args.mode),
                      "kernel_ms": kern_s * 1e3, "work_per_pair": W, "grid": launch["grid"],
                      "lds_bytes": launch["lds_bytes"], "items": launch["items"]},
     }
