@@ -1,0 +1,87 @@
+"""GPU parity on the shapes of the batched-covariance and large full-sky
+configurations (reduced sizes the oracle finishes in seconds), plus the
+isotropic closed form on the device."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_1208_3658_amd as pc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(cat):
+    return tuple(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in cat)
+
+
+@pytest.mark.parametrize("mode", [pc.PC_MIXED, pc.PC_FP64_PLAIN])
+def test_batched_mocks_against_shared_random(mode):
+    """Many mocks, each DD and DR against one resident random catalogue, and
+    RR once -- one persistent launch; every job exact and equal to running
+    it alone."""
+    c = synth.config_batched(n_mocks=12, n_random=30_000, parents_lo=100, parents_hi=500)
+    e, R = c["edges"], c["R"]
+    hR = pc.pc_catalog_upload(dev(R))
+    try:
+        mocks = [dev(m) for m in c["mocks"]]
+        jobs = []
+        for m in mocks:
+            jobs.append({"A": m, "edges": e})
+            jobs.append({"A": m, "B": R, "edges": e, "auto": False})
+        jobs.append({"A": dev(R), "edges": e})
+        got = pc.pc_count_batch(jobs, mode=mode)
+        for q, m in enumerate(c["mocks"]):
+            assert got[2 * q].tolist() == oracle.count(m, e).tolist(), q
+            assert got[2 * q + 1].tolist() == oracle.count(m, e, B=R, auto=False).tolist(), q
+        rr = got[-1]
+        assert rr.tolist() == pc.pc_count_h(hR, e, mode=mode).tolist()
+        assert int(rr.sum()) == R[0].size * (R[0].size - 1) // 2
+        alone = pc.pc_count_ex(mocks[5], e, B=R, auto=False, mode=mode)
+        assert alone.tolist() == got[11].tolist()
+    finally:
+        pc.pc_catalog_release(hR)
+
+
+def test_large_full_sky_shape_and_closed_form():
+    """Full-sky clustered data (sigma log-uniform 0.01-0.2 deg) and full-sky
+    randoms, 50 log bins 0.005-30 deg: sampled rows against the oracle, exact
+    totals, and RR against the isotropic closed form
+    p_k = (cos t_k - cos t_k+1)/2 with variance M p (1-p)."""
+    c = synth.config_large(n_parents=2_000, n_random=300_000)
+    D, R, e = c["D"], c["R"], c["edges"]
+    Dd, Rd = dev(D), dev(R)
+    dd, dr, rr = pc.pc_count_batch([{"A": Dd, "edges": e}, {"A": Dd, "B": Rd, "edges": e, "auto": False},
+                                    {"A": Rd, "edges": e}])
+    n, nr = D[0].size, R[0].size
+    assert int(dd.sum()) == n * (n - 1) // 2 and int(dr.sum()) == n * nr
+    assert int(rr.sum()) == nr * (nr - 1) // 2
+    assert dd.tolist() == oracle.count(D, e).tolist()
+    for rows in [(0, 50), (20_000, 20_040), (n - 30, n)]:
+        assert pc.pc_count_ex(Dd, e, B=Rd, auto=False, rows=rows).tolist() == \
+            oracle.count(D, e, B=R, auto=False, rows=rows).tolist()
+    for rows in [(0, 20), (nr // 2, nr // 2 + 20)]:
+        assert pc.pc_count_ex(Rd, e, rows=rows).tolist() == oracle.count(R, e, rows=rows).tolist()
+    M = nr * (nr - 1) / 2
+    full = np.concatenate([[0.0], e, [180.0]])
+    worst = 0.0
+    for k in range(full.size - 1):
+        t1, t2 = math.radians(full[k]), math.radians(full[k + 1])
+        p = math.sin(0.5 * (t1 + t2)) * math.sin(0.5 * (t2 - t1))
+        z = (float(rr[k]) - M * p) / math.sqrt(M * p * (1 - p))
+        worst = max(worst, abs(z))
+    assert worst < 5.0, worst
+
+
+def test_paper_shape_254_bins_dr():
+    """The paper's timing shape (Table 1): DR on RA, Dec in [0, 90) deg with
+    254 log bins, at a size the oracle finishes quickly."""
+    c = synth.paper_shape(4000)
+    D, R, e = c["D"], c["R"], c["edges"]
+    got = pc.pc_count(dev(D), e, B=dev(R), auto=False)
+    assert got.tolist() == oracle.count(D, e, B=R, auto=False).tolist()
+    assert int(got.sum()) == 4000 * 4000

@@ -200,3 +200,12 @@ def test_invalid_row_range_and_wtheta_arguments():
     assert ex.value.code == pc.PC_ERR_INVALID
     with pytest.raises(pc.PcError):
         pc.pc_wtheta([1], [1], [1], 1, 5)
+
+
+def test_server_config_is_validated_before_the_device():
+    with pytest.raises(pc.PcError) as ex:
+        pc.Server({"no_such_key": 1})
+    assert ex.value.code == pc.PC_ERR_INVALID
+    with pytest.raises(pc.PcError) as ex:
+        pc.Server({"mode": 5})
+    assert ex.value.code == pc.PC_ERR_INVALID
