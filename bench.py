@@ -122,12 +122,55 @@ def serve_run(pc, torch, gpairs_s: float, n_req: int, seed_config: int = 5):
             "wall_s": wall, "batches": st["batches"], "rr_cached": st["rr_cached"]}
 
 
+def build_workload(name, torch, pc):
+    """Jobs of one step, the (DD, DR, RR) job indices of each w(theta), total
+    pairs and bin count."""
+    import synth
+
+    def dev(cat):
+        return tuple(torch.from_numpy(x).cuda() for x in cat)
+
+    if name in ("1m", "large", "paper"):
+        c = {"1m": synth.config_1m, "large": synth.config_large}.get(name, lambda: synth.paper_shape(1_000_000))()
+        D, R, e = dev(c["D"]), dev(c["R"]), c["edges"]
+        nD, nR = D[0].numel(), R[0].numel()
+        c["describe"] = {"n_data": nD, "n_random": nR, "theta_deg": [float(e[0]), float(e[-1])]}
+        if name == "paper":
+            jobs = [{"A": D, "B": R, "edges": e, "auto": False}]
+            return c, jobs, [], nD * nR, e.size - 1
+        jobs = [{"A": D, "edges": e}, {"A": D, "B": R, "edges": e, "auto": False}, {"A": R, "edges": e}]
+        pairs = nD * (nD - 1) // 2 + nD * nR + nR * (nR - 1) // 2
+        return c, jobs, [(0, 1, 2, nD, nR)], pairs, e.size - 1
+    c = synth.config_batched()
+    R, e = dev(c["R"]), c["edges"]
+    nR = R[0].numel()
+    jobs, est, pairs = [], [], 0
+    rr = 2 * len(c["mocks"])
+    for m in c["mocks"]:
+        M = dev(m)
+        n = M[0].numel()
+        est.append((len(jobs), len(jobs) + 1, rr, n, nR))
+        jobs += [{"A": M, "edges": e}, {"A": M, "B": R, "edges": e, "auto": False}]
+        pairs += n * (n - 1) // 2 + n * nR
+    jobs.append({"A": R, "edges": e})
+    pairs += nR * (nR - 1) // 2
+    c["describe"] = {"n_mocks": len(c["mocks"]), "n_data_total": sum(m[0].size for m in c["mocks"]),
+                     "n_random": nR, "theta_deg": [float(e[0]), float(e[-1])]}
+    c.pop("mocks")
+    return c, jobs, est, pairs, e.size - 1
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--workload", choices=["1m", "batched", "large", "paper"], default="1m",
+                    help="1m: 1M clustered + 1M random (default); batched: 256 mocks x shared 1M random; "
+                         "large: 4M + 8M full sky; paper: DR of 1M + 1M uniform, 254 log bins")
+    ap.add_argument("--per-job-launches", action="store_true",
+                    help="also time the same jobs with one launch each")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
@@ -156,22 +199,15 @@ def main():
         torch.cuda.synchronize()
         log(f"copied {args.copy_calibration} MiB")
         return
-    log("generating workload")
-    c = synth.config_1m()
-    D = tuple(torch.from_numpy(x).cuda() for x in c["D"])
-    R = tuple(torch.from_numpy(x).cuda() for x in c["R"])
-    e = c["edges"]
-    nD, nR = D[0].numel(), R[0].numel()
-    n_bins = e.size - 1
-    pairs = nD * (nD - 1) // 2 + nD * nR + nR * (nR - 1) // 2
+    log(f"generating workload {args.workload}")
+    c, jobs, est, pairs, n_bins = build_workload(args.workload, torch, pc)
     mode = pc.PC_MIXED if args.mode == "mixed" else pc.PC_FP64_PLAIN
     stream = torch.cuda.current_stream()
-    jobs = [{"A": D, "edges": e}, {"A": D, "B": R, "edges": e, "auto": False}, {"A": R, "edges": e}]
 
     def step(m):
-        dd, dr, rr = pc.pc_count_batch(jobs, mode=m, stream=stream)
-        w = pc.pc_wtheta(dd[1:-1], dr[1:-1], rr[1:-1], nD, nR)
-        return dd, dr, rr, w
+        counts = pc.pc_count_batch(jobs, mode=m, stream=stream)
+        ws = [pc.pc_wtheta(counts[a][1:-1], counts[b][1:-1], counts[r][1:-1], nd, nr) for a, b, r, nd, nr in est]
+        return counts, ws
 
     pc.pc_debug_set_timing(True)
     for k in range(args.warmup):
@@ -181,13 +217,13 @@ def main():
     kern = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        dd, dr, rr, w = step(mode)
+        counts, ws = step(mode)
         kern.append(pc.pc_debug_last_launch()["kernel_ms"])
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     launch = pc.pc_debug_last_launch()
-    assert int(dd.sum() + dr.sum() + rr.sum()) == pairs
+    assert sum(int(x.sum()) for x in counts) == pairs
     value = pairs * args.steps / dt / 1e9
     kern_s = float(np.mean(kern)) / 1e3
     W = work_per_pair(n_bins)
@@ -197,10 +233,11 @@ def main():
         "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64" if mode == pc.PC_MIXED else "f64", "data": "synthetic",
-        "config": {"workload": c["name"], "n_data": nD, "n_random": nR, "bins": n_bins,
-                   "theta_deg": [float(e[0]), float(e[-1])], "pairs_per_step": pairs, "mode": args.mode},
+        "config": {"workload": c["name"], **c["describe"], "bins": n_bins, "jobs_per_launch": len(jobs),
+                   "pairs_per_step": pairs, "mode": args.mode},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": recorded_traffic(args.mode),
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": recorded_traffic(args.mode) if args.workload == "1m" else None,
                      "kernel_ms": kern_s * 1e3, "work_per_pair": W, "grid": launch["grid"],
                      "lds_bytes": launch["lds_bytes"], "items": launch["items"]},
     }
@@ -209,16 +246,25 @@ def main():
         step(pc.PC_FP64_PLAIN)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        dd2, dr2, rr2, _ = step(pc.PC_FP64_PLAIN)
+        counts2, _ = step(pc.PC_FP64_PLAIN)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
-        same = dd2.tolist() == dd.tolist() and dr2.tolist() == dr.tolist() and rr2.tolist() == rr.tolist()
+        same = all(a.tolist() == b.tolist() for a, b in zip(counts, counts2))
         out["fp64_plain"] = {"value": pairs / t64 / 1e9, "ms_per_step": t64 * 1e3, "identical_counts": same}
         log(f"fp64 plain step {t64 * 1e3:.1f} ms, identical counts: {same}")
-    if args.serve_requests > 0:
+    if args.per_job_launches:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        single = [pc.pc_count_batch([j], mode=mode, stream=stream)[0] for j in jobs]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t1
+        out["per_job_launches"] = {"value": pairs / t1 / 1e9, "ms": t1 * 1e3, "launches": len(jobs),
+                                   "identical_counts": all(a.tolist() == b.tolist() for a, b in zip(counts, single))}
+        log(f"one launch per job: {t1 * 1e3:.1f} ms")
+    if args.serve_requests > 0 and args.workload == "1m":
         out["serve"] = serve_run(pc, torch, value, args.serve_requests)
         log(f"serve: p50 {out['serve']['p50_s']:.3f} s, p99 {out['serve']['p99_s']:.3f} s")
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "1m":
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds)
     print(json.dumps(out), flush=True)
