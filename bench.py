@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-prune-compare", action="store_true",
+                    help="skip the extra step that visits every pair")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (for scaling HBM counters) and exit")
@@ -220,6 +222,7 @@ def main():
         counts, ws = step(mode)
         kern.append(pc.pc_debug_last_launch()["kernel_ms"])
         log(f"step {k + 1}/{args.steps} done")
+    prn = pc.pc_debug_last_pruning()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     launch = pc.pc_debug_last_launch()
@@ -227,7 +230,9 @@ def main():
     value = pairs * args.steps / dt / 1e9
     kern_s = float(np.mean(kern)) / 1e3
     W = work_per_pair(n_bins)
-    achieved = pairs * W / kern_s / 1e12
+    # the pair kernel's own rate: the pairs it visits one by one (tile pairs
+    # binned whole by the bounding-sphere test never reach it)
+    achieved = prn["pairs_computed"] * W / kern_s / 1e12
     out = {
         "metric": "Gpairs/s binned (DD+DR+RR) at N=1M; p50/p99 latency of served w(theta) jobs",
         "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -239,9 +244,25 @@ def main():
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": recorded_traffic(args.mode) if args.workload == "1m" else None,
                      "kernel_ms": kern_s * 1e3, "work_per_pair": W, "grid": launch["grid"],
-                     "lds_bytes": launch["lds_bytes"], "items": launch["items"]},
+                     "lds_bytes": launch["lds_bytes"], "items": launch["items"],
+                     "pairs_computed": prn["pairs_computed"], "survivor_items": prn["survivors"],
+                     "computed_gpairs_s": prn["pairs_computed"] / kern_s / 1e9},
+        "pairs_binned_whole": pairs - prn["pairs_computed"],
     }
     pc.pc_debug_set_timing(False)
+    if args.no_prune_compare is False:
+        # the same step visiting every pair (no whole-tile-pair binning)
+        pc.pc_debug_set_timing(True)
+        t1 = time.perf_counter()
+        counts3, _ = step(mode | pc.PC_NO_PRUNE)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t1
+        k3 = pc.pc_debug_last_launch()["kernel_ms"] / 1e3
+        pc.pc_debug_set_timing(False)
+        out["every_pair"] = {"value": pairs / t1 / 1e9, "ms_per_step": t1 * 1e3, "kernel_ms": k3 * 1e3,
+                             "roofline_frac": pairs * W / k3 / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+                             "identical_counts": all(a.tolist() == b.tolist() for a, b in zip(counts, counts3))}
+        log(f"every-pair step {t1 * 1e3:.1f} ms")
     if not args.no_fp64_compare and mode == pc.PC_MIXED:
         step(pc.PC_FP64_PLAIN)
         torch.cuda.synchronize()

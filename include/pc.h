@@ -48,7 +48,10 @@ enum pc_status {
 
 enum pc_mode {
     PC_MIXED = 0,      /* binary32 chord^2 + binary64 re-check in the guard band (default) */
-    PC_FP64_PLAIN = 1  /* binary64 chord^2 for every pair (baseline kernel)                */
+    PC_FP64_PLAIN = 1, /* binary64 chord^2 for every pair (baseline kernel)                */
+    /* flag, or-ed into a mode: visit every pair even where a whole pair of
+       tiles provably falls into one bin (same counts; for testing and timing) */
+    PC_NO_PRUNE = 0x100
 };
 
 /* A catalogue of n points: RA and Dec in degrees, binary64.  Paper Sec. 2.2

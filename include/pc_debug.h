@@ -44,6 +44,13 @@ int pc_debug_set_timing(int32_t on);
  */
 int pc_debug_last_launch(double *kernel_ms, uint64_t *items, int32_t *grid, uint32_t *lds_bytes);
 
+/*
+ * pc_debug_last_pruning -- the calling thread's last counting launch: work
+ * items (tile pairs) left for the pair kernel after whole-tile-pair binning,
+ * pairs visited one by one, and all pairs counted.  Any pointer may be NULL.
+ */
+int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_t *pairs_total);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpc.so")
 
 PC_OK, PC_ERR_INVALID, PC_ERR_NOMEM, PC_ERR_DEVICE, PC_ERR_BUSY, PC_ERR_CANCELLED = range(6)
 PC_MIXED, PC_FP64_PLAIN = 0, 1
+PC_NO_PRUNE = 0x100
 
 
 class PcError(RuntimeError):
@@ -60,6 +61,7 @@ _SIGNATURES = {
     "pc_debug_lut32": ([_vp, _i32, _vp, _vp, _i64], ctypes.c_int),
     "pc_debug_set_timing": ([_i32], ctypes.c_int),
     "pc_debug_last_launch": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "pc_debug_last_pruning": ([_vp, _vp, _vp], ctypes.c_int),
     "pc_server_create": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
     "pc_server_set_random": ([_vp, _i32, _PCAT], ctypes.c_int),
     "pc_server_submit": ([_vp, _PCAT, _i32, _vp, _i32, ctypes.POINTER(_u64)], ctypes.c_int),
@@ -282,6 +284,14 @@ def pc_debug_last_launch() -> dict:
     lds = ctypes.c_uint32(0)
     _check(lib().pc_debug_last_launch(ctypes.byref(ms), ctypes.byref(items), ctypes.byref(grid), ctypes.byref(lds)))
     return {"kernel_ms": ms.value, "items": int(items.value), "grid": int(grid.value), "lds_bytes": int(lds.value)}
+
+
+def pc_debug_last_pruning() -> dict:
+    surv = _u64(0)
+    comp = _u64(0)
+    tot = _u64(0)
+    _check(lib().pc_debug_last_pruning(ctypes.byref(surv), ctypes.byref(comp), ctypes.byref(tot)))
+    return {"survivors": int(surv.value), "pairs_computed": int(comp.value), "pairs_total": int(tot.value)}
 
 
 # ------------------------------------------------------------------ serving

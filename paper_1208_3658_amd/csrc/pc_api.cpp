@@ -25,8 +25,13 @@ hipError_t launch_convert(const double *ra, const double *dec, int64_t n, double
                           int *err, hipStream_t st);
 hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st);
 hipError_t launch_count(bool fp64, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
-                        uint64_t total_items, uint32_t lut_lds_off, uint32_t lds_bytes, int grid,
-                        hipStream_t st);
+                        const uint64_t *items, const unsigned long long *n_items, uint64_t total_items,
+                        uint32_t lut_lds_off, uint32_t lds_bytes, int grid, hipStream_t st);
+size_t sort_scratch_words(int64_t n);
+hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
+                       float4 *a32s, double4 *bounds, hipStream_t st);
+hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, uint64_t total_items,
+                        uint64_t *survivors, unsigned long long *meta, hipStream_t st);
 hipError_t count_occupancy(bool fp64, uint32_t lds_bytes, int *blocks_per_cu);
 hipError_t set_max_lds(uint32_t bytes);
 
@@ -232,9 +237,7 @@ static int get_resident(uint64_t h, std::shared_ptr<Resident> *out) {
     return PC_OK;
 }
 
-// Workspace for one batch: converted copies of the non-resident catalogues,
-// staging for host inputs, error flags, counters and descriptors, in one
-// stream-ordered allocation.
+// Stream-ordered device allocation released when the batch ends.
 struct Workspace {
     void *mem = nullptr;
     hipStream_t st = nullptr;
@@ -252,6 +255,8 @@ struct Arena {
     }
 };
 
+static int64_t n_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+
 // ------------------------------------------------------------------- batch
 
 // optional per-thread timing of the counting kernel (HIP events on its stream)
@@ -259,8 +264,10 @@ static thread_local bool t_timing = false;
 static thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
 static thread_local BatchStats t_last;
 
-int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, BatchStats *stats) {
+int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st, BatchStats *stats) {
     if (jobs.empty()) return fail(PC_ERR_INVALID, "no jobs");
+    const int mode = mode_flags & ~PC_NO_PRUNE;
+    const bool prune = (mode_flags & PC_NO_PRUNE) == 0;
     if (mode != PC_MIXED && mode != PC_FP64_PLAIN) return fail(PC_ERR_INVALID, "unknown mode");
     const bool fp64 = mode == PC_FP64_PLAIN;
     // host-side validation first, so bad arguments are reported as such
@@ -287,63 +294,102 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, Batch
     int rc = device_info(&di);
     if (rc) return rc;
 
-    // ---- unique catalogues to convert
-    struct Conv {
-        const pc_catalog *c;
-        size_t o_a64, o_a32, o_ra, o_dec;
-    };
-    std::vector<Conv> convs;
-    std::map<std::tuple<const double *, const double *, int64_t>, int> conv_idx;
-    struct Side {
-        int conv = -1;                       // index into convs, or -1
-        std::shared_ptr<Resident> res;       // resident catalogue
-        int64_t n = 0;
-    };
-    std::vector<Side> sideA(jobs.size()), sideB(jobs.size());
     Arena ar;
-    auto add_side = [&](const BatchJob &j, bool is_a, Side &sd) -> int {
-        if (is_a ? j.hA : j.hB) {
-            int r = get_resident(is_a ? j.hA : j.hB, &sd.res);
+    // ---- sources: catalogues as binary64 unit vectors in the caller's order
+    struct Source {
+        const pc_catalog *c = nullptr;
+        std::shared_ptr<Resident> res;
+        int64_t n = 0;
+        size_t o_a64 = 0, o_ra = 0, o_dec = 0;
+    };
+    std::vector<Source> srcs;
+    std::map<std::tuple<const double *, const double *, int64_t>, int> src_of_ptr;
+    std::map<uint64_t, int> src_of_handle;
+    auto add_source = [&](const pc_catalog *c, uint64_t h, int *out) -> int {
+        if (h) {
+            auto it = src_of_handle.find(h);
+            if (it != src_of_handle.end()) { *out = it->second; return PC_OK; }
+            Source sc;
+            int r = get_resident(h, &sc.res);
             if (r) return r;
-            sd.n = sd.res->n;
+            sc.n = sc.res->n;
+            *out = static_cast<int>(srcs.size());
+            src_of_handle.emplace(h, *out);
+            srcs.push_back(sc);
             return PC_OK;
         }
-        const pc_catalog *c = is_a ? j.A : j.B;
-        sd.n = c->n;
         auto key = std::make_tuple(c->ra_deg, c->dec_deg, c->n);
-        auto it = conv_idx.find(key);
-        if (it != conv_idx.end()) {
-            sd.conv = it->second;
-            return PC_OK;
-        }
-        Conv cv;
-        cv.c = c;
-        cv.o_a64 = ar.take(sizeof(double4) * static_cast<size_t>(std::max<int64_t>(c->n, 1)));
-        cv.o_a32 = ar.take(sizeof(float4) * static_cast<size_t>(std::max<int64_t>(c->n, 1)));
-        cv.o_ra = cv.o_dec = 0;
+        auto it = src_of_ptr.find(key);
+        if (it != src_of_ptr.end()) { *out = it->second; return PC_OK; }
+        Source sc;
+        sc.c = c;
+        sc.n = c->n;
+        sc.o_a64 = ar.take(sizeof(double4) * static_cast<size_t>(std::max<int64_t>(c->n, 1)));
         if (!c->on_device && c->n > 0) {
-            cv.o_ra = ar.take(sizeof(double) * static_cast<size_t>(c->n));
-            cv.o_dec = ar.take(sizeof(double) * static_cast<size_t>(c->n));
+            sc.o_ra = ar.take(sizeof(double) * static_cast<size_t>(c->n));
+            sc.o_dec = ar.take(sizeof(double) * static_cast<size_t>(c->n));
         }
-        sd.conv = static_cast<int>(convs.size());
-        conv_idx.emplace(key, sd.conv);
-        convs.push_back(cv);
+        *out = static_cast<int>(srcs.size());
+        src_of_ptr.emplace(key, *out);
+        srcs.push_back(sc);
         return PC_OK;
+    };
+
+    // ---- views: spatially ordered copies of source index ranges
+    struct View {
+        int src = -1;
+        int64_t b = 0, e = 0;
+        bool resident_full = false;
+        size_t o_a64s = 0, o_a32s = 0, o_bounds = 0;
+    };
+    std::vector<View> views;
+    std::map<std::tuple<int, int64_t, int64_t>, int> view_of;
+    int64_t max_sort_n = 0;
+    auto add_view = [&](int src, int64_t b, int64_t e) -> int {
+        auto key = std::make_tuple(src, b, e);
+        auto it = view_of.find(key);
+        if (it != view_of.end()) return it->second;
+        View v;
+        v.src = src;
+        v.b = b;
+        v.e = e;
+        const int64_t n = e - b;
+        if (srcs[src].res && b == 0 && e == srcs[src].n) {
+            v.resident_full = true;
+        } else if (n > 0) {
+            v.o_a64s = ar.take(sizeof(double4) * static_cast<size_t>(n));
+            v.o_a32s = ar.take(sizeof(float4) * static_cast<size_t>(n));
+            v.o_bounds = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(n)));
+            max_sort_n = std::max(max_sort_n, n);
+        }
+        const int id = static_cast<int>(views.size());
+        view_of.emplace(key, id);
+        views.push_back(v);
+        return id;
     };
 
     std::vector<std::shared_ptr<DevTable>> tabs;
     std::map<const DevTable *, int> tab_idx;
-    std::vector<int> job_tab(jobs.size());
-    std::vector<size_t> job_counts_off(jobs.size());
+    struct JobPlan {
+        int tab = 0;
+        size_t o_counts = 0;
+        int vi_tri = -1, vi_rect = -1, vj_rect = -1;
+    };
+    std::vector<JobPlan> plan(jobs.size());
     for (size_t q = 0; q < jobs.size(); ++q) {
         const BatchJob &j = jobs[q];
-        if (j.auto_flag != 0 && j.auto_flag != 1) return fail(PC_ERR_INVALID, "auto_flag must be 0 or 1");
-        rc = add_side(j, true, sideA[q]);
+        int sa = -1, sb = -1;
+        rc = add_source(j.A, j.hA, &sa);
         if (rc) return rc;
         if (!j.auto_flag) {
-            rc = add_side(j, false, sideB[q]);
+            rc = add_source(j.B, j.hB, &sb);
             if (rc) return rc;
         }
+        const int64_t nA = srcs[sa].n;
+        const int64_t r0 = j.row_begin, r1 = j.row_end < 0 ? nA : j.row_end;
+        if (r0 < 0 || r1 > nA || r0 > r1)
+            return fail(PC_ERR_INVALID, "row range [" + std::to_string(r0) + ", " + std::to_string(r1) +
+                                            ") outside [0, " + std::to_string(nA) + "]");
         std::shared_ptr<DevTable> t;
         rc = get_table(j.theta, j.n_edges, &t);
         if (rc) return rc;
@@ -352,54 +398,58 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, Batch
             it = tab_idx.emplace(t.get(), static_cast<int>(tabs.size())).first;
             tabs.push_back(t);
         }
-        job_tab[q] = it->second;
-        const int64_t nA = sideA[q].n;
-        const int64_t r0 = j.row_begin, r1 = j.row_end < 0 ? nA : j.row_end;
-        if (r0 < 0 || r1 > nA || r0 > r1)
-            return fail(PC_ERR_INVALID, "row range [" + std::to_string(r0) + ", " + std::to_string(r1) +
-                                            ") outside [0, " + std::to_string(nA) + "]");
-        if (!j.counts) return fail(PC_ERR_INVALID, "counts is NULL");
-        job_counts_off[q] = ar.take(sizeof(unsigned long long) * static_cast<size_t>(j.n_edges + 1));
+        plan[q].tab = it->second;
+        plan[q].o_counts = ar.take(sizeof(unsigned long long) * static_cast<size_t>(j.n_edges + 1));
+        if (j.auto_flag) {
+            // pairs i<j with i in [r0, r1): triangle on [r0, r1) + rectangle [r0, r1) x [r1, n)
+            plan[q].vi_tri = add_view(sa, r0, r1);
+            if (r1 < nA && r1 > r0) {
+                plan[q].vi_rect = plan[q].vi_tri;
+                plan[q].vj_rect = add_view(sa, r1, nA);
+            }
+        } else {
+            plan[q].vi_rect = add_view(sa, r0, r1);
+            plan[q].vj_rect = add_view(sb, 0, srcs[sb].n);
+        }
     }
-    const size_t o_err = ar.take(sizeof(int) * std::max<size_t>(convs.size(), 1));
+    const size_t o_err = ar.take(sizeof(int) * std::max<size_t>(srcs.size(), 1));
+    const size_t o_scratch = ar.take(sizeof(uint32_t) * (max_sort_n > 0 ? sort_scratch_words(max_sort_n) : 1));
 
     // ---- segments
     std::vector<SegDesc> segs;
     uint64_t items = 0;
-    auto tiles = [](int64_t n) { return (n + kTile - 1) / kTile; };
+    auto view_n = [&](int v) { return views[v].e - views[v].b; };
     for (size_t q = 0; q < jobs.size(); ++q) {
-        const BatchJob &j = jobs[q];
-        const int64_t nA = sideA[q].n;
-        const int64_t r0 = j.row_begin, r1 = j.row_end < 0 ? nA : j.row_end;
-        auto add = [&](bool tri, int64_t i0, int64_t ni, int64_t j0, int64_t nj) {
-            if (ni <= 0 || nj <= 0) return;
-            SegDesc s;
-            memset(&s, 0, sizeof(s));
-            s.tri = tri ? 1 : 0;
-            s.i0 = i0;
-            s.ni = ni;
-            s.j0 = j0;
-            s.nj = nj;
-            s.tiles_i = tiles(ni);
-            s.tiles_j = tiles(nj);
-            s.n_items = tri ? static_cast<uint64_t>(s.tiles_i) * static_cast<uint64_t>(s.tiles_i + 1) / 2
-                            : static_cast<uint64_t>(s.tiles_i) * static_cast<uint64_t>(s.tiles_j);
-            s.item0 = items;
-            items += s.n_items;
-            s.tab = job_tab[q];
-            s.job = static_cast<int32_t>(q);
-            s.pad = j.auto_flag ? 1 : 0;  // side B of the segment is side A of the job
-            segs.push_back(s);
+        auto add = [&](bool tri, int vi, int vj) {
+            const int64_t ni = view_n(vi), nj = view_n(vj);
+            if (ni <= 0 || nj <= 0 || (tri && ni < 2)) return;
+            SegDesc sd;
+            memset(&sd, 0, sizeof(sd));
+            sd.tri = tri ? 1 : 0;
+            sd.i0 = 0;
+            sd.ni = ni;
+            sd.j0 = 0;
+            sd.nj = nj;
+            sd.tiles_i = n_tiles(ni);
+            sd.tiles_j = n_tiles(nj);
+            sd.n_items = tri ? static_cast<uint64_t>(sd.tiles_i) * static_cast<uint64_t>(sd.tiles_i + 1) / 2
+                             : static_cast<uint64_t>(sd.tiles_i) * static_cast<uint64_t>(sd.tiles_j);
+            sd.item0 = items;
+            items += sd.n_items;
+            sd.tab = plan[q].tab;
+            sd.job = static_cast<int32_t>(q);
+            // view indices parked in the pointer slots until the workspace exists
+            sd.i0 = vi;
+            sd.j0 = vj;
+            segs.push_back(sd);
         };
-        if (j.auto_flag) {
-            add(true, r0, r1 - r0, r0, r1 - r0);
-            add(false, r0, r1 - r0, r1, nA - r1);
-        } else {
-            add(false, r0, r1 - r0, 0, sideB[q].n);
-        }
+        if (plan[q].vi_tri >= 0) add(true, plan[q].vi_tri, plan[q].vi_tri);
+        if (plan[q].vi_rect >= 0 && plan[q].vj_rect >= 0) add(false, plan[q].vi_rect, plan[q].vj_rect);
     }
     const size_t o_segs = ar.take(sizeof(SegDesc) * std::max<size_t>(segs.size(), 1));
     const size_t o_tabs = ar.take(sizeof(TableDesc) * tabs.size());
+    const size_t o_meta = ar.take(sizeof(unsigned long long) * 4);
+    const size_t o_surv = ar.take(sizeof(uint64_t) * std::max<uint64_t>(prune ? items : 1, 1));
 
     // ---- allocate the workspace
     Workspace ws;
@@ -407,56 +457,71 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, Batch
     PC_HIP(hipMallocAsync(&ws.mem, ar.size, st), "hipMallocAsync(workspace)");
     unsigned char *W = static_cast<unsigned char *>(ws.mem);
 
-    // ---- convert catalogues, check their validity flags
-    if (!convs.empty()) {
-        PC_HIP(hipMemsetAsync(W + o_err, 0, sizeof(int) * convs.size(), st), "hipMemsetAsync(err)");
-        bool any_device_input = false;
-        for (size_t k = 0; k < convs.size(); ++k) {
-            const pc_catalog *c = convs[k].c;
-            if (c->n <= 0) continue;
-            const double *ra = c->ra_deg, *dec = c->dec_deg;
-            if (!c->on_device) {
-                double *dra = reinterpret_cast<double *>(W + convs[k].o_ra);
-                double *ddec = reinterpret_cast<double *>(W + convs[k].o_dec);
-                PC_HIP(hipMemcpyAsync(dra, ra, sizeof(double) * c->n, hipMemcpyHostToDevice, st), "H2D ra");
-                PC_HIP(hipMemcpyAsync(ddec, dec, sizeof(double) * c->n, hipMemcpyHostToDevice, st), "H2D dec");
-                ra = dra;
-                dec = ddec;
-            } else {
-                any_device_input = true;
-            }
-            PC_HIP(launch_convert(ra, dec, c->n, reinterpret_cast<double4 *>(W + convs[k].o_a64),
-                                  reinterpret_cast<float4 *>(W + convs[k].o_a32),
-                                  reinterpret_cast<int *>(W + o_err) + k, st),
-                   "convert");
+    // ---- convert the sources (validity flags read back at the end)
+    PC_HIP(hipMemsetAsync(W + o_err, 0, sizeof(int) * std::max<size_t>(srcs.size(), 1), st), "hipMemsetAsync(err)");
+    std::vector<const double4 *> src_a64(srcs.size(), nullptr);
+    for (size_t k = 0; k < srcs.size(); ++k) {
+        if (srcs[k].res) {
+            src_a64[k] = srcs[k].res->a64;
+            continue;
         }
-        if (any_device_input) {
-            std::vector<int> flags(convs.size());
-            PC_HIP(hipMemcpyAsync(flags.data(), W + o_err, sizeof(int) * convs.size(), hipMemcpyDeviceToHost, st),
-                   "D2H flags");
-            PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
-            for (size_t k = 0; k < convs.size(); ++k)
-                if (flags[k]) return fail(PC_ERR_INVALID, "catalogue has non-finite RA/Dec or |Dec| > 90");
+        const pc_catalog *c = srcs[k].c;
+        src_a64[k] = reinterpret_cast<const double4 *>(W + srcs[k].o_a64);
+        if (c->n <= 0) continue;
+        const double *ra = c->ra_deg, *dec = c->dec_deg;
+        if (!c->on_device) {
+            double *dra = reinterpret_cast<double *>(W + srcs[k].o_ra);
+            double *ddec = reinterpret_cast<double *>(W + srcs[k].o_dec);
+            PC_HIP(hipMemcpyAsync(dra, ra, sizeof(double) * c->n, hipMemcpyHostToDevice, st), "H2D ra");
+            PC_HIP(hipMemcpyAsync(ddec, dec, sizeof(double) * c->n, hipMemcpyHostToDevice, st), "H2D dec");
+            ra = dra;
+            dec = ddec;
         }
+        PC_HIP(launch_convert(ra, dec, c->n, reinterpret_cast<double4 *>(W + srcs[k].o_a64), nullptr,
+                              reinterpret_cast<int *>(W + o_err) + k, st),
+               "convert");
+    }
+
+    // ---- spatially ordered views and their tile bounds
+    struct ViewPtrs {
+        const double4 *a64s = nullptr;
+        const float4 *a32s = nullptr;
+        const double4 *bounds = nullptr;
+    };
+    std::vector<ViewPtrs> vp(views.size());
+    for (size_t v = 0; v < views.size(); ++v) {
+        const View &vw = views[v];
+        if (vw.resident_full) {
+            const Resident &r = *srcs[vw.src].res;
+            vp[v].a64s = r.a64s;
+            vp[v].a32s = r.a32s;
+            vp[v].bounds = r.bounds;
+            continue;
+        }
+        const int64_t n = vw.e - vw.b;
+        if (n <= 0) continue;
+        double4 *a64s = reinterpret_cast<double4 *>(W + vw.o_a64s);
+        float4 *a32s = reinterpret_cast<float4 *>(W + vw.o_a32s);
+        double4 *bnd = reinterpret_cast<double4 *>(W + vw.o_bounds);
+        PC_HIP(launch_sort(src_a64[vw.src], vw.b, n, reinterpret_cast<uint32_t *>(W + o_scratch), a64s, a32s, bnd, st),
+               "sort");
+        vp[v].a64s = a64s;
+        vp[v].a32s = a32s;
+        vp[v].bounds = bnd;
     }
 
     // ---- descriptors
-    auto side_ptrs = [&](const Side &sd, const float4 **p32, const double4 **p64) {
-        if (sd.res) {
-            *p32 = sd.res->a32;
-            *p64 = sd.res->a64;
-        } else {
-            *p32 = reinterpret_cast<const float4 *>(W + convs[sd.conv].o_a32);
-            *p64 = reinterpret_cast<const double4 *>(W + convs[sd.conv].o_a64);
-        }
-    };
-    for (SegDesc &s : segs) {
-        const size_t q = static_cast<size_t>(s.job);
-        side_ptrs(sideA[q], &s.i32, &s.i64);
-        if (s.pad) side_ptrs(sideA[q], &s.j32, &s.j64);
-        else side_ptrs(sideB[q], &s.j32, &s.j64);
-        s.pad = 0;
-        s.counts = reinterpret_cast<unsigned long long *>(W + job_counts_off[q]);
+    for (SegDesc &sd : segs) {
+        const int vi = static_cast<int>(sd.i0), vj = static_cast<int>(sd.j0);
+        sd.i0 = 0;
+        sd.j0 = 0;
+        sd.i32 = vp[vi].a32s;
+        sd.i64 = vp[vi].a64s;
+        sd.ib = vp[vi].bounds;
+        sd.j32 = vp[vj].a32s;
+        sd.j64 = vp[vj].a64s;
+        sd.jb = vp[vj].bounds;
+        sd.counts = reinterpret_cast<unsigned long long *>(W + plan[static_cast<size_t>(sd.job)].o_counts);
     }
     std::vector<TableDesc> tds;
     uint32_t hist_max = 0, lut_max = 0;
@@ -466,9 +531,6 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, Batch
         table_lds(*t, fp64, &h, &l);
         hist_max = std::max(hist_max, h);
         lut_max = std::max(lut_max, l);
-    }
-    for (size_t k = 0; k < tds.size(); ++k) {
-        // nothing
     }
     const uint32_t lut_off = (hist_max + 15u) & ~15u;
     const uint32_t lds_bytes = lut_off + std::max<uint32_t>(lut_max, 16u);
@@ -481,17 +543,20 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, Batch
                "H2D segments");
     PC_HIP(hipMemcpyAsync(W + o_tabs, tds.data(), sizeof(TableDesc) * tds.size(), hipMemcpyHostToDevice, st),
            "H2D tables");
-    int64_t n_counts = 0;
-    for (auto &j : jobs) n_counts += j.n_edges + 1;
-    // counters are contiguous in job order (taken consecutively from the arena
-    // after each job's table lookup); zero each job's block
     for (size_t q = 0; q < jobs.size(); ++q)
-        PC_HIP(launch_zero(reinterpret_cast<unsigned long long *>(W + job_counts_off[q]), jobs[q].n_edges + 1, st),
+        PC_HIP(launch_zero(reinterpret_cast<unsigned long long *>(W + plan[q].o_counts), jobs[q].n_edges + 1, st),
                "zero counts");
+    unsigned long long *meta = reinterpret_cast<unsigned long long *>(W + o_meta);
+    PC_HIP(launch_zero(meta, 4, st), "zero meta");
 
-    // ---- launch
+    // ---- whole-tile-pair binning, then the counting kernel over the rest
+    const SegDesc *d_segs = reinterpret_cast<const SegDesc *>(W + o_segs);
+    const TableDesc *d_tabs = reinterpret_cast<const TableDesc *>(W + o_tabs);
+    uint64_t *surv = reinterpret_cast<uint64_t *>(W + o_surv);
     int grid = 0;
     if (items > 0) {
+        if (prune)
+            PC_HIP(launch_prune(d_segs, static_cast<int32_t>(segs.size()), d_tabs, items, surv, meta, st), "prune");
         int per_cu = 0;
         PC_HIP(count_occupancy(fp64, lds_bytes, &per_cu), "occupancy");
         per_cu = std::max(per_cu, 1);
@@ -507,36 +572,50 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, Batch
             }
             PC_HIP(hipEventRecord(t_ev0, st), "hipEventRecord");
         }
-        PC_HIP(launch_count(fp64, reinterpret_cast<const SegDesc *>(W + o_segs), static_cast<int32_t>(segs.size()),
-                            reinterpret_cast<const TableDesc *>(W + o_tabs), items, lut_off, lds_bytes, grid, st),
+        PC_HIP(launch_count(fp64, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
+                            prune ? meta : nullptr, items, lut_off, lds_bytes, grid, st),
                "count kernel");
         if (timed) PC_HIP(hipEventRecord(t_ev1, st), "hipEventRecord");
     }
 
-    // ---- results
-    for (size_t q = 0; q < jobs.size(); ++q)
-        PC_HIP(hipMemcpyAsync(jobs[q].counts, W + job_counts_off[q], sizeof(uint64_t) * (jobs[q].n_edges + 1),
+    // ---- results: counts, validity flags and pruning figures under one sync
+    std::vector<std::vector<uint64_t>> host_counts(jobs.size());
+    for (size_t q = 0; q < jobs.size(); ++q) {
+        host_counts[q].resize(static_cast<size_t>(jobs[q].n_edges + 1));
+        PC_HIP(hipMemcpyAsync(host_counts[q].data(), W + plan[q].o_counts, sizeof(uint64_t) * host_counts[q].size(),
                               hipMemcpyDeviceToHost, st),
                "D2H counts");
+    }
+    std::vector<int> flags(std::max<size_t>(srcs.size(), 1), 0);
+    PC_HIP(hipMemcpyAsync(flags.data(), W + o_err, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, st), "D2H flags");
+    unsigned long long hmeta[4] = {0, 0, 0, 0};
+    PC_HIP(hipMemcpyAsync(hmeta, meta, sizeof(hmeta), hipMemcpyDeviceToHost, st), "D2H meta");
     PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    for (size_t k = 0; k < srcs.size(); ++k)
+        if (flags[k]) return fail(PC_ERR_INVALID, "catalogue has non-finite RA/Dec or |Dec| > 90");
+    for (size_t q = 0; q < jobs.size(); ++q)
+        memcpy(jobs[q].counts, host_counts[q].data(), sizeof(uint64_t) * host_counts[q].size());
+
+    uint64_t total_pairs = 0;
+    for (const SegDesc &sd : segs) {
+        const uint64_t ni = static_cast<uint64_t>(sd.ni), nj = static_cast<uint64_t>(sd.nj);
+        total_pairs += sd.tri ? ni * (ni - 1) / 2 : ni * nj;
+    }
     t_last = BatchStats();
     t_last.items = items;
     t_last.grid = grid;
     t_last.lds_bytes = lds_bytes;
     t_last.segments = static_cast<int>(segs.size());
     t_last.kernel_ms = -1.0;
+    t_last.survivors = prune ? hmeta[0] : items;
+    t_last.pairs_total = total_pairs;
+    t_last.pairs_computed = prune ? hmeta[1] : total_pairs;
     if (t_timing && items > 0) {
         float ms = 0.0f;
         PC_HIP(hipEventElapsedTime(&ms, t_ev0, t_ev1), "hipEventElapsedTime");
         t_last.kernel_ms = ms;
     }
-    if (stats) {
-        stats->items = items;
-        stats->grid = grid;
-        stats->lds_bytes = lds_bytes;
-        stats->segments = static_cast<int>(segs.size());
-    }
-    (void)n_counts;
+    if (stats) *stats = t_last;
     return PC_OK;
 }
 
@@ -554,7 +633,11 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
     Arena ar;
     const size_t o64 = ar.take(sizeof(double4) * n);
     const size_t o32 = ar.take(sizeof(float4) * n);
+    const size_t o64s = ar.take(sizeof(double4) * n);
+    const size_t o32s = ar.take(sizeof(float4) * n);
+    const size_t ob = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(static_cast<int64_t>(n))));
     const size_t oerr = ar.take(sizeof(int));
+    const size_t osc = ar.take(sizeof(uint32_t) * sort_scratch_words(static_cast<int64_t>(n)));
     size_t ora = 0, odec = 0;
     if (!c->on_device) {
         ora = ar.take(sizeof(double) * n);
@@ -564,6 +647,9 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
     unsigned char *W = static_cast<unsigned char *>(r->d_mem);
     r->a64 = reinterpret_cast<double4 *>(W + o64);
     r->a32 = reinterpret_cast<float4 *>(W + o32);
+    r->a64s = reinterpret_cast<double4 *>(W + o64s);
+    r->a32s = reinterpret_cast<float4 *>(W + o32s);
+    r->bounds = reinterpret_cast<double4 *>(W + ob);
     PC_HIP(hipMemsetAsync(W + oerr, 0, sizeof(int), st), "hipMemsetAsync");
     if (c->n > 0) {
         const double *ra = c->ra_deg, *dec = c->dec_deg;
@@ -574,6 +660,8 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
             dec = reinterpret_cast<const double *>(W + odec);
         }
         PC_HIP(launch_convert(ra, dec, c->n, r->a64, r->a32, reinterpret_cast<int *>(W + oerr), st), "convert");
+        PC_HIP(launch_sort(r->a64, 0, c->n, reinterpret_cast<uint32_t *>(W + osc), r->a64s, r->a32s, r->bounds, st),
+               "sort");
     }
     int flag = 0;
     PC_HIP(hipMemcpyAsync(&flag, W + oerr, sizeof(int), hipMemcpyDeviceToHost, st), "D2H flag");
@@ -769,6 +857,14 @@ extern "C" int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, in
 extern "C" int pc_debug_set_timing(int32_t on) {
     clear_error();
     t_timing = on != 0;
+    return PC_OK;
+}
+
+extern "C" int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_t *pairs_total) {
+    clear_error();
+    if (survivors) *survivors = t_last.survivors;
+    if (pairs_computed) *pairs_computed = t_last.pairs_computed;
+    if (pairs_total) *pairs_total = t_last.pairs_total;
     return PC_OK;
 }
 

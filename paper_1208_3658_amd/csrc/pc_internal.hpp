@@ -65,8 +65,9 @@ struct TableDesc {
 struct SegDesc {
     uint64_t item0;         // first global work item of the segment
     uint64_t n_items;
-    const float4 *i32, *j32;
-    const double4 *i64, *j64;
+    const float4 *i32, *j32;          // spatially ordered binary32 points
+    const double4 *i64, *j64;         // the same points in binary64
+    const double4 *ib, *jb;           // tile bounds (centre, radius) of each side
     int64_t i0, ni, j0, nj;
     int64_t tiles_i, tiles_j;
     int32_t tri, tab, job, pad;

@@ -24,7 +24,9 @@ namespace pc {
 struct KParams {
     const SegDesc *segs;
     const TableDesc *tabs;
-    uint64_t total_items;
+    const uint64_t *items;                 // work items to visit (survivors), or null: all items
+    const unsigned long long *n_items;     // device count of `items`
+    uint64_t total_items;                  // number of items when `items` is null
     int32_t n_segs;
     uint32_t lut_lds_off;  // byte offset of the cell table in LDS (after the histogram)
 };
@@ -56,7 +58,7 @@ __global__ void __launch_bounds__(256) k_convert(const double *__restrict__ ra,
     const double y = cd * sa;
     const double z = sd;
     a64[i] = make_double4(x, y, z, 0.0);
-    a32[i] = make_float4(static_cast<float>(x), static_cast<float>(y), static_cast<float>(z), 0.0f);
+    if (a32) a32[i] = make_float4(static_cast<float>(x), static_cast<float>(y), static_cast<float>(z), 0.0f);
 }
 
 __global__ void __launch_bounds__(256) k_zero_u64(unsigned long long *p, int64_t n) {
@@ -198,6 +200,11 @@ __device__ __forceinline__ int find_seg(const SegDesc *segs, int n, uint64_t ite
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    return static_cast<uint64_t>(uniform(static_cast<uint32_t>(x))) |
+           (static_cast<uint64_t>(uniform(static_cast<uint32_t>(x >> 32))) << 32);
+}
+
 template <typename T>
 __device__ __forceinline__ const T *uniform_ptr(const T *p) {
     const uint64_t v = reinterpret_cast<uint64_t>(p);
@@ -295,7 +302,7 @@ __device__ __forceinline__ void step32(unsigned char *lds, const float4 *__restr
             for (int r = 0; r < kR; ++r) {
                 const float c = chord2_32(ax[r], ay[r], az[r], b[q]);
                 const uint4 en = lds_read4(cell_addr(key32(c, k.klo, k.khi), k.shift, k.lut_base));
-                bool band = !(c > __uint_as_float(en.w)) & (c >= __uint_as_float(en.z));
+                bool band = !(c > __uint_as_float(en.w)) && (c >= __uint_as_float(en.z));
                 if (MASKED) {
                     const int32_t ir = r * kWave + lane;
                     band &= ir < i_lim && (!diag || ir < j_rel + jj + q);
@@ -402,12 +409,15 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     // consecutive blocks land on different XCDs; give each XCD a contiguous
     // run of work items so its L2 sees neighbouring tiles
     const uint32_t w = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
-    const uint64_t per = p.total_items / nb, rem = p.total_items % nb;
+    const uint64_t total = p.items ? static_cast<uint64_t>(*(const __attribute__((address_space(4))) unsigned long long *)(p.n_items))
+                                   : p.total_items;
+    const uint64_t per = total / nb, rem = total % nb;
     const uint64_t beg = per * w + min<uint64_t>(w, rem);
     const uint64_t end = beg + per + (w < rem ? 1u : 0u);
     if (beg >= end) return;
 
-    int s = find_seg(p.segs, p.n_segs, beg);
+    const uint64_t it0 = p.items ? p.items[beg] : beg;
+    int s = find_seg(p.segs, p.n_segs, it0);
     SegDesc sd = ld_const_struct(p.segs + s);
     int cur_tab = -1, cur_job = -1;
     int32_t n_edges = 0, cols = 64, clear_words = 0;
@@ -423,9 +433,10 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     float fx[kR], fy[kR], fz[kR];
     double dx[kR], dy[kR], dz[kR];
 
-    for (uint64_t it = beg; it < end; ++it) {
-        while (it >= sd.item0 + sd.n_items) {
-            ++s;
+    for (uint64_t wi = beg; wi < end; ++wi) {
+        const uint64_t it = p.items ? static_cast<uint64_t>(uniform_u64(p.items[wi])) : wi;
+        if (it < sd.item0 || it >= sd.item0 + sd.n_items) {
+            s = find_seg(p.segs, p.n_segs, it);
             sd = ld_const_struct(p.segs + s);
         }
         if (sd.tab != cur_tab || sd.job != cur_job || since_flush >= (1ull << 21)) {
@@ -551,11 +562,13 @@ hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_count(bool fp64, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
-                        uint64_t total_items, uint32_t lut_lds_off, uint32_t lds_bytes, int grid,
-                        hipStream_t st) {
+                        const uint64_t *items, const unsigned long long *n_items, uint64_t total_items,
+                        uint32_t lut_lds_off, uint32_t lds_bytes, int grid, hipStream_t st) {
     KParams p;
     p.segs = segs;
     p.tabs = tabs;
+    p.items = items;
+    p.n_items = n_items;
     p.total_items = total_items;
     p.n_segs = n_segs;
     p.lut_lds_off = lut_lds_off;

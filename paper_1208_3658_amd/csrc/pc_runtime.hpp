@@ -41,8 +41,11 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
 // A converted catalogue kept on the device.
 struct Resident {
     void *d_mem = nullptr;
-    double4 *a64 = nullptr;
-    float4 *a32 = nullptr;
+    double4 *a64 = nullptr;     // caller order
+    float4 *a32 = nullptr;      // caller order
+    double4 *a64s = nullptr;    // spatially ordered copy
+    float4 *a32s = nullptr;
+    double4 *bounds = nullptr;  // tile bounds of the ordered copy
     int64_t n = 0;
     int device = 0;
     ~Resident();
@@ -71,6 +74,9 @@ struct BatchStats {
     uint32_t lds_bytes = 0;
     int segments = 0;
     double kernel_ms = -1.0;
+    uint64_t survivors = 0;       // work items left after whole-tile-pair binning
+    uint64_t pairs_total = 0;     // pairs counted by the launch
+    uint64_t pairs_computed = 0;  // pairs visited one by one
 };
 
 // Runs the jobs in one persistent launch on `st` and blocks until the host

@@ -206,3 +206,42 @@ def test_1m_config_sampled_rows_and_decompositions():
             oracle.count(D, e, B=R, auto=False, rows=r).tolist(), r
     parts = [pc.pc_count_ex(Dd, e, rows=r) for r in [(0, 333_333), (333_333, 777_777), (777_777, n)]]
     assert np.sum(parts, axis=0).tolist() == mixed[0].tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_whole_tile_pair_binning_matches_every_pair(mode):
+    """Compact clusters far apart: whole tile pairs fall inside one bin (an
+    interior bin, the overflow, and -- for piled-up duplicates -- the
+    underflow), so they are binned without visiting their pairs; counts must
+    equal the oracle and the run that visits every pair."""
+    rng = np.random.default_rng(21)
+    parts = []
+    for ra0, dec0, s, n in [(10, 0, 0.02, 700), (40, 5, 0.02, 900), (11, 1, 0.03, 600), (200, -40, 0.02, 800)]:
+        parts.append((ra0 + s * rng.standard_normal(n), np.clip(dec0 + s * rng.standard_normal(n), -90, 90)))
+    parts.append((np.full(600, 123.0), np.full(600, -7.0)))          # 600 identical points
+    A = (np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts]))
+    B = synth.uniform_patch(1500, synth.FULL_SKY, rng)
+    e = np.array([0.001, 0.5, 2.0, 25.0, 35.0, 120.0])
+    want_a = oracle.count(A, e)
+    want_c = oracle.count(A, e, B=B, auto=False)
+    got = pc.pc_count_ex(dev(A), e, mode=mode)
+    stats = pc.pc_debug_last_pruning()
+    assert got.tolist() == want_a.tolist()
+    assert stats["survivors"] < stats["pairs_total"]
+    assert stats["pairs_computed"] < stats["pairs_total"]
+    assert pc.pc_count_ex(dev(A), e, mode=mode | pc.PC_NO_PRUNE).tolist() == want_a.tolist()
+    assert pc.pc_count_ex(dev(A), e, B=dev(B), auto=False, mode=mode).tolist() == want_c.tolist()
+    assert pc.pc_count_ex(dev(A), e, B=dev(B), auto=False, mode=mode | pc.PC_NO_PRUNE).tolist() == want_c.tolist()
+    # rows and the pruned path together
+    assert pc.pc_count_ex(dev(A), e, rows=(650, 2900), mode=mode).tolist() == \
+        oracle.count(A, e, rows=(650, 2900)).tolist()
+
+
+def test_pruning_skips_most_pairs_on_the_1m_shape():
+    c = synth.config_1m(n_parents=5_000, n_random=100_000)
+    D, R, e = dev(c["D"]), dev(c["R"]), c["edges"]
+    got = pc.pc_count_ex(D, e, B=R, auto=False)
+    st = pc.pc_debug_last_pruning()
+    assert st["pairs_total"] == 100_000 * 100_000
+    assert st["pairs_computed"] < 0.35 * st["pairs_total"]
+    assert got.tolist() == pc.pc_count_ex(D, e, B=R, auto=False, mode=pc.PC_NO_PRUNE).tolist()
