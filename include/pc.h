@@ -51,7 +51,13 @@ enum pc_mode {
     PC_FP64_PLAIN = 1, /* binary64 chord^2 for every pair (baseline kernel)                */
     /* flag, or-ed into a mode: visit every pair even where a whole pair of
        tiles provably falls into one bin (same counts; for testing and timing) */
-    PC_NO_PRUNE = 0x100
+    PC_NO_PRUNE = 0x100,
+    /* flag, or-ed into PC_MIXED: full tile pairs whose chords are all at least
+       twice the smaller tile's radius get their binary32 chords from the
+       matrix cores (the Gram form |a'|^2 + |b'|^2 - 2 a'.b' of tile-centred
+       coordinates, with its own guard band); same counts.  Ignored with
+       PC_FP64_PLAIN or PC_NO_PRUNE. */
+    PC_MATRIX_CORES = 0x200
 };
 
 /* A catalogue of n points: RA and Dec in degrees, binary64.  Paper Sec. 2.2

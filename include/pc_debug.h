@@ -20,15 +20,32 @@ extern "C" {
  *   info      host int64[8], written: {n_cells, shift, clamp_lo_bits,
  *             clamp_hi_bits, row_bytes, cols, multi_band_cells, 0}.
  *   entries   host uint32[4 * max_cells] or NULL; written with n_cells entries
- *             {row offset if c <= hi, row offset if c > hi, bits(lo), bits(hi)}
+ *             {row offset if c <= hi, bits(lo), bits(hi), row offset if c > hi}
  *             when n_cells <= max_cells.
  * A binary32 chord c in [0, 4.0001] is looked up as: key = clamp(bits(c),
  * clamp_lo, clamp_hi); cell = (key >> shift) - (clamp_lo >> shift); bin row =
- * (c > hi ? off_hi : off_lo) / row_bytes; lo <= c <= hi means re-check.
+ * (c > hi ? off_hi : off_lo) / row_bytes; lo <= c <= hi means re-check.  A
+ * finite hi implies off_hi = off_lo + row_bytes (the kernel relies on it).
  * Returns PC_OK or PC_ERR_INVALID (bad edges).
  */
 int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, int64_t *info,
                    uint32_t *entries, int64_t max_cells);
+
+/*
+ * pc_debug_lut32_gram -- the same for the matrix-core path, whose binary32
+ * chords are formed from coordinates centred on the tile of smaller bounding
+ * radius r, for tile pairs whose chords are all at least 2 r: guard bands
+ * from that (relative) error bound.
+ */
+int pc_debug_lut32_gram(const double *theta_edges_deg, int32_t n_edges, int64_t *info,
+                        uint32_t *entries, int64_t max_cells);
+
+/*
+ * pc_debug_guard_band_gram -- the per-edge guard band of the matrix-core path
+ * (lo, hi: host arrays of n_edges floats, written), with the meaning of
+ * pc_guard_band for chords formed as pc_debug_lut32_gram describes.
+ */
+int pc_debug_guard_band_gram(const double *theta_edges_deg, int32_t n_edges, float *lo, float *hi);
 
 /*
  * pc_debug_set_timing -- on != 0: the calling thread's later counting calls
@@ -47,9 +64,13 @@ int pc_debug_last_launch(double *kernel_ms, uint64_t *items, int32_t *grid, uint
 /*
  * pc_debug_last_pruning -- the calling thread's last counting launch: work
  * items (tile pairs) left for the pair kernel after whole-tile-pair binning,
- * pairs visited one by one, and all pairs counted.  Any pointer may be NULL.
+ * pairs visited one by one, all pairs counted, how many of the left items went
+ * through the matrix cores, and how many had at most 3 edges inside their
+ * chord interval (binned by comparing with those edges alone).  Any pointer
+ * may be NULL.
  */
-int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_t *pairs_total);
+int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_t *pairs_total,
+                          uint64_t *mfma_items, uint64_t *few_items);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libpc.so")
 PC_OK, PC_ERR_INVALID, PC_ERR_NOMEM, PC_ERR_DEVICE, PC_ERR_BUSY, PC_ERR_CANCELLED = range(6)
 PC_MIXED, PC_FP64_PLAIN = 0, 1
 PC_NO_PRUNE = 0x100
+PC_MATRIX_CORES = 0x200
 
 
 class PcError(RuntimeError):
@@ -61,7 +62,9 @@ _SIGNATURES = {
     "pc_debug_lut32": ([_vp, _i32, _vp, _vp, _i64], ctypes.c_int),
     "pc_debug_set_timing": ([_i32], ctypes.c_int),
     "pc_debug_last_launch": ([_vp, _vp, _vp, _vp], ctypes.c_int),
-    "pc_debug_last_pruning": ([_vp, _vp, _vp], ctypes.c_int),
+    "pc_debug_last_pruning": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "pc_debug_lut32_gram": ([_vp, _i32, _vp, _vp, _i64], ctypes.c_int),
+    "pc_debug_guard_band_gram": ([_vp, _i32, _vp, _vp], ctypes.c_int),
     "pc_server_create": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
     "pc_server_set_random": ([_vp, _i32, _PCAT], ctypes.c_int),
     "pc_server_submit": ([_vp, _PCAT, _i32, _vp, _i32, ctypes.POINTER(_u64)], ctypes.c_int),
@@ -255,20 +258,24 @@ def pc_chord2_edges(theta_edges) -> np.ndarray:
     return e
 
 
-def pc_guard_band(theta_edges):
+def pc_guard_band(theta_edges, gram: bool = False):
+    """Per-edge binary32 guard band (lo, hi); gram=True: the matrix-core
+    path's band (tile-centred chords)."""
     t, tp = _edges(theta_edges)
     lo = np.empty(t.size, dtype=np.float32)
     hi = np.empty(t.size, dtype=np.float32)
-    _check(lib().pc_guard_band(tp, t.size, lo.ctypes.data, hi.ctypes.data))
+    f = lib().pc_debug_guard_band_gram if gram else lib().pc_guard_band
+    _check(f(tp, t.size, lo.ctypes.data, hi.ctypes.data))
     return lo, hi
 
 
-def pc_debug_lut32(theta_edges):
+def pc_debug_lut32(theta_edges, gram: bool = False):
     t, tp = _edges(theta_edges)
+    f = lib().pc_debug_lut32_gram if gram else lib().pc_debug_lut32
     info = np.zeros(8, dtype=np.int64)
-    _check(lib().pc_debug_lut32(tp, t.size, info.ctypes.data, None, 0))
+    _check(f(tp, t.size, info.ctypes.data, None, 0))
     ent = np.zeros((int(info[0]), 4), dtype=np.uint32)
-    _check(lib().pc_debug_lut32(tp, t.size, info.ctypes.data, ent.ctypes.data, int(info[0])))
+    _check(f(tp, t.size, info.ctypes.data, ent.ctypes.data, int(info[0])))
     keys = ["n_cells", "shift", "clamp_lo", "clamp_hi", "row_bytes", "cols", "multi", "_"]
     return dict(zip(keys, (int(v) for v in info))), ent
 
@@ -290,8 +297,12 @@ def pc_debug_last_pruning() -> dict:
     surv = _u64(0)
     comp = _u64(0)
     tot = _u64(0)
-    _check(lib().pc_debug_last_pruning(ctypes.byref(surv), ctypes.byref(comp), ctypes.byref(tot)))
-    return {"survivors": int(surv.value), "pairs_computed": int(comp.value), "pairs_total": int(tot.value)}
+    mf = _u64(0)
+    few = _u64(0)
+    _check(lib().pc_debug_last_pruning(ctypes.byref(surv), ctypes.byref(comp), ctypes.byref(tot), ctypes.byref(mf),
+                                       ctypes.byref(few)))
+    return {"survivors": int(surv.value), "pairs_computed": int(comp.value), "pairs_total": int(tot.value),
+            "mfma_items": int(mf.value), "few_items": int(few.value)}
 
 
 # ------------------------------------------------------------------ serving

@@ -24,15 +24,16 @@ namespace pc {
 hipError_t launch_convert(const double *ra, const double *dec, int64_t n, double4 *a64, float4 *a32,
                           int *err, hipStream_t st);
 hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st);
-hipError_t launch_count(bool fp64, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
+hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
                         const uint64_t *items, const unsigned long long *n_items, uint64_t total_items,
-                        uint32_t lut_lds_off, uint32_t lds_bytes, int grid, hipStream_t st);
+                        uint32_t lut_lds_off, uint32_t lutg_lds_off, uint32_t stage_lds_off,
+                        unsigned long long *queue, uint32_t lds_bytes, int grid, hipStream_t st);
 size_t sort_scratch_words(int64_t n);
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
                        float4 *a32s, double4 *bounds, hipStream_t st);
 hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, uint64_t total_items,
-                        uint64_t *survivors, unsigned long long *meta, hipStream_t st);
-hipError_t count_occupancy(bool fp64, uint32_t lds_bytes, int *blocks_per_cu);
+                        uint64_t *survivors, unsigned long long *meta, int32_t mfma_ok, hipStream_t st);
+hipError_t count_occupancy(bool fp64, bool mc, uint32_t lds_bytes, int *blocks_per_cu);
 hipError_t set_max_lds(uint32_t bytes);
 
 // ------------------------------------------------------------------ errors
@@ -133,16 +134,27 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
     std::string err;
     if (!build_table(theta, n_edges, t->host, err)) return fail(PC_ERR_INVALID, err);
     const HostTable &h = t->host;
-    // one device block: e64 | lut32 | lut64
+    // one device block: e64 | band | band_g | lut32 | lut32g | lut64
     const size_t b_e = sizeof(double) * h.e64.size();
-    const size_t o_l32 = (b_e + 255) & ~size_t(255);
-    const size_t b_l32 = sizeof(LutEntry32) * h.lut32.size();
-    const size_t o_l64 = (o_l32 + b_l32 + 255) & ~size_t(255);
+    const size_t b_b = 2 * sizeof(float) * h.e64.size();
+    const size_t o_b = (b_e + 255) & ~size_t(255);
+    const size_t o_bg = (o_b + b_b + 255) & ~size_t(255);
+    const size_t o_l32 = (o_bg + b_b + 255) & ~size_t(255);
+    const size_t b_l32 = sizeof(LutEntry32) * h.lut32.entries.size();
+    const size_t o_l32g = (o_l32 + b_l32 + 255) & ~size_t(255);
+    const size_t b_l32g = sizeof(LutEntry32) * h.lut32g.entries.size();
+    const size_t o_l64 = (o_l32g + b_l32g + 255) & ~size_t(255);
     const size_t b_l64 = sizeof(LutEntry64) * h.lut64.size();
     const size_t total = o_l64 + b_l64 + 256;
     std::vector<unsigned char> blob(total, 0);
     memcpy(blob.data(), h.e64.data(), b_e);
-    if (b_l32) memcpy(blob.data() + o_l32, h.lut32.data(), b_l32);
+    for (size_t k = 0; k < h.e64.size(); ++k) {
+        const float bb[4] = {h.lo[k], h.hi[k], h.lo_g[k], h.hi_g[k]};
+        memcpy(blob.data() + o_b + 8 * k, bb, 8);
+        memcpy(blob.data() + o_bg + 8 * k, bb + 2, 8);
+    }
+    if (b_l32) memcpy(blob.data() + o_l32, h.lut32.entries.data(), b_l32);
+    if (b_l32g) memcpy(blob.data() + o_l32g, h.lut32g.entries.data(), b_l32g);
     if (b_l64) memcpy(blob.data() + o_l64, h.lut64.data(), b_l64);
     void *d = nullptr;
     PC_HIP(hipMalloc(&d, total), "hipMalloc(tables)");
@@ -150,7 +162,10 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
     PC_HIP(hipMemcpy(d, blob.data(), total, hipMemcpyHostToDevice), "hipMemcpy(tables)");
     unsigned char *base = static_cast<unsigned char *>(d);
     t->d_e64 = reinterpret_cast<const double *>(base);
+    t->d_band = reinterpret_cast<const float *>(base + o_b);
+    t->d_band_g = reinterpret_cast<const float *>(base + o_bg);
     t->d_lut32 = base + o_l32;
+    t->d_lut32g = base + o_l32g;
     t->d_lut64 = base + o_l64;
     std::lock_guard<std::mutex> lk(g_tab_mu);
     auto it = g_tabs.find(key);
@@ -181,25 +196,37 @@ TableDesc table_desc(const DevTable &t, bool fp64) {
     } else {
         d.cols = h.cols32;
         d.lut = t.d_lut32;
-        d.clamp_lo = h.clamp_lo32;
-        d.clamp_hi = h.clamp_hi32;
-        d.shift = h.shift32;
-        d.key0 = h.clamp_lo32 >> h.shift32;
-        d.n_cells = static_cast<int32_t>(h.lut32.size());
+        d.clamp_lo = h.lut32.clamp_lo;
+        d.clamp_hi = h.lut32.clamp_hi;
+        d.shift = h.lut32.shift;
+        d.key0 = h.lut32.clamp_lo >> h.lut32.shift;
+        d.n_cells = static_cast<int32_t>(h.lut32.entries.size());
         d.search = 0;
+        d.lut_g = t.d_lut32g;
+        d.g_clamp_lo = h.lut32g.clamp_lo;
+        d.g_clamp_hi = h.lut32g.clamp_hi;
+        d.g_shift = h.lut32g.shift;
+        d.g_key0 = h.lut32g.clamp_lo >> h.lut32g.shift;
+        d.g_n_cells = static_cast<int32_t>(h.lut32g.entries.size());
+        d.band = t.d_band;
+        d.band_g = t.d_band_g;
     }
     return d;
 }
 
-// LDS bytes a table needs: histogram rows, then the cell table (or edges)
-static void table_lds(const DevTable &t, bool fp64, uint32_t *hist, uint32_t *lut) {
+// LDS bytes a table needs: histogram rows, then the cell table (or edges),
+// then (mixed) the matrix-core path's cell table
+static void table_lds(const DevTable &t, bool fp64, uint32_t *hist, uint32_t *lut, uint32_t *lut_g) {
     const HostTable &h = t.host;
     *hist = static_cast<uint32_t>(h.e64.size() + 2) * (fp64 ? h.row_bytes64 : h.row_bytes32);
-    if (fp64)
+    *lut_g = 0;
+    if (fp64) {
         *lut = h.search64 ? static_cast<uint32_t>(8 * h.e64.size())
                           : static_cast<uint32_t>(16 * h.lut64.size());
-    else
-        *lut = static_cast<uint32_t>(16 * h.lut32.size());
+    } else {
+        *lut = static_cast<uint32_t>(16 * h.lut32.entries.size());
+        *lut_g = static_cast<uint32_t>(16 * h.lut32g.entries.size());
+    }
 }
 
 // ------------------------------------------------------------- catalogues
@@ -266,10 +293,12 @@ static thread_local BatchStats t_last;
 
 int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st, BatchStats *stats) {
     if (jobs.empty()) return fail(PC_ERR_INVALID, "no jobs");
-    const int mode = mode_flags & ~PC_NO_PRUNE;
+    const int mode = mode_flags & ~(PC_NO_PRUNE | PC_MATRIX_CORES);
     const bool prune = (mode_flags & PC_NO_PRUNE) == 0;
     if (mode != PC_MIXED && mode != PC_FP64_PLAIN) return fail(PC_ERR_INVALID, "unknown mode");
     const bool fp64 = mode == PC_FP64_PLAIN;
+    // the matrix-core path needs the prune pass's marks; binary32 only
+    const bool mc = (mode_flags & PC_MATRIX_CORES) != 0 && prune && !fp64;
     // host-side validation first, so bad arguments are reported as such
     for (const BatchJob &j : jobs) {
         if (j.auto_flag != 0 && j.auto_flag != 1) return fail(PC_ERR_INVALID, "auto_flag must be 0 or 1");
@@ -446,9 +475,13 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         if (plan[q].vi_tri >= 0) add(true, plan[q].vi_tri, plan[q].vi_tri);
         if (plan[q].vi_rect >= 0 && plan[q].vj_rect >= 0) add(false, plan[q].vi_rect, plan[q].vj_rect);
     }
+    if (items > kItemMask)
+        return fail(PC_ERR_INVALID, "too many tile pairs in one call (" + std::to_string(items) +
+                                        "); split the catalogues into row ranges");
     const size_t o_segs = ar.take(sizeof(SegDesc) * std::max<size_t>(segs.size(), 1));
     const size_t o_tabs = ar.take(sizeof(TableDesc) * tabs.size());
-    const size_t o_meta = ar.take(sizeof(unsigned long long) * 4);
+    // meta[0..4]: pruning results; meta[8..15]: the counting kernel's work queue
+    const size_t o_meta = ar.take(sizeof(unsigned long long) * 16);
     const size_t o_surv = ar.take(sizeof(uint64_t) * std::max<uint64_t>(prune ? items : 1, 1));
 
     // ---- allocate the workspace
@@ -524,16 +557,19 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         sd.counts = reinterpret_cast<unsigned long long *>(W + plan[static_cast<size_t>(sd.job)].o_counts);
     }
     std::vector<TableDesc> tds;
-    uint32_t hist_max = 0, lut_max = 0;
+    uint32_t hist_max = 0, lut_max = 0, lutg_max = 0;
     for (auto &t : tabs) {
         tds.push_back(table_desc(*t, fp64));
-        uint32_t h, l;
-        table_lds(*t, fp64, &h, &l);
+        uint32_t h, l, g;
+        table_lds(*t, fp64, &h, &l, &g);
         hist_max = std::max(hist_max, h);
         lut_max = std::max(lut_max, l);
+        lutg_max = std::max(lutg_max, g);
     }
     const uint32_t lut_off = (hist_max + 15u) & ~15u;
-    const uint32_t lds_bytes = lut_off + std::max<uint32_t>(lut_max, 16u);
+    const uint32_t lutg_off = lut_off + ((std::max<uint32_t>(lut_max, 16u) + 15u) & ~15u);
+    const uint32_t stage_off = lutg_off + ((lutg_max + 15u) & ~15u);
+    const uint32_t lds_bytes = stage_off + ((mc && !PC_AREG) ? 16u * kWave * 4u : 0u);
     if (lds_bytes > di->lds_per_block)
         return fail(PC_ERR_INVALID, "edge set needs " + std::to_string(lds_bytes) +
                                         " bytes of LDS per wave; the device allows " +
@@ -547,7 +583,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         PC_HIP(launch_zero(reinterpret_cast<unsigned long long *>(W + plan[q].o_counts), jobs[q].n_edges + 1, st),
                "zero counts");
     unsigned long long *meta = reinterpret_cast<unsigned long long *>(W + o_meta);
-    PC_HIP(launch_zero(meta, 4, st), "zero meta");
+    PC_HIP(launch_zero(meta, 16, st), "zero meta");
 
     // ---- whole-tile-pair binning, then the counting kernel over the rest
     const SegDesc *d_segs = reinterpret_cast<const SegDesc *>(W + o_segs);
@@ -556,9 +592,10 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     int grid = 0;
     if (items > 0) {
         if (prune)
-            PC_HIP(launch_prune(d_segs, static_cast<int32_t>(segs.size()), d_tabs, items, surv, meta, st), "prune");
+            PC_HIP(launch_prune(d_segs, static_cast<int32_t>(segs.size()), d_tabs, items, surv, meta, mc ? 1 : 0, st),
+                   "prune");
         int per_cu = 0;
-        PC_HIP(count_occupancy(fp64, lds_bytes, &per_cu), "occupancy");
+        PC_HIP(count_occupancy(fp64, mc, lds_bytes, &per_cu), "occupancy");
         per_cu = std::max(per_cu, 1);
         int64_t g = static_cast<int64_t>(di->cus) * per_cu;
         g = std::min<int64_t>(g, static_cast<int64_t>(items));
@@ -572,8 +609,8 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             }
             PC_HIP(hipEventRecord(t_ev0, st), "hipEventRecord");
         }
-        PC_HIP(launch_count(fp64, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
-                            prune ? meta : nullptr, items, lut_off, lds_bytes, grid, st),
+        PC_HIP(launch_count(fp64, mc, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
+                            prune ? meta : nullptr, items, lut_off, lutg_off, stage_off, meta + 8, lds_bytes, grid, st),
                "count kernel");
         if (timed) PC_HIP(hipEventRecord(t_ev1, st), "hipEventRecord");
     }
@@ -588,7 +625,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     }
     std::vector<int> flags(std::max<size_t>(srcs.size(), 1), 0);
     PC_HIP(hipMemcpyAsync(flags.data(), W + o_err, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, st), "D2H flags");
-    unsigned long long hmeta[4] = {0, 0, 0, 0};
+    unsigned long long hmeta[5] = {0, 0, 0, 0, 0};
     PC_HIP(hipMemcpyAsync(hmeta, meta, sizeof(hmeta), hipMemcpyDeviceToHost, st), "D2H meta");
     PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
     for (size_t k = 0; k < srcs.size(); ++k)
@@ -610,6 +647,8 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     t_last.survivors = prune ? hmeta[0] : items;
     t_last.pairs_total = total_pairs;
     t_last.pairs_computed = prune ? hmeta[1] : total_pairs;
+    t_last.mfma_items = prune ? hmeta[3] : 0;
+    t_last.few_items = prune ? hmeta[4] : 0;
     if (t_timing && items > 0) {
         float ms = 0.0f;
         PC_HIP(hipEventElapsedTime(&ms, t_ev0, t_ev1), "hipEventElapsedTime");
@@ -834,23 +873,45 @@ int pc_guard_band(const double *theta_edges_deg, int32_t n_edges, float *lo, flo
 
 }  // extern "C"
 
-extern "C" int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, int64_t *info, uint32_t *entries,
-                              int64_t max_cells) {
+static int debug_lut(const double *theta_edges_deg, int32_t n_edges, int64_t *info, uint32_t *entries,
+                     int64_t max_cells, bool gram) {
     clear_error();
     if (!theta_edges_deg || !info) return fail(PC_ERR_INVALID, "NULL argument");
     HostTable t;
     std::string err;
     if (!build_table(theta_edges_deg, n_edges, t, err)) return fail(PC_ERR_INVALID, err);
-    info[0] = static_cast<int64_t>(t.lut32.size());
-    info[1] = t.shift32;
-    info[2] = t.clamp_lo32;
-    info[3] = t.clamp_hi32;
+    const Lut32 &L = gram ? t.lut32g : t.lut32;
+    info[0] = static_cast<int64_t>(L.entries.size());
+    info[1] = L.shift;
+    info[2] = L.clamp_lo;
+    info[3] = L.clamp_hi;
     info[4] = t.row_bytes32;
     info[5] = t.cols32;
-    info[6] = t.multi32;
+    info[6] = L.multi;
     info[7] = 0;
-    if (entries && static_cast<int64_t>(t.lut32.size()) <= max_cells)
-        memcpy(entries, t.lut32.data(), sizeof(LutEntry32) * t.lut32.size());
+    if (entries && static_cast<int64_t>(L.entries.size()) <= max_cells)
+        memcpy(entries, L.entries.data(), sizeof(LutEntry32) * L.entries.size());
+    return PC_OK;
+}
+
+extern "C" int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, int64_t *info, uint32_t *entries,
+                              int64_t max_cells) {
+    return debug_lut(theta_edges_deg, n_edges, info, entries, max_cells, false);
+}
+
+extern "C" int pc_debug_lut32_gram(const double *theta_edges_deg, int32_t n_edges, int64_t *info,
+                                   uint32_t *entries, int64_t max_cells) {
+    return debug_lut(theta_edges_deg, n_edges, info, entries, max_cells, true);
+}
+
+extern "C" int pc_debug_guard_band_gram(const double *theta_edges_deg, int32_t n_edges, float *lo, float *hi) {
+    clear_error();
+    if (!theta_edges_deg || !lo || !hi) return fail(PC_ERR_INVALID, "NULL argument");
+    HostTable t;
+    std::string err;
+    if (!build_table(theta_edges_deg, n_edges, t, err)) return fail(PC_ERR_INVALID, err);
+    memcpy(lo, t.lo_g.data(), sizeof(float) * static_cast<size_t>(n_edges));
+    memcpy(hi, t.hi_g.data(), sizeof(float) * static_cast<size_t>(n_edges));
     return PC_OK;
 }
 
@@ -860,8 +921,11 @@ extern "C" int pc_debug_set_timing(int32_t on) {
     return PC_OK;
 }
 
-extern "C" int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_t *pairs_total) {
+extern "C" int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_t *pairs_total,
+                                     uint64_t *mfma_items, uint64_t *few_items) {
     clear_error();
+    if (few_items) *few_items = t_last.few_items;
+    if (mfma_items) *mfma_items = t_last.mfma_items;
     if (survivors) *survivors = t_last.survivors;
     if (pairs_computed) *pairs_computed = t_last.pairs_computed;
     if (pairs_total) *pairs_total = t_last.pairs_total;

@@ -12,8 +12,11 @@ namespace pc {
 #ifndef PC_R
 #define PC_R 4              // i-points held per lane
 #endif
+#ifndef PC_AREG
+#define PC_AREG 0           // matrix-core A operands in registers (else staged in LDS)
+#endif
 #ifndef PC_COLS32
-#define PC_COLS32 32        // widest histogram of the mixed kernel (lane columns)
+#define PC_COLS32 16        // widest histogram of the mixed kernel (lane columns)
 #endif
 #ifndef PC_COLS64
 #define PC_COLS64 16        // widest histogram of the binary64 kernel
@@ -34,10 +37,14 @@ inline uint32_t row_bytes_for(int cols) { return static_cast<uint32_t>(cols) * 4
 
 // Cell lookup entry of the mixed (binary32) kernel.  For a squared chord c in
 // the cell: c > hi -> histogram row offset off_hi, else off_lo; lo <= c <= hi
-// -> re-check in binary64.  Offsets are byte offsets of histogram rows.
+// -> re-check in binary64.  Offsets are byte offsets of histogram rows.  A
+// finite hi only occurs in a cell that one band meets, where off_hi = off_lo
+// + one row, so the kernel reads the first 12 bytes alone and adds the row
+// when c > hi.
 struct LutEntry32 {
-    uint32_t off_lo, off_hi;
+    uint32_t off_lo;
     float lo, hi;
+    uint32_t off_hi;
 };
 
 // Cell lookup entry of the binary64 kernel: c >= e -> off_hi, else off_lo.
@@ -58,6 +65,31 @@ struct TableDesc {
     int32_t n_edges;
     int32_t search;         // fp64 only: 1 = no exact cell table, binary search per pair
     int32_t cols;           // histogram lane columns (power of two <= 64)
+    // cell table of the matrix-core path (tile-centred chords; mixed only)
+    const void *lut_g;
+    uint32_t g_clamp_lo, g_clamp_hi, g_shift, g_key0;
+    int32_t g_n_cells, g_pad;
+    // guard bands as (lo, hi) binary32 pairs per edge, plain and matrix-core
+    // (mixed only; device)
+    const float *band, *band_g;
+};
+
+// A survivor work item (one tile pair left after whole-tile-pair binning), as
+// the prune pass writes it for the counting kernel:
+//   bits  0..39  item number within the launch
+//   bits 40..50  k0: edges at or below the item's whole chord interval
+//   bits 51..52  m: edges inside the interval when at most kFewMax, else 0
+//   bit  62      matrix-core path centred on the j-tile
+//   bit  63      matrix-core path
+constexpr int kItemBits = 40;
+constexpr int kFewMax = 3;
+constexpr uint64_t kItemMask = (1ull << kItemBits) - 1;
+
+// A binary32 cell table (see pc_tables.cpp).
+struct Lut32 {
+    uint32_t clamp_lo = 0, clamp_hi = 0, shift = 0;
+    std::vector<LutEntry32> entries;
+    int multi = 0;  // cells that always re-check (bands closer than the cell width)
 };
 
 // A block of tile pairs of one job: a triangle (unordered pairs i<j inside
@@ -83,10 +115,10 @@ struct HostTable {
     std::vector<double> theta;
     std::vector<double> e64;
     std::vector<float> lo, hi;
-    // mixed kernel
-    uint32_t clamp_lo32 = 0, clamp_hi32 = 0, shift32 = 0;
-    std::vector<LutEntry32> lut32;
-    int multi32 = 0;  // cells that always re-check (bands closer than the cell width)
+    // mixed kernel: direct chords (binary32 unit vectors) and tile-centred
+    // chords formed by the matrix cores, each with its own guard band
+    std::vector<float> lo_g, hi_g;
+    Lut32 lut32, lut32g;
     // fp64 kernel
     uint32_t clamp_lo64 = 0, clamp_hi64 = 0, shift64 = 0;
     std::vector<LutEntry64> lut64;
@@ -102,5 +134,10 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
 // The guard band of one squared-chord edge e (binary64): binary32 lo, hi with
 //   c32 > hi  =>  c64 >= e,     c32 < lo  =>  c64 < e.
 void guard_band(double e, float *lo, float *hi);
+
+// The same for chords formed from tile-centred binary32 coordinates by the
+// matrix cores (coordinates centred on the tile of smaller bounding radius r,
+// every pair of the tile pair at chord >= 2 r).
+void guard_band_gram(double e, float *lo, float *hi);
 
 }  // namespace pc

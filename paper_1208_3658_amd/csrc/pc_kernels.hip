@@ -28,7 +28,10 @@ struct KParams {
     const unsigned long long *n_items;     // device count of `items`
     uint64_t total_items;                  // number of items when `items` is null
     int32_t n_segs;
-    uint32_t lut_lds_off;  // byte offset of the cell table in LDS (after the histogram)
+    uint32_t lut_lds_off;   // byte offset of the cell table in LDS (after the histogram)
+    uint32_t lutg_lds_off;  // byte offset of the matrix-core path's cell table
+    uint32_t stage_lds_off; // byte offset of the matrix-core path's A-operand block (16 x 64 floats)
+    unsigned long long *queue;  // 8 zeroed chunk counters, one per slice of the items
 };
 
 // -------------------------------------------------------------- conversion
@@ -75,6 +78,12 @@ __device__ __forceinline__ float4 ld_const(const float4 *p) {
     using CF = const __attribute__((address_space(4))) float;
     CF *q = (CF *)(p);
     return make_float4(q[0], q[1], q[2], q[3]);
+}
+
+__device__ __forceinline__ float2 ld_const_f2(const float *p) {
+    using CF = const __attribute__((address_space(4))) float;
+    CF *q = (CF *)(p);
+    return make_float2(q[0], q[1]);
 }
 
 __device__ __forceinline__ double4 ld_const(const double4 *p) {
@@ -135,6 +144,15 @@ __device__ __forceinline__ uint32_t lds_addr(const unsigned char *p) {
 __device__ __forceinline__ void lds_add(unsigned char *, uint32_t addr, uint32_t v) {
     __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)(addr), v, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+using lds_u3 = __attribute__((address_space(3))) const u32x3;
+
+// first 12 bytes of a 16-byte aligned cell entry: (off_lo, bits(lo), bits(hi))
+__device__ __forceinline__ uint3 lds_read3(uint32_t addr) {
+    const u32x3 v = *(lds_u3 *)(uintptr_t)(addr);
+    return make_uint3(v.x, v.y, v.z);
 }
 
 __device__ __forceinline__ uint4 lds_read4(uint32_t addr) {
@@ -267,19 +285,19 @@ __device__ __forceinline__ void step32(unsigned char *lds, const float4 *__restr
             c2[q][r] = chord2_32(ax[r], ay[r], az[r], b[q]);
             a[q][r] = cell_addr(key32(c2[q][r], k.klo, k.khi), k.shift, k.lut_base);
         }
-    uint4 e[NJ][kR];
+    uint3 e[NJ][kR];
 #pragma unroll
     for (int q = 0; q < NJ; ++q)
 #pragma unroll
-        for (int r = 0; r < kR; ++r) e[q][r] = lds_read4(a[q][r]);
+        for (int r = 0; r < kR; ++r) e[q][r] = lds_read3(a[q][r]);
     bool any_band = false;
 #pragma unroll
     for (int q = 0; q < NJ; ++q)
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
-            const bool gt = c2[q][r] > __uint_as_float(e[q][r].w);
-            const bool band = !gt & (c2[q][r] >= __uint_as_float(e[q][r].z));
-            uint32_t off = (gt ? e[q][r].y : e[q][r].x) + k.lane_off;
+            const bool gt = c2[q][r] > __uint_as_float(e[q][r].z);
+            const bool band = !gt & (c2[q][r] >= __uint_as_float(e[q][r].y));
+            uint32_t off = e[q][r].x + (gt ? k.row_bytes : 0u) + k.lane_off;
             if (MASKED) {
                 // i slot valid, and on a diagonal tile i < j (positions
                 // relative to the tile start: i = r*64 + lane, j = j_rel + jj + q)
@@ -300,9 +318,10 @@ __device__ __forceinline__ void step32(unsigned char *lds, const float4 *__restr
         for (int q = 0; q < NJ; ++q) {
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
-                const float c = chord2_32(ax[r], ay[r], az[r], b[q]);
-                const uint4 en = lds_read4(cell_addr(key32(c, k.klo, k.khi), k.shift, k.lut_base));
-                bool band = !(c > __uint_as_float(en.w)) && (c >= __uint_as_float(en.z));
+                float c = chord2_32(ax[r], ay[r], az[r], b[q]);
+                asm volatile("" : "+v"(c));
+                const uint3 en = lds_read3(cell_addr(key32(c, k.klo, k.khi), k.shift, k.lut_base));
+                bool band = !(c > __uint_as_float(en.z)) && (c >= __uint_as_float(en.y));
                 if (MASKED) {
                     const int32_t ir = r * kWave + lane;
                     band &= ir < i_lim && (!diag || ir < j_rel + jj + q);
@@ -339,6 +358,373 @@ __device__ __forceinline__ void tile32(unsigned char *lds, const float4 *__restr
         step32<MASKED, PC_JUNROLL>(lds, Jt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
     for (; jj < jn; ++jj)
         step32<MASKED, 1>(lds, Jt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+}
+
+// ------------------------------------------------------- few-edge items
+//
+// When the whole chord interval of a tile pair contains only M <= kFewMax
+// edges (k0 .. k0+M-1; the prune pass proved every exact chord to lie above
+// edge k0-1 and below edge k0+M), a chord's row is k0 + #{k < M : c > hi_k}
+// and only those M bands need checking.  Each lane counts, per k, its chords
+// above band k in a register over the whole item and adds the counts to its
+// histogram column at the end: no cell table read and no histogram atomic per
+// pair.  In-band chords are re-checked in binary64; their correction (+1 on
+// the exact row, -1 on the provisional one) goes to the histogram directly.
+
+struct FewCtx {
+    float lo[kFewMax], hi[kFewMax];  // bands of edges k0 .. k0+M-1
+    uint32_t k0;
+};
+
+// n += (c > hi); band |= (c >= lo) & !(c > hi), band a lane mask.  Three
+// vector instructions (two compares, an add with carry-in) and two scalar
+// ones; written out because the compiler otherwise recomputes !(c > hi) as a
+// third compare.  Compares with a NaN are false: a NaN chord counts nowhere.
+__device__ __forceinline__ void few_count(float c, float lo, float hi, uint32_t &n, uint64_t &band) {
+    uint64_t gt, ge;
+    asm volatile(
+        "v_cmp_gt_f32_e64 %[gt], %[c], %[hi]\n\t"
+        "v_cmp_ge_f32_e64 %[ge], %[c], %[lo]\n\t"
+        "s_andn2_b64 %[ge], %[ge], %[gt]\n\t"
+        "s_or_b64 %[band], %[band], %[ge]\n\t"
+        "v_addc_co_u32_e64 %[n], %[gt], 0, %[n], %[gt]"
+        : [n] "+v"(n), [band] "+s"(band), [gt] "=&s"(gt), [ge] "=&s"(ge)
+        : [c] "v"(c), [lo] "v"(lo), [hi] "v"(hi)
+        : "scc");
+}
+
+// Add a lane's few-edge register counts to its histogram column: rows k0 ..
+// k0+M get (chords above band t-1) - (chords above band t), with `total`
+// valid chords above "band -1".
+template <int M>
+__device__ __forceinline__ void few_flush(unsigned char *lds, const uint32_t (&ngt)[M], uint32_t total,
+                                          const FewCtx &f, const TileCtx &k) {
+    uint32_t prev = total;
+#pragma unroll
+    for (int t = 0; t <= M; ++t) {
+        const uint32_t above = t < M ? ngt[t] : 0u;
+        const uint32_t cnt = prev - above;
+        if (cnt) lds_add(lds, (f.k0 + static_cast<uint32_t>(t)) * k.row_bytes + k.lane_off, cnt);
+        prev = above;
+    }
+}
+
+// binary64 re-check of one in-band chord (provisional row k0 + #{c > hi_k})
+template <int M>
+__device__ __forceinline__ void few_recheck(unsigned char *lds, float c, const double4 &a64, const double4 &b64,
+                                            const FewCtx &f, const TileCtx &k) {
+    uint32_t prov = f.k0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) prov += c > f.hi[t] ? 1u : 0u;
+    const double c64 = chord2_64(a64.x, a64.y, a64.z, b64.x, b64.y, b64.z);
+    const uint32_t exact = bin_search(k.e64, k.n_edges, c64);
+    if (exact != prov) {
+        lds_add(lds, exact * k.row_bytes + k.lane_off, 1u);
+        lds_add(lds, prov * k.row_bytes + k.lane_off, 0xFFFFFFFFu);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ bool few_in_band(float c, const FewCtx &f) {
+    bool band = false;
+#pragma unroll
+    for (int t = 0; t < M; ++t) band |= !(c > f.hi[t]) & (c >= f.lo[t]);
+    return band;
+}
+
+template <bool MASKED, int M, int NJ>
+__device__ __forceinline__ void step32_few(unsigned char *lds, const float4 *__restrict__ Jt,
+                                           const double4 *__restrict__ J64t, int32_t jj,
+                                           const float (&ax)[kR], const float (&ay)[kR],
+                                           const float (&az)[kR], const double4 *__restrict__ I64,
+                                           int64_t ibeg, int32_t i_lim, int32_t j_rel, bool diag,
+                                           const TileCtx &k, const FewCtx &f, uint32_t (&ngt)[M]) {
+    const int32_t lane = static_cast<int32_t>(threadIdx.x);
+    float4 b[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) b[q] = ld_const(Jt + jj + q);
+    uint64_t band = 0;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q)
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            float c = chord2_32(ax[r], ay[r], az[r], b[q]);
+            if (MASKED) {
+                // a masked-out pair becomes NaN, which no compare counts
+                const int32_t ir = r * kWave + lane;
+                const bool ok = ir < i_lim && (!diag || ir < j_rel + jj + q);
+                c = ok ? c : __builtin_nanf("");
+            }
+#pragma unroll
+            for (int t = 0; t < M; ++t) few_count(c, f.lo[t], f.hi[t], ngt[t], band);
+        }
+    if (__builtin_expect(band != 0, 0)) {
+#pragma unroll
+        for (int q = 0; q < NJ; ++q)
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                float c = chord2_32(ax[r], ay[r], az[r], b[q]);
+                asm volatile("" : "+v"(c));
+                bool band = few_in_band<M>(c, f);
+                if (MASKED) {
+                    const int32_t ir = r * kWave + lane;
+                    band &= ir < i_lim && (!diag || ir < j_rel + jj + q);
+                }
+                if (band) few_recheck<M>(lds, c, I64[ibeg + r * kWave + lane], J64t[jj + q], f, k);
+            }
+    }
+}
+
+// One tile pair of a few-edge item in binary32 (masking as in tile32).
+template <bool MASKED, int M>
+__device__ __forceinline__ void tile32_few(unsigned char *lds, const float4 *__restrict__ Jt,
+                                           const double4 *__restrict__ J64t, int32_t jn,
+                                           const float (&ax)[kR], const float (&ay)[kR],
+                                           const float (&az)[kR], const double4 *__restrict__ I64,
+                                           int64_t ibeg, int32_t i_lim, int32_t j_rel, bool diag,
+                                           const TileCtx &k, const FewCtx &f) {
+    uint32_t ngt[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) ngt[t] = 0u;
+    int32_t jj = 0;
+    for (; jj + PC_JUNROLL <= jn; jj += PC_JUNROLL)
+        step32_few<MASKED, M, PC_JUNROLL>(lds, Jt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k, f, ngt);
+    for (; jj < jn; ++jj)
+        step32_few<MASKED, M, 1>(lds, Jt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k, f, ngt);
+    // valid chords of this lane: slot r holds i = r*64 + lane; on a diagonal
+    // tile only j with i < j count
+    uint32_t total = 0;
+    const int32_t lane = static_cast<int32_t>(threadIdx.x);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int32_t ir = r * kWave + lane;
+        if (!MASKED) {
+            total += static_cast<uint32_t>(jn);
+        } else if (ir < i_lim) {
+            const int32_t skip = diag ? min(max(ir - j_rel + 1, 0), jn) : 0;
+            total += static_cast<uint32_t>(jn - skip);
+        }
+    }
+    few_flush<M>(lds, ngt, total, f, k);
+}
+
+// ----------------------------------------------------------- matrix cores
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+#ifndef PC_MB
+#define PC_MB 2             // 16x16 blocks binned together (4 chords per lane each)
+#endif
+#ifndef PC_BIUNROLL
+#define PC_BIUNROLL 1
+#endif
+
+// Cell-table binning of the chords one lane holds after MB 16x16x4 matrix
+// multiplies: D[m][v] is the pair (i = (bi0 + m)*16 + 4*kq + v, j = bj*16 +
+// l16) of the tile pair.  All cell-table reads are issued before any compare,
+// so 4 MB lookups overlap; in-band chords are re-checked in binary64 like in
+// step32.
+template <int MB>
+__device__ __forceinline__ void bin_mfma(unsigned char *lds, const f32x4 (&D)[MB], const double4 *__restrict__ I64t,
+                                         const double4 *__restrict__ J64t, int bi0, int bj, const TileCtx &g) {
+    const int lane = static_cast<int>(threadIdx.x);
+    const int l16 = lane & 15, kq = lane >> 4;
+    float c[4 * MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        c[4 * m + 0] = D[m].x;
+        c[4 * m + 1] = D[m].y;
+        c[4 * m + 2] = D[m].z;
+        c[4 * m + 3] = D[m].w;
+    }
+    uint32_t a[4 * MB];
+#pragma unroll
+    for (int v = 0; v < 4 * MB; ++v) a[v] = cell_addr(key32(c[v], g.klo, g.khi), g.shift, g.lut_base);
+    uint3 e[4 * MB];
+#pragma unroll
+    for (int v = 0; v < 4 * MB; ++v) e[v] = lds_read3(a[v]);
+    bool any_band = false;
+#pragma unroll
+    for (int v = 0; v < 4 * MB; ++v) {
+        const bool gt = c[v] > __uint_as_float(e[v].z);
+        any_band |= !gt & (c[v] >= __uint_as_float(e[v].y));
+        lds_add(lds, e[v].x + (gt ? g.row_bytes : 0u) + g.lane_off, 1u);
+    }
+    if (__builtin_expect(any_band, 0)) {
+#pragma unroll
+        for (int v = 0; v < 4 * MB; ++v) {
+            float cv = c[v];
+            asm volatile("" : "+v"(cv));
+            const uint3 en = lds_read3(cell_addr(key32(cv, g.klo, g.khi), g.shift, g.lut_base));
+            const bool band = !(cv > __uint_as_float(en.z)) && (cv >= __uint_as_float(en.y));
+            if (band) {
+                // formed here, not hoisted out of the caller's loops (64
+                // loop-invariant addresses would otherwise stay live)
+                int row = (bi0 + v / 4) * 16 + 4 * kq + (v & 3);
+                asm volatile("" : "+v"(row));
+                const double4 p = I64t[row];
+                const double4 q = J64t[bj * 16 + l16];
+                const double c64 = chord2_64(p.x, p.y, p.z, q.x, q.y, q.z);
+                const uint32_t exact = bin_search(g.e64, g.n_edges, c64) * g.row_bytes + g.lane_off;
+                const uint32_t prov = en.x + g.lane_off;
+                if (exact != prov) {
+                    lds_add(lds, exact, 1u);
+                    lds_add(lds, prov, 0xFFFFFFFFu);
+                }
+            }
+        }
+    }
+}
+
+// Few-edge binning of the chords one lane holds after MB matrix multiplies
+// (see the few-edge items above).
+template <int MB, int M>
+__device__ __forceinline__ void bin_mfma_few(unsigned char *lds, const f32x4 (&D)[MB], const double4 *__restrict__ I64t,
+                                             const double4 *__restrict__ J64t, int bi0, int bj, const TileCtx &g,
+                                             const FewCtx &f, uint32_t (&ngt)[M]) {
+    const int lane = static_cast<int>(threadIdx.x);
+    const int l16 = lane & 15, kq = lane >> 4;
+    float c[4 * MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        c[4 * m + 0] = D[m].x;
+        c[4 * m + 1] = D[m].y;
+        c[4 * m + 2] = D[m].z;
+        c[4 * m + 3] = D[m].w;
+    }
+    uint64_t band = 0;
+#pragma unroll
+    for (int v = 0; v < 4 * MB; ++v)
+#pragma unroll
+        for (int t = 0; t < M; ++t) few_count(c[v], f.lo[t], f.hi[t], ngt[t], band);
+    if (__builtin_expect(band != 0, 0)) {
+#pragma unroll
+        for (int v = 0; v < 4 * MB; ++v) {
+            // an opaque copy: the compares are redone here rather than their
+            // results kept live (in scalar registers) through the main path
+            float cv = c[v];
+            asm volatile("" : "+v"(cv));
+            if (few_in_band<M>(cv, f)) {
+                int row = (bi0 + v / 4) * 16 + 4 * kq + (v & 3);
+                asm volatile("" : "+v"(row));
+                few_recheck<M>(lds, cv, I64t[row], J64t[bj * 16 + l16], f, g);
+            }
+        }
+    }
+}
+
+template <int MB, int M>
+__device__ __forceinline__ void bin_mfma_any(unsigned char *lds, const f32x4 (&D)[MB], const double4 *__restrict__ I64t,
+                                             const double4 *__restrict__ J64t, int bi0, int bj, const TileCtx &g,
+                                             const FewCtx &f, uint32_t (&ngt)[M > 0 ? M : 1]) {
+    if constexpr (M == 0) bin_mfma<MB>(lds, D, I64t, J64t, bi0, bj, g);
+    else bin_mfma_few<MB, M>(lds, D, I64t, J64t, bi0, bj, g, f, ngt);
+}
+
+// One full 256 x 256 tile pair through the matrix cores.  Coordinates are
+// centred on o (the bounding-sphere centre of the tile with the smaller
+// radius) in binary64 and rounded to binary32: a' = a - o, b' = b - o.  With
+// A_i = (a'_x, a'_y, a'_z, |a'_i|^2), B_j = (-2 b'_x, -2 b'_y, -2 b'_z, 1) and
+// the addend |b'_j|^2, one v_mfma_f32_16x16x4f32 gives |a'_i - b'_j|^2 for a
+// 16 x 16 block of pairs (operand layout: lane l holds row l%16, k = l/16 of
+// A and column l%16, k = l/16 of B).  The lane's A operands of all 16
+// i-blocks stay in registers; the j-block loop loads the next block's point
+// one iteration ahead.  Only tile pairs whose chord lower bound is at least
+// twice that radius come here; their guard band is the g table's.
+// M > 0: a few-edge item (bands in f), else binned through the cell table.
+template <int M>
+__device__ __forceinline__ void tile_mfma(unsigned char *lds, uint32_t a_stage, const double4 *__restrict__ I64t,
+                                          const double4 *__restrict__ J64t, double ox, double oy, double oz,
+                                          const TileCtx &g, const FewCtx &f) {
+    const int lane = static_cast<int>(threadIdx.x);
+    const int l16 = lane & 15, kq = lane >> 4;
+    constexpr int MB = PC_MB;
+    uint32_t ngt[M > 0 ? M : 1];
+#pragma unroll
+    for (int t = 0; t < (M > 0 ? M : 1); ++t) ngt[t] = 0u;
+    static_assert(16 % MB == 0, "blocks per binning step");
+#if PC_AREG
+    (void)a_stage;
+    float A[16];
+#pragma unroll
+    for (int bi = 0; bi < 16; ++bi) {
+        const double4 p = I64t[bi * 16 + l16];
+        const float x = static_cast<float>(p.x - ox);
+        const float y = static_cast<float>(p.y - oy);
+        const float z = static_cast<float>(p.z - oz);
+        const float na = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
+        A[bi] = kq == 0 ? x : kq == 1 ? y : kq == 2 ? z : na;
+        // at most 4 blocks' loads in flight: all 16 at once would need 128
+        // registers for the binary64 points
+        if ((bi & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+#else
+    using lds_f32 = __attribute__((address_space(3))) float;
+#pragma unroll 4
+    for (int bi = 0; bi < 16; ++bi) {
+        const double4 p = I64t[bi * 16 + l16];
+        const float x = static_cast<float>(p.x - ox);
+        const float y = static_cast<float>(p.y - oy);
+        const float z = static_cast<float>(p.z - oz);
+        const float na = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
+        *(lds_f32 *)(uintptr_t)(a_stage + (bi * kWave + lane) * 4u) = kq == 0 ? x : kq == 1 ? y : kq == 2 ? z : na;
+    }
+#endif
+    double4 q = J64t[l16];
+#pragma unroll 1
+    for (int bj = 0; bj < 16; ++bj) {
+        const double4 qn = J64t[min(bj + 1, 15) * 16 + l16];
+        const float x = static_cast<float>(q.x - ox);
+        const float y = static_cast<float>(q.y - oy);
+        const float z = static_cast<float>(q.z - oz);
+        const float nb = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
+        const float B = kq == 0 ? -2.0f * x : kq == 1 ? -2.0f * y : kq == 2 ? -2.0f * z : 1.0f;
+        const f32x4 C = {nb, nb, nb, nb};
+#if PC_AREG
+        // software-pipelined: the next MB blocks are multiplied before the
+        // current ones are binned
+        f32x4 Dc[MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) Dc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[m], B, C, 0, 0, 0);
+#pragma unroll PC_BIUNROLL
+        for (int bi = 0; bi < 16; bi += MB) {
+            f32x4 Dn[MB];
+            if (bi + MB < 16) {
+#pragma unroll
+                for (int m = 0; m < MB; ++m) Dn[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[bi + MB + m], B, C, 0, 0, 0);
+            }
+            bin_mfma_any<MB, M>(lds, Dc, I64t, J64t, bi, bj, g, f, ngt);
+            if (bi + MB < 16) {
+#pragma unroll
+                for (int m = 0; m < MB; ++m) Dc[m] = Dn[m];
+            }
+            // keep the unrolled steps apart: hoisting later steps' work
+            // would only raise register pressure
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#else
+        f32x4 Dc[MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+            Dc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(*(const lds_f32 *)(uintptr_t)(a_stage + (m * kWave + lane) * 4u),
+                                                         B, C, 0, 0, 0);
+#pragma unroll 2
+        for (int bi = 0; bi < 16; bi += MB) {
+            const int nx = bi + MB < 16 ? bi + MB : bi;
+            f32x4 Dn[MB];
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                const float An = *(const lds_f32 *)(uintptr_t)(a_stage + ((nx + m) * kWave + lane) * 4u);
+                Dn[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(An, B, C, 0, 0, 0);
+            }
+            bin_mfma_any<MB, M>(lds, Dc, I64t, J64t, bi, bj, g, f, ngt);
+#pragma unroll
+            for (int m = 0; m < MB; ++m) Dc[m] = Dn[m];
+        }
+#endif
+        q = qn;
+    }
+    if constexpr (M > 0) few_flush<M>(lds, ngt, 16u * 16u * 4u, f, g);
 }
 
 // ------------------------------------------------------------------ fp64
@@ -399,57 +785,86 @@ __device__ __forceinline__ void tile64(unsigned char *lds, const double4 *__rest
 #define PC_OCCUPANCY
 #endif
 
-template <bool FP64>
+// MC: tile pairs marked by the prune pass go through the matrix cores (a
+// separate instance, so the binary32-only instance keeps its lower register
+// count and occupancy).
+template <bool FP64, bool MC>
 __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t lds0 = lds_addr(lds);
     const uint32_t lane = threadIdx.x;
-    const uint32_t nb = gridDim.x;
     const uint32_t b = blockIdx.x;
-    // consecutive blocks land on different XCDs; give each XCD a contiguous
-    // run of work items so its L2 sees neighbouring tiles
-    const uint32_t w = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
     const uint64_t total = p.items ? static_cast<uint64_t>(*(const __attribute__((address_space(4))) unsigned long long *)(p.n_items))
                                    : p.total_items;
-    const uint64_t per = total / nb, rem = total % nb;
-    const uint64_t beg = per * w + min<uint64_t>(w, rem);
-    const uint64_t end = beg + per + (w < rem ? 1u : 0u);
-    if (beg >= end) return;
+    // Work queue: the items are cut into 8 contiguous slices, one per XCD
+    // (consecutive workgroups are dispatched to different XCDs, so each XCD's
+    // L2 sees neighbouring tiles); a wave takes kChunk items at a time from its
+    // own XCD's slice, then from the others.  Waves that become resident late
+    // simply find less work, so the launch ends evenly whatever the residency.
+    constexpr uint64_t kChunk = 4;
+    const uint32_t x0 = b & 7u;
+    uint32_t xs = 0;
+    uint64_t wi = 0, end = 0;
 
-    const uint64_t it0 = p.items ? p.items[beg] : beg;
-    int s = find_seg(p.segs, p.n_segs, it0);
-    SegDesc sd = ld_const_struct(p.segs + s);
+    int s = 0;
+    SegDesc sd = ld_const_struct(p.segs);
     int cur_tab = -1, cur_job = -1;
     int32_t n_edges = 0, cols = 64, clear_words = 0;
     uint32_t row_bytes = 0, lane_off = 0;
     unsigned long long *cur_counts = nullptr;
     uint32_t clo = 0, chi = 0, shift = 0, lut_base = 0, trash_off = 0;
+    uint32_t g_clo = 0, g_chi = 0, g_shift = 0, g_lut_base = 0;
     bool search = false;
     const double *e64 = nullptr;
-    uint64_t since_flush = 0;
+    const float *band = nullptr, *band_g = nullptr;
+    uint64_t since_flush = 0, flush_every = 1;
 
-    int64_t cur_t = -1;
-    int cur_t_seg = -1;
-    float fx[kR], fy[kR], fz[kR];
-    double dx[kR], dy[kR], dz[kR];
 
-    for (uint64_t wi = beg; wi < end; ++wi) {
-        const uint64_t it = p.items ? static_cast<uint64_t>(uniform_u64(p.items[wi])) : wi;
+    for (;; ++wi) {
+        if (wi >= end) {
+            bool got = false;
+            for (; xs < 8u; ++xs) {
+                const uint32_t x = (x0 + xs) & 7u;
+                const uint64_t s0 = total * x / 8u, s1 = total * (x + 1u) / 8u;
+                unsigned long long c = 0;
+                if (lane == 0) c = atomicAdd(p.queue + x, static_cast<unsigned long long>(kChunk));
+                c = uniform_u64(c);
+                if (s0 + c < s1) {
+                    wi = s0 + c;
+                    end = min<uint64_t>(s1, s0 + c + kChunk);
+                    got = true;
+                    break;
+                }
+            }
+            if (!got) break;
+        }
+        const uint64_t raw = p.items ? static_cast<uint64_t>(uniform_u64(p.items[wi])) : wi;
+        // marked by the prune pass (layout next to kItemBits)
+        const bool to_mfma = !FP64 && (raw >> 63) != 0;
+        const bool centre_j = ((raw >> 62) & 1u) != 0;
+        const uint32_t few_m = FP64 ? 0u : static_cast<uint32_t>((raw >> (kItemBits + 11)) & 3u);
+        const uint32_t few_k0 = static_cast<uint32_t>((raw >> kItemBits) & 2047u);
+        const uint64_t it = raw & kItemMask;
         if (it < sd.item0 || it >= sd.item0 + sd.n_items) {
             s = find_seg(p.segs, p.n_segs, it);
             sd = ld_const_struct(p.segs + s);
         }
-        if (sd.tab != cur_tab || sd.job != cur_job || since_flush >= (1ull << 21)) {
+        // a lane adds at most kTile * kR per item to a word it shares with
+        // kWave / cols - 1 other lanes: flush before a 32-bit word can wrap
+        if (sd.tab != cur_tab || sd.job != cur_job || since_flush >= flush_every) {
             if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);
             if (sd.tab != cur_tab) {
                 const TableDesc td = ld_const_struct(p.tabs + sd.tab);
                 n_edges = td.n_edges;
+                band = td.band;
+                band_g = td.band_g;
                 clo = td.clamp_lo;
                 chi = td.clamp_hi;
                 shift = td.shift;
                 search = td.search != 0;
                 e64 = td.e64;
                 cols = td.cols;
+                flush_every = 0xFFFFFFFFull / (static_cast<uint64_t>(kTile) * kR * static_cast<uint64_t>(kWave / cols));
                 row_bytes = static_cast<uint32_t>(cols) * 4u;
                 // absolute LDS addresses: histogram at lds0, cell table at lds0 + lut_lds_off
                 lane_off = lds0 + (lane & static_cast<uint32_t>(cols - 1)) * 4u;
@@ -464,6 +879,15 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                     const uint4 *src = reinterpret_cast<const uint4 *>(td.lut);
                     uint4 *dst = reinterpret_cast<uint4 *>(lds + p.lut_lds_off);
                     for (int32_t k = lane; k < td.n_cells; k += kWave) dst[k] = src[k];
+                }
+                if (!FP64) {
+                    g_clo = td.g_clamp_lo;
+                    g_chi = td.g_clamp_hi;
+                    g_shift = td.g_shift;
+                    g_lut_base = lds0 + p.lutg_lds_off - (td.g_key0 << 4);
+                    const uint4 *src = reinterpret_cast<const uint4 *>(td.lut_g);
+                    uint4 *dst = reinterpret_cast<uint4 *>(lds + p.lutg_lds_off);
+                    for (int32_t k = lane; k < td.g_n_cells; k += kWave) dst[k] = src[k];
                 }
                 // histogram words this table uses; anything beyond what was
                 // cleared before is cleared now
@@ -485,7 +909,12 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         const int64_t iend = sd.i0 + sd.ni;
         const int64_t ibeg = sd.i0 + t * kTile;
         const int32_t i_lim = static_cast<int32_t>(uniform(static_cast<uint32_t>(min<int64_t>(kTile, iend - ibeg))));
-        if (t != cur_t || s != cur_t_seg) {
+        // the lane's i-points, reloaded per item (4 loads against 1024
+        // pairs; keeping them across items would hold registers in the
+        // matrix-core path too)
+        float fx[kR], fy[kR], fz[kR];
+        double dx[kR], dy[kR], dz[kR];
+        if (FP64 || !(MC && to_mfma)) {
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 const int32_t ir = r * kWave + static_cast<int32_t>(lane);
@@ -502,8 +931,6 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                     fz[r] = v.z;
                 }
             }
-            cur_t = t;
-            cur_t_seg = s;
         }
         const int64_t jbeg = sd.j0 + u * kTile;
         const int32_t jn = static_cast<int32_t>(uniform(static_cast<uint32_t>(min<int64_t>(kTile, sd.j0 + sd.nj - jbeg))));
@@ -534,14 +961,50 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                     tile64<false, false>(lds, J64t, jn, dx, dy, dz, i_lim, j_rel, diag, clo, chi, k);
             }
         } else {
-            const float4 *Jt = uniform_ptr(sd.j32 + jbeg);
-            if (masked)
-                tile32<true>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
-            else
-                tile32<false>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
+            // bands of the few-edge item's edges k0 .. k0+m-1 (the matrix-core
+            // path's own bands there)
+            FewCtx f;
+            f.k0 = few_k0;
+            if (few_m) {
+                const float *bd = (MC && to_mfma) ? band_g : band;
+#pragma unroll
+                for (int q = 0; q < kFewMax; ++q) {
+                    const uint32_t e = min(few_k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
+                    const float2 v = ld_const_f2(bd + 2u * e);
+                    f.lo[q] = v.x;
+                    f.hi[q] = v.y;
+                }
+            }
+            if (MC && to_mfma) {
+                TileCtx g = k;
+                g.shift = g_shift;
+                g.lut_base = g_lut_base;
+                g.klo = __uint_as_float(g_clo);
+                g.khi = __uint_as_float(g_chi);
+                const double4 o = ld_const(centre_j ? sd.jb + u : sd.ib + t);
+                const double4 *I64t = uniform_ptr(sd.i64 + ibeg);
+                const uint32_t st = lds0 + p.stage_lds_off;
+                if (few_m == 1) tile_mfma<1>(lds, st, I64t, J64t, o.x, o.y, o.z, g, f);
+                else if (few_m == 2) tile_mfma<2>(lds, st, I64t, J64t, o.x, o.y, o.z, g, f);
+                else if (few_m == 3) tile_mfma<3>(lds, st, I64t, J64t, o.x, o.y, o.z, g, f);
+                else tile_mfma<0>(lds, st, I64t, J64t, o.x, o.y, o.z, g, f);
+            } else {
+                const float4 *Jt = uniform_ptr(sd.j32 + jbeg);
+                if (masked) {
+                    if (few_m == 1) tile32_few<true, 1>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
+                    else if (few_m == 2) tile32_few<true, 2>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
+                    else if (few_m == 3) tile32_few<true, 3>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
+                    else tile32<true>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
+                } else {
+                    if (few_m == 1) tile32_few<false, 1>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
+                    else if (few_m == 2) tile32_few<false, 2>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
+                    else if (few_m == 3) tile32_few<false, 3>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
+                    else tile32<false>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
+                }
+            }
         }
     }
-    flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);
+    if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -561,10 +1024,12 @@ hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_count(bool fp64, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
+hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
                         const uint64_t *items, const unsigned long long *n_items, uint64_t total_items,
-                        uint32_t lut_lds_off, uint32_t lds_bytes, int grid, hipStream_t st) {
+                        uint32_t lut_lds_off, uint32_t lutg_lds_off, uint32_t stage_lds_off,
+                        unsigned long long *queue, uint32_t lds_bytes, int grid, hipStream_t st) {
     KParams p;
+    p.queue = queue;
     p.segs = segs;
     p.tabs = tabs;
     p.items = items;
@@ -572,25 +1037,34 @@ hipError_t launch_count(bool fp64, const SegDesc *segs, int32_t n_segs, const Ta
     p.total_items = total_items;
     p.n_segs = n_segs;
     p.lut_lds_off = lut_lds_off;
+    p.lutg_lds_off = lutg_lds_off;
+    p.stage_lds_off = stage_lds_off;
     if (fp64)
-        k_count<true><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
+        k_count<true, false><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
+    else if (mc)
+        k_count<false, true><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
     else
-        k_count<false><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
+        k_count<false, false><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
     return hipGetLastError();
 }
 
-hipError_t count_occupancy(bool fp64, uint32_t lds_bytes, int *blocks_per_cu) {
+hipError_t count_occupancy(bool fp64, bool mc, uint32_t lds_bytes, int *blocks_per_cu) {
     if (fp64)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<true>, kWave, lds_bytes);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<false>, kWave, lds_bytes);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<true, false>, kWave, lds_bytes);
+    if (mc)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<false, true>, kWave, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<false, false>, kWave, lds_bytes);
 }
 
 hipError_t set_max_lds(uint32_t bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_count<true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_count<false>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void *fs[3] = {reinterpret_cast<const void *>(k_count<true, false>),
+                         reinterpret_cast<const void *>(k_count<false, false>),
+                         reinterpret_cast<const void *>(k_count<false, true>)};
+    for (const void *f : fs) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace pc

@@ -2,8 +2,8 @@
 // catalogues, tile bounding spheres, and exact whole-tile-pair binning.
 //
 // Counts do not depend on the order of a catalogue, so each index range a job
-// uses is copied in a spatial order (counting sort on a 3-D Morton key of the
-// unit vector; the order inside a key bucket is arbitrary).  Consecutive
+// uses is copied in a spatial order (counting sort on a cube-face Hilbert key
+// of the unit vector; the order inside a key bucket is arbitrary).  Consecutive
 // tiles of 256 points are then compact, each gets a bounding sphere (centre,
 // radius), and a tile pair whose squared-chord interval lies inside one bin
 // is binned as a whole without visiting its pairs (the paper, Sec. 2.2: time
@@ -12,7 +12,12 @@
 
 namespace pc {
 
-// ------------------------------------------------------------ Morton keys
+// ---------------------------------------------------------- ordering keys
+// Cube-face Hilbert key: the face of the cube the unit vector points through
+// (axis and sign of its largest component), then the 2-D Hilbert index of the
+// two other components divided by the largest one, quantised to 2^bits per
+// axis.  Points close on the sphere get close keys, without the long jumps of
+// a Morton order.
 
 __device__ __forceinline__ uint32_t quantize(double x, uint32_t bits) {
     // x in [-1, 1] -> [0, 2^bits)
@@ -24,20 +29,44 @@ __device__ __forceinline__ uint32_t quantize(double x, uint32_t bits) {
     return v > m ? m : v;
 }
 
-__device__ __forceinline__ uint32_t spread3(uint32_t v, uint32_t bits) {
-    uint32_t r = 0;
-    for (uint32_t b = 0; b < bits; ++b) r |= ((v >> b) & 1u) << (3u * b);
-    return r;
+__device__ __forceinline__ uint32_t hilbert2d(uint32_t bits, uint32_t x, uint32_t y) {
+    const uint32_t n = 1u << bits;
+    uint32_t d = 0;
+    for (uint32_t s = n >> 1; s > 0; s >>= 1) {
+        const uint32_t rx = (x & s) ? 1u : 0u;
+        const uint32_t ry = (y & s) ? 1u : 0u;
+        d += s * s * ((3u * rx) ^ ry);
+        if (ry == 0u) {
+            if (rx == 1u) {
+                x = n - 1u - x;
+                y = n - 1u - y;
+            }
+            const uint32_t t = x;
+            x = y;
+            y = t;
+        }
+    }
+    return d;
 }
 
-__global__ void __launch_bounds__(256) k_morton(const double4 *__restrict__ src, int64_t base, int64_t n,
-                                                uint32_t bits, uint32_t *__restrict__ keys,
-                                                uint32_t *__restrict__ hist) {
+__device__ __forceinline__ uint32_t order_key(double4 v, uint32_t bits) {
+    const double ax = fabs(v.x), ay = fabs(v.y), az = fabs(v.z);
+    uint32_t face;
+    double major, u, w;
+    if (ax >= ay && ax >= az) { face = 0; major = v.x; u = v.y; w = v.z; }
+    else if (ay >= az) { face = 2; major = v.y; u = v.x; w = v.z; }
+    else { face = 4; major = v.z; u = v.x; w = v.y; }
+    if (major < 0.0) face += 1;
+    const double inv = 1.0 / fmax(fabs(major), 1e-300);
+    return (face << (2u * bits)) | hilbert2d(bits, quantize(u * inv, bits), quantize(w * inv, bits));
+}
+
+__global__ void __launch_bounds__(256) k_keys(const double4 *__restrict__ src, int64_t base, int64_t n,
+                                              uint32_t bits, uint32_t *__restrict__ keys,
+                                              uint32_t *__restrict__ hist) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double4 v = src[base + i];
-    const uint32_t k = spread3(quantize(v.x, bits), bits) | (spread3(quantize(v.y, bits), bits) << 1) |
-                       (spread3(quantize(v.z, bits), bits) << 2);
+    const uint32_t k = order_key(src[base + i], bits);
     keys[i] = k;
     atomicAdd(hist + k, 1u);
 }
@@ -219,8 +248,10 @@ __device__ __forceinline__ uint32_t count_le(const double *e, int32_t n, double 
 __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs, int32_t n_segs,
                                                const TableDesc *__restrict__ tabs, uint64_t total_items,
                                                uint64_t *__restrict__ survivors,
-                                               unsigned long long *__restrict__ meta) {
-    // meta[0] = survivors, meta[1] = pairs in survivors, meta[2] = pairs binned whole
+                                               unsigned long long *__restrict__ meta, int32_t mfma_ok) {
+    // meta[0] = survivors, meta[1] = pairs in survivors, meta[2] = pairs binned
+    // whole, meta[3] = survivors marked for the matrix cores, meta[4] =
+    // survivors with at most kFewMax edges in their chord interval
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * blockDim.x; base < total_items; base += stride) {
         const uint64_t it = base + threadIdx.x;
@@ -228,7 +259,8 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
         unsigned long long *dst = nullptr;
         unsigned long long cnt = 0;
         bool survive = false;
-        uint64_t pairs = 0;
+        bool mfma = false, centre_j = false;
+        uint64_t pairs = 0, few = 0;
         if (valid) {
             const int s = find_seg_p(segs, n_segs, it);
             const SegDesc &sd = segs[s];
@@ -268,6 +300,17 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                 cnt = pairs;
             } else {
                 survive = true;
+                // full tiles whose chord lower bound is at least twice the
+                // smaller bounding radius: eligible for the matrix-core path
+                // (bit 63), centred on the j-tile when that one is smaller
+                // (bit 62)
+                centre_j = bj.w < bi.w;
+                // edges inside the interval: k_lo .. k_hi-1; few of them are
+                // compared one by one instead of through the cell table
+                const uint32_t m = k_hi - k_lo;
+                few = (static_cast<uint64_t>(k_lo) << kItemBits) |
+                      (static_cast<uint64_t>(m <= static_cast<uint32_t>(kFewMax) ? m : 0u) << (kItemBits + 11));
+                mfma = mfma_ok && !diag && ni == kTile && nj == kTile && 2.0 * fmin(bi.w, bj.w) <= lo;
             }
         }
         // survivors: one atomic per wave
@@ -280,12 +323,20 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                 at = atomicAdd(meta + 0, static_cast<unsigned long long>(__popcll(sm)));
             }
             at = __shfl(at, __ffsll(static_cast<long long>(sm)) - 1, kWave);
-            if (survive) survivors[at + __popcll(below)] = it;
-            // pairs in survivors
+            if (survive)
+                survivors[at + __popcll(below)] = it | few | (mfma ? (1ull << 63) : 0ull) |
+                                                  ((mfma && centre_j) ? (1ull << 62) : 0ull);
+            // pairs in survivors, and survivors for the matrix cores
             unsigned long long p = survive ? pairs : 0ull;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
-            if (lane == 0) atomicAdd(meta + 1, p);
+            const uint64_t mm = __ballot(survive && mfma);
+            const uint64_t mf = __ballot(survive && (few >> (kItemBits + 11)) != 0);
+            if (lane == 0) {
+                atomicAdd(meta + 1, p);
+                if (mm) atomicAdd(meta + 3, static_cast<unsigned long long>(__popcll(mm)));
+                if (mf) atomicAdd(meta + 4, static_cast<unsigned long long>(__popcll(mf)));
+            }
         }
         // whole-item counts: sum lanes with equal destinations
         uint64_t pend = __ballot(dst != nullptr);
@@ -314,16 +365,18 @@ __global__ void __launch_bounds__(256) k_zero_u32(uint32_t *p, int64_t n) {
     if (i < n) p[i] = 0u;
 }
 
-// Morton bits per axis for n points: about 32 points per occupied bucket on a
-// quarter of the sphere, between 2 and 7 bits (at most 2^21 buckets).
-uint32_t morton_bits(int64_t n) {
+// Key bits per face axis for n points: 4^(bits+1) * 4 <= n, between 2 and 9
+// (at most 6 * 4^9 buckets).
+uint32_t order_bits(int64_t n) {
     uint32_t b = 2;
-    while (b < 7 && (int64_t(1) << (2 * (b + 1))) * 25 <= n) ++b;
+    while (b < 9 && (int64_t(1) << (2 * (b + 1))) * 4 <= n) ++b;
     return b;
 }
 
+static int64_t n_buckets(uint32_t bits) { return int64_t(6) << (2 * bits); }
+
 size_t sort_scratch_words(int64_t n) {
-    const int64_t m = int64_t(1) << (3 * morton_bits(n));
+    const int64_t m = n_buckets(order_bits(n));
     return static_cast<size_t>(n + m + (m + kScanChunk - 1) / kScanChunk + 64);
 }
 
@@ -332,15 +385,15 @@ size_t sort_scratch_words(int64_t n) {
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
                        float4 *a32s, double4 *bounds, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    const uint32_t bits = morton_bits(n);
-    const int64_t m = int64_t(1) << (3 * bits);
+    const uint32_t bits = order_bits(n);
+    const int64_t m = n_buckets(bits);
     const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
     uint32_t *keys = scratch;
     uint32_t *hist = scratch + n;
     uint32_t *sums = hist + m;
     const uint32_t gn = static_cast<uint32_t>((n + 255) / 256);
     k_zero_u32<<<dim3(static_cast<uint32_t>((m + 255) / 256)), dim3(256), 0, st>>>(hist, m);
-    k_morton<<<dim3(gn), dim3(256), 0, st>>>(src, base, n, bits, keys, hist);
+    k_keys<<<dim3(gn), dim3(256), 0, st>>>(src, base, n, bits, keys, hist);
     k_scan_local<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(hist, m, sums);
     k_scan_sums<<<dim3(1), dim3(kScanBlock), 0, st>>>(sums, nb);
     k_scan_add<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(hist, m, sums);
@@ -351,11 +404,11 @@ hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *sc
 }
 
 hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, uint64_t total_items,
-                        uint64_t *survivors, unsigned long long *meta, hipStream_t st) {
+                        uint64_t *survivors, unsigned long long *meta, int32_t mfma_ok, hipStream_t st) {
     if (total_items == 0) return hipSuccess;
     const uint64_t want = (total_items + 255) / 256;
     const uint32_t grid = static_cast<uint32_t>(want < 16384 ? want : 16384);
-    k_prune<<<dim3(grid), dim3(256), 0, st>>>(segs, n_segs, tabs, total_items, survivors, meta);
+    k_prune<<<dim3(grid), dim3(256), 0, st>>>(segs, n_segs, tabs, total_items, survivors, meta, mfma_ok);
     return hipGetLastError();
 }
 

@@ -32,7 +32,10 @@ struct DevTable {
     HostTable host;
     void *d_mem = nullptr;
     const double *d_e64 = nullptr;
+    const float *d_band = nullptr;    // (lo, hi) per edge, binary32 guard band
+    const float *d_band_g = nullptr;  // the same for the matrix-core path
     const void *d_lut32 = nullptr;
+    const void *d_lut32g = nullptr;
     const void *d_lut64 = nullptr;
     ~DevTable();
 };
@@ -77,6 +80,8 @@ struct BatchStats {
     uint64_t survivors = 0;       // work items left after whole-tile-pair binning
     uint64_t pairs_total = 0;     // pairs counted by the launch
     uint64_t pairs_computed = 0;  // pairs visited one by one
+    uint64_t mfma_items = 0;      // of the survivors, tile pairs done on the matrix cores
+    uint64_t few_items = 0;       // of the survivors, tile pairs with at most kFewMax edges inside
 };
 
 // Runs the jobs in one persistent launch on `st` and blocks until the host

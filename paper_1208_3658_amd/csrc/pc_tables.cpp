@@ -75,7 +75,11 @@ float round_down32(double x) {
 
 }  // namespace
 
-void guard_band(double e, float *lo, float *hi) {
+// Band from an error bound E(c) that is increasing in c with E(c)/c
+// decreasing: hi from e+ ; lo from e- when K E(e-) <= e-/2 (then c - K E(c)
+// is increasing for c >= e-, since E'(c) <= E(c)/c), else -inf.
+template <typename ErrFn>
+void band_from(double e, ErrFn err, float *lo, float *hi) {
     const float ninf = -std::numeric_limits<float>::infinity();
     if (e <= 0.0) {
         *lo = ninf;
@@ -86,14 +90,43 @@ void guard_band(double e, float *lo, float *hi) {
     // outward by a further 8v for the rounding of these expressions
     const double ep = (e + 5.0 * 0x1p-1074) / (1.0 - g5) * (1.0 + 8.0 * kV);
     const double em = (e - 5.0 * 0x1p-1074) / (1.0 + g5) * (1.0 - 8.0 * kV);
-    *hi = round_up32(ep + kK * err32(ep));
-    if (em > 0.0 && std::sqrt(em) >= 4.0 * kK * delta0()) {
-        const double l = em - kK * err32(em);
-        *lo = l > 0.0 ? round_down32(l) : ninf;
-    } else {
-        *lo = ninf;
-    }
+    *hi = round_up32(ep + kK * err(ep));
+    const double ke = kK * err(em);
+    if (em > 0.0 && ke <= 0.5 * em) *lo = round_down32(em - ke);
+    else *lo = ninf;
 }
+
+void guard_band(double e, float *lo, float *hi) { band_from(e, err32, lo, hi); }
+
+// Tile-centred chords (the matrix-core path).  o = centre of whichever tile
+// of the pair has the smaller bounding radius r; say the i-tile (the other
+// case swaps the roles of a and b).  A = a - o with |A| <= r, B = b - o with
+// |B| <= |b - a| + |a - o| <= sqrt(c) + r.  The binary32 copies a' = RN(A),
+// b' = RN(B) (A, B formed in binary64) move by alpha <= u r (1+2^-52) +
+// sqrt(3) t and beta <= u (sqrt(c) + r)(1+2^-52) + sqrt(3) t; |a'|^2 and
+// |b'|^2 are formed in binary32 (3 roundings each, g3); the matrix core sums
+// |a'|^2 + |b'|^2 - 2 a'.b' from 4 products and an addend, bounded here by 8
+// roundings on the sum of absolute terms, <= g8 (|a'| + |b'|)^2 (1 + g3)
+// (denormal operands flushed to zero are covered by the t terms).  Then
+//   |c32 - c| <= 2 sqrt(c)(alpha + beta) + (alpha + beta)^2
+//                + g3 (|a'|^2 + |b'|^2) + g8 (|a'| + |b'|)^2 (1 + g3) + 20 t.
+// The path only takes tile pairs whose chord lower bound is at least 2r, so
+// r <= sqrt(c)/2 for every pair it sees; the bound grows with r and is taken
+// at r = sqrt(c)/2, which makes it relative (about 50 u c) plus underflow
+// terms: increasing in c, with E(c)/c decreasing, as band_from needs.
+double err_gram(double c) {
+    const double sc = std::sqrt(c);
+    const double r = 0.5 * sc;
+    const double al = kU * r * (1.0 + 0x1p-52) + 1.7320508075688772 * kTau;
+    const double be = kU * (sc + r) * (1.0 + 0x1p-52) + 1.7320508075688772 * kTau;
+    const double na = r + al, nb = sc + r + be;
+    const double g3 = 3.0 * kU / (1.0 - 3.0 * kU);
+    const double g8 = 8.0 * kU / (1.0 - 8.0 * kU);
+    return 2.0 * sc * (al + be) + (al + be) * (al + be) + g3 * (na * na + nb * nb) +
+           g8 * (na + nb) * (na + nb) * (1.0 + g3) + 20.0 * kTau;
+}
+
+void guard_band_gram(double e, float *lo, float *hi) { band_from(e, err_gram, lo, hi); }
 
 namespace {
 
@@ -105,21 +138,25 @@ namespace {
 // none: (k_base, k_base, +inf, +inf); several: (k_base, k_base, -inf, +inf),
 // i.e. always re-check.  Bands are sorted (lo and hi non-decreasing in e).
 
-void build_lut32(HostTable &t) {
-    const int n = static_cast<int>(t.e64.size());
+void build_lut32(const std::vector<float> &lo, const std::vector<float> &hi, uint32_t row_bytes, Lut32 &out) {
+    const int n = static_cast<int>(lo.size());
     const float inf = std::numeric_limits<float>::infinity();
     float lo_min = inf, hi_max = -inf;
     bool any_neg_lo = false;
     for (int k = 0; k < n; ++k) {
-        if (t.hi[k] < 0.0f) continue;  // zero edge: always below every c32
-        if (t.lo[k] <= 0.0f) any_neg_lo = true;
-        lo_min = std::min(lo_min, t.lo[k]);
-        hi_max = std::max(hi_max, t.hi[k]);
+        if (hi[k] < 0.0f) continue;  // always below every c32
+        if (lo[k] <= 0.0f) any_neg_lo = true;
+        lo_min = std::min(lo_min, lo[k]);
+        hi_max = std::max(hi_max, hi[k]);
+    }
+    if (hi_max < 0.0f) {  // every edge always passed: one cell
+        lo_min = 1.0f;
+        hi_max = 1.0f;
     }
     const uint32_t clo = any_neg_lo ? 0u : f2u(lo_min);
     const uint32_t chi = f2u(hi_max);
     // band cell-key intervals (lo clipped at +0)
-    auto key_lo = [&](int k) { return t.lo[k] <= 0.0f ? 0u : f2u(t.lo[k]); };
+    auto key_lo = [&](int k) { return lo[k] <= 0.0f ? 0u : f2u(lo[k]); };
     int best_s = -1, best_multi = 1 << 30;
     for (int s = 23; s >= 4; --s) {
         const uint64_t cells = static_cast<uint64_t>(chi >> s) - (clo >> s) + 1;
@@ -127,8 +164,8 @@ void build_lut32(HostTable &t) {
         int multi = 0;
         int prev = -1;
         for (int k = 0; k < n; ++k) {
-            if (t.hi[k] < 0.0f) continue;
-            if (prev >= 0 && (f2u(t.hi[prev]) >> s) >= (key_lo(k) >> s)) ++multi;
+            if (hi[k] < 0.0f) continue;
+            if (prev >= 0 && (f2u(hi[prev]) >> s) >= (key_lo(k) >> s)) ++multi;
             prev = k;
         }
         if (multi < best_multi) {
@@ -139,38 +176,38 @@ void build_lut32(HostTable &t) {
     }
     if (best_s < 0) best_s = 23;  // cannot happen: S = 23 needs < 300 cells
     const uint32_t s = static_cast<uint32_t>(best_s);
-    t.shift32 = s;
-    t.clamp_lo32 = clo;
-    t.clamp_hi32 = chi;
+    out.shift = s;
+    out.clamp_lo = clo;
+    out.clamp_hi = chi;
     const uint32_t c0 = clo >> s, c1 = chi >> s;
-    t.lut32.clear();
-    t.multi32 = 0;
+    out.entries.clear();
+    out.multi = 0;
     for (uint32_t c = c0; c <= c1; ++c) {
         const float mn = u2f(c << s);
         const float mx = u2f(static_cast<uint32_t>(((static_cast<uint64_t>(c) + 1) << s) - 1));
         uint32_t k_base = 0;
         int n_in = 0, k_in = -1;
         for (int k = 0; k < n; ++k) {
-            if (t.hi[k] < mn) ++k_base;
-            else if (t.lo[k] <= mx) { ++n_in; k_in = k; }
+            if (hi[k] < mn) ++k_base;
+            else if (lo[k] <= mx) { ++n_in; k_in = k; }
         }
         LutEntry32 e;
-        e.off_lo = k_base * t.row_bytes32;
+        e.off_lo = k_base * row_bytes;
         if (n_in == 0) {
             e.off_hi = e.off_lo;
             e.lo = inf;
             e.hi = inf;
         } else if (n_in == 1) {
-            e.off_hi = (k_base + 1) * t.row_bytes32;
-            e.lo = t.lo[k_in];
-            e.hi = t.hi[k_in];
+            e.off_hi = (k_base + 1) * row_bytes;
+            e.lo = lo[k_in];
+            e.hi = hi[k_in];
         } else {
             e.off_hi = e.off_lo;
             e.lo = -inf;
             e.hi = inf;
-            ++t.multi32;
+            ++out.multi;
         }
-        t.lut32.push_back(e);
+        out.entries.push_back(e);
     }
 }
 
@@ -270,9 +307,12 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
     t.e64.resize(n_edges);
     t.lo.resize(n_edges);
     t.hi.resize(n_edges);
+    t.lo_g.resize(n_edges);
+    t.hi_g.resize(n_edges);
     for (int k = 0; k < n_edges; ++k) {
         t.e64[k] = chord2_of_theta(theta_deg[k]);
         guard_band(t.e64[k], &t.lo[k], &t.hi[k]);
+        guard_band_gram(t.e64[k], &t.lo_g[k], &t.hi_g[k]);
     }
     // widest histogram (up to the kernel's preferred width) that keeps the
     // per-wave histogram within the LDS target; narrower histograms let more
@@ -286,7 +326,8 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
     t.cols64 = pick(PC_COLS64);
     t.row_bytes32 = row_bytes_for(t.cols32);
     t.row_bytes64 = row_bytes_for(t.cols64);
-    build_lut32(t);
+    build_lut32(t.lo, t.hi, t.row_bytes32, t.lut32);
+    build_lut32(t.lo_g, t.hi_g, t.row_bytes32, t.lut32g);
     build_lut64(t);
     return true;
 }

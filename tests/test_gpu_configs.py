@@ -19,7 +19,7 @@ def dev(cat):
     return tuple(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in cat)
 
 
-@pytest.mark.parametrize("mode", [pc.PC_MIXED, pc.PC_FP64_PLAIN])
+@pytest.mark.parametrize("mode", [pc.PC_MIXED, pc.PC_MIXED | pc.PC_MATRIX_CORES, pc.PC_FP64_PLAIN])
 def test_batched_mocks_against_shared_random(mode):
     """Many mocks, each DD and DR against one resident random catalogue, and
     RR once -- one persistent launch; every job exact and equal to running

@@ -1,8 +1,8 @@
 """GPU parity: libpc.so on gfx950 against the CPU oracle, through the C ABI.
 
 Counts must be bit-exact (integers); unit vectors bit-exact; w(theta) within
-1e-12 relative.  Both kernels (mixed binary32 + binary64 re-check, and plain
-binary64) are checked."""
+1e-12 relative.  Every kernel is checked: mixed binary32 + binary64 re-check
+(with and without the matrix-core path) and plain binary64."""
 import numpy as np
 import pytest
 
@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 import paper_1208_3658_amd as pc  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-MODES = [pc.PC_MIXED, pc.PC_FP64_PLAIN]
+MODES = [pc.PC_MIXED, pc.PC_MIXED | pc.PC_MATRIX_CORES, pc.PC_FP64_PLAIN]
 
 
 def dev(cat):
@@ -193,9 +193,14 @@ def test_1m_config_sampled_rows_and_decompositions():
     Dd, Rd = dev(D), dev(R)
     jobs = [{"A": Dd, "edges": e}, {"A": Dd, "B": Rd, "edges": e, "auto": False}, {"A": Rd, "edges": e}]
     mixed = pc.pc_count_batch(jobs, mode=pc.PC_MIXED)
+    st = pc.pc_debug_last_pruning()
+    assert st["few_items"] > 0
     plain = pc.pc_count_batch(jobs, mode=pc.PC_FP64_PLAIN)
-    for m, p in zip(mixed, plain):
+    matrix = pc.pc_count_batch(jobs, mode=pc.PC_MIXED | pc.PC_MATRIX_CORES)
+    assert pc.pc_debug_last_pruning()["mfma_items"] > 0
+    for m, p, x in zip(mixed, plain, matrix):
         assert m.tolist() == p.tolist()
+        assert m.tolist() == x.tolist()
     assert int(mixed[0].sum()) == n * (n - 1) // 2
     assert int(mixed[1].sum()) == n * R[0].size
     assert int(mixed[2].sum()) == R[0].size * (R[0].size - 1) // 2
@@ -244,4 +249,31 @@ def test_pruning_skips_most_pairs_on_the_1m_shape():
     st = pc.pc_debug_last_pruning()
     assert st["pairs_total"] == 100_000 * 100_000
     assert st["pairs_computed"] < 0.35 * st["pairs_total"]
+    assert 0 < st["few_items"] <= st["survivors"]
     assert got.tolist() == pc.pc_count_ex(D, e, B=R, auto=False, mode=pc.PC_NO_PRUNE).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_matrix_core_path_far_clusters_and_edge_pairs(mode):
+    """Two compact clusters 15 deg apart, each 10 full tiles, and a copy of the
+    first shifted by exactly 12 deg along the meridian (2560 pairs on the 12
+    deg edge): with the matrix-core flag, full tile pairs whose chords are all
+    at least twice the smaller tile radius get their chords from the matrix
+    cores with their own guard band; counts must equal the oracle."""
+    rng = np.random.default_rng(33)
+    n = 2560
+    ra1, dec1 = 100 + 0.5 * rng.standard_normal(n), 0.5 * rng.standard_normal(n)
+    ra2, dec2 = 100 + 0.5 * rng.standard_normal(n), 15 + 0.5 * rng.standard_normal(n)
+    A = (np.concatenate([ra1, ra2]), np.concatenate([dec1, dec2]))
+    B = (ra1.copy(), dec1 + 12.0)
+    e = np.array([0.01, 1.0, 5.0, 9.0, 11.0, 11.9, 12.0, 12.1, 13.0, 14.0, 15.0, 16.0, 18.0, 30.0])
+    got = pc.pc_count_ex(dev(A), e, mode=mode)
+    st = pc.pc_debug_last_pruning()
+    assert got.tolist() == oracle.count(A, e).tolist()
+    gotc = pc.pc_count_ex(dev(A), e, B=dev(B), auto=False, mode=mode)
+    stc = pc.pc_debug_last_pruning()
+    assert gotc.tolist() == oracle.count(A, e, B=B, auto=False).tolist()
+    if mode & pc.PC_MATRIX_CORES:
+        assert st["mfma_items"] > 0 and stc["mfma_items"] > 0
+    else:
+        assert st["mfma_items"] == 0 and stc["mfma_items"] == 0

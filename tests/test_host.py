@@ -140,9 +140,10 @@ def _emulate_kernel(theta, A, B=None):
         key = np.clip(c32.view(np.uint32), info["clamp_lo"], info["clamp_hi"])
         cell = (key >> info["shift"]) - (info["clamp_lo"] >> info["shift"])
         E = ent[cell]
-        lo = E[:, 2].view(np.float32)
-        hi = E[:, 3].view(np.float32)
-        row = np.where(c32 > hi, E[:, 1], E[:, 0]) // info["row_bytes"]
+        lo = E[:, 1].view(np.float32)
+        hi = E[:, 2].view(np.float32)
+        # as the kernel does it: off_lo, plus one row when c > hi
+        row = (E[:, 0] + np.where(c32 > hi, info["row_bytes"], 0)) // info["row_bytes"]
         band = (c32 >= lo) & ~(c32 > hi)
         row = row.astype(np.int64)
         row[band] = np.searchsorted(e64, c64[band], side="right")
@@ -163,6 +164,104 @@ def test_cell_table_logic_reproduces_oracle(name):
     want = oracle.count(A, theta, B=c["R"], auto=False)
     for got in _emulate_kernel(theta, A, c["R"]):
         assert got.tolist() == want.tolist()
+
+
+def _gram_c32_variants(a64, b64, rng):
+    """binary32 squared chords as the matrix-core path forms them: both points
+    centred on o (within half the pair's chord of a, or of b), rounded to
+    binary32, c = |b'|^2 + |a'|^2 + sum_k a'_k (-2 b'_k) summed in several
+    orders (one rounding at the end, or a rounding after every product and
+    addition, forward and backward)."""
+    s = np.sqrt(_c64(a64, b64))
+    w = rng.normal(size=a64.shape)
+    w /= np.linalg.norm(w, axis=1)[:, None]
+    r = (0.5 * s * rng.uniform(0.0, 0.999, s.size))[:, None]
+    out = []
+    for near in (a64, b64):
+        o = near + r * w
+        A = (a64 - o).astype(np.float32)
+        B = (b64 - o).astype(np.float32)
+        f = lambda x: x.astype(np.float32)
+        na = f(f(f(A[:, 0] * A[:, 0]) + f(A[:, 1] * A[:, 1])) + f(A[:, 2] * A[:, 2]))
+        nb = f(f(f(B[:, 0] * B[:, 0]) + f(B[:, 1] * B[:, 1])) + f(B[:, 2] * B[:, 2]))
+        terms = [nb.astype(np.float64)] + [A[:, k].astype(np.float64) * (-2.0 * B[:, k].astype(np.float64))
+                                           for k in range(3)] + [na.astype(np.float64)]
+        out.append(f(sum(terms)))                          # exact sum, one rounding
+        acc = f(terms[0])
+        for t in terms[1:]:
+            acc = f(acc + f(t))                            # rounded products and sums
+        out.append(acc)
+        acc = f(terms[-1])
+        for t in terms[-2::-1]:
+            acc = f(acc + f(t))
+        out.append(acc)
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(EDGE_SETS))
+def test_gram_guard_band_separates_matrix_core_chords(name):
+    """The matrix-core path's band holds for chords formed from coordinates
+    centred within half the chord of either point."""
+    theta = EDGE_SETS[name]
+    e = oracle.chord2_edges(theta)
+    lo, hi = pc.pc_guard_band(theta, gram=True)
+    ra1, dec1, ra2, dec2 = _pairs_near_edges(theta, seed=7)
+    a = oracle.unit_vectors(ra1, dec1)
+    b = oracle.unit_vectors(ra2, dec2)
+    c64 = _c64(a, b)
+    rng = np.random.default_rng(11)
+    for c32 in _gram_c32_variants(a, b, rng):
+        for k in range(e.size):
+            assert np.all(c64[c32 > hi[k]] >= e[k]), (name, k)
+            assert np.all(c64[c32 < lo[k]] < e[k]), (name, k)
+    # relative error bound: the band is narrow at every scale
+    pos = e > 1e-30
+    assert np.all((hi[pos].astype(np.float64) - lo[pos]) / e[pos] < 1e-4)
+    assert np.all(hi >= lo)
+
+
+@pytest.mark.parametrize("name", ["log_40", "paper_254", "linear_zero_180", "tiny"])
+def test_gram_cell_table_bins_like_the_oracle(name):
+    """Cell table + band + binary64 re-check of the matrix-core path, on
+    emulated centred chords, reproduces the binary64 bins."""
+    theta = EDGE_SETS[name]
+    info, ent = pc.pc_debug_lut32(theta, gram=True)
+    e64 = oracle.chord2_edges(theta)
+    ra1, dec1, ra2, dec2 = _pairs_near_edges(theta, per_edge=200, seed=3)
+    rng = np.random.default_rng(5)
+    n = ra1.size
+    # plus pairs at random separations
+    ra1 = np.concatenate([ra1, rng.uniform(0, 360, 4000)])
+    dec1 = np.concatenate([dec1, np.degrees(np.arcsin(rng.uniform(-1, 1, 4000)))])
+    ra2 = np.concatenate([ra2, rng.uniform(0, 360, 4000)])
+    dec2 = np.concatenate([dec2, np.degrees(np.arcsin(rng.uniform(-1, 1, 4000)))])
+    a = oracle.unit_vectors(ra1, dec1)
+    b = oracle.unit_vectors(ra2, dec2)
+    c64 = _c64(a, b)
+    want = np.searchsorted(e64, c64, side="right")
+    assert n > 0
+    for c32 in _gram_c32_variants(a, b, rng):
+        key = np.clip(c32.view(np.uint32), info["clamp_lo"], info["clamp_hi"])
+        cell = (key >> info["shift"]) - (info["clamp_lo"] >> info["shift"])
+        E = ent[cell]
+        lo = E[:, 1].view(np.float32)
+        hi = E[:, 2].view(np.float32)
+        row = ((E[:, 0] + np.where(c32 > hi, info["row_bytes"], 0)) // info["row_bytes"]).astype(np.int64)
+        band = (c32 >= lo) & ~(c32 > hi)
+        row[band] = want[band]
+        assert np.array_equal(row, want)
+
+
+@pytest.mark.parametrize("gram", [False, True])
+@pytest.mark.parametrize("name", sorted(EDGE_SETS))
+def test_cell_entries_finite_hi_means_next_row(name, gram):
+    """The kernel reads (off_lo, lo, hi) only and adds one row when c > hi:
+    valid because a finite hi occurs only in one-band cells."""
+    info, ent = pc.pc_debug_lut32(EDGE_SETS[name], gram=gram)
+    hi = ent[:, 2].view(np.float32)
+    fin = np.isfinite(hi)
+    assert np.all(ent[fin, 3] == ent[fin, 0] + info["row_bytes"])
+    assert np.all(hi[~fin] == np.inf)
 
 
 def test_wtheta_matches_oracle_bitwise():
