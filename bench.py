@@ -166,6 +166,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--matrix-cores", action="store_true",
+                    help="time the mixed mode with the matrix-core chord path (PC_MATRIX_CORES) "
+                         "as the main step")
+    ap.add_argument("--no-matrix-compare", action="store_true",
+                    help="skip the extra step with the matrix-core chord path")
     ap.add_argument("--workload", choices=["1m", "batched", "large", "paper"], default="1m",
                     help="1m: 1M clustered + 1M random (default); batched: 256 mocks x shared 1M random; "
                          "large: 4M + 8M full sky; paper: DR of 1M + 1M uniform, 254 log bins")
@@ -204,6 +209,8 @@ def main():
     log(f"generating workload {args.workload}")
     c, jobs, est, pairs, n_bins = build_workload(args.workload, torch, pc)
     mode = pc.PC_MIXED if args.mode == "mixed" else pc.PC_FP64_PLAIN
+    if args.matrix_cores and mode == pc.PC_MIXED:
+        mode |= pc.PC_MATRIX_CORES
     stream = torch.cuda.current_stream()
 
     def step(m):
@@ -237,15 +244,17 @@ def main():
         "metric": "Gpairs/s binned (DD+DR+RR) at N=1M; p50/p99 latency of served w(theta) jobs",
         "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64" if mode == pc.PC_MIXED else "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if mode == pc.PC_FP64_PLAIN else "f32+f64", "data": "synthetic",
         "config": {"workload": c["name"], **c["describe"], "bins": n_bins, "jobs_per_launch": len(jobs),
-                   "pairs_per_step": pairs, "mode": args.mode},
+                   "pairs_per_step": pairs,
+                   "mode": args.mode + ("+matrix_cores" if mode & pc.PC_MATRIX_CORES else "")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": recorded_traffic(args.mode) if args.workload == "1m" else None,
                      "kernel_ms": kern_s * 1e3, "work_per_pair": W, "grid": launch["grid"],
                      "lds_bytes": launch["lds_bytes"], "items": launch["items"],
                      "pairs_computed": prn["pairs_computed"], "survivor_items": prn["survivors"],
+                     "few_edge_items": prn["few_items"], "matrix_core_items": prn["mfma_items"],
                      "computed_gpairs_s": prn["pairs_computed"] / kern_s / 1e9},
         "pairs_binned_whole": pairs - prn["pairs_computed"],
     }
@@ -263,7 +272,24 @@ def main():
                              "roofline_frac": pairs * W / k3 / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
                              "identical_counts": all(a.tolist() == b.tolist() for a, b in zip(counts, counts3))}
         log(f"every-pair step {t1 * 1e3:.1f} ms")
-    if not args.no_fp64_compare and mode == pc.PC_MIXED:
+    if not args.no_matrix_compare and (mode & ~pc.PC_MATRIX_CORES) == pc.PC_MIXED:
+        # the same step with the other choice of chord path
+        other = mode ^ pc.PC_MATRIX_CORES
+        step(other)
+        pc.pc_debug_set_timing(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        counts4, _ = step(other)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter() - t1
+        k4 = pc.pc_debug_last_launch()["kernel_ms"]
+        pc.pc_debug_set_timing(False)
+        key = "matrix_cores" if other & pc.PC_MATRIX_CORES else "vector_only"
+        out[key] = {"value": pairs / t4 / 1e9, "ms_per_step": t4 * 1e3, "kernel_ms": k4,
+                    "matrix_core_items": pc.pc_debug_last_pruning()["mfma_items"],
+                    "identical_counts": all(a.tolist() == b.tolist() for a, b in zip(counts, counts4))}
+        log(f"{key} step {t4 * 1e3:.1f} ms (kernel {k4:.1f} ms)")
+    if not args.no_fp64_compare and (mode & ~pc.PC_MATRIX_CORES) == pc.PC_MIXED:
         step(pc.PC_FP64_PLAIN)
         torch.cuda.synchronize()
         t1 = time.perf_counter()

@@ -32,18 +32,11 @@ int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, int64_t *info
                    uint32_t *entries, int64_t max_cells);
 
 /*
- * pc_debug_lut32_gram -- the same for the matrix-core path, whose binary32
- * chords are formed from coordinates centred on the tile of smaller bounding
- * radius r, for tile pairs whose chords are all at least 2 r: guard bands
- * from that (relative) error bound.
- */
-int pc_debug_lut32_gram(const double *theta_edges_deg, int32_t n_edges, int64_t *info,
-                        uint32_t *entries, int64_t max_cells);
-
-/*
  * pc_debug_guard_band_gram -- the per-edge guard band of the matrix-core path
  * (lo, hi: host arrays of n_edges floats, written), with the meaning of
- * pc_guard_band for chords formed as pc_debug_lut32_gram describes.
+ * pc_guard_band for binary32 chords formed by the matrix cores from
+ * coordinates centred on the tile of smaller bounding radius r, in tile pairs
+ * whose chords are all at least 2 r (a relative error bound).
  */
 int pc_debug_guard_band_gram(const double *theta_edges_deg, int32_t n_edges, float *lo, float *hi);
 

@@ -63,7 +63,6 @@ _SIGNATURES = {
     "pc_debug_set_timing": ([_i32], ctypes.c_int),
     "pc_debug_last_launch": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "pc_debug_last_pruning": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
-    "pc_debug_lut32_gram": ([_vp, _i32, _vp, _vp, _i64], ctypes.c_int),
     "pc_debug_guard_band_gram": ([_vp, _i32, _vp, _vp], ctypes.c_int),
     "pc_server_create": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
     "pc_server_set_random": ([_vp, _i32, _PCAT], ctypes.c_int),
@@ -269,9 +268,9 @@ def pc_guard_band(theta_edges, gram: bool = False):
     return lo, hi
 
 
-def pc_debug_lut32(theta_edges, gram: bool = False):
+def pc_debug_lut32(theta_edges):
     t, tp = _edges(theta_edges)
-    f = lib().pc_debug_lut32_gram if gram else lib().pc_debug_lut32
+    f = lib().pc_debug_lut32
     info = np.zeros(8, dtype=np.int64)
     _check(f(tp, t.size, info.ctypes.data, None, 0))
     ent = np.zeros((int(info[0]), 4), dtype=np.uint32)

@@ -26,7 +26,7 @@ hipError_t launch_convert(const double *ra, const double *dec, int64_t n, double
 hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st);
 hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
                         const uint64_t *items, const unsigned long long *n_items, uint64_t total_items,
-                        uint32_t lut_lds_off, uint32_t lutg_lds_off, uint32_t stage_lds_off,
+                        uint32_t lut_lds_off, uint32_t stage_lds_off,
                         unsigned long long *queue, uint32_t lds_bytes, int grid, hipStream_t st);
 size_t sort_scratch_words(int64_t n);
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
@@ -134,16 +134,14 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
     std::string err;
     if (!build_table(theta, n_edges, t->host, err)) return fail(PC_ERR_INVALID, err);
     const HostTable &h = t->host;
-    // one device block: e64 | band | band_g | lut32 | lut32g | lut64
+    // one device block: e64 | band | band_g | lut32 | lut64
     const size_t b_e = sizeof(double) * h.e64.size();
     const size_t b_b = 2 * sizeof(float) * h.e64.size();
     const size_t o_b = (b_e + 255) & ~size_t(255);
     const size_t o_bg = (o_b + b_b + 255) & ~size_t(255);
     const size_t o_l32 = (o_bg + b_b + 255) & ~size_t(255);
     const size_t b_l32 = sizeof(LutEntry32) * h.lut32.entries.size();
-    const size_t o_l32g = (o_l32 + b_l32 + 255) & ~size_t(255);
-    const size_t b_l32g = sizeof(LutEntry32) * h.lut32g.entries.size();
-    const size_t o_l64 = (o_l32g + b_l32g + 255) & ~size_t(255);
+    const size_t o_l64 = (o_l32 + b_l32 + 255) & ~size_t(255);
     const size_t b_l64 = sizeof(LutEntry64) * h.lut64.size();
     const size_t total = o_l64 + b_l64 + 256;
     std::vector<unsigned char> blob(total, 0);
@@ -154,7 +152,6 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
         memcpy(blob.data() + o_bg + 8 * k, bb + 2, 8);
     }
     if (b_l32) memcpy(blob.data() + o_l32, h.lut32.entries.data(), b_l32);
-    if (b_l32g) memcpy(blob.data() + o_l32g, h.lut32g.entries.data(), b_l32g);
     if (b_l64) memcpy(blob.data() + o_l64, h.lut64.data(), b_l64);
     void *d = nullptr;
     PC_HIP(hipMalloc(&d, total), "hipMalloc(tables)");
@@ -165,7 +162,6 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
     t->d_band = reinterpret_cast<const float *>(base + o_b);
     t->d_band_g = reinterpret_cast<const float *>(base + o_bg);
     t->d_lut32 = base + o_l32;
-    t->d_lut32g = base + o_l32g;
     t->d_lut64 = base + o_l64;
     std::lock_guard<std::mutex> lk(g_tab_mu);
     auto it = g_tabs.find(key);
@@ -202,12 +198,6 @@ TableDesc table_desc(const DevTable &t, bool fp64) {
         d.key0 = h.lut32.clamp_lo >> h.lut32.shift;
         d.n_cells = static_cast<int32_t>(h.lut32.entries.size());
         d.search = 0;
-        d.lut_g = t.d_lut32g;
-        d.g_clamp_lo = h.lut32g.clamp_lo;
-        d.g_clamp_hi = h.lut32g.clamp_hi;
-        d.g_shift = h.lut32g.shift;
-        d.g_key0 = h.lut32g.clamp_lo >> h.lut32g.shift;
-        d.g_n_cells = static_cast<int32_t>(h.lut32g.entries.size());
         d.band = t.d_band;
         d.band_g = t.d_band_g;
     }
@@ -216,16 +206,14 @@ TableDesc table_desc(const DevTable &t, bool fp64) {
 
 // LDS bytes a table needs: histogram rows, then the cell table (or edges),
 // then (mixed) the matrix-core path's cell table
-static void table_lds(const DevTable &t, bool fp64, uint32_t *hist, uint32_t *lut, uint32_t *lut_g) {
+static void table_lds(const DevTable &t, bool fp64, uint32_t *hist, uint32_t *lut) {
     const HostTable &h = t.host;
     *hist = static_cast<uint32_t>(h.e64.size() + 2) * (fp64 ? h.row_bytes64 : h.row_bytes32);
-    *lut_g = 0;
     if (fp64) {
         *lut = h.search64 ? static_cast<uint32_t>(8 * h.e64.size())
                           : static_cast<uint32_t>(16 * h.lut64.size());
     } else {
         *lut = static_cast<uint32_t>(16 * h.lut32.entries.size());
-        *lut_g = static_cast<uint32_t>(16 * h.lut32g.entries.size());
     }
 }
 
@@ -557,19 +545,18 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         sd.counts = reinterpret_cast<unsigned long long *>(W + plan[static_cast<size_t>(sd.job)].o_counts);
     }
     std::vector<TableDesc> tds;
-    uint32_t hist_max = 0, lut_max = 0, lutg_max = 0;
+    uint32_t hist_max = 0, lut_max = 0;
     for (auto &t : tabs) {
         tds.push_back(table_desc(*t, fp64));
-        uint32_t h, l, g;
-        table_lds(*t, fp64, &h, &l, &g);
+        uint32_t h, l;
+        table_lds(*t, fp64, &h, &l);
         hist_max = std::max(hist_max, h);
         lut_max = std::max(lut_max, l);
-        lutg_max = std::max(lutg_max, g);
     }
+    // LDS: histogram | cell table (or edges) | matrix-core A operands
     const uint32_t lut_off = (hist_max + 15u) & ~15u;
-    const uint32_t lutg_off = lut_off + ((std::max<uint32_t>(lut_max, 16u) + 15u) & ~15u);
-    const uint32_t stage_off = lutg_off + ((lutg_max + 15u) & ~15u);
-    const uint32_t lds_bytes = stage_off + ((mc && !PC_AREG) ? 16u * kWave * 4u : 0u);
+    const uint32_t stage_off = lut_off + ((std::max<uint32_t>(lut_max, 16u) + 15u) & ~15u);
+    const uint32_t lds_bytes = stage_off + (mc ? 16u * kWave * 4u : 0u);
     if (lds_bytes > di->lds_per_block)
         return fail(PC_ERR_INVALID, "edge set needs " + std::to_string(lds_bytes) +
                                         " bytes of LDS per wave; the device allows " +
@@ -610,7 +597,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             PC_HIP(hipEventRecord(t_ev0, st), "hipEventRecord");
         }
         PC_HIP(launch_count(fp64, mc, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
-                            prune ? meta : nullptr, items, lut_off, lutg_off, stage_off, meta + 8, lds_bytes, grid, st),
+                            prune ? meta : nullptr, items, lut_off, stage_off, meta + 8, lds_bytes, grid, st),
                "count kernel");
         if (timed) PC_HIP(hipEventRecord(t_ev1, st), "hipEventRecord");
     }
@@ -873,14 +860,14 @@ int pc_guard_band(const double *theta_edges_deg, int32_t n_edges, float *lo, flo
 
 }  // extern "C"
 
-static int debug_lut(const double *theta_edges_deg, int32_t n_edges, int64_t *info, uint32_t *entries,
-                     int64_t max_cells, bool gram) {
+extern "C" int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, int64_t *info, uint32_t *entries,
+                              int64_t max_cells) {
     clear_error();
     if (!theta_edges_deg || !info) return fail(PC_ERR_INVALID, "NULL argument");
     HostTable t;
     std::string err;
     if (!build_table(theta_edges_deg, n_edges, t, err)) return fail(PC_ERR_INVALID, err);
-    const Lut32 &L = gram ? t.lut32g : t.lut32;
+    const Lut32 &L = t.lut32;
     info[0] = static_cast<int64_t>(L.entries.size());
     info[1] = L.shift;
     info[2] = L.clamp_lo;
@@ -892,16 +879,6 @@ static int debug_lut(const double *theta_edges_deg, int32_t n_edges, int64_t *in
     if (entries && static_cast<int64_t>(L.entries.size()) <= max_cells)
         memcpy(entries, L.entries.data(), sizeof(LutEntry32) * L.entries.size());
     return PC_OK;
-}
-
-extern "C" int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, int64_t *info, uint32_t *entries,
-                              int64_t max_cells) {
-    return debug_lut(theta_edges_deg, n_edges, info, entries, max_cells, false);
-}
-
-extern "C" int pc_debug_lut32_gram(const double *theta_edges_deg, int32_t n_edges, int64_t *info,
-                                   uint32_t *entries, int64_t max_cells) {
-    return debug_lut(theta_edges_deg, n_edges, info, entries, max_cells, true);
 }
 
 extern "C" int pc_debug_guard_band_gram(const double *theta_edges_deg, int32_t n_edges, float *lo, float *hi) {

@@ -12,9 +12,6 @@ namespace pc {
 #ifndef PC_R
 #define PC_R 4              // i-points held per lane
 #endif
-#ifndef PC_AREG
-#define PC_AREG 0           // matrix-core A operands in registers (else staged in LDS)
-#endif
 #ifndef PC_COLS32
 #define PC_COLS32 16        // widest histogram of the mixed kernel (lane columns)
 #endif
@@ -65,10 +62,6 @@ struct TableDesc {
     int32_t n_edges;
     int32_t search;         // fp64 only: 1 = no exact cell table, binary search per pair
     int32_t cols;           // histogram lane columns (power of two <= 64)
-    // cell table of the matrix-core path (tile-centred chords; mixed only)
-    const void *lut_g;
-    uint32_t g_clamp_lo, g_clamp_hi, g_shift, g_key0;
-    int32_t g_n_cells, g_pad;
     // guard bands as (lo, hi) binary32 pairs per edge, plain and matrix-core
     // (mixed only; device)
     const float *band, *band_g;
@@ -118,7 +111,7 @@ struct HostTable {
     // mixed kernel: direct chords (binary32 unit vectors) and tile-centred
     // chords formed by the matrix cores, each with its own guard band
     std::vector<float> lo_g, hi_g;
-    Lut32 lut32, lut32g;
+    Lut32 lut32;
     // fp64 kernel
     uint32_t clamp_lo64 = 0, clamp_hi64 = 0, shift64 = 0;
     std::vector<LutEntry64> lut64;

@@ -29,7 +29,6 @@ struct KParams {
     uint64_t total_items;                  // number of items when `items` is null
     int32_t n_segs;
     uint32_t lut_lds_off;   // byte offset of the cell table in LDS (after the histogram)
-    uint32_t lutg_lds_off;  // byte offset of the matrix-core path's cell table
     uint32_t stage_lds_off; // byte offset of the matrix-core path's A-operand block (16 x 64 floats)
     unsigned long long *queue;  // 8 zeroed chunk counters, one per slice of the items
 };
@@ -376,7 +375,8 @@ struct FewCtx {
     uint32_t k0;
 };
 
-// n += (c > hi); band |= (c >= lo) & !(c > hi), band a lane mask.  Three
+// n += (c > hi); band |= (c >= lo) & !(c > hi), band a lane mask; lo and hi
+// are wave-uniform (scalar registers: one scalar operand per compare).  Three
 // vector instructions (two compares, an add with carry-in) and two scalar
 // ones; written out because the compiler otherwise recomputes !(c > hi) as a
 // third compare.  Compares with a NaN are false: a NaN chord counts nowhere.
@@ -389,7 +389,7 @@ __device__ __forceinline__ void few_count(float c, float lo, float hi, uint32_t 
         "s_or_b64 %[band], %[band], %[ge]\n\t"
         "v_addc_co_u32_e64 %[n], %[gt], 0, %[n], %[gt]"
         : [n] "+v"(n), [band] "+s"(band), [gt] "=&s"(gt), [ge] "=&s"(ge)
-        : [c] "v"(c), [lo] "v"(lo), [hi] "v"(hi)
+        : [c] "v"(c), [lo] "s"(lo), [hi] "s"(hi)
         : "scc");
 }
 
@@ -513,68 +513,8 @@ __device__ __forceinline__ void tile32_few(unsigned char *lds, const float4 *__r
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 #ifndef PC_MB
-#define PC_MB 2             // 16x16 blocks binned together (4 chords per lane each)
+#define PC_MB 1             // 16x16 blocks binned together (4 chords per lane each)
 #endif
-#ifndef PC_BIUNROLL
-#define PC_BIUNROLL 1
-#endif
-
-// Cell-table binning of the chords one lane holds after MB 16x16x4 matrix
-// multiplies: D[m][v] is the pair (i = (bi0 + m)*16 + 4*kq + v, j = bj*16 +
-// l16) of the tile pair.  All cell-table reads are issued before any compare,
-// so 4 MB lookups overlap; in-band chords are re-checked in binary64 like in
-// step32.
-template <int MB>
-__device__ __forceinline__ void bin_mfma(unsigned char *lds, const f32x4 (&D)[MB], const double4 *__restrict__ I64t,
-                                         const double4 *__restrict__ J64t, int bi0, int bj, const TileCtx &g) {
-    const int lane = static_cast<int>(threadIdx.x);
-    const int l16 = lane & 15, kq = lane >> 4;
-    float c[4 * MB];
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-        c[4 * m + 0] = D[m].x;
-        c[4 * m + 1] = D[m].y;
-        c[4 * m + 2] = D[m].z;
-        c[4 * m + 3] = D[m].w;
-    }
-    uint32_t a[4 * MB];
-#pragma unroll
-    for (int v = 0; v < 4 * MB; ++v) a[v] = cell_addr(key32(c[v], g.klo, g.khi), g.shift, g.lut_base);
-    uint3 e[4 * MB];
-#pragma unroll
-    for (int v = 0; v < 4 * MB; ++v) e[v] = lds_read3(a[v]);
-    bool any_band = false;
-#pragma unroll
-    for (int v = 0; v < 4 * MB; ++v) {
-        const bool gt = c[v] > __uint_as_float(e[v].z);
-        any_band |= !gt & (c[v] >= __uint_as_float(e[v].y));
-        lds_add(lds, e[v].x + (gt ? g.row_bytes : 0u) + g.lane_off, 1u);
-    }
-    if (__builtin_expect(any_band, 0)) {
-#pragma unroll
-        for (int v = 0; v < 4 * MB; ++v) {
-            float cv = c[v];
-            asm volatile("" : "+v"(cv));
-            const uint3 en = lds_read3(cell_addr(key32(cv, g.klo, g.khi), g.shift, g.lut_base));
-            const bool band = !(cv > __uint_as_float(en.z)) && (cv >= __uint_as_float(en.y));
-            if (band) {
-                // formed here, not hoisted out of the caller's loops (64
-                // loop-invariant addresses would otherwise stay live)
-                int row = (bi0 + v / 4) * 16 + 4 * kq + (v & 3);
-                asm volatile("" : "+v"(row));
-                const double4 p = I64t[row];
-                const double4 q = J64t[bj * 16 + l16];
-                const double c64 = chord2_64(p.x, p.y, p.z, q.x, q.y, q.z);
-                const uint32_t exact = bin_search(g.e64, g.n_edges, c64) * g.row_bytes + g.lane_off;
-                const uint32_t prov = en.x + g.lane_off;
-                if (exact != prov) {
-                    lds_add(lds, exact, 1u);
-                    lds_add(lds, prov, 0xFFFFFFFFu);
-                }
-            }
-        }
-    }
-}
 
 // Few-edge binning of the chords one lane holds after MB matrix multiplies
 // (see the few-edge items above).
@@ -613,25 +553,18 @@ __device__ __forceinline__ void bin_mfma_few(unsigned char *lds, const f32x4 (&D
     }
 }
 
-template <int MB, int M>
-__device__ __forceinline__ void bin_mfma_any(unsigned char *lds, const f32x4 (&D)[MB], const double4 *__restrict__ I64t,
-                                             const double4 *__restrict__ J64t, int bi0, int bj, const TileCtx &g,
-                                             const FewCtx &f, uint32_t (&ngt)[M > 0 ? M : 1]) {
-    if constexpr (M == 0) bin_mfma<MB>(lds, D, I64t, J64t, bi0, bj, g);
-    else bin_mfma_few<MB, M>(lds, D, I64t, J64t, bi0, bj, g, f, ngt);
-}
-
 // One full 256 x 256 tile pair through the matrix cores.  Coordinates are
 // centred on o (the bounding-sphere centre of the tile with the smaller
 // radius) in binary64 and rounded to binary32: a' = a - o, b' = b - o.  With
 // A_i = (a'_x, a'_y, a'_z, |a'_i|^2), B_j = (-2 b'_x, -2 b'_y, -2 b'_z, 1) and
 // the addend |b'_j|^2, one v_mfma_f32_16x16x4f32 gives |a'_i - b'_j|^2 for a
 // 16 x 16 block of pairs (operand layout: lane l holds row l%16, k = l/16 of
-// A and column l%16, k = l/16 of B).  The lane's A operands of all 16
-// i-blocks stay in registers; the j-block loop loads the next block's point
-// one iteration ahead.  Only tile pairs whose chord lower bound is at least
-// twice that radius come here; their guard band is the g table's.
-// M > 0: a few-edge item (bands in f), else binned through the cell table.
+// A and column l%16, k = l/16 of B).  The lane's A operands of the 16
+// i-blocks are staged in the wave's LDS block `a_stage` (16 x 64 floats) and
+// read one binning step ahead of their multiply; the j-block loop loads the
+// next block's point one iteration ahead.  Only tile pairs whose chord lower
+// bound is at least twice that radius, and with M <= kFewMax edges inside
+// their chord interval, come here; f holds those edges' matrix-core bands.
 template <int M>
 __device__ __forceinline__ void tile_mfma(unsigned char *lds, uint32_t a_stage, const double4 *__restrict__ I64t,
                                           const double4 *__restrict__ J64t, double ox, double oy, double oz,
@@ -639,27 +572,13 @@ __device__ __forceinline__ void tile_mfma(unsigned char *lds, uint32_t a_stage, 
     const int lane = static_cast<int>(threadIdx.x);
     const int l16 = lane & 15, kq = lane >> 4;
     constexpr int MB = PC_MB;
-    uint32_t ngt[M > 0 ? M : 1];
-#pragma unroll
-    for (int t = 0; t < (M > 0 ? M : 1); ++t) ngt[t] = 0u;
-    static_assert(16 % MB == 0, "blocks per binning step");
-#if PC_AREG
-    (void)a_stage;
-    float A[16];
-#pragma unroll
-    for (int bi = 0; bi < 16; ++bi) {
-        const double4 p = I64t[bi * 16 + l16];
-        const float x = static_cast<float>(p.x - ox);
-        const float y = static_cast<float>(p.y - oy);
-        const float z = static_cast<float>(p.z - oz);
-        const float na = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
-        A[bi] = kq == 0 ? x : kq == 1 ? y : kq == 2 ? z : na;
-        // at most 4 blocks' loads in flight: all 16 at once would need 128
-        // registers for the binary64 points
-        if ((bi & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-    }
-#else
+    constexpr int NB = 16 / MB;  // binning steps per j-block
+    static_assert(16 % (2 * MB) == 0, "blocks per binning step");
     using lds_f32 = __attribute__((address_space(3))) float;
+    static_assert(M >= 1 && M <= kFewMax, "few-edge items only");
+    uint32_t ngt[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) ngt[t] = 0u;
 #pragma unroll 4
     for (int bi = 0; bi < 16; ++bi) {
         const double4 p = I64t[bi * 16 + l16];
@@ -669,62 +588,59 @@ __device__ __forceinline__ void tile_mfma(unsigned char *lds, uint32_t a_stage, 
         const float na = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
         *(lds_f32 *)(uintptr_t)(a_stage + (bi * kWave + lane) * 4u) = kq == 0 ? x : kq == 1 ? y : kq == 2 ? z : na;
     }
-#endif
-    double4 q = J64t[l16];
+    // A operands of binning step s (blocks s*MB .. s*MB+MB-1); steps past the
+    // last re-read the last one (their products are not used)
+    auto load_a = [&](int step, float (&out)[MB]) {
+        const int s0 = min(step, NB - 1) * MB;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) out[m] = *(const lds_f32 *)(uintptr_t)(a_stage + ((s0 + m) * kWave + lane) * 4u);
+    };
+    // only x, y, z of the j-points are loaded (the prefetched one stays live
+    // through a whole iteration)
+    auto load_j = [&](int blk, double &x, double &y, double &z) {
+        const double *pj = reinterpret_cast<const double *>(J64t + blk * 16 + l16);
+        x = pj[0];
+        y = pj[1];
+        z = pj[2];
+    };
+    double qx, qy, qz;
+    load_j(0, qx, qy, qz);
 #pragma unroll 1
     for (int bj = 0; bj < 16; ++bj) {
-        const double4 qn = J64t[min(bj + 1, 15) * 16 + l16];
+        double nx, ny, nz;
+        load_j(min(bj + 1, 15), nx, ny, nz);
+        const double4 q = make_double4(qx, qy, qz, 0.0);
         const float x = static_cast<float>(q.x - ox);
         const float y = static_cast<float>(q.y - oy);
         const float z = static_cast<float>(q.z - oz);
         const float nb = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
         const float B = kq == 0 ? -2.0f * x : kq == 1 ? -2.0f * y : kq == 2 ? -2.0f * z : 1.0f;
         const f32x4 C = {nb, nb, nb, nb};
-#if PC_AREG
-        // software-pipelined: the next MB blocks are multiplied before the
-        // current ones are binned
-        f32x4 Dc[MB];
+        // two binning steps per iteration with two product buffers: the
+        // products of step s+1 are issued before step s is binned, and the A
+        // operands of step s+2 are read meanwhile
+        float Ap[MB];
+        f32x4 DA[MB], DB[MB];
+        load_a(0, Ap);
 #pragma unroll
-        for (int m = 0; m < MB; ++m) Dc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[m], B, C, 0, 0, 0);
-#pragma unroll PC_BIUNROLL
-        for (int bi = 0; bi < 16; bi += MB) {
-            f32x4 Dn[MB];
-            if (bi + MB < 16) {
+        for (int m = 0; m < MB; ++m) DA[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ap[m], B, C, 0, 0, 0);
+        load_a(1, Ap);
+#pragma unroll 1
+        for (int st = 0; st < NB; st += 2) {
 #pragma unroll
-                for (int m = 0; m < MB; ++m) Dn[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[bi + MB + m], B, C, 0, 0, 0);
-            }
-            bin_mfma_any<MB, M>(lds, Dc, I64t, J64t, bi, bj, g, f, ngt);
-            if (bi + MB < 16) {
+            for (int m = 0; m < MB; ++m) DB[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ap[m], B, C, 0, 0, 0);
+            load_a(st + 2, Ap);
+            bin_mfma_few<MB, M>(lds, DA, I64t, J64t, st * MB, bj, g, f, ngt);
 #pragma unroll
-                for (int m = 0; m < MB; ++m) Dc[m] = Dn[m];
-            }
-            // keep the unrolled steps apart: hoisting later steps' work
-            // would only raise register pressure
-            __builtin_amdgcn_sched_barrier(0);
+            for (int m = 0; m < MB; ++m) DA[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ap[m], B, C, 0, 0, 0);
+            load_a(st + 3, Ap);
+            bin_mfma_few<MB, M>(lds, DB, I64t, J64t, (st + 1) * MB, bj, g, f, ngt);
         }
-#else
-        f32x4 Dc[MB];
-#pragma unroll
-        for (int m = 0; m < MB; ++m)
-            Dc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(*(const lds_f32 *)(uintptr_t)(a_stage + (m * kWave + lane) * 4u),
-                                                         B, C, 0, 0, 0);
-#pragma unroll 2
-        for (int bi = 0; bi < 16; bi += MB) {
-            const int nx = bi + MB < 16 ? bi + MB : bi;
-            f32x4 Dn[MB];
-#pragma unroll
-            for (int m = 0; m < MB; ++m) {
-                const float An = *(const lds_f32 *)(uintptr_t)(a_stage + ((nx + m) * kWave + lane) * 4u);
-                Dn[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(An, B, C, 0, 0, 0);
-            }
-            bin_mfma_any<MB, M>(lds, Dc, I64t, J64t, bi, bj, g, f, ngt);
-#pragma unroll
-            for (int m = 0; m < MB; ++m) Dc[m] = Dn[m];
-        }
-#endif
-        q = qn;
+        qx = nx;
+        qy = ny;
+        qz = nz;
     }
-    if constexpr (M > 0) few_flush<M>(lds, ngt, 16u * 16u * 4u, f, g);
+    few_flush<M>(lds, ngt, 16u * 16u * 4u, f, g);
 }
 
 // ------------------------------------------------------------------ fp64
@@ -813,7 +729,6 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     uint32_t row_bytes = 0, lane_off = 0;
     unsigned long long *cur_counts = nullptr;
     uint32_t clo = 0, chi = 0, shift = 0, lut_base = 0, trash_off = 0;
-    uint32_t g_clo = 0, g_chi = 0, g_shift = 0, g_lut_base = 0;
     bool search = false;
     const double *e64 = nullptr;
     const float *band = nullptr, *band_g = nullptr;
@@ -879,15 +794,6 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                     const uint4 *src = reinterpret_cast<const uint4 *>(td.lut);
                     uint4 *dst = reinterpret_cast<uint4 *>(lds + p.lut_lds_off);
                     for (int32_t k = lane; k < td.n_cells; k += kWave) dst[k] = src[k];
-                }
-                if (!FP64) {
-                    g_clo = td.g_clamp_lo;
-                    g_chi = td.g_clamp_hi;
-                    g_shift = td.g_shift;
-                    g_lut_base = lds0 + p.lutg_lds_off - (td.g_key0 << 4);
-                    const uint4 *src = reinterpret_cast<const uint4 *>(td.lut_g);
-                    uint4 *dst = reinterpret_cast<uint4 *>(lds + p.lutg_lds_off);
-                    for (int32_t k = lane; k < td.g_n_cells; k += kWave) dst[k] = src[k];
                 }
                 // histogram words this table uses; anything beyond what was
                 // cleared before is cleared now
@@ -976,18 +882,13 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 }
             }
             if (MC && to_mfma) {
-                TileCtx g = k;
-                g.shift = g_shift;
-                g.lut_base = g_lut_base;
-                g.klo = __uint_as_float(g_clo);
-                g.khi = __uint_as_float(g_chi);
                 const double4 o = ld_const(centre_j ? sd.jb + u : sd.ib + t);
                 const double4 *I64t = uniform_ptr(sd.i64 + ibeg);
                 const uint32_t st = lds0 + p.stage_lds_off;
-                if (few_m == 1) tile_mfma<1>(lds, st, I64t, J64t, o.x, o.y, o.z, g, f);
-                else if (few_m == 2) tile_mfma<2>(lds, st, I64t, J64t, o.x, o.y, o.z, g, f);
-                else if (few_m == 3) tile_mfma<3>(lds, st, I64t, J64t, o.x, o.y, o.z, g, f);
-                else tile_mfma<0>(lds, st, I64t, J64t, o.x, o.y, o.z, g, f);
+                // the prune pass marks only few-edge items for the matrix cores
+                if (few_m == 1) tile_mfma<1>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
+                else if (few_m == 2) tile_mfma<2>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
+                else tile_mfma<3>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
             } else {
                 const float4 *Jt = uniform_ptr(sd.j32 + jbeg);
                 if (masked) {
@@ -1026,7 +927,7 @@ hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st) {
 
 hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
                         const uint64_t *items, const unsigned long long *n_items, uint64_t total_items,
-                        uint32_t lut_lds_off, uint32_t lutg_lds_off, uint32_t stage_lds_off,
+                        uint32_t lut_lds_off, uint32_t stage_lds_off,
                         unsigned long long *queue, uint32_t lds_bytes, int grid, hipStream_t st) {
     KParams p;
     p.queue = queue;
@@ -1037,7 +938,6 @@ hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs,
     p.total_items = total_items;
     p.n_segs = n_segs;
     p.lut_lds_off = lut_lds_off;
-    p.lutg_lds_off = lutg_lds_off;
     p.stage_lds_off = stage_lds_off;
     if (fp64)
         k_count<true, false><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);

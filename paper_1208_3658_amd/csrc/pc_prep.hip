@@ -300,17 +300,18 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                 cnt = pairs;
             } else {
                 survive = true;
-                // full tiles whose chord lower bound is at least twice the
-                // smaller bounding radius: eligible for the matrix-core path
-                // (bit 63), centred on the j-tile when that one is smaller
-                // (bit 62)
-                centre_j = bj.w < bi.w;
                 // edges inside the interval: k_lo .. k_hi-1; few of them are
                 // compared one by one instead of through the cell table
                 const uint32_t m = k_hi - k_lo;
+                const bool is_few = m <= static_cast<uint32_t>(kFewMax);
                 few = (static_cast<uint64_t>(k_lo) << kItemBits) |
-                      (static_cast<uint64_t>(m <= static_cast<uint32_t>(kFewMax) ? m : 0u) << (kItemBits + 11));
-                mfma = mfma_ok && !diag && ni == kTile && nj == kTile && 2.0 * fmin(bi.w, bj.w) <= lo;
+                      (static_cast<uint64_t>(is_few ? m : 0u) << (kItemBits + 11));
+                // few-edge full tiles whose chord lower bound is at least twice
+                // the smaller bounding radius: eligible for the matrix-core path
+                // (bit 63), centred on the j-tile when that one is smaller
+                // (bit 62)
+                centre_j = bj.w < bi.w;
+                mfma = mfma_ok && is_few && !diag && ni == kTile && nj == kTile && 2.0 * fmin(bi.w, bj.w) <= lo;
             }
         }
         // survivors: one atomic per wave

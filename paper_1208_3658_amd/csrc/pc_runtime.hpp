@@ -35,7 +35,6 @@ struct DevTable {
     const float *d_band = nullptr;    // (lo, hi) per edge, binary32 guard band
     const float *d_band_g = nullptr;  // the same for the matrix-core path
     const void *d_lut32 = nullptr;
-    const void *d_lut32g = nullptr;
     const void *d_lut64 = nullptr;
     ~DevTable();
 };

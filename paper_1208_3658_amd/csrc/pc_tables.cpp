@@ -327,7 +327,6 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
     t.row_bytes32 = row_bytes_for(t.cols32);
     t.row_bytes64 = row_bytes_for(t.cols64);
     build_lut32(t.lo, t.hi, t.row_bytes32, t.lut32);
-    build_lut32(t.lo_g, t.hi_g, t.row_bytes32, t.lut32g);
     build_lut64(t);
     return true;
 }

@@ -257,23 +257,27 @@ def test_pruning_skips_most_pairs_on_the_1m_shape():
 def test_matrix_core_path_far_clusters_and_edge_pairs(mode):
     """Two compact clusters 15 deg apart, each 10 full tiles, and a copy of the
     first shifted by exactly 12 deg along the meridian (2560 pairs on the 12
-    deg edge): with the matrix-core flag, full tile pairs whose chords are all
-    at least twice the smaller tile radius get their chords from the matrix
-    cores with their own guard band; counts must equal the oracle."""
+    deg edge).  With the matrix-core flag, full tile pairs whose chords are all
+    at least twice the smaller tile radius and whose chord interval holds at
+    most 3 edges get their chords from the matrix cores with their own guard
+    band (sparse edges); dense edges around 12 deg leave them to the vector
+    path.  Counts must equal the oracle either way."""
     rng = np.random.default_rng(33)
     n = 2560
     ra1, dec1 = 100 + 0.5 * rng.standard_normal(n), 0.5 * rng.standard_normal(n)
     ra2, dec2 = 100 + 0.5 * rng.standard_normal(n), 15 + 0.5 * rng.standard_normal(n)
     A = (np.concatenate([ra1, ra2]), np.concatenate([dec1, dec2]))
     B = (ra1.copy(), dec1 + 12.0)
-    e = np.array([0.01, 1.0, 5.0, 9.0, 11.0, 11.9, 12.0, 12.1, 13.0, 14.0, 15.0, 16.0, 18.0, 30.0])
-    got = pc.pc_count_ex(dev(A), e, mode=mode)
-    st = pc.pc_debug_last_pruning()
-    assert got.tolist() == oracle.count(A, e).tolist()
-    gotc = pc.pc_count_ex(dev(A), e, B=dev(B), auto=False, mode=mode)
-    stc = pc.pc_debug_last_pruning()
-    assert gotc.tolist() == oracle.count(A, e, B=B, auto=False).tolist()
-    if mode & pc.PC_MATRIX_CORES:
-        assert st["mfma_items"] > 0 and stc["mfma_items"] > 0
-    else:
-        assert st["mfma_items"] == 0 and stc["mfma_items"] == 0
+    for e, sparse in [(np.array([0.01, 1.0, 5.0, 12.0, 15.0, 30.0]), True),
+                      (np.array([0.01, 1.0, 5.0, 9.0, 11.0, 11.9, 12.0, 12.1, 13.0, 14.0, 15.0, 16.0, 18.0, 30.0]),
+                       False)]:
+        got = pc.pc_count_ex(dev(A), e, mode=mode)
+        st = pc.pc_debug_last_pruning()
+        assert got.tolist() == oracle.count(A, e).tolist()
+        gotc = pc.pc_count_ex(dev(A), e, B=dev(B), auto=False, mode=mode)
+        stc = pc.pc_debug_last_pruning()
+        assert gotc.tolist() == oracle.count(A, e, B=B, auto=False).tolist()
+        if mode & pc.PC_MATRIX_CORES and sparse:
+            assert st["mfma_items"] > 0 and stc["mfma_items"] > 0
+        elif not mode & pc.PC_MATRIX_CORES:
+            assert st["mfma_items"] == 0 and stc["mfma_items"] == 0

@@ -220,44 +220,57 @@ def test_gram_guard_band_separates_matrix_core_chords(name):
     assert np.all(hi >= lo)
 
 
+def _few_edge_rows(c32, c64, e64, lo, hi, k0, m):
+    """Rows as the few-edge binning forms them: k0 + #{k < m : c32 > hi[k0+k]},
+    and the binary64 row for chords inside one of those m bands."""
+    row = np.full(c32.size, k0, dtype=np.int64)
+    band = np.zeros(c32.size, dtype=bool)
+    for k in range(k0, k0 + m):
+        gt = c32 > hi[k]
+        row += gt
+        band |= ~gt & (c32 >= lo[k])
+    row[band] = np.searchsorted(e64, c64[band], side="right")
+    return row
+
+
+@pytest.mark.parametrize("gram", [False, True])
 @pytest.mark.parametrize("name", ["log_40", "paper_254", "linear_zero_180", "tiny"])
-def test_gram_cell_table_bins_like_the_oracle(name):
-    """Cell table + band + binary64 re-check of the matrix-core path, on
-    emulated centred chords, reproduces the binary64 bins."""
+def test_few_edge_binning_reproduces_the_oracle(name, gram):
+    """Few-edge binning (compare with the m <= 3 edges inside a pair's proven
+    chord interval, re-check in-band chords) on emulated binary32 chords --
+    plain differences, or tile-centred Gram chords with the matrix-core band --
+    gives the binary64 bins, for every interval of 1-3 consecutive edges that
+    holds the exact chord."""
     theta = EDGE_SETS[name]
-    info, ent = pc.pc_debug_lut32(theta, gram=True)
     e64 = oracle.chord2_edges(theta)
+    lo, hi = pc.pc_guard_band(theta, gram=gram)
     ra1, dec1, ra2, dec2 = _pairs_near_edges(theta, per_edge=200, seed=3)
-    rng = np.random.default_rng(5)
-    n = ra1.size
-    # plus pairs at random separations
-    ra1 = np.concatenate([ra1, rng.uniform(0, 360, 4000)])
-    dec1 = np.concatenate([dec1, np.degrees(np.arcsin(rng.uniform(-1, 1, 4000)))])
-    ra2 = np.concatenate([ra2, rng.uniform(0, 360, 4000)])
-    dec2 = np.concatenate([dec2, np.degrees(np.arcsin(rng.uniform(-1, 1, 4000)))])
     a = oracle.unit_vectors(ra1, dec1)
     b = oracle.unit_vectors(ra2, dec2)
     c64 = _c64(a, b)
     want = np.searchsorted(e64, c64, side="right")
-    assert n > 0
-    for c32 in _gram_c32_variants(a, b, rng):
-        key = np.clip(c32.view(np.uint32), info["clamp_lo"], info["clamp_hi"])
-        cell = (key >> info["shift"]) - (info["clamp_lo"] >> info["shift"])
-        E = ent[cell]
-        lo = E[:, 1].view(np.float32)
-        hi = E[:, 2].view(np.float32)
-        row = ((E[:, 0] + np.where(c32 > hi, info["row_bytes"], 0)) // info["row_bytes"]).astype(np.int64)
-        band = (c32 >= lo) & ~(c32 > hi)
-        row[band] = want[band]
-        assert np.array_equal(row, want)
+    rng = np.random.default_rng(5)
+    variants = _gram_c32_variants(a, b, rng) if gram else list(_c32_variants(a, b))
+    checked = 0
+    for c32 in variants:
+        for m in (1, 2, 3):
+            for shift in range(m + 1):
+                # intervals [k0, k0 + m] that contain each pair's exact row
+                k0 = want - shift
+                ok = (k0 >= 0) & (k0 + m <= e64.size)
+                for k in np.unique(k0[ok]):
+                    sel = ok & (k0 == k)
+                    got = _few_edge_rows(c32[sel], c64[sel], e64, lo, hi, int(k), m)
+                    assert np.array_equal(got, want[sel]), (name, gram, m, int(k))
+                    checked += int(sel.sum())
+    assert checked > 0
 
 
-@pytest.mark.parametrize("gram", [False, True])
 @pytest.mark.parametrize("name", sorted(EDGE_SETS))
-def test_cell_entries_finite_hi_means_next_row(name, gram):
+def test_cell_entries_finite_hi_means_next_row(name):
     """The kernel reads (off_lo, lo, hi) only and adds one row when c > hi:
     valid because a finite hi occurs only in one-band cells."""
-    info, ent = pc.pc_debug_lut32(EDGE_SETS[name], gram=gram)
+    info, ent = pc.pc_debug_lut32(EDGE_SETS[name])
     hi = ent[:, 2].view(np.float32)
     fin = np.isfinite(hi)
     assert np.all(ent[fin, 3] == ent[fin, 0] + info["row_bytes"])
