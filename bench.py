@@ -254,7 +254,8 @@ def main():
                      "kernel_ms": kern_s * 1e3, "work_per_pair": W, "grid": launch["grid"],
                      "lds_bytes": launch["lds_bytes"], "items": launch["items"],
                      "pairs_computed": prn["pairs_computed"], "survivor_items": prn["survivors"],
-                     "few_edge_items": prn["few_items"], "matrix_core_items": prn["mfma_items"],
+                     "few_edge_items": prn["few_items"], "gram_form_items": prn["gram_items"],
+                     "matrix_core_items": prn["mfma_items"],
                      "computed_gpairs_s": prn["pairs_computed"] / kern_s / 1e9},
         "pairs_binned_whole": pairs - prn["pairs_computed"],
     }

@@ -153,7 +153,8 @@ const char *pc_version(void);
 
 /*
  * pc_catalog_upload -- convert a catalogue once (RA/Dec -> binary64 and
- * binary32 unit vectors, 48 bytes per point) and keep it resident on the
+ * binary32 unit vectors in caller order and in a spatially ordered copy with
+ * its tile bounds, about 112 bytes per point) and keep it resident on the
  * current device.  *handle receives a nonzero id.  Paper Sec. 2.1: positions
  * are copied to GPU global memory once and reused for every submatrix.
  */

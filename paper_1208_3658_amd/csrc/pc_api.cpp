@@ -30,7 +30,7 @@ hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs,
                         unsigned long long *queue, uint32_t lds_bytes, int grid, hipStream_t st);
 size_t sort_scratch_words(int64_t n);
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
-                       float4 *a32s, double4 *bounds, hipStream_t st);
+                       float4 *a32s, float4 *g32s, double4 *bounds, hipStream_t st);
 hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, uint64_t total_items,
                         uint64_t *survivors, unsigned long long *meta, int32_t mfma_ok, hipStream_t st);
 hipError_t count_occupancy(bool fp64, bool mc, uint32_t lds_bytes, int *blocks_per_cu);
@@ -357,7 +357,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         int src = -1;
         int64_t b = 0, e = 0;
         bool resident_full = false;
-        size_t o_a64s = 0, o_a32s = 0, o_bounds = 0;
+        size_t o_a64s = 0, o_a32s = 0, o_g32s = 0, o_bounds = 0;
     };
     std::vector<View> views;
     std::map<std::tuple<int, int64_t, int64_t>, int> view_of;
@@ -376,6 +376,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         } else if (n > 0) {
             v.o_a64s = ar.take(sizeof(double4) * static_cast<size_t>(n));
             v.o_a32s = ar.take(sizeof(float4) * static_cast<size_t>(n));
+            v.o_g32s = ar.take(sizeof(float4) * static_cast<size_t>(n));
             v.o_bounds = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(n)));
             max_sort_n = std::max(max_sort_n, n);
         }
@@ -468,7 +469,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
                                         "); split the catalogues into row ranges");
     const size_t o_segs = ar.take(sizeof(SegDesc) * std::max<size_t>(segs.size(), 1));
     const size_t o_tabs = ar.take(sizeof(TableDesc) * tabs.size());
-    // meta[0..4]: pruning results; meta[8..15]: the counting kernel's work queue
+    // meta[0..5]: pruning results; meta[8..15]: the counting kernel's work queue
     const size_t o_meta = ar.take(sizeof(unsigned long long) * 16);
     const size_t o_surv = ar.take(sizeof(uint64_t) * std::max<uint64_t>(prune ? items : 1, 1));
 
@@ -507,6 +508,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     struct ViewPtrs {
         const double4 *a64s = nullptr;
         const float4 *a32s = nullptr;
+        const float4 *g32s = nullptr;
         const double4 *bounds = nullptr;
     };
     std::vector<ViewPtrs> vp(views.size());
@@ -516,6 +518,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             const Resident &r = *srcs[vw.src].res;
             vp[v].a64s = r.a64s;
             vp[v].a32s = r.a32s;
+            vp[v].g32s = r.g32s;
             vp[v].bounds = r.bounds;
             continue;
         }
@@ -523,11 +526,14 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         if (n <= 0) continue;
         double4 *a64s = reinterpret_cast<double4 *>(W + vw.o_a64s);
         float4 *a32s = reinterpret_cast<float4 *>(W + vw.o_a32s);
+        float4 *g32s = reinterpret_cast<float4 *>(W + vw.o_g32s);
         double4 *bnd = reinterpret_cast<double4 *>(W + vw.o_bounds);
-        PC_HIP(launch_sort(src_a64[vw.src], vw.b, n, reinterpret_cast<uint32_t *>(W + o_scratch), a64s, a32s, bnd, st),
+        PC_HIP(launch_sort(src_a64[vw.src], vw.b, n, reinterpret_cast<uint32_t *>(W + o_scratch), a64s, a32s, g32s,
+                           bnd, st),
                "sort");
         vp[v].a64s = a64s;
         vp[v].a32s = a32s;
+        vp[v].g32s = g32s;
         vp[v].bounds = bnd;
     }
 
@@ -542,6 +548,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         sd.j32 = vp[vj].a32s;
         sd.j64 = vp[vj].a64s;
         sd.jb = vp[vj].bounds;
+        sd.jg = vp[vj].g32s;
         sd.counts = reinterpret_cast<unsigned long long *>(W + plan[static_cast<size_t>(sd.job)].o_counts);
     }
     std::vector<TableDesc> tds;
@@ -612,7 +619,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     }
     std::vector<int> flags(std::max<size_t>(srcs.size(), 1), 0);
     PC_HIP(hipMemcpyAsync(flags.data(), W + o_err, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, st), "D2H flags");
-    unsigned long long hmeta[5] = {0, 0, 0, 0, 0};
+    unsigned long long hmeta[6] = {0, 0, 0, 0, 0, 0};
     PC_HIP(hipMemcpyAsync(hmeta, meta, sizeof(hmeta), hipMemcpyDeviceToHost, st), "D2H meta");
     PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
     for (size_t k = 0; k < srcs.size(); ++k)
@@ -636,6 +643,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     t_last.pairs_computed = prune ? hmeta[1] : total_pairs;
     t_last.mfma_items = prune ? hmeta[3] : 0;
     t_last.few_items = prune ? hmeta[4] : 0;
+    t_last.gram_items = prune ? hmeta[5] : 0;
     if (t_timing && items > 0) {
         float ms = 0.0f;
         PC_HIP(hipEventElapsedTime(&ms, t_ev0, t_ev1), "hipEventElapsedTime");
@@ -661,6 +669,7 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
     const size_t o32 = ar.take(sizeof(float4) * n);
     const size_t o64s = ar.take(sizeof(double4) * n);
     const size_t o32s = ar.take(sizeof(float4) * n);
+    const size_t og32s = ar.take(sizeof(float4) * n);
     const size_t ob = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(static_cast<int64_t>(n))));
     const size_t oerr = ar.take(sizeof(int));
     const size_t osc = ar.take(sizeof(uint32_t) * sort_scratch_words(static_cast<int64_t>(n)));
@@ -675,6 +684,7 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
     r->a32 = reinterpret_cast<float4 *>(W + o32);
     r->a64s = reinterpret_cast<double4 *>(W + o64s);
     r->a32s = reinterpret_cast<float4 *>(W + o32s);
+    r->g32s = reinterpret_cast<float4 *>(W + og32s);
     r->bounds = reinterpret_cast<double4 *>(W + ob);
     PC_HIP(hipMemsetAsync(W + oerr, 0, sizeof(int), st), "hipMemsetAsync");
     if (c->n > 0) {
@@ -686,7 +696,8 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
             dec = reinterpret_cast<const double *>(W + odec);
         }
         PC_HIP(launch_convert(ra, dec, c->n, r->a64, r->a32, reinterpret_cast<int *>(W + oerr), st), "convert");
-        PC_HIP(launch_sort(r->a64, 0, c->n, reinterpret_cast<uint32_t *>(W + osc), r->a64s, r->a32s, r->bounds, st),
+        PC_HIP(launch_sort(r->a64, 0, c->n, reinterpret_cast<uint32_t *>(W + osc), r->a64s, r->a32s, r->g32s,
+                           r->bounds, st),
                "sort");
     }
     int flag = 0;
@@ -899,8 +910,9 @@ extern "C" int pc_debug_set_timing(int32_t on) {
 }
 
 extern "C" int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_t *pairs_total,
-                                     uint64_t *mfma_items, uint64_t *few_items) {
+                                     uint64_t *mfma_items, uint64_t *few_items, uint64_t *gram_items) {
     clear_error();
+    if (gram_items) *gram_items = t_last.gram_items;
     if (few_items) *few_items = t_last.few_items;
     if (mfma_items) *mfma_items = t_last.mfma_items;
     if (survivors) *survivors = t_last.survivors;

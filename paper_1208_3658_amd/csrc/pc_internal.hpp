@@ -72,10 +72,14 @@ struct TableDesc {
 //   bits  0..39  item number within the launch
 //   bits 40..50  k0: edges at or below the item's whole chord interval
 //   bits 51..52  m: edges inside the interval when at most kFewMax, else 0
+//   bit  61      vector path, chords in Gram form centred on the j-tile
 //   bit  62      matrix-core path centred on the j-tile
 //   bit  63      matrix-core path
 constexpr int kItemBits = 40;
-constexpr int kFewMax = 3;
+constexpr int kFewMax = 3;  // at most 3: m has two bits
+#ifndef PC_FEWCUT
+#define PC_FEWCUT 2         // items with at most this many edges use few-edge binning (<= kFewMax)
+#endif
 constexpr uint64_t kItemMask = (1ull << kItemBits) - 1;
 
 // A binary32 cell table (see pc_tables.cpp).
@@ -93,6 +97,8 @@ struct SegDesc {
     const float4 *i32, *j32;          // spatially ordered binary32 points
     const double4 *i64, *j64;         // the same points in binary64
     const double4 *ib, *jb;           // tile bounds (centre, radius) of each side
+    const float4 *jg;                 // j side in Gram form, centred on its own tile
+                                      // (-2 b'_x, -2 b'_y, -2 b'_z, |b'|^2)
     int64_t i0, ni, j0, nj;
     int64_t tiles_i, tiles_j;
     int32_t tri, tab, job, pad;

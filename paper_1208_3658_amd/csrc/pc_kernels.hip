@@ -508,6 +508,79 @@ __device__ __forceinline__ void tile32_few(unsigned char *lds, const float4 *__r
     few_flush<M>(lds, ngt, total, f, k);
 }
 
+// Few-edge items whose j-tile radius r satisfies 2 r <= the chord lower
+// bound: chords in Gram form centred on the j-tile's centre o, on the vector
+// ALU.  The j side comes precomputed per point as (-2 b'_x, -2 b'_y, -2 b'_z,
+// |b'|^2) with b' = RN32(b - o); the lane's i-points are centred here, a' =
+// RN32(a - o), with |a'|^2 in binary32.  A chord is then
+// a'_x B_x + (a'_y B_y + (a'_z B_z + (|a'|^2 + |b'|^2))): one add and three
+// fused multiply-adds, four roundings, against six instructions for the
+// difference form; the matrix-core band bounds its error (same centring
+// condition, at most eight roundings).  i slots past the end of the range
+// get |a'|^2 = NaN, so all their chords are NaN and count nowhere.
+template <int M, int NJ>
+__device__ __forceinline__ void step32_gram(unsigned char *lds, const float4 *__restrict__ Jg,
+                                            const double4 *__restrict__ J64t, int32_t jj, const float (&ax)[kR],
+                                            const float (&ay)[kR], const float (&az)[kR], const float (&na)[kR],
+                                            const double4 *__restrict__ I64, int64_t ibeg, const TileCtx &k,
+                                            const FewCtx &f, uint32_t (&ngt)[M]) {
+    const int32_t lane = static_cast<int32_t>(threadIdx.x);
+    float4 b[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) b[q] = ld_const(Jg + jj + q);
+    uint64_t band = 0;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q)
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const float c = __builtin_fmaf(ax[r], b[q].x, __builtin_fmaf(ay[r], b[q].y,
+                                           __builtin_fmaf(az[r], b[q].z, na[r] + b[q].w)));
+#pragma unroll
+            for (int t = 0; t < M; ++t) few_count(c, f.lo[t], f.hi[t], ngt[t], band);
+        }
+    if (__builtin_expect(band != 0, 0)) {
+#pragma unroll
+        for (int q = 0; q < NJ; ++q)
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                float c = __builtin_fmaf(ax[r], b[q].x, __builtin_fmaf(ay[r], b[q].y,
+                                         __builtin_fmaf(az[r], b[q].z, na[r] + b[q].w)));
+                asm volatile("" : "+v"(c));
+                if (few_in_band<M>(c, f)) few_recheck<M>(lds, c, I64[ibeg + r * kWave + lane], J64t[jj + q], f, k);
+            }
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void tile32_gram(unsigned char *lds, const float4 *__restrict__ Jg,
+                                            const double4 *__restrict__ J64t, int32_t jn,
+                                            const double4 *__restrict__ I64, int64_t ibeg, int32_t i_lim,
+                                            double ox, double oy, double oz, const TileCtx &k, const FewCtx &f) {
+    const int32_t lane = static_cast<int32_t>(threadIdx.x);
+    float ax[kR], ay[kR], az[kR], na[kR];
+    uint32_t valid = 0;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int32_t ir = r * kWave + lane;
+        const bool ok = ir < i_lim;
+        const double4 p = I64[ibeg + (ok ? ir : 0)];
+        ax[r] = static_cast<float>(p.x - ox);
+        ay[r] = static_cast<float>(p.y - oy);
+        az[r] = static_cast<float>(p.z - oz);
+        const float n2 = __builtin_fmaf(az[r], az[r], __builtin_fmaf(ay[r], ay[r], ax[r] * ax[r]));
+        na[r] = ok ? n2 : __builtin_nanf("");
+        valid += ok ? 1u : 0u;
+    }
+    uint32_t ngt[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) ngt[t] = 0u;
+    int32_t jj = 0;
+    for (; jj + PC_JUNROLL <= jn; jj += PC_JUNROLL)
+        step32_gram<M, PC_JUNROLL>(lds, Jg, J64t, jj, ax, ay, az, na, I64, ibeg, k, f, ngt);
+    for (; jj < jn; ++jj) step32_gram<M, 1>(lds, Jg, J64t, jj, ax, ay, az, na, I64, ibeg, k, f, ngt);
+    few_flush<M>(lds, ngt, valid * static_cast<uint32_t>(jn), f, k);
+}
+
 // ----------------------------------------------------------- matrix cores
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -757,6 +830,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         // marked by the prune pass (layout next to kItemBits)
         const bool to_mfma = !FP64 && (raw >> 63) != 0;
         const bool centre_j = ((raw >> 62) & 1u) != 0;
+        const bool gram_j = !FP64 && ((raw >> 61) & 1u) != 0;
         const uint32_t few_m = FP64 ? 0u : static_cast<uint32_t>((raw >> (kItemBits + 11)) & 3u);
         const uint32_t few_k0 = static_cast<uint32_t>((raw >> kItemBits) & 2047u);
         const uint64_t it = raw & kItemMask;
@@ -820,7 +894,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         // matrix-core path too)
         float fx[kR], fy[kR], fz[kR];
         double dx[kR], dy[kR], dz[kR];
-        if (FP64 || !(MC && to_mfma)) {
+        if (FP64 || !((MC && to_mfma) || gram_j)) {
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 const int32_t ir = r * kWave + static_cast<int32_t>(lane);
@@ -872,7 +946,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
             FewCtx f;
             f.k0 = few_k0;
             if (few_m) {
-                const float *bd = (MC && to_mfma) ? band_g : band;
+                const float *bd = ((MC && to_mfma) || gram_j) ? band_g : band;
 #pragma unroll
                 for (int q = 0; q < kFewMax; ++q) {
                     const uint32_t e = min(few_k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
@@ -889,6 +963,14 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 if (few_m == 1) tile_mfma<1>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
                 else if (few_m == 2) tile_mfma<2>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
                 else tile_mfma<3>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
+            } else if (gram_j && few_m) {
+                // not a diagonal tile; i slots past a ragged end are NaN
+                const double4 o = ld_const(sd.jb + u);
+                const float4 *Jg = uniform_ptr(sd.jg + jbeg);
+                const double4 *I64 = sd.i64;
+                if (few_m == 1) tile32_gram<1>(lds, Jg, J64t, jn, I64, ibeg, i_lim, o.x, o.y, o.z, k, f);
+                else if (few_m == 2) tile32_gram<2>(lds, Jg, J64t, jn, I64, ibeg, i_lim, o.x, o.y, o.z, k, f);
+                else tile32_gram<3>(lds, Jg, J64t, jn, I64, ibeg, i_lim, o.x, o.y, o.z, k, f);
             } else {
                 const float4 *Jt = uniform_ptr(sd.j32 + jbeg);
                 if (masked) {

@@ -169,9 +169,12 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // One wave per tile of kTile sorted points: centre = normalised mean, radius
 // = largest distance from the centre, rounded outward.  Written as
-// (cx, cy, cz, r).
+// (cx, cy, cz, r).  Each point is also written in Gram form centred on that
+// centre: b' = RN32(b - c) (difference in binary64), (-2 b'_x, -2 b'_y,
+// -2 b'_z, |b'|^2) with |b'|^2 formed in binary32 as z*z + (y*y + x*x) by
+// fused multiply-adds.
 __global__ void __launch_bounds__(kWave) k_bounds(const double4 *__restrict__ a64s, int64_t n,
-                                                  double4 *__restrict__ bounds) {
+                                                  double4 *__restrict__ bounds, float4 *__restrict__ g32s) {
     const int64_t t = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t b = t * kTile;
@@ -214,6 +217,16 @@ __global__ void __launch_bounds__(kWave) k_bounds(const double4 *__restrict__ a6
     }
     m = wave_max(m);
     if (lane == 0) bounds[t] = make_double4(cx, cy, cz, sqrt(m) * (1.0 + 0x1p-40) + 0x1p-60);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        if (ok[r]) {
+            const float x = static_cast<float>(p[r].x - cx);
+            const float y = static_cast<float>(p[r].y - cy);
+            const float z = static_cast<float>(p[r].z - cz);
+            g32s[b + r * kWave + lane] =
+                make_float4(-2.0f * x, -2.0f * y, -2.0f * z, __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x)));
+        }
+    }
 }
 
 // ----------------------------------------------------------------- prune
@@ -251,7 +264,8 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                                                unsigned long long *__restrict__ meta, int32_t mfma_ok) {
     // meta[0] = survivors, meta[1] = pairs in survivors, meta[2] = pairs binned
     // whole, meta[3] = survivors marked for the matrix cores, meta[4] =
-    // survivors with at most kFewMax edges in their chord interval
+    // survivors with at most kFewMax edges in their chord interval, meta[5] =
+    // survivors whose vector-path chords are formed in Gram form
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * blockDim.x; base < total_items; base += stride) {
         const uint64_t it = base + threadIdx.x;
@@ -259,7 +273,7 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
         unsigned long long *dst = nullptr;
         unsigned long long cnt = 0;
         bool survive = false;
-        bool mfma = false, centre_j = false;
+        bool mfma = false, centre_j = false, gram_j = false;
         uint64_t pairs = 0, few = 0;
         if (valid) {
             const int s = find_seg_p(segs, n_segs, it);
@@ -303,7 +317,8 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                 // edges inside the interval: k_lo .. k_hi-1; few of them are
                 // compared one by one instead of through the cell table
                 const uint32_t m = k_hi - k_lo;
-                const bool is_few = m <= static_cast<uint32_t>(kFewMax);
+                static_assert(PC_FEWCUT >= 1 && PC_FEWCUT <= kFewMax, "few-edge cut");
+                const bool is_few = m <= static_cast<uint32_t>(PC_FEWCUT);
                 few = (static_cast<uint64_t>(k_lo) << kItemBits) |
                       (static_cast<uint64_t>(is_few ? m : 0u) << (kItemBits + 11));
                 // few-edge full tiles whose chord lower bound is at least twice
@@ -312,6 +327,9 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                 // (bit 62)
                 centre_j = bj.w < bi.w;
                 mfma = mfma_ok && is_few && !diag && ni == kTile && nj == kTile && 2.0 * fmin(bi.w, bj.w) <= lo;
+                // otherwise the vector path forms Gram chords centred on the
+                // j-tile (bit 61) under the same condition on the j radius
+                gram_j = !mfma && is_few && !diag && 2.0 * bj.w <= lo;
             }
         }
         // survivors: one atomic per wave
@@ -326,17 +344,20 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
             at = __shfl(at, __ffsll(static_cast<long long>(sm)) - 1, kWave);
             if (survive)
                 survivors[at + __popcll(below)] = it | few | (mfma ? (1ull << 63) : 0ull) |
-                                                  ((mfma && centre_j) ? (1ull << 62) : 0ull);
+                                                  ((mfma && centre_j) ? (1ull << 62) : 0ull) |
+                                                  (gram_j ? (1ull << 61) : 0ull);
             // pairs in survivors, and survivors for the matrix cores
             unsigned long long p = survive ? pairs : 0ull;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
             const uint64_t mm = __ballot(survive && mfma);
             const uint64_t mf = __ballot(survive && (few >> (kItemBits + 11)) != 0);
+            const uint64_t mg = __ballot(survive && gram_j);
             if (lane == 0) {
                 atomicAdd(meta + 1, p);
                 if (mm) atomicAdd(meta + 3, static_cast<unsigned long long>(__popcll(mm)));
                 if (mf) atomicAdd(meta + 4, static_cast<unsigned long long>(__popcll(mf)));
+                if (mg) atomicAdd(meta + 5, static_cast<unsigned long long>(__popcll(mg)));
             }
         }
         // whole-item counts: sum lanes with equal destinations
@@ -384,7 +405,7 @@ size_t sort_scratch_words(int64_t n) {
 // Spatially ordered copy of src[base, base+n) into a64s/a32s, and the tile
 // bounds.  scratch: sort_scratch_words(n) uint32 words.
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
-                       float4 *a32s, double4 *bounds, hipStream_t st) {
+                       float4 *a32s, float4 *g32s, double4 *bounds, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const uint32_t bits = order_bits(n);
     const int64_t m = n_buckets(bits);
@@ -400,7 +421,7 @@ hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *sc
     k_scan_add<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(hist, m, sums);
     k_scatter<<<dim3(gn), dim3(256), 0, st>>>(src, base, n, keys, hist, a64s, a32s);
     const int64_t tiles = (n + kTile - 1) / kTile;
-    k_bounds<<<dim3(static_cast<uint32_t>(tiles)), dim3(kWave), 0, st>>>(a64s, n, bounds);
+    k_bounds<<<dim3(static_cast<uint32_t>(tiles)), dim3(kWave), 0, st>>>(a64s, n, bounds, g32s);
     return hipGetLastError();
 }
 

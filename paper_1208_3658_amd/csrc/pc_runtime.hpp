@@ -47,6 +47,7 @@ struct Resident {
     float4 *a32 = nullptr;      // caller order
     double4 *a64s = nullptr;    // spatially ordered copy
     float4 *a32s = nullptr;
+    float4 *g32s = nullptr;     // ordered copy in Gram form, centred on its tile
     double4 *bounds = nullptr;  // tile bounds of the ordered copy
     int64_t n = 0;
     int device = 0;
@@ -81,6 +82,7 @@ struct BatchStats {
     uint64_t pairs_computed = 0;  // pairs visited one by one
     uint64_t mfma_items = 0;      // of the survivors, tile pairs done on the matrix cores
     uint64_t few_items = 0;       // of the survivors, tile pairs with at most kFewMax edges inside
+    uint64_t gram_items = 0;      // of the survivors, tile pairs with Gram-form chords on the vector path
 };
 
 // Runs the jobs in one persistent launch on `st` and blocks until the host

@@ -5,7 +5,8 @@
 // catalogue), RR and the Landy-Szalay w(theta) (paper Sec. 2, Eq. 2).
 //
 //  * Admission: a request enters the device only while the memory it needs
-//    (48 bytes per point for its converted catalogue plus 16 bytes of staging)
+//    (128 bytes per point: its converted catalogue, the spatially ordered
+//    copies and the sort's staging)
 //    fits in the free device memory minus a configured budget, and while fewer
 //    than max_inflight requests are on the device.  A request that can never
 //    fit fails with PC_ERR_NOMEM.
@@ -412,7 +413,7 @@ int pc_server_submit(void *server, const pc_catalog *data, int32_t patch_id, con
             memcpy(r->dec.data(), data->dec_deg, sizeof(double) * n);
         }
     }
-    r->need_bytes = 64ull * std::max<size_t>(n, 1) + (1u << 20);
+    r->need_bytes = 128ull * std::max<size_t>(n, 1) + (1u << 20);
     std::lock_guard<std::mutex> lk(s->mu);
     auto pit = s->patches.find(patch_id);
     if (pit == s->patches.end()) return fail(PC_ERR_INVALID, "no random catalogue registered for this patch");

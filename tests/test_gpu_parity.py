@@ -194,7 +194,7 @@ def test_1m_config_sampled_rows_and_decompositions():
     jobs = [{"A": Dd, "edges": e}, {"A": Dd, "B": Rd, "edges": e, "auto": False}, {"A": Rd, "edges": e}]
     mixed = pc.pc_count_batch(jobs, mode=pc.PC_MIXED)
     st = pc.pc_debug_last_pruning()
-    assert st["few_items"] > 0
+    assert st["few_items"] > 0 and st["gram_items"] > 0
     plain = pc.pc_count_batch(jobs, mode=pc.PC_FP64_PLAIN)
     matrix = pc.pc_count_batch(jobs, mode=pc.PC_MIXED | pc.PC_MATRIX_CORES)
     assert pc.pc_debug_last_pruning()["mfma_items"] > 0
@@ -279,5 +279,7 @@ def test_matrix_core_path_far_clusters_and_edge_pairs(mode):
         assert gotc.tolist() == oracle.count(A, e, B=B, auto=False).tolist()
         if mode & pc.PC_MATRIX_CORES and sparse:
             assert st["mfma_items"] > 0 and stc["mfma_items"] > 0
+        if mode == pc.PC_MIXED and sparse:
+            assert st["gram_items"] > 0 and stc["gram_items"] > 0
         elif not mode & pc.PC_MATRIX_CORES:
             assert st["mfma_items"] == 0 and stc["mfma_items"] == 0

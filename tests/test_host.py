@@ -167,11 +167,12 @@ def test_cell_table_logic_reproduces_oracle(name):
 
 
 def _gram_c32_variants(a64, b64, rng):
-    """binary32 squared chords as the matrix-core path forms them: both points
-    centred on o (within half the pair's chord of a, or of b), rounded to
-    binary32, c = |b'|^2 + |a'|^2 + sum_k a'_k (-2 b'_k) summed in several
-    orders (one rounding at the end, or a rounding after every product and
-    addition, forward and backward)."""
+    """binary32 squared chords in Gram form as the matrix cores and the vector
+    path form them: both points centred on o (within half the pair's chord of
+    a, or of b), rounded to binary32, c = |b'|^2 + |a'|^2 + sum_k a'_k (-2 b'_k)
+    summed in several orders (one rounding at the end; a rounding after every
+    product and addition, forward and backward; the vector path's fused
+    multiply-add chain)."""
     s = np.sqrt(_c64(a64, b64))
     w = rng.normal(size=a64.shape)
     w /= np.linalg.norm(w, axis=1)[:, None]
@@ -194,6 +195,12 @@ def _gram_c32_variants(a64, b64, rng):
         acc = f(terms[-1])
         for t in terms[-2::-1]:
             acc = f(acc + f(t))
+        out.append(acc)
+        # the vector path's order: (|a'|^2 + |b'|^2), then fused
+        # multiply-adds of z, y, x (each product exact, one rounding each)
+        acc = f(na.astype(np.float64) + nb.astype(np.float64))
+        for k in (2, 1, 0):
+            acc = f(A[:, k].astype(np.float64) * (-2.0 * B[:, k].astype(np.float64)) + acc.astype(np.float64))
         out.append(acc)
     return out
 
