@@ -142,6 +142,28 @@ int pc_count_batch(const pc_job *jobs, int32_t n_jobs, int32_t mode, void *strea
 int pc_wtheta(const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_t n_bins,
               int64_t nD, int64_t nR, double *w);
 
+/*
+ * pc_estimator -- w(theta) by one of several estimators from in-range bin
+ * counts.  Sec. 2 uses Landy-Szalay and notes that other estimators are easy
+ * to try with the same counts; these are the usual ones, all on counts
+ * normalised as in pc_wtheta (dd = DD/(nD(nD-1)/2), dr = DR/(nD nR),
+ * rr = RR/(nR(nR-1)/2)), binary64, this operation order, no fused multiply-add:
+ *   PC_EST_LANDY_SZALAY   ((dd - 2 dr) + rr) / rr      (same as pc_wtheta)
+ *   PC_EST_NATURAL        dd / rr - 1                  (DR unused, may be NULL)
+ *   PC_EST_DAVIS_PEEBLES  dd / dr - 1                  (RR unused, may be NULL)
+ *   PC_EST_HAMILTON       (dd * rr) / (dr * dr) - 1
+ * A zero denominator gives IEEE inf or NaN.  nD, nR >= 2; n_bins >= 1.
+ * Host computation; no device needed.
+ */
+enum pc_estimator_kind {
+    PC_EST_LANDY_SZALAY = 0,
+    PC_EST_NATURAL = 1,
+    PC_EST_DAVIS_PEEBLES = 2,
+    PC_EST_HAMILTON = 3
+};
+int pc_estimator(int32_t kind, const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_t n_bins,
+                 int64_t nD, int64_t nR, double *w);
+
 /* Thread-local description of the last error on this thread ("" if none).
  * Valid until the next pc_* call on the same thread. */
 const char *pc_last_error(void);

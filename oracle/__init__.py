@@ -37,6 +37,8 @@ def lib():
         L.oracle_count.restype = ctypes.c_int
         L.oracle_wtheta.argtypes = [_up, _up, _up, _i32, _i64, _i64, _dp]
         L.oracle_wtheta.restype = None
+        L.oracle_estimator.argtypes = [_i32, _up, _up, _up, _i32, _i64, _i64, _dp]
+        L.oracle_estimator.restype = None
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -120,6 +122,17 @@ def wtheta(DD, DR, RR, nD: int, nR: int) -> np.ndarray:
     RR, p3 = _u(RR)
     out = np.empty(DD.size, dtype=np.float64)
     lib().oracle_wtheta(p1, p2, p3, DD.size, int(nD), int(nR), out.ctypes.data_as(_dp))
+    return out
+
+
+def estimator(kind: int, DD, DR, RR, nD: int, nR: int) -> np.ndarray:
+    """kind 0 Landy-Szalay, 1 natural, 2 Davis-Peebles, 3 Hamilton (DR or RR
+    may be None where the estimator does not use it)."""
+    DD, p1 = _u(DD)
+    p2 = _u(DR)[1] if DR is not None else None
+    p3 = _u(RR)[1] if RR is not None else None
+    out = np.empty(DD.size, dtype=np.float64)
+    lib().oracle_estimator(int(kind), p1, p2, p3, DD.size, int(nD), int(nR), out.ctypes.data_as(_dp))
     return out
 
 

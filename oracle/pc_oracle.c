@@ -238,6 +238,36 @@ void oracle_wtheta(const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, i
     }
 }
 
+/* The other usual estimators on the same normalised counts (Sec. 2 notes that
+ * the choice of estimator is open): kind 1 natural dd/rr - 1, kind 2
+ * Davis-Peebles dd/dr - 1, kind 3 Hamilton dd*rr/dr^2 - 1; kind 0 is
+ * oracle_wtheta.  Each written from its textbook definition. */
+void oracle_estimator(int32_t kind, const uint64_t *DD, const uint64_t *DR, const uint64_t *RR,
+                      int32_t n_bins, int64_t nD, int64_t nR, double *w)
+{
+    if (kind == 0) {
+        oracle_wtheta(DD, DR, RR, n_bins, nD, nR, w);
+        return;
+    }
+    double fD = (double)nD, fR = (double)nR;
+    double nDD = 0.5 * fD * (fD - 1.0);
+    double nDR = fD * fR;
+    double nRR = 0.5 * fR * (fR - 1.0);
+    for (int32_t k = 0; k < n_bins; ++k) {
+        double dd = (double)DD[k] / nDD;
+        double dr = DR ? (double)DR[k] / nDR : 0.0;
+        double rr = RR ? (double)RR[k] / nRR : 0.0;
+        double ratio;
+        if (kind == 1)
+            ratio = dd / rr;
+        else if (kind == 2)
+            ratio = dd / dr;
+        else
+            ratio = (dd * rr) / (dr * dr);
+        w[k] = ratio - 1.0;
+    }
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

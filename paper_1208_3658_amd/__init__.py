@@ -59,6 +59,7 @@ _SIGNATURES = {
     "pc_unit_vectors": ([_PCAT, _vp, _vp, _vp], ctypes.c_int),
     "pc_chord2_edges": ([_vp, _i32, _vp], ctypes.c_int),
     "pc_guard_band": ([_vp, _i32, _vp, _vp], ctypes.c_int),
+    "pc_estimator": ([_i32, _vp, _vp, _vp, _i32, _i64, _i64, _vp], ctypes.c_int),
     "pc_debug_lut32": ([_vp, _i32, _vp, _vp, _i64], ctypes.c_int),
     "pc_debug_set_timing": ([_i32], ctypes.c_int),
     "pc_debug_last_launch": ([_vp, _vp, _vp, _vp], ctypes.c_int),
@@ -219,6 +220,22 @@ def pc_wtheta(DD, DR, RR, nD: int, nR: int) -> np.ndarray:
     w = np.empty(DD.size, dtype=np.float64)
     _check(lib().pc_wtheta(DD.ctypes.data, DR.ctypes.data, RR.ctypes.data, DD.size, int(nD), int(nR),
                            w.ctypes.data))
+    return w
+
+
+PC_EST_LANDY_SZALAY, PC_EST_NATURAL, PC_EST_DAVIS_PEEBLES, PC_EST_HAMILTON = 0, 1, 2, 3
+
+
+def pc_estimator(kind: int, DD, DR, RR, nD: int, nR: int) -> np.ndarray:
+    """w(theta) by estimator `kind` (PC_EST_*) from in-range bin counts; DR
+    (natural) or RR (Davis-Peebles) may be None."""
+    arrs = [None if x is None else np.ascontiguousarray(x, dtype=np.uint64) for x in (DD, DR, RR)]
+    n = arrs[0].size
+    if any(a is not None and a.size != n for a in arrs):
+        raise ValueError("DD, DR, RR differ in length")
+    w = np.empty(n, dtype=np.float64)
+    ptrs = [None if a is None else a.ctypes.data for a in arrs]
+    _check(lib().pc_estimator(int(kind), ptrs[0], ptrs[1], ptrs[2], n, int(nD), int(nR), w.ctypes.data))
     return w
 
 

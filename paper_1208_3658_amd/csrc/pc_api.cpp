@@ -789,6 +789,18 @@ int pc_wtheta(const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_
     return PC_OK;
 }
 
+int pc_estimator(int32_t kind, const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_t n_bins,
+                 int64_t nD, int64_t nR, double *w) {
+    clear_error();
+    if (kind < PC_EST_LANDY_SZALAY || kind > PC_EST_HAMILTON) return fail(PC_ERR_INVALID, "unknown estimator");
+    const bool need_dr = kind != PC_EST_NATURAL, need_rr = kind != PC_EST_DAVIS_PEEBLES;
+    if (!DD || !w || (need_dr && !DR) || (need_rr && !RR)) return fail(PC_ERR_INVALID, "NULL argument");
+    if (n_bins < 1) return fail(PC_ERR_INVALID, "n_bins must be >= 1");
+    if (nD < 2 || nR < 2) return fail(PC_ERR_INVALID, "nD and nR must be >= 2");
+    estimator(kind, DD, DR, RR, n_bins, nD, nR, w);
+    return PC_OK;
+}
+
 int pc_catalog_upload(const pc_catalog *c, void *stream, uint64_t *handle) {
     clear_error();
     return upload_catalog(c, static_cast<hipStream_t>(stream), handle);

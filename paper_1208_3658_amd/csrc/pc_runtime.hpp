@@ -90,6 +90,9 @@ struct BatchStats {
 int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, BatchStats *stats);
 
 // Landy-Szalay in binary64, fixed operation order, no contraction.
+// kind: 0 Landy-Szalay, 1 natural, 2 Davis-Peebles, 3 Hamilton (see pc.h)
+void estimator(int32_t kind, const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_t n_bins,
+               int64_t nD, int64_t nR, double *w);
 void landy_szalay(const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_t n_bins, int64_t nD,
                   int64_t nR, double *w);
 

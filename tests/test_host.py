@@ -297,6 +297,26 @@ def test_wtheta_matches_oracle_bitwise():
     assert np.array_equal(got[f].view(np.uint64), want[f].view(np.uint64))
 
 
+def test_estimators_match_oracle_bitwise():
+    rng = np.random.default_rng(23)
+    DD = rng.integers(0, 10**12, 60).astype(np.uint64)
+    DR = rng.integers(0, 10**12, 60).astype(np.uint64)
+    RR = rng.integers(0, 10**12, 60).astype(np.uint64)
+    DR[5] = 0
+    RR[7] = 0
+    for kind in range(4):
+        got = pc.pc_estimator(kind, DD, DR, RR, 777_777, 3_000_001)
+        want = oracle.estimator(kind, DD, DR, RR, 777_777, 3_000_001)
+        assert np.array_equal(np.isnan(got), np.isnan(want)), kind
+        f = ~np.isnan(want)
+        assert np.array_equal(got[f].view(np.uint64), want[f].view(np.uint64)), kind
+    assert np.array_equal(pc.pc_estimator(1, DD, None, RR, 10, 20), oracle.estimator(1, DD, None, RR, 10, 20))
+    with pytest.raises(pc.PcError):
+        pc.pc_estimator(4, DD, DR, RR, 10, 20)
+    with pytest.raises(pc.PcError):
+        pc.pc_estimator(3, DD, None, RR, 10, 20)
+
+
 @pytest.mark.parametrize("args,fragment", [
     (((np.zeros(3), np.array([0.0, 91.0, 0.0])), [1.0, 2.0]), "Dec"),
     (((np.array([0.0, np.nan]), np.zeros(2)), [1.0, 2.0]), "finite"),

@@ -268,3 +268,43 @@ def test_wtheta_exact_rational_and_identities():
     c = np.array([500, 0], dtype=np.uint64)
     w = oracle.wtheta(c, np.array([1001, 0], dtype=np.uint64), c, nD, nR)
     assert w[0] == 0.0 and math.isnan(w[1])
+
+
+def _estimators_exact(DD, DR, RR, nD, nR):
+    """The four estimators in exact rational arithmetic (textbook forms)."""
+    nDD = Fraction(nD * (nD - 1), 2)
+    nDR = Fraction(nD * nR)
+    nRR = Fraction(nR * (nR - 1), 2)
+    out = {0: [], 1: [], 2: [], 3: []}
+    for a, b, c in zip(DD, DR, RR):
+        dd, dr, rr = Fraction(int(a)) / nDD, Fraction(int(b)) / nDR, Fraction(int(c)) / nRR
+        out[0].append((dd - 2 * dr + rr) / rr)
+        out[1].append(dd / rr - 1)
+        out[2].append(dd / dr - 1)
+        out[3].append(dd * rr / (dr * dr) - 1)
+    return out
+
+
+def test_estimators_exact_rational_and_zero_for_proportional_counts():
+    rng = np.random.default_rng(19)
+    nD, nR = 54_321, 700_001
+    DD = rng.integers(1, 10**10, 30).astype(np.uint64)
+    DR = rng.integers(1, 10**11, 30).astype(np.uint64)
+    RR = rng.integers(1, 10**11, 30).astype(np.uint64)
+    want = _estimators_exact(DD, DR, RR, nD, nR)
+    for kind in range(4):
+        got = oracle.estimator(kind, DD, DR, RR, nD, nR)
+        for g, wv in zip(got, want[kind]):
+            assert abs(g - float(wv)) <= 1e-13 * max(1.0, abs(float(wv))), kind
+    assert np.array_equal(oracle.estimator(0, DD, DR, RR, nD, nR), oracle.wtheta(DD, DR, RR, nD, nR))
+    # counts proportional to the pair totals (an unclustered sky) give 0 for
+    # every estimator: nD = nR = n, DD = RR = c, DR = 2cn/(n-1)
+    n = 1001
+    c = np.array([500, 1500], dtype=np.uint64)
+    dr = np.array([1001, 3003], dtype=np.uint64)
+    for kind in range(4):
+        assert np.all(oracle.estimator(kind, c, dr, c, n, n) == 0.0), kind
+    # natural ignores DR, Davis-Peebles ignores RR
+    assert np.array_equal(oracle.estimator(1, DD, None, RR, nD, nR), oracle.estimator(1, DD, DR, RR, nD, nR))
+    assert np.array_equal(oracle.estimator(2, DD, DR, None, nD, nR), oracle.estimator(2, DD, DR, RR, nD, nR))
+
