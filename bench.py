@@ -171,6 +171,8 @@ def main():
                          "as the main step")
     ap.add_argument("--no-matrix-compare", action="store_true",
                     help="skip the extra step with the matrix-core chord path")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the default launch parameters instead of tuning them on the first step")
     ap.add_argument("--workload", choices=["1m", "batched", "large", "paper"], default="1m",
                     help="1m: 1M clustered + 1M random (default); batched: 256 mocks x shared 1M random; "
                          "large: 4M + 8M full sky; paper: DR of 1M + 1M uniform, 254 log bins")
@@ -218,6 +220,13 @@ def main():
         ws = [pc.pc_wtheta(counts[a][1:-1], counts[b][1:-1], counts[r][1:-1], nd, nr) for a, b, r, nd, nr in est]
         return counts, ws
 
+    tuned = None
+    if not args.no_autotune and not (mode & pc.PC_MATRIX_CORES):
+        # choose the launch parameters on this batch (untimed; counts checked
+        # equal across all candidates), then run the steps with them
+        _, tuned = pc.pc_autotune(jobs, mode=mode, stream=stream)
+        mode |= pc.PC_TUNED
+        log(f"autotune: {tuned}")
     pc.pc_debug_set_timing(True)
     for k in range(args.warmup):
         step(mode)
@@ -244,10 +253,11 @@ def main():
         "metric": "Gpairs/s binned (DD+DR+RR) at N=1M; p50/p99 latency of served w(theta) jobs",
         "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if mode == pc.PC_FP64_PLAIN else "f32+f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if (mode & 0xFF) == pc.PC_FP64_PLAIN else "f32+f64", "data": "synthetic",
         "config": {"workload": c["name"], **c["describe"], "bins": n_bins, "jobs_per_launch": len(jobs),
                    "pairs_per_step": pairs,
-                   "mode": args.mode + ("+matrix_cores" if mode & pc.PC_MATRIX_CORES else "")},
+                   "mode": args.mode + ("+matrix_cores" if mode & pc.PC_MATRIX_CORES else "")
+                   + ("+tuned" if mode & pc.PC_TUNED else "")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": recorded_traffic(args.mode) if args.workload == "1m" else None,
@@ -258,6 +268,7 @@ def main():
                      "matrix_core_items": prn["mfma_items"],
                      "computed_gpairs_s": prn["pairs_computed"] / kern_s / 1e9},
         "pairs_binned_whole": pairs - prn["pairs_computed"],
+        "launch_tuning": tuned,
     }
     pc.pc_debug_set_timing(False)
     if args.no_prune_compare is False:
@@ -273,9 +284,12 @@ def main():
                              "roofline_frac": pairs * W / k3 / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
                              "identical_counts": all(a.tolist() == b.tolist() for a, b in zip(counts, counts3))}
         log(f"every-pair step {t1 * 1e3:.1f} ms")
-    if not args.no_matrix_compare and (mode & ~pc.PC_MATRIX_CORES) == pc.PC_MIXED:
-        # the same step with the other choice of chord path
-        other = mode ^ pc.PC_MATRIX_CORES
+    base_mode = mode & ~(pc.PC_MATRIX_CORES | pc.PC_TUNED)
+    main_mc = bool(tuned["matrix_cores"]) if tuned else bool(mode & pc.PC_MATRIX_CORES)
+    if not args.no_matrix_compare and base_mode == pc.PC_MIXED:
+        # the same step with the other choice of chord path (default launch
+        # parameters otherwise)
+        other = pc.PC_MIXED | (0 if main_mc else pc.PC_MATRIX_CORES)
         step(other)
         pc.pc_debug_set_timing(True)
         torch.cuda.synchronize()
@@ -290,7 +304,7 @@ def main():
                     "matrix_core_items": pc.pc_debug_last_pruning()["mfma_items"],
                     "identical_counts": all(a.tolist() == b.tolist() for a, b in zip(counts, counts4))}
         log(f"{key} step {t4 * 1e3:.1f} ms (kernel {k4:.1f} ms)")
-    if not args.no_fp64_compare and (mode & ~pc.PC_MATRIX_CORES) == pc.PC_MIXED:
+    if not args.no_fp64_compare and base_mode == pc.PC_MIXED:
         step(pc.PC_FP64_PLAIN)
         torch.cuda.synchronize()
         t1 = time.perf_counter()

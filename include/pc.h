@@ -57,7 +57,11 @@ enum pc_mode {
        matrix cores (the Gram form |a'|^2 + |b'|^2 - 2 a'.b' of tile-centred
        coordinates, with its own guard band); same counts.  Ignored with
        PC_FP64_PLAIN or PC_NO_PRUNE. */
-    PC_MATRIX_CORES = 0x200
+    PC_MATRIX_CORES = 0x200,
+    /* flag: use the launch parameters pc_autotune chose for a batch of this
+       shape (device, edge count class, pair count class), if there is one;
+       otherwise the defaults.  Same counts. */
+    PC_TUNED = 0x400
 };
 
 /* A catalogue of n points: RA and Dec in degrees, binary64.  Paper Sec. 2.2
@@ -163,6 +167,28 @@ enum pc_estimator_kind {
 };
 int pc_estimator(int32_t kind, const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_t n_bins,
                  int64_t nD, int64_t nR, double *w);
+
+/*
+ * pc_autotune -- time the batch (as pc_count_batch would run it in `mode`)
+ * under each candidate launch configuration -- histogram lane columns
+ * {8, 16, 32}, work items taken from the queue at a time {2, 4, 8}, matrix
+ * cores off/on (on only in PC_MIXED) -- check that every candidate gives the
+ * same counts, and remember the fastest for batches of this shape (device,
+ * ceil(log2(max n_edges)), floor(log2(pairs))); later calls with PC_TUNED use
+ * it.  Each job's counts are written as pc_count_batch writes them.
+ *   cache_path   NULL, or a file of tuned entries (one JSON object per line)
+ *                that the result is added to (created if missing).
+ *   result       NULL, or a host buffer of result_len bytes receiving a JSON
+ *                object {"cols", "chunk", "matrix_cores", "kernel_ms",
+ *                "candidates"}.
+ * Returns PC_ERR_DEVICE if two candidates disagree (a library fault).
+ */
+int pc_autotune(const pc_job *jobs, int32_t n_jobs, int32_t mode, const char *cache_path, void *stream,
+                char *result, int32_t result_len);
+
+/* pc_autotune_load -- add the tuned entries of a file written by pc_autotune
+ * (for any device) to this process's table.  Host only. */
+int pc_autotune_load(const char *cache_path);
 
 /* Thread-local description of the last error on this thread ("" if none).
  * Valid until the next pc_* call on the same thread. */

@@ -21,6 +21,7 @@ PC_OK, PC_ERR_INVALID, PC_ERR_NOMEM, PC_ERR_DEVICE, PC_ERR_BUSY, PC_ERR_CANCELLE
 PC_MIXED, PC_FP64_PLAIN = 0, 1
 PC_NO_PRUNE = 0x100
 PC_MATRIX_CORES = 0x200
+PC_TUNED = 0x400
 
 
 class PcError(RuntimeError):
@@ -60,6 +61,8 @@ _SIGNATURES = {
     "pc_chord2_edges": ([_vp, _i32, _vp], ctypes.c_int),
     "pc_guard_band": ([_vp, _i32, _vp, _vp], ctypes.c_int),
     "pc_estimator": ([_i32, _vp, _vp, _vp, _i32, _i64, _i64, _vp], ctypes.c_int),
+    "pc_autotune": ([_vp, _i32, _i32, ctypes.c_char_p, _vp, ctypes.c_char_p, _i32], ctypes.c_int),
+    "pc_autotune_load": ([ctypes.c_char_p], ctypes.c_int),
     "pc_debug_lut32": ([_vp, _i32, _vp, _vp, _i64], ctypes.c_int),
     "pc_debug_set_timing": ([_i32], ctypes.c_int),
     "pc_debug_last_launch": ([_vp, _vp, _vp, _vp], ctypes.c_int),
@@ -179,6 +182,47 @@ def pc_count_ex(A, theta_edges, B=None, auto: bool = True, mode: int = PC_MIXED,
     _check(lib().pc_count_ex(a.ref(), None if b is None else b.ref(), tp, t.size, 1 if auto else 0,
                              int(mode), int(rows[0]), int(rows[1]), out.ctypes.data, _stream(stream)))
     return out
+
+
+def _job_array(jobs, keep):
+    cats = {}
+
+    def cat(x):
+        key = id(x)
+        if key not in cats:
+            cats[key] = as_catalog(x)
+        return cats[key]
+
+    arr = (pc_job * len(jobs))()
+    outs = []
+    for q, j in enumerate(jobs):
+        a = cat(j["A"])
+        auto = bool(j.get("auto", True))
+        b = None if auto else cat(j["B"])
+        t, tp = _edges(j["edges"])
+        out = np.zeros(t.size + 1, dtype=np.uint64)
+        r0, r1 = j.get("rows", (0, -1))
+        keep += [a, b, t, out]
+        arr[q] = pc_job(ctypes.pointer(a.c), None if b is None else ctypes.pointer(b.c), tp, t.size,
+                        1 if auto else 0, int(r0), int(r1), out.ctypes.data)
+        outs.append(out)
+    return arr, outs
+
+
+def pc_autotune(jobs, mode: int = PC_MIXED, cache_path=None, stream=None):
+    """Time the batch under each candidate launch configuration, keep the
+    fastest for batches of this shape (used with PC_TUNED) and add it to
+    cache_path if given.  Returns (counts per job, chosen configuration)."""
+    keep = []
+    arr, outs = _job_array(jobs, keep)
+    buf = ctypes.create_string_buffer(1024)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().pc_autotune(arr, len(jobs), int(mode), path, _stream(stream), buf, len(buf)))
+    return outs, json.loads(buf.value.decode())
+
+
+def pc_autotune_load(cache_path) -> None:
+    _check(lib().pc_autotune_load(os.fsencode(cache_path)))
 
 
 def pc_count_batch(jobs, mode: int = PC_MIXED, stream=None):

@@ -27,7 +27,7 @@ hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st);
 hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
                         const uint64_t *items, const unsigned long long *n_items, uint64_t total_items,
                         uint32_t lut_lds_off, uint32_t stage_lds_off,
-                        unsigned long long *queue, uint32_t lds_bytes, int grid, hipStream_t st);
+                        unsigned long long *queue, int chunk, uint32_t lds_bytes, int grid, hipStream_t st);
 size_t sort_scratch_words(int64_t n);
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
                        float4 *a32s, float4 *g32s, double4 *bounds, hipStream_t st);
@@ -98,9 +98,11 @@ int device_info(DeviceInfo **out) {
 
 struct TableKey {
     int device;
+    int cols;
     std::vector<uint64_t> bits;
     bool operator<(const TableKey &o) const {
         if (device != o.device) return device < o.device;
+        if (cols != o.cols) return cols < o.cols;
         return bits < o.bits;
     }
 };
@@ -112,7 +114,7 @@ DevTable::~DevTable() {
     if (d_mem) (void)hipFree(d_mem);
 }
 
-int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *out) {
+int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *out, int cols) {
     if (!theta) return fail(PC_ERR_INVALID, "theta_edges_deg is NULL");
     if (n_edges < 2) return fail(PC_ERR_INVALID, "n_edges must be >= 2");
     DeviceInfo *di = nullptr;
@@ -120,6 +122,7 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
     if (rc) return rc;
     TableKey key;
     key.device = di->device;
+    key.cols = cols;
     key.bits.resize(static_cast<size_t>(n_edges));
     memcpy(key.bits.data(), theta, sizeof(double) * static_cast<size_t>(n_edges));
     {
@@ -132,7 +135,7 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
     }
     auto t = std::make_shared<DevTable>();
     std::string err;
-    if (!build_table(theta, n_edges, t->host, err)) return fail(PC_ERR_INVALID, err);
+    if (!build_table(theta, n_edges, t->host, err, cols)) return fail(PC_ERR_INVALID, err);
     const HostTable &h = t->host;
     // one device block: e64 | band | band_g | lut32 | lut64
     const size_t b_e = sizeof(double) * h.e64.size();
@@ -276,17 +279,33 @@ static int64_t n_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
 
 // optional per-thread timing of the counting kernel (HIP events on its stream)
 static thread_local bool t_timing = false;
+
+bool thread_timing() { return t_timing; }
+void set_thread_timing(bool on) { t_timing = on; }
 static thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
 static thread_local BatchStats t_last;
 
-int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st, BatchStats *stats) {
+int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st, BatchStats *stats,
+              const LaunchTune *tune) {
     if (jobs.empty()) return fail(PC_ERR_INVALID, "no jobs");
-    const int mode = mode_flags & ~(PC_NO_PRUNE | PC_MATRIX_CORES);
+    const int mode = mode_flags & ~(PC_NO_PRUNE | PC_MATRIX_CORES | PC_TUNED);
     const bool prune = (mode_flags & PC_NO_PRUNE) == 0;
     if (mode != PC_MIXED && mode != PC_FP64_PLAIN) return fail(PC_ERR_INVALID, "unknown mode");
     const bool fp64 = mode == PC_FP64_PLAIN;
+    // launch parameters: explicit, tuned for this shape (PC_TUNED), or defaults
+    LaunchTune lt;
+    if (tune) {
+        lt = *tune;
+    } else if (mode_flags & PC_TUNED) {
+        TuneEntry te;
+        if (tune_lookup(tune_key_of(jobs), &te) == PC_OK) lt = te.tune;
+        else lt.matrix_cores = (mode_flags & PC_MATRIX_CORES) != 0;
+    } else {
+        lt.matrix_cores = (mode_flags & PC_MATRIX_CORES) != 0;
+    }
+    if (lt.chunk < 1 || lt.chunk > 64) return fail(PC_ERR_INVALID, "work chunk must be in [1, 64]");
     // the matrix-core path needs the prune pass's marks; binary32 only
-    const bool mc = (mode_flags & PC_MATRIX_CORES) != 0 && prune && !fp64;
+    const bool mc = lt.matrix_cores && prune && !fp64;
     // host-side validation first, so bad arguments are reported as such
     for (const BatchJob &j : jobs) {
         if (j.auto_flag != 0 && j.auto_flag != 1) return fail(PC_ERR_INVALID, "auto_flag must be 0 or 1");
@@ -375,8 +394,9 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             v.resident_full = true;
         } else if (n > 0) {
             v.o_a64s = ar.take(sizeof(double4) * static_cast<size_t>(n));
-            v.o_a32s = ar.take(sizeof(float4) * static_cast<size_t>(n));
-            v.o_g32s = ar.take(sizeof(float4) * static_cast<size_t>(n));
+            // binary32 copies padded: the kernel reads a step of j-points ahead
+            v.o_a32s = ar.take(sizeof(float4) * static_cast<size_t>(n + kJPad));
+            v.o_g32s = ar.take(sizeof(float4) * static_cast<size_t>(n + kJPad));
             v.o_bounds = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(n)));
             max_sort_n = std::max(max_sort_n, n);
         }
@@ -409,7 +429,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             return fail(PC_ERR_INVALID, "row range [" + std::to_string(r0) + ", " + std::to_string(r1) +
                                             ") outside [0, " + std::to_string(nA) + "]");
         std::shared_ptr<DevTable> t;
-        rc = get_table(j.theta, j.n_edges, &t);
+        rc = get_table(j.theta, j.n_edges, &t, fp64 ? 0 : lt.cols);
         if (rc) return rc;
         auto it = tab_idx.find(t.get());
         if (it == tab_idx.end()) {
@@ -604,7 +624,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             PC_HIP(hipEventRecord(t_ev0, st), "hipEventRecord");
         }
         PC_HIP(launch_count(fp64, mc, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
-                            prune ? meta : nullptr, items, lut_off, stage_off, meta + 8, lds_bytes, grid, st),
+                            prune ? meta : nullptr, items, lut_off, stage_off, meta + 8, lt.chunk, lds_bytes, grid, st),
                "count kernel");
         if (timed) PC_HIP(hipEventRecord(t_ev1, st), "hipEventRecord");
     }
@@ -668,8 +688,8 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
     const size_t o64 = ar.take(sizeof(double4) * n);
     const size_t o32 = ar.take(sizeof(float4) * n);
     const size_t o64s = ar.take(sizeof(double4) * n);
-    const size_t o32s = ar.take(sizeof(float4) * n);
-    const size_t og32s = ar.take(sizeof(float4) * n);
+    const size_t o32s = ar.take(sizeof(float4) * (n + kJPad));  // padded as in run_batch
+    const size_t og32s = ar.take(sizeof(float4) * (n + kJPad));
     const size_t ob = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(static_cast<int64_t>(n))));
     const size_t oerr = ar.take(sizeof(int));
     const size_t osc = ar.take(sizeof(uint32_t) * sort_scratch_words(static_cast<int64_t>(n)));
@@ -728,6 +748,23 @@ int release_catalog(uint64_t h) {
 
 int resident_catalog(uint64_t h, std::shared_ptr<Resident> *out) { return get_resident(h, out); }
 
+int jobs_from_abi(const pc_job *jobs, int32_t n_jobs, std::vector<BatchJob> *out) {
+    if (!jobs || n_jobs < 1) return fail(PC_ERR_INVALID, "jobs is NULL or n_jobs < 1");
+    std::vector<BatchJob> &v = *out;
+    v.assign(static_cast<size_t>(n_jobs), BatchJob());
+    for (int32_t q = 0; q < n_jobs; ++q) {
+        v[q].A = jobs[q].A;
+        v[q].B = jobs[q].B;
+        v[q].theta = jobs[q].theta_edges_deg;
+        v[q].n_edges = jobs[q].n_edges;
+        v[q].auto_flag = jobs[q].auto_flag;
+        v[q].row_begin = jobs[q].row_begin;
+        v[q].row_end = jobs[q].row_end;
+        v[q].counts = jobs[q].counts;
+    }
+    return PC_OK;
+}
+
 }  // namespace pc
 
 // ===================================================================== C ABI
@@ -764,18 +801,9 @@ int pc_count(const pc_catalog *A, const pc_catalog *B, const double *theta_edges
 
 int pc_count_batch(const pc_job *jobs, int32_t n_jobs, int32_t mode, void *stream) {
     clear_error();
-    if (!jobs || n_jobs < 1) return fail(PC_ERR_INVALID, "jobs is NULL or n_jobs < 1");
-    std::vector<BatchJob> v(static_cast<size_t>(n_jobs));
-    for (int32_t q = 0; q < n_jobs; ++q) {
-        v[q].A = jobs[q].A;
-        v[q].B = jobs[q].B;
-        v[q].theta = jobs[q].theta_edges_deg;
-        v[q].n_edges = jobs[q].n_edges;
-        v[q].auto_flag = jobs[q].auto_flag;
-        v[q].row_begin = jobs[q].row_begin;
-        v[q].row_end = jobs[q].row_end;
-        v[q].counts = jobs[q].counts;
-    }
+    std::vector<BatchJob> v;
+    const int rc = jobs_from_abi(jobs, n_jobs, &v);
+    if (rc) return rc;
     return run_batch(v, mode, static_cast<hipStream_t>(stream), nullptr);
 }
 

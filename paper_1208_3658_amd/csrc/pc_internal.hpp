@@ -22,6 +22,7 @@ namespace pc {
 constexpr int kWave = 64;                 // gfx950 wavefront
 constexpr int kR = PC_R;                  // i-points held per lane
 constexpr int kTile = kWave * kR;         // points per tile, both axes (square tiles)
+constexpr int kJPad = 16;               // readable points past the end of an ordered binary32 copy
 constexpr int kMaxLutCells = 1024;        // per table, 16 bytes each
 constexpr uint32_t kLdsTarget = 16 * 1024;  // per-wave histogram bytes aimed for at most
 
@@ -127,8 +128,10 @@ struct HostTable {
 // Checks theta edges: 2..1024 values, finite, in [0, 180], strictly increasing.
 bool validate_edges(const double *theta_deg, int n_edges, std::string &err);
 
-// Validates theta edges; fills e64, the guard band and both cell tables.
-bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string &err);
+// Validates theta edges; fills e64, the guard bands and both cell tables.
+// cols32 > 0 fixes the mixed kernel's histogram lane columns (a power of two
+// in [8, 64]); 0 picks the widest up to PC_COLS32 within the LDS target.
+bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string &err, int cols32 = 0);
 
 // The guard band of one squared-chord edge e (binary64): binary32 lo, hi with
 //   c32 > hi  =>  c64 >= e,     c32 < lo  =>  c64 < e.

@@ -31,6 +31,7 @@ struct KParams {
     uint32_t lut_lds_off;   // byte offset of the cell table in LDS (after the histogram)
     uint32_t stage_lds_off; // byte offset of the matrix-core path's A-operand block (16 x 64 floats)
     unsigned long long *queue;  // 8 zeroed chunk counters, one per slice of the items
+    uint32_t chunk;             // items taken from the queue at a time
 };
 
 // -------------------------------------------------------------- conversion
@@ -261,20 +262,28 @@ struct TileCtx {
 #define PC_JUNROLL 2        // j-points per inner iteration
 #endif
 
+// The j-points of one step (wave-uniform, scalar loads), issued a step ahead
+// of their use.  The ordered binary32 copies are allocated kJPad points
+// longer than the catalogue, so a read-ahead past the last j-point of the
+// last tile stays inside the allocation (its values are not used).
+template <int NJ>
+__device__ __forceinline__ void load_j(const float4 *__restrict__ J, float4 (&b)[NJ]) {
+    static_assert(NJ <= kJPad, "read-ahead beyond the padding");
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) b[q] = ld_const(J + q);
+}
+
 // NJ consecutive j-points against the lane's kR i-points: all chords first,
 // then all cell-table reads, then all histogram adds, so the LDS latency of
 // NJ * kR lookups overlaps.  Slot r of lane l holds i = ibeg + r*64 + l.
 template <bool MASKED, int NJ>
-__device__ __forceinline__ void step32(unsigned char *lds, const float4 *__restrict__ Jt,
+__device__ __forceinline__ void step32(unsigned char *lds, const float4 (&b)[NJ],
                                        const double4 *__restrict__ J64t, int32_t jj,
                                        const float (&ax)[kR], const float (&ay)[kR],
                                        const float (&az)[kR], const double4 *__restrict__ I64,
                                        int64_t ibeg, int32_t i_lim, int32_t j_rel, bool diag,
                                        const TileCtx &k) {
     const int32_t lane = static_cast<int32_t>(threadIdx.x);
-    float4 b[NJ];
-#pragma unroll
-    for (int q = 0; q < NJ; ++q) b[q] = ld_const(Jt + jj + q);
     float c2[NJ][kR];
     uint32_t a[NJ][kR];
 #pragma unroll
@@ -352,11 +361,26 @@ __device__ __forceinline__ void tile32(unsigned char *lds, const float4 *__restr
                                        const float (&az)[kR], const double4 *__restrict__ I64,
                                        int64_t ibeg, int32_t i_lim, int32_t j_rel, bool diag,
                                        const TileCtx &k) {
+    constexpr int NJ = PC_JUNROLL;
     int32_t jj = 0;
-    for (; jj + PC_JUNROLL <= jn; jj += PC_JUNROLL)
-        step32<MASKED, PC_JUNROLL>(lds, Jt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
-    for (; jj < jn; ++jj)
-        step32<MASKED, 1>(lds, Jt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+    // two j buffers in turn: the next step's points load while this step runs
+    float4 b0[NJ], b1[NJ];
+    load_j<NJ>(Jt, b0);
+    for (; jj + 2 * NJ <= jn; jj += 2 * NJ) {
+        load_j<NJ>(Jt + jj + NJ, b1);
+        step32<MASKED, NJ>(lds, b0, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+        load_j<NJ>(Jt + jj + 2 * NJ, b0);
+        step32<MASKED, NJ>(lds, b1, J64t, jj + NJ, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+    }
+    if (jj + NJ <= jn) {
+        step32<MASKED, NJ>(lds, b0, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+        jj += NJ;
+    }
+    for (; jj < jn; ++jj) {
+        float4 bt[1];
+        load_j<1>(Jt + jj, bt);
+        step32<MASKED, 1>(lds, bt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+    }
 }
 
 // ------------------------------------------------------- few-edge items
@@ -433,16 +457,13 @@ __device__ __forceinline__ bool few_in_band(float c, const FewCtx &f) {
 }
 
 template <bool MASKED, int M, int NJ>
-__device__ __forceinline__ void step32_few(unsigned char *lds, const float4 *__restrict__ Jt,
+__device__ __forceinline__ void step32_few(unsigned char *lds, const float4 (&b)[NJ],
                                            const double4 *__restrict__ J64t, int32_t jj,
                                            const float (&ax)[kR], const float (&ay)[kR],
                                            const float (&az)[kR], const double4 *__restrict__ I64,
                                            int64_t ibeg, int32_t i_lim, int32_t j_rel, bool diag,
                                            const TileCtx &k, const FewCtx &f, uint32_t (&ngt)[M]) {
     const int32_t lane = static_cast<int32_t>(threadIdx.x);
-    float4 b[NJ];
-#pragma unroll
-    for (int q = 0; q < NJ; ++q) b[q] = ld_const(Jt + jj + q);
     uint64_t band = 0;
 #pragma unroll
     for (int q = 0; q < NJ; ++q)
@@ -486,11 +507,26 @@ __device__ __forceinline__ void tile32_few(unsigned char *lds, const float4 *__r
     uint32_t ngt[M];
 #pragma unroll
     for (int t = 0; t < M; ++t) ngt[t] = 0u;
+    constexpr int NJ = PC_JUNROLL;
     int32_t jj = 0;
-    for (; jj + PC_JUNROLL <= jn; jj += PC_JUNROLL)
-        step32_few<MASKED, M, PC_JUNROLL>(lds, Jt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k, f, ngt);
-    for (; jj < jn; ++jj)
-        step32_few<MASKED, M, 1>(lds, Jt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k, f, ngt);
+    // two j buffers in turn: the next step's points load while this step runs
+    float4 b0[NJ], b1[NJ];
+    load_j<NJ>(Jt, b0);
+    for (; jj + 2 * NJ <= jn; jj += 2 * NJ) {
+        load_j<NJ>(Jt + jj + NJ, b1);
+        step32_few<MASKED, M, NJ>(lds, b0, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k, f, ngt);
+        load_j<NJ>(Jt + jj + 2 * NJ, b0);
+        step32_few<MASKED, M, NJ>(lds, b1, J64t, jj + NJ, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k, f, ngt);
+    }
+    if (jj + NJ <= jn) {
+        step32_few<MASKED, M, NJ>(lds, b0, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k, f, ngt);
+        jj += NJ;
+    }
+    for (; jj < jn; ++jj) {
+        float4 bt[1];
+        load_j<1>(Jt + jj, bt);
+        step32_few<MASKED, M, 1>(lds, bt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k, f, ngt);
+    }
     // valid chords of this lane: slot r holds i = r*64 + lane; on a diagonal
     // tile only j with i < j count
     uint32_t total = 0;
@@ -519,15 +555,12 @@ __device__ __forceinline__ void tile32_few(unsigned char *lds, const float4 *__r
 // condition, at most eight roundings).  i slots past the end of the range
 // get |a'|^2 = NaN, so all their chords are NaN and count nowhere.
 template <int M, int NJ>
-__device__ __forceinline__ void step32_gram(unsigned char *lds, const float4 *__restrict__ Jg,
+__device__ __forceinline__ void step32_gram(unsigned char *lds, const float4 (&b)[NJ],
                                             const double4 *__restrict__ J64t, int32_t jj, const float (&ax)[kR],
                                             const float (&ay)[kR], const float (&az)[kR], const float (&na)[kR],
                                             const double4 *__restrict__ I64, int64_t ibeg, const TileCtx &k,
                                             const FewCtx &f, uint32_t (&ngt)[M]) {
     const int32_t lane = static_cast<int32_t>(threadIdx.x);
-    float4 b[NJ];
-#pragma unroll
-    for (int q = 0; q < NJ; ++q) b[q] = ld_const(Jg + jj + q);
     uint64_t band = 0;
 #pragma unroll
     for (int q = 0; q < NJ; ++q)
@@ -574,10 +607,26 @@ __device__ __forceinline__ void tile32_gram(unsigned char *lds, const float4 *__
     uint32_t ngt[M];
 #pragma unroll
     for (int t = 0; t < M; ++t) ngt[t] = 0u;
+    constexpr int NJ = PC_JUNROLL;
     int32_t jj = 0;
-    for (; jj + PC_JUNROLL <= jn; jj += PC_JUNROLL)
-        step32_gram<M, PC_JUNROLL>(lds, Jg, J64t, jj, ax, ay, az, na, I64, ibeg, k, f, ngt);
-    for (; jj < jn; ++jj) step32_gram<M, 1>(lds, Jg, J64t, jj, ax, ay, az, na, I64, ibeg, k, f, ngt);
+    // two j buffers in turn: the next step's points load while this step runs
+    float4 b0[NJ], b1[NJ];
+    load_j<NJ>(Jg, b0);
+    for (; jj + 2 * NJ <= jn; jj += 2 * NJ) {
+        load_j<NJ>(Jg + jj + NJ, b1);
+        step32_gram<M, NJ>(lds, b0, J64t, jj, ax, ay, az, na, I64, ibeg, k, f, ngt);
+        load_j<NJ>(Jg + jj + 2 * NJ, b0);
+        step32_gram<M, NJ>(lds, b1, J64t, jj + NJ, ax, ay, az, na, I64, ibeg, k, f, ngt);
+    }
+    if (jj + NJ <= jn) {
+        step32_gram<M, NJ>(lds, b0, J64t, jj, ax, ay, az, na, I64, ibeg, k, f, ngt);
+        jj += NJ;
+    }
+    for (; jj < jn; ++jj) {
+        float4 bt[1];
+        load_j<1>(Jg + jj, bt);
+        step32_gram<M, 1>(lds, bt, J64t, jj, ax, ay, az, na, I64, ibeg, k, f, ngt);
+    }
     few_flush<M>(lds, ngt, valid * static_cast<uint32_t>(jn), f, k);
 }
 
@@ -790,7 +839,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     // L2 sees neighbouring tiles); a wave takes kChunk items at a time from its
     // own XCD's slice, then from the others.  Waves that become resident late
     // simply find less work, so the launch ends evenly whatever the residency.
-    constexpr uint64_t kChunk = 4;
+    const uint64_t kChunk = p.chunk;
     const uint32_t x0 = b & 7u;
     uint32_t xs = 0;
     uint64_t wi = 0, end = 0;
@@ -1010,9 +1059,10 @@ hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st) {
 hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
                         const uint64_t *items, const unsigned long long *n_items, uint64_t total_items,
                         uint32_t lut_lds_off, uint32_t stage_lds_off,
-                        unsigned long long *queue, uint32_t lds_bytes, int grid, hipStream_t st) {
+                        unsigned long long *queue, int chunk, uint32_t lds_bytes, int grid, hipStream_t st) {
     KParams p;
     p.queue = queue;
+    p.chunk = static_cast<uint32_t>(chunk);
     p.segs = segs;
     p.tabs = tabs;
     p.items = items;

@@ -6,6 +6,7 @@
 
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pc.h"
@@ -38,7 +39,8 @@ struct DevTable {
     const void *d_lut64 = nullptr;
     ~DevTable();
 };
-int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *out);
+// cols: histogram lane columns of the mixed kernel's tables (0 = default)
+int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *out, int cols = 0);
 
 // A converted catalogue kept on the device.
 struct Resident {
@@ -85,9 +87,46 @@ struct BatchStats {
     uint64_t gram_items = 0;      // of the survivors, tile pairs with Gram-form chords on the vector path
 };
 
+// Launch parameters a tuner may choose (all give the same counts):
+// histogram lane columns of the mixed kernel (0 = the table's default), work
+// items taken from the queue at a time, and the matrix-core chord path.
+struct LaunchTune {
+    int cols = 0;
+    int chunk = 4;
+    bool matrix_cores = false;
+};
+
 // Runs the jobs in one persistent launch on `st` and blocks until the host
-// counts are written.
-int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, BatchStats *stats);
+// counts are written.  `tune` (may be null) overrides the launch parameters;
+// with PC_TUNED in `mode` and no `tune`, a tuned entry for the batch's shape
+// is used when one exists.
+int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, BatchStats *stats,
+              const LaunchTune *tune = nullptr);
+
+// Tuned entries: keyed by device, edge count class and pair count class.
+struct TuneKey {
+    std::string device;
+    int edges_class = 0;  // ceil(log2(max n_edges over the jobs))
+    int pairs_class = 0;  // floor(log2(pairs in the batch))
+    bool operator<(const TuneKey &o) const {
+        return std::tie(device, edges_class, pairs_class) < std::tie(o.device, o.edges_class, o.pairs_class);
+    }
+};
+struct TuneEntry {
+    LaunchTune tune;
+    double kernel_ms = 0.0;
+};
+TuneKey tune_key_of(const std::vector<BatchJob> &jobs);
+int tune_lookup(const TuneKey &k, TuneEntry *e);
+void tune_store(const TuneKey &k, const TuneEntry &e);
+int tune_load_file(const char *path);
+int tune_save_file(const char *path);
+
+// pc_job array -> BatchJob list (validates the pointer and count only)
+int jobs_from_abi(const pc_job *jobs, int32_t n_jobs, std::vector<BatchJob> *out);
+// per-thread HIP-event timing of the counting kernel (see pc_debug_set_timing)
+bool thread_timing();
+void set_thread_timing(bool on);
 
 // Landy-Szalay in binary64, fixed operation order, no contraction.
 // kind: 0 Landy-Szalay, 1 natural, 2 Davis-Peebles, 3 Hamilton (see pc.h)

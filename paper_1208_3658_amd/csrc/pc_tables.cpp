@@ -301,7 +301,7 @@ bool validate_edges(const double *theta_deg, int n_edges, std::string &err) {
     return true;
 }
 
-bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string &err) {
+bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string &err, int cols32) {
     if (!validate_edges(theta_deg, n_edges, err)) return false;
     t.theta.assign(theta_deg, theta_deg + n_edges);
     t.e64.resize(n_edges);
@@ -322,7 +322,11 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
             if (static_cast<uint64_t>(n_edges + 2) * row_bytes_for(c) <= kLdsTarget) return c;
         return 8;
     };
-    t.cols32 = pick(PC_COLS32);
+    if (cols32 != 0 && (cols32 < 8 || cols32 > 64 || (cols32 & (cols32 - 1)) != 0)) {
+        err = "histogram columns must be a power of two in [8, 64]";
+        return false;
+    }
+    t.cols32 = cols32 ? cols32 : pick(PC_COLS32);
     t.cols64 = pick(PC_COLS64);
     t.row_bytes32 = row_bytes_for(t.cols32);
     t.row_bytes64 = row_bytes_for(t.cols64);

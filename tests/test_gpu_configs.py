@@ -85,3 +85,29 @@ def test_paper_shape_254_bins_dr():
     got = pc.pc_count(dev(D), e, B=dev(R), auto=False)
     assert got.tolist() == oracle.count(D, e, B=R, auto=False).tolist()
     assert int(got.sum()) == 4000 * 4000
+
+
+def test_autotune_chooses_a_configuration_and_tuned_runs_are_exact(tmp_path):
+    """pc_autotune times every launch candidate on the batch (all must agree),
+    records the fastest in the cache file, and PC_TUNED runs use it with the
+    same exact counts."""
+    c = synth.config_small(scale=0.4)
+    D, R, e = dev(c["D"]), dev(c["R"]), c["edges"]
+    jobs = [{"A": D, "edges": e}, {"A": D, "B": R, "edges": e, "auto": False}, {"A": R, "edges": e}]
+    cache = tmp_path / "tune.jsonl"
+    counts, cfg = pc.pc_autotune(jobs, cache_path=cache)
+    assert cfg["cols"] in (8, 16, 32) and cfg["chunk"] in (2, 4, 8) and cfg["candidates"] == 18
+    assert cfg["kernel_ms"] > 0
+    want = [oracle.count(c["D"], e), oracle.count(c["D"], e, B=c["R"], auto=False), oracle.count(c["R"], e)]
+    for got, w in zip(counts, want):
+        assert got.tolist() == w.tolist()
+    tuned = pc.pc_count_batch(jobs, mode=pc.PC_MIXED | pc.PC_TUNED)
+    for got, w in zip(tuned, want):
+        assert got.tolist() == w.tolist()
+    lines = [l for l in cache.read_text().splitlines() if l.strip()]
+    assert len(lines) == 1 and '"cols": %d' % cfg["cols"] in lines[0]
+    pc.pc_autotune_load(cache)
+    # the binary64 kernel tunes its chunk only
+    counts64, cfg64 = pc.pc_autotune(jobs[:1], mode=pc.PC_FP64_PLAIN)
+    assert cfg64["candidates"] == 3 and counts64[0].tolist() == want[0].tolist()
+

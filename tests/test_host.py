@@ -172,7 +172,7 @@ def _gram_c32_variants(a64, b64, rng):
     a, or of b), rounded to binary32, c = |b'|^2 + |a'|^2 + sum_k a'_k (-2 b'_k)
     summed in several orders (one rounding at the end; a rounding after every
     product and addition, forward and backward; the vector path's fused
-    multiply-add chain)."""
+    multiply-add chain with |a'|^2 added exactly)."""
     s = np.sqrt(_c64(a64, b64))
     w = rng.normal(size=a64.shape)
     w /= np.linalg.norm(w, axis=1)[:, None]
@@ -196,12 +196,14 @@ def _gram_c32_variants(a64, b64, rng):
         for t in terms[-2::-1]:
             acc = f(acc + f(t))
         out.append(acc)
-        # the vector path's order: (|a'|^2 + |b'|^2), then fused
-        # multiply-adds of z, y, x (each product exact, one rounding each)
-        acc = f(na.astype(np.float64) + nb.astype(np.float64))
+        # the vector path's order: fused multiply-adds of z, y, x from
+        # |b'|^2 (each product exact, one rounding each), then |a'|^2 added
+        # exactly (the kernel compares the partial sum with thresholds
+        # shifted by |a'|^2)
+        acc = nb
         for k in (2, 1, 0):
             acc = f(A[:, k].astype(np.float64) * (-2.0 * B[:, k].astype(np.float64)) + acc.astype(np.float64))
-        out.append(acc)
+        out.append(na.astype(np.float64) + acc.astype(np.float64))
     return out
 
 
@@ -348,3 +350,24 @@ def test_server_config_is_validated_before_the_device():
     with pytest.raises(pc.PcError) as ex:
         pc.Server({"mode": 5})
     assert ex.value.code == pc.PC_ERR_INVALID
+
+
+def test_tuning_cache_file_is_validated(tmp_path):
+    good = tmp_path / "tune.jsonl"
+    good.write_text('{"device": "gfx950:256", "edges_class": 6, "pairs_class": 40, "cols": 16, "chunk": 4, '
+                    '"matrix_cores": 0, "kernel_ms": 70.1}\n\n'
+                    '{"device": "gfx950:256", "edges_class": 5, "pairs_class": 45, "cols": 32, "chunk": 8, '
+                    '"matrix_cores": 1, "kernel_ms": 500.0}\n')
+    pc.pc_autotune_load(good)
+    for bad in ['{"device": "x", "edges_class": 6, "pairs_class": 40, "cols": 12, "chunk": 4, "matrix_cores": 0}',
+                '{"device": "x", "edges_class": 6, "pairs_class": 40, "cols": 16, "chunk": 0, "matrix_cores": 0}',
+                '{"device": "x", "edges_class": 6, "cols": 16, "chunk": 4, "matrix_cores": 0}',
+                '{"device": "x", "edges_class": 6, "pairs_class": 40, "cols": 16, "chunk": 4, "matrix_cores": 2}']:
+        f = tmp_path / "bad.jsonl"
+        f.write_text(bad + "\n")
+        with pytest.raises(pc.PcError) as ex:
+            pc.pc_autotune_load(f)
+        assert ex.value.code == pc.PC_ERR_INVALID
+    with pytest.raises(pc.PcError):
+        pc.pc_autotune_load(tmp_path / "missing.jsonl")
+
