@@ -173,6 +173,9 @@ def main():
                     help="skip the extra step with the matrix-core chord path")
     ap.add_argument("--no-autotune", action="store_true",
                     help="run the default launch parameters instead of tuning them on the first step")
+    ap.add_argument("--tune-cache", default=None, metavar="PATH",
+                    help="tuned launch parameters: use the entries in PATH if it exists (no tuning run), "
+                         "else tune and write them there")
     ap.add_argument("--workload", choices=["1m", "batched", "large", "paper"], default="1m",
                     help="1m: 1M clustered + 1M random (default); batched: 256 mocks x shared 1M random; "
                          "large: 4M + 8M full sky; paper: DR of 1M + 1M uniform, 254 log bins")
@@ -222,9 +225,14 @@ def main():
 
     tuned = None
     if not args.no_autotune and not (mode & pc.PC_MATRIX_CORES):
-        # choose the launch parameters on this batch (untimed; counts checked
-        # equal across all candidates), then run the steps with them
-        _, tuned = pc.pc_autotune(jobs, mode=mode, stream=stream)
+        if args.tune_cache and os.path.exists(args.tune_cache):
+            pc.pc_autotune_load(args.tune_cache)
+            with open(args.tune_cache) as f:
+                tuned = {"loaded_from": args.tune_cache, "entries": [json.loads(l) for l in f if l.strip()]}
+        else:
+            # choose the launch parameters on this batch (untimed; counts
+            # checked equal across all candidates), then run the steps with them
+            _, tuned = pc.pc_autotune(jobs, mode=mode, cache_path=args.tune_cache, stream=stream)
         mode |= pc.PC_TUNED
         log(f"autotune: {tuned}")
     pc.pc_debug_set_timing(True)
@@ -285,7 +293,7 @@ def main():
                              "identical_counts": all(a.tolist() == b.tolist() for a, b in zip(counts, counts3))}
         log(f"every-pair step {t1 * 1e3:.1f} ms")
     base_mode = mode & ~(pc.PC_MATRIX_CORES | pc.PC_TUNED)
-    main_mc = bool(tuned["matrix_cores"]) if tuned else bool(mode & pc.PC_MATRIX_CORES)
+    main_mc = bool(tuned.get("matrix_cores", 0)) if tuned else bool(mode & pc.PC_MATRIX_CORES)
     if not args.no_matrix_compare and base_mode == pc.PC_MIXED:
         # the same step with the other choice of chord path (default launch
         # parameters otherwise)

@@ -31,7 +31,7 @@ hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs,
 size_t sort_scratch_words(int64_t n);
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
                        float4 *a32s, float4 *g32s, double4 *bounds, hipStream_t st);
-hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, uint64_t total_items,
+hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, int64_t total_rows,
                         uint64_t *survivors, unsigned long long *meta, int32_t mfma_ok, hipStream_t st);
 hipError_t count_occupancy(bool fp64, bool mc, uint32_t lds_bytes, int *blocks_per_cu);
 hipError_t set_max_lds(uint32_t bytes);
@@ -456,6 +456,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     // ---- segments
     std::vector<SegDesc> segs;
     uint64_t items = 0;
+    int64_t prune_rows = 0;
     auto view_n = [&](int v) { return views[v].e - views[v].b; };
     for (size_t q = 0; q < jobs.size(); ++q) {
         auto add = [&](bool tri, int vi, int vj) {
@@ -474,6 +475,9 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
                              : static_cast<uint64_t>(sd.tiles_i) * static_cast<uint64_t>(sd.tiles_j);
             sd.item0 = items;
             items += sd.n_items;
+            // rows of the prune pass (see k_prune)
+            sd.prow0 = prune_rows;
+            prune_rows += tri ? (sd.tiles_i + 1) / 2 : sd.tiles_i;
             sd.tab = plan[q].tab;
             sd.job = static_cast<int32_t>(q);
             // view indices parked in the pointer slots until the workspace exists
@@ -606,7 +610,8 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     int grid = 0;
     if (items > 0) {
         if (prune)
-            PC_HIP(launch_prune(d_segs, static_cast<int32_t>(segs.size()), d_tabs, items, surv, meta, mc ? 1 : 0, st),
+            PC_HIP(launch_prune(d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune_rows, surv, meta, mc ? 1 : 0,
+                                st),
                    "prune");
         int per_cu = 0;
         PC_HIP(count_occupancy(fp64, mc, lds_bytes, &per_cu), "occupancy");

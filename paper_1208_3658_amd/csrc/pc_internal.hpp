@@ -22,6 +22,7 @@ namespace pc {
 constexpr int kWave = 64;                 // gfx950 wavefront
 constexpr int kR = PC_R;                  // i-points held per lane
 constexpr int kTile = kWave * kR;         // points per tile, both axes (square tiles)
+constexpr int kMaxEdges = 1024;       // theta edges per table
 constexpr int kJPad = 16;               // readable points past the end of an ordered binary32 copy
 constexpr int kMaxLutCells = 1024;        // per table, 16 bytes each
 constexpr uint32_t kLdsTarget = 16 * 1024;  // per-wave histogram bytes aimed for at most
@@ -102,6 +103,7 @@ struct SegDesc {
                                       // (-2 b'_x, -2 b'_y, -2 b'_z, |b'|^2)
     int64_t i0, ni, j0, nj;
     int64_t tiles_i, tiles_j;
+    int64_t prow0;          // first row of the segment in the prune pass's row space
     int32_t tri, tab, job, pad;
     unsigned long long *counts;  // the job's n_edges+1 device counters
 };

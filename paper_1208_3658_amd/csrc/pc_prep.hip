@@ -231,17 +231,9 @@ __global__ void __launch_bounds__(kWave) k_bounds(const double4 *__restrict__ a6
 
 // ----------------------------------------------------------------- prune
 
-__device__ __forceinline__ int find_seg_p(const SegDesc *segs, int n, uint64_t item) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (segs[mid].item0 <= item) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
-__device__ __forceinline__ uint32_t count_le(const double *e, int32_t n, double c) {
+template <typename P>
+__device__ __forceinline__ uint32_t count_le(P e, int32_t n, double c) {
     int32_t lo = 0, hi = n;
     while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
@@ -251,131 +243,218 @@ __device__ __forceinline__ uint32_t count_le(const double *e, int32_t n, double 
     return static_cast<uint32_t>(lo);
 }
 
-// One thread per work item.  The chord of every pair of a tile pair lies in
-// [d - rI - rJ, d + rI + rJ] (triangle inequality in R^3, d = distance of the
-// centres); when the squared interval, widened by 1e-12 relative for the
-// rounding of these bounds and of the binary64 chord itself, sits inside one
-// bin, all the item's pairs are added to that bin here.  Other items are
-// appended to the survivor list.  Lanes adding to the same counter are summed
-// first (one atomic per distinct counter per wave).
+// The prune decision for one tile pair.  The chord of every pair of a tile
+// pair lies in [d - rI - rJ, d + rI + rJ] (triangle inequality in R^3, d =
+// distance of the centres); when the squared interval, widened by 1e-12
+// relative for the rounding of these bounds and of the binary64 chord itself,
+// sits inside one bin, all the item's pairs belong to that bin (bin >= 0).
+// Otherwise the item survives (bin = -1) with its tags: k0 = edges at or below
+// the interval, m = edges inside (kept when m <= PC_FEWCUT), and the Gram /
+// matrix-core eligibility.
+struct PruneOut {
+    int32_t bin;
+    uint64_t pairs;
+    uint64_t tags;  // bits 40..63 of the survivor entry
+};
+
+template <typename P>
+__device__ __forceinline__ PruneOut prune_item(const SegDesc &sd, int64_t t, int64_t u, P e, int32_t n_edges,
+                                               int32_t mfma_ok) {
+    PruneOut o;
+    const int64_t ni = min<int64_t>(kTile, sd.ni - t * kTile);
+    const int64_t nj = min<int64_t>(kTile, sd.nj - u * kTile);
+    const bool diag = sd.tri && t == u;
+    o.pairs = diag ? static_cast<uint64_t>(ni * (ni - 1) / 2) : static_cast<uint64_t>(ni * nj);
+    const double4 bi = sd.ib[t];
+    const double4 bj = sd.jb[u];
+    // outward-rounded bounds: distance of the centres (+-2^-45 relative),
+    // radii (+2^-45), absolute 2^-50 for the subtraction, then the squared
+    // chord interval widened by 1e-12 relative and 1e-300 absolute
+    const double dx = bi.x - bj.x, dy = bi.y - bj.y, dz = bi.z - bj.z;
+    const double d = sqrt(dx * dx + dy * dy + dz * dz);
+    const double rs = (bi.w + bj.w) * (1.0 + 0x1p-45);
+    const double lo = fmax(0.0, d * (1.0 - 0x1p-45) - rs - 0x1p-50);
+    const double hi = d * (1.0 + 0x1p-45) + rs + 0x1p-50;
+    const double c_lo = lo * lo * (1.0 - 1e-12) - 1e-300;
+    const double c_hi = hi * hi * (1.0 + 1e-12) + 1e-300;
+    const uint32_t k_lo = count_le(e, n_edges, c_lo);
+    const uint32_t k_hi = count_le(e, n_edges, c_hi);
+    if (k_lo == k_hi) {
+        o.bin = static_cast<int32_t>(k_lo);
+        o.tags = 0;
+        return o;
+    }
+    o.bin = -1;
+    // edges inside the interval: k_lo .. k_hi-1; few of them are compared one
+    // by one instead of through the cell table
+    const uint32_t m = k_hi - k_lo;
+    static_assert(PC_FEWCUT >= 1 && PC_FEWCUT <= kFewMax, "few-edge cut");
+    const bool is_few = m <= static_cast<uint32_t>(PC_FEWCUT);
+    // few-edge full tiles whose chord lower bound is at least twice the
+    // smaller bounding radius: eligible for the matrix-core path (bit 63),
+    // centred on the j-tile when that one is smaller (bit 62); otherwise the
+    // vector path forms Gram chords centred on the j-tile (bit 61) under the
+    // same condition on the j radius
+    const bool mfma = mfma_ok && is_few && !diag && ni == kTile && nj == kTile && 2.0 * fmin(bi.w, bj.w) <= lo;
+    const bool gram_j = !mfma && is_few && !diag && 2.0 * bj.w <= lo;
+    o.tags = (static_cast<uint64_t>(k_lo) << kItemBits) |
+             (static_cast<uint64_t>(is_few ? m : 0u) << (kItemBits + 11)) | (mfma ? (1ull << 63) : 0ull) |
+             ((mfma && bj.w < bi.w) ? (1ull << 62) : 0ull) | (gram_j ? (1ull << 61) : 0ull);
+    return o;
+}
+
+// (t, u) and item number of column c of prune row r (map_item's fold for a
+// triangle: row r holds (r, r..T-1) then (T-1-r, T-1-r..T-1))
+__device__ __forceinline__ bool row_item(const SegDesc &sd, int64_t r, int64_t c, int64_t &t, int64_t &u,
+                                         uint64_t &q) {
+    const int64_t T = sd.tiles_i;
+    if (sd.tri) {
+        q = static_cast<uint64_t>(r * (T + 1) + c);
+        if (c < T - r) {
+            t = r;
+            u = r + c;
+        } else {
+            t = T - 1 - r;
+            u = t + (c - (T - r));
+        }
+        return c < T + 1 && q < sd.n_items;
+    }
+    t = r;
+    u = c;
+    q = static_cast<uint64_t>(r * sd.tiles_j + c);
+    return c < sd.tiles_j;
+}
+
+// One workgroup per row of tile pairs (one i-tile, or the two i-tiles of a
+// folded triangle row), threads across its columns: (t, u) and the item
+// number come without divisions, and the edges of the row's table sit in LDS.
+// Whole tile pairs are added to an LDS histogram and survivors counted in a
+// first pass; the workgroup then reserves its survivors' slots with one global
+// atomic and writes them in a second pass (the decision is recomputed), and
+// flushes its histogram and statistics with one atomic per non-zero entry --
+// global atomics on a few shared counters would otherwise serialise the pass.
 __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs, int32_t n_segs,
-                                               const TableDesc *__restrict__ tabs, uint64_t total_items,
+                                               const TableDesc *__restrict__ tabs,
                                                uint64_t *__restrict__ survivors,
                                                unsigned long long *__restrict__ meta, int32_t mfma_ok) {
     // meta[0] = survivors, meta[1] = pairs in survivors, meta[2] = pairs binned
     // whole, meta[3] = survivors marked for the matrix cores, meta[4] =
     // survivors with at most kFewMax edges in their chord interval, meta[5] =
     // survivors whose vector-path chords are formed in Gram form
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * blockDim.x; base < total_items; base += stride) {
-        const uint64_t it = base + threadIdx.x;
-        const bool valid = it < total_items;
-        unsigned long long *dst = nullptr;
-        unsigned long long cnt = 0;
+    __shared__ double e_lds[kMaxEdges];
+    __shared__ unsigned long long h_lds[kMaxEdges + 1];
+    __shared__ unsigned long long s_stat[5];  // survivors, pairs, matrix-core, few-edge, Gram
+    __shared__ unsigned long long s_base, s_whole;
+    __shared__ unsigned int s_cursor;
+    const int64_t row_g = blockIdx.x;
+    int s = 0;  // last segment with prow0 <= row_g
+    {
+        int lo = 0, hi = n_segs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segs[mid].prow0 <= row_g) lo = mid;
+            else hi = mid - 1;
+        }
+        s = lo;
+    }
+    const SegDesc &sd = segs[s];
+    const TableDesc &td = tabs[sd.tab];
+    const int32_t n_edges = td.n_edges;
+    const int tid = static_cast<int>(threadIdx.x);
+    const int lane = tid & (kWave - 1);
+    for (int32_t k = tid; k < n_edges; k += blockDim.x) e_lds[k] = td.e64[k];
+    for (int32_t k = tid; k <= n_edges; k += blockDim.x) h_lds[k] = 0ull;
+    if (tid < 5) s_stat[tid] = 0ull;
+    if (tid == 0) {
+        s_whole = 0ull;
+        s_cursor = 0u;
+    }
+    __syncthreads();
+    const int64_t r = row_g - sd.prow0;
+    const int64_t cols = sd.tri ? sd.tiles_i + 1 : sd.tiles_j;
+
+    // pass 1: histogram of whole tile pairs, statistics of survivors
+    for (int64_t c0 = 0; c0 < cols; c0 += blockDim.x) {
+        int64_t t, u;
+        uint64_t q;
+        const bool valid = row_item(sd, r, c0 + tid, t, u, q);
         bool survive = false;
-        bool mfma = false, centre_j = false, gram_j = false;
-        uint64_t pairs = 0, few = 0;
+        uint64_t pairs = 0, tags = 0;
         if (valid) {
-            const int s = find_seg_p(segs, n_segs, it);
-            const SegDesc &sd = segs[s];
-            const uint64_t q = it - sd.item0;
-            int64_t t, u;
-            if (sd.tri) {
-                const int64_t T = sd.tiles_i;
-                const int64_t r = static_cast<int64_t>(q / static_cast<uint64_t>(T + 1));
-                const int64_t c = static_cast<int64_t>(q % static_cast<uint64_t>(T + 1));
-                if (c < T - r) { t = r; u = r + c; }
-                else { t = T - 1 - r; u = t + (c - (T - r)); }
-            } else {
-                t = static_cast<int64_t>(q / static_cast<uint64_t>(sd.tiles_j));
-                u = static_cast<int64_t>(q % static_cast<uint64_t>(sd.tiles_j));
-            }
-            const int64_t ni = min<int64_t>(kTile, sd.ni - t * kTile);
-            const int64_t nj = min<int64_t>(kTile, sd.nj - u * kTile);
-            const bool diag = sd.tri && t == u;
-            pairs = diag ? static_cast<uint64_t>(ni * (ni - 1) / 2) : static_cast<uint64_t>(ni * nj);
-            const double4 bi = sd.ib[t];
-            const double4 bj = sd.jb[u];
-            // outward-rounded bounds: distance of the centres (+-2^-45 relative),
-            // radii (+2^-45), absolute 2^-50 for the subtraction, then the squared
-            // chord interval widened by 1e-12 relative and 1e-300 absolute
-            const double dx = bi.x - bj.x, dy = bi.y - bj.y, dz = bi.z - bj.z;
-            const double d = sqrt(dx * dx + dy * dy + dz * dz);
-            const double rs = (bi.w + bj.w) * (1.0 + 0x1p-45);
-            const double lo = fmax(0.0, d * (1.0 - 0x1p-45) - rs - 0x1p-50);
-            const double hi = d * (1.0 + 0x1p-45) + rs + 0x1p-50;
-            const double c_lo = lo * lo * (1.0 - 1e-12) - 1e-300;
-            const double c_hi = hi * hi * (1.0 + 1e-12) + 1e-300;
-            const TableDesc &td = tabs[sd.tab];
-            const uint32_t k_lo = count_le(td.e64, td.n_edges, c_lo);
-            const uint32_t k_hi = count_le(td.e64, td.n_edges, c_hi);
-            if (k_lo == k_hi) {
-                dst = sd.counts + k_lo;
-                cnt = pairs;
-            } else {
+            const PruneOut o = prune_item(sd, t, u, e_lds, n_edges, mfma_ok);
+            if (o.bin >= 0) atomicAdd(&h_lds[o.bin], static_cast<unsigned long long>(o.pairs));
+            else {
                 survive = true;
-                // edges inside the interval: k_lo .. k_hi-1; few of them are
-                // compared one by one instead of through the cell table
-                const uint32_t m = k_hi - k_lo;
-                static_assert(PC_FEWCUT >= 1 && PC_FEWCUT <= kFewMax, "few-edge cut");
-                const bool is_few = m <= static_cast<uint32_t>(PC_FEWCUT);
-                few = (static_cast<uint64_t>(k_lo) << kItemBits) |
-                      (static_cast<uint64_t>(is_few ? m : 0u) << (kItemBits + 11));
-                // few-edge full tiles whose chord lower bound is at least twice
-                // the smaller bounding radius: eligible for the matrix-core path
-                // (bit 63), centred on the j-tile when that one is smaller
-                // (bit 62)
-                centre_j = bj.w < bi.w;
-                mfma = mfma_ok && is_few && !diag && ni == kTile && nj == kTile && 2.0 * fmin(bi.w, bj.w) <= lo;
-                // otherwise the vector path forms Gram chords centred on the
-                // j-tile (bit 61) under the same condition on the j radius
-                gram_j = !mfma && is_few && !diag && 2.0 * bj.w <= lo;
+                pairs = o.pairs;
+                tags = o.tags;
             }
         }
-        // survivors: one atomic per wave
         const uint64_t sm = __ballot(survive);
         if (sm) {
-            const int lane = threadIdx.x & (kWave - 1);
-            const uint64_t below = sm & ((lane == 0) ? 0ull : (~0ull >> (kWave - lane)));
-            unsigned long long at = 0;
-            if (lane == __ffsll(static_cast<long long>(sm)) - 1) {
-                at = atomicAdd(meta + 0, static_cast<unsigned long long>(__popcll(sm)));
-            }
-            at = __shfl(at, __ffsll(static_cast<long long>(sm)) - 1, kWave);
-            if (survive)
-                survivors[at + __popcll(below)] = it | few | (mfma ? (1ull << 63) : 0ull) |
-                                                  ((mfma && centre_j) ? (1ull << 62) : 0ull) |
-                                                  (gram_j ? (1ull << 61) : 0ull);
-            // pairs in survivors, and survivors for the matrix cores
             unsigned long long p = survive ? pairs : 0ull;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
-            const uint64_t mm = __ballot(survive && mfma);
-            const uint64_t mf = __ballot(survive && (few >> (kItemBits + 11)) != 0);
-            const uint64_t mg = __ballot(survive && gram_j);
+            const uint64_t mm = __ballot(survive && (tags >> 63) != 0);
+            const uint64_t mf = __ballot(survive && ((tags >> (kItemBits + 11)) & 3u) != 0);
+            const uint64_t mg = __ballot(survive && ((tags >> 61) & 1u) != 0);
             if (lane == 0) {
-                atomicAdd(meta + 1, p);
-                if (mm) atomicAdd(meta + 3, static_cast<unsigned long long>(__popcll(mm)));
-                if (mf) atomicAdd(meta + 4, static_cast<unsigned long long>(__popcll(mf)));
-                if (mg) atomicAdd(meta + 5, static_cast<unsigned long long>(__popcll(mg)));
+                atomicAdd(&s_stat[0], static_cast<unsigned long long>(__popcll(sm)));
+                atomicAdd(&s_stat[1], p);
+                atomicAdd(&s_stat[2], static_cast<unsigned long long>(__popcll(mm)));
+                atomicAdd(&s_stat[3], static_cast<unsigned long long>(__popcll(mf)));
+                atomicAdd(&s_stat[4], static_cast<unsigned long long>(__popcll(mg)));
             }
         }
-        // whole-item counts: sum lanes with equal destinations
-        uint64_t pend = __ballot(dst != nullptr);
-        while (pend) {
-            const int lead = __ffsll(static_cast<long long>(pend)) - 1;
-            const uint64_t key = __shfl(reinterpret_cast<uint64_t>(dst), lead, kWave);
-            const bool mine = dst != nullptr && reinterpret_cast<uint64_t>(dst) == key;
-            unsigned long long c = mine ? cnt : 0ull;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
-            const int lane = threadIdx.x & (kWave - 1);
-            if (lane == lead) {
-                atomicAdd(reinterpret_cast<unsigned long long *>(key), c);
-                atomicAdd(meta + 2, c);
+    }
+    __syncthreads();
+    if (tid == 0) s_base = s_stat[0] ? atomicAdd(meta + 0, s_stat[0]) : 0ull;
+    __syncthreads();
+
+    // pass 2: the survivors, written into the workgroup's reserved slots
+    if (s_stat[0]) {
+        for (int64_t c0 = 0; c0 < cols; c0 += blockDim.x) {
+            int64_t t, u;
+            uint64_t q;
+            const bool valid = row_item(sd, r, c0 + tid, t, u, q);
+            bool survive = false;
+            uint64_t tags = 0;
+            if (valid) {
+                const PruneOut o = prune_item(sd, t, u, e_lds, n_edges, mfma_ok);
+                survive = o.bin < 0;
+                tags = o.tags;
             }
-            if (mine) dst = nullptr;
-            pend = __ballot(dst != nullptr);
+            const uint64_t sm = __ballot(survive);
+            if (sm) {
+                const uint64_t below = sm & ((lane == 0) ? 0ull : (~0ull >> (kWave - lane)));
+                unsigned int at = 0;
+                if (lane == __ffsll(static_cast<long long>(sm)) - 1)
+                    at = atomicAdd(&s_cursor, static_cast<unsigned int>(__popcll(sm)));
+                at = __shfl(at, __ffsll(static_cast<long long>(sm)) - 1, kWave);
+                if (survive) survivors[s_base + at + __popcll(below)] = (sd.item0 + q) | tags;
+            }
+        }
+    }
+
+    // flush: one atomic per non-zero bin and per statistic
+    unsigned long long whole = 0;
+    for (int32_t k = tid; k <= n_edges; k += blockDim.x) {
+        const unsigned long long v = h_lds[k];
+        if (v) {
+            atomicAdd(sd.counts + k, v);
+            whole += v;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) whole += __shfl_xor(whole, o, kWave);
+    if (lane == 0 && whole) atomicAdd(&s_whole, whole);
+    __syncthreads();
+    if (tid == 0) {
+        if (s_whole) atomicAdd(meta + 2, s_whole);
+        if (s_stat[0]) {
+            atomicAdd(meta + 1, s_stat[1]);
+            if (s_stat[2]) atomicAdd(meta + 3, s_stat[2]);
+            if (s_stat[3]) atomicAdd(meta + 4, s_stat[3]);
+            if (s_stat[4]) atomicAdd(meta + 5, s_stat[4]);
         }
     }
 }
@@ -425,12 +504,12 @@ hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *sc
     return hipGetLastError();
 }
 
-hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, uint64_t total_items,
+hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, int64_t total_rows,
                         uint64_t *survivors, unsigned long long *meta, int32_t mfma_ok, hipStream_t st) {
-    if (total_items == 0) return hipSuccess;
-    const uint64_t want = (total_items + 255) / 256;
-    const uint32_t grid = static_cast<uint32_t>(want < 16384 ? want : 16384);
-    k_prune<<<dim3(grid), dim3(256), 0, st>>>(segs, n_segs, tabs, total_items, survivors, meta, mfma_ok);
+    if (total_rows <= 0) return hipSuccess;
+    if (total_rows > 0x7FFFFFFF) return hipErrorInvalidValue;
+    k_prune<<<dim3(static_cast<uint32_t>(total_rows)), dim3(256), 0, st>>>(segs, n_segs, tabs, survivors, meta,
+                                                                          mfma_ok);
     return hipGetLastError();
 }
 

@@ -283,7 +283,7 @@ bool validate_edges(const double *theta_deg, int n_edges, std::string &err) {
         err = "n_edges must be >= 2";
         return false;
     }
-    if (n_edges > 1024) {
+    if (n_edges > kMaxEdges) {
         err = "n_edges must be <= 1024";
         return false;
     }
