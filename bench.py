@@ -75,51 +75,52 @@ def cpu_baseline(c, target_s: float):
             "sample": f"DD, DR and RR over the first {r} rows of the 1M workload ({pairs:.3e} pairs, {dt:.1f} s)"}
 
 
-def serve_run(pc, torch, gpairs_s: float, n_req: int, seed_config: int = 5):
-    """Poisson stream of w(theta) requests (config: N log-uniform 1e3..2e6,
-    clustered on one of 4 pool patches of side 5-50 deg, 10-50 log bins) at
-    0.7 x the measured capacity; returns latency and throughput."""
+def serve_run(pc, n_req: int, seed_config: int = 5):
+    """Stream of w(theta) requests (config: N log-uniform 1e3..2e6, clustered
+    on one of 4 pool patches of side 5-50 deg, 10-50 log bins).  The server's
+    capacity on this stream is measured first (every request submitted at
+    once); then Poisson arrivals at 0.7 x that capacity give the latencies of
+    the mixed-precision batched server, and the same arrivals are replayed
+    against a binary64 server that runs one request per launch."""
     import numpy as np
     import synth
     from synth.catalogs import pool_random, request_catalog
     patches, reqs = synth.serve_stream(n_req, rate_hz=1.0, n_patches=4, seed_config=seed_config)
-    nR = patches[0]["n_random"]
     cats = [request_catalog(patches, r, seed_config) for r in reqs]
-    pairs = []
-    seen = set()
-    for r, cat in zip(reqs, cats):
-        n = cat[0].size
-        key = (r["patch"], r["edges"].tobytes())
-        p = n * (n - 1) / 2 + n * nR + (0 if key in seen else nR * (nR - 1) / 2)
-        seen.add(key)
-        pairs.append(p)
-    mean_pairs = float(np.mean(pairs))
-    rate = 0.7 * gpairs_s * 1e9 / mean_pairs
+    randoms = [pool_random(patches, p, seed_config) for p in range(len(patches))]
+
+    def run(arrivals, cfg):
+        srv = pc.Server(cfg)
+        for p, R in enumerate(randoms):
+            srv.set_random(p, R)
+        t0 = time.perf_counter()
+        ids = []
+        for k, (r, cat) in enumerate(zip(reqs, cats)):
+            wait = arrivals[k] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            ids.append(srv.submit(cat, r["patch"], r["edges"]))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        res = [srv.poll(j) for j in ids]
+        st = srv.stats()
+        srv.close()
+        lat = np.sort(np.array([x["latency_s"] for x in res]))
+        return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "gpairs_s": st["pairs"] / wall / 1e9, "wall_s": wall, "batches": st["batches"],
+                "rr_cached": st["rr_cached"]}, res
+
+    mixed_cfg = {"streams": 2, "max_inflight": 64}
+    closed, _ = run(np.zeros(n_req), mixed_cfg)
+    rate = 0.7 * n_req / closed["wall_s"]
     gaps = np.random.Generator(np.random.PCG64(1000 * seed_config + 4)).exponential(1.0 / rate, n_req)
     arrivals = np.cumsum(gaps)
-    srv = pc.Server({"streams": 2, "max_inflight": 64})
-    for p in range(len(patches)):
-        srv.set_random(p, pool_random(patches, p, seed_config))
-    log(f"serve: {n_req} requests at {rate:.2f}/s (0.7 x capacity), mean {mean_pairs:.3e} pairs/request")
-    t0 = time.perf_counter()
-    ids = []
-    for k, (r, cat) in enumerate(zip(reqs, cats)):
-        wait = arrivals[k] - (time.perf_counter() - t0)
-        if wait > 0:
-            time.sleep(wait)
-        ids.append(srv.submit(cat, r["patch"], r["edges"]))
-    srv.drain()
-    wall = time.perf_counter() - t0
-    lat = []
-    for jid in ids:
-        res = srv.poll(jid)
-        lat.append(res["latency_s"])
-    st = srv.stats()
-    srv.close()
-    lat = np.sort(np.array(lat))
-    return {"requests": n_req, "rate_hz": rate, "p50_s": float(np.percentile(lat, 50)),
-            "p99_s": float(np.percentile(lat, 99)), "gpairs_s": st["pairs"] / wall / 1e9,
-            "wall_s": wall, "batches": st["batches"], "rr_cached": st["rr_cached"]}
+    log(f"serve: capacity {n_req / closed['wall_s']:.2f} requests/s on this stream; Poisson at {rate:.2f}/s")
+    mixed, res_m = run(arrivals, mixed_cfg)
+    single64, res_f = run(arrivals, {"streams": 1, "max_inflight": 64, "max_batch_pairs": 1, "mode": pc.PC_FP64_PLAIN})
+    same = all(a[k].tolist() == b[k].tolist() for a, b in zip(res_m, res_f) for k in ("DD", "DR", "RR"))
+    return {"requests": n_req, "rate_hz": rate, "capacity_rps": n_req / closed["wall_s"], **mixed,
+            "fp64_one_request_per_launch": single64, "identical_counts": same}
 
 
 def build_workload(name, torch, pc):
@@ -332,8 +333,10 @@ def main():
                                    "identical_counts": all(a.tolist() == b.tolist() for a, b in zip(counts, single))}
         log(f"one launch per job: {t1 * 1e3:.1f} ms")
     if args.serve_requests > 0 and args.workload == "1m":
-        out["serve"] = serve_run(pc, torch, value, args.serve_requests)
-        log(f"serve: p50 {out['serve']['p50_s']:.3f} s, p99 {out['serve']['p99_s']:.3f} s")
+        out["serve"] = serve_run(pc, args.serve_requests)
+        log(f"serve: p50 {out['serve']['p50_s']:.3f} s, p99 {out['serve']['p99_s']:.3f} s; binary64 one per launch: "
+            f"p50 {out['serve']['fp64_one_request_per_launch']['p50_s']:.3f} s, "
+            f"p99 {out['serve']['fp64_one_request_per_launch']['p99_s']:.3f} s")
     if not args.no_cpu_baseline and args.workload == "1m":
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds)
