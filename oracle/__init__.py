@@ -17,12 +17,14 @@ _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
 _dp = ctypes.POINTER(ctypes.c_double)
 _up = ctypes.POINTER(ctypes.c_uint64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        srcs = [os.path.join(os.path.dirname(LIB), f) for f in ("pc_oracle.c", "ap_oracle.c")]
+        if not os.path.exists(LIB) or any(os.path.getmtime(f) > os.path.getmtime(LIB) for f in srcs):
             build()
         L = ctypes.CDLL(LIB)
         L.oracle_sincosd.argtypes = [ctypes.c_double, _dp, _dp]
@@ -39,6 +41,15 @@ def lib():
         L.oracle_wtheta.restype = None
         L.oracle_estimator.argtypes = [_i32, _up, _up, _up, _i32, _i64, _i64, _dp]
         L.oracle_estimator.restype = None
+        L.oracle_q_nfw.argtypes = [ctypes.c_double]
+        L.oracle_q_nfw.restype = ctypes.c_double
+        L.oracle_aperture_points.argtypes = [_i64, _dp, _dp, _dp, _dp, _i64, _dp, _dp, ctypes.c_double,
+                                             ctypes.c_double, _dp, _dp, _u32p, _dp]
+        L.oracle_aperture_points.restype = None
+        L.oracle_aperture_grid.argtypes = [_i64, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, _i32, _i32, ctypes.c_double,
+                                           ctypes.c_double, _dp, _dp, _u32p, _dp]
+        L.oracle_aperture_grid.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -134,6 +145,50 @@ def estimator(kind: int, DD, DR, RR, nD: int, nR: int) -> np.ndarray:
     out = np.empty(DD.size, dtype=np.float64)
     lib().oracle_estimator(int(kind), p1, p2, p3, DD.size, int(nD), int(nR), out.ctypes.data_as(_dp))
     return out
+
+
+def q_nfw(x: float) -> float:
+    """Eq. 4 filter at x = theta / theta_max."""
+    return lib().oracle_q_nfw(float(x))
+
+
+def _ap_out(m):
+    out = {"map": np.empty(m), "snr": np.empty(m), "n_in": np.empty(m, dtype=np.uint32),
+           "sums": np.empty((m, 3))}
+    ptrs = (out["map"].ctypes.data_as(_dp), out["snr"].ctypes.data_as(_dp),
+            out["n_in"].ctypes.data_as(_u32p), out["sums"].ctypes.data_as(_dp))
+    return out, ptrs
+
+
+def _ap_unpack(out):
+    s = out.pop("sums")
+    out["s1"], out["s2"], out["qe_abs"] = s[:, 0].copy(), s[:, 1].copy(), s[:, 2].copy()
+    return out
+
+
+def aperture_points(cat, px, py, theta_max: float, n_gal: float) -> dict:
+    """Aperture mass (Eq. 3) and SNR (Eq. 5) at the points (px, py) for the
+    shear catalogue cat = (x, y, e1, e2).  Returns map, snr, n_in and the raw
+    sums s1 = sum Q eps_t, s2 = sum Q^2 |eps|^2, qe_abs = sum Q |eps|."""
+    (x, p0), (y, p1), (e1, p2), (e2, p3) = (_d(a) for a in cat)
+    px, pp = _d(px)
+    py, pq = _d(py)
+    out, ptrs = _ap_out(px.size)
+    lib().oracle_aperture_points(x.size, p0, p1, p2, p3, px.size, pp, pq, float(theta_max), float(n_gal), *ptrs)
+    return _ap_unpack(out)
+
+
+def aperture_grid(cat, grid, theta_max: float, n_gal: float) -> dict:
+    """The same on grid = (x0, y0, dx, dy, nx, ny): point (ix, iy) at
+    (x0 + ix*dx, y0 + iy*dy), flattened row-major (index iy*nx + ix)."""
+    (x, p0), (y, p1), (e1, p2), (e2, p3) = (_d(a) for a in cat)
+    x0, y0, dx, dy, nx, ny = grid
+    out, ptrs = _ap_out(int(nx) * int(ny))
+    rc = lib().oracle_aperture_grid(x.size, p0, p1, p2, p3, float(x0), float(y0), float(dx), float(dy),
+                                    int(nx), int(ny), float(theta_max), float(n_gal), *ptrs)
+    if rc != 0:
+        raise MemoryError("oracle_aperture_grid: out of memory")
+    return _ap_unpack(out)
 
 
 def num_threads() -> int:

@@ -1,4 +1,5 @@
-"""Compile the CPU oracle into oracle/libpc_oracle.so (test infrastructure).
+"""Compile the CPU oracle into oracle/libpc_oracle.so (test infrastructure):
+pair counting (pc_oracle.c) and aperture-mass maps (ap_oracle.c).
 
 Flags: binary64 throughout, no fused multiply-add (-ffp-contract=off; GCC's
 default for GNU C would contract), no fast-math, SSE2 arithmetic (x86-64
@@ -9,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "pc_oracle.c")
+SRCS = [os.path.join(HERE, "pc_oracle.c"), os.path.join(HERE, "ap_oracle.c")]
 LIB = os.path.join(HERE, "libpc_oracle.so")
 
 FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
@@ -17,7 +18,7 @@ FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", *FLAGS, SRC, "-o", LIB + ".tmp", "-lm"]
+    cmd = ["gcc", *FLAGS, *SRCS, "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
