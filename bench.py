@@ -8,6 +8,11 @@ sigma 0.05 deg) and 1,000,000 area-uniform randoms on a 100 x 100 deg patch,
 A step = one batched launch counting DD, DR and RR (1,999,999,000,000 pairs)
 from float64 RA/Dec already resident in device memory, plus w(theta).
 
+--workload aperture times the paper's second workload instead (Sec. 3):
+aperture-mass and SNR maps of 10^6 synthetic galaxies at 35 per square
+arcmin on a 2048 x 2048 grid with a 32 arcmin NFW filter, plus the other
+grid sizes and filter radii of the paper's Table 2.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
@@ -46,6 +51,116 @@ def recorded_traffic(mode: str):
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     return r["traffic_bytes_per_launch"] if r.get("kernel_source_sha256") == sha else None
+
+
+# Aperture mass (Sec. 3): algorithmic flops per galaxy-point pair inside the
+# aperture, each elementary function counted as one operation: separation 5
+# (2 sub, 2 mul, 1 add), cut 1, x = sqrt(d2)/theta 2, Eq. 4 13 (two
+# exponentials with their arguments 6, 1 + a + b 2, reciprocal 1,
+# tanh(u)/u with u = x/0.15 3, product 1), tangential ellipticity 8
+# (cos 2phi 2, sin 2phi 3, e1 c + e2 s 3), sums 5 (Q eps_t and its add 2,
+# Q^2 |eps|^2 and its add 3).
+AP_FLOPS_PER_PAIR = 34
+AP_GRIDS = (512, 1024, 2048)
+AP_THETAS = (2.0, 4.0, 8.0, 16.0, 32.0)
+# Table 2 of the paper: seconds per map on a Tesla M2070 (data transfer
+# included) and on one CPU core; context only (other hardware).
+AP_PAPER_GPU_S = {512: (11, 12, 15, 23, 45), 1024: (38, 41, 50, 78, 162), 2048: (143, 156, 190, 297, 627)}
+AP_PAPER_CPU_S = {512: (558, 781, 1478, 4108, 12794), 1024: (2105, 2627, 5204, 15311, 48474),
+                  2048: (8855, 11941, 22546, 61406, 189861)}
+
+
+def aperture_main(args):
+    import numpy as np
+    import torch
+    import synth
+    import paper_1208_3658_amd as pc
+
+    torch.cuda.set_device(0)
+    log("generating the shear catalogue (10^6 galaxies)")
+    cat, side = synth.config_aperture()
+    dcat = tuple(torch.from_numpy(a).cuda() for a in cat)
+    stream = torch.cuda.current_stream()
+    outs = {}
+
+    def run(grid_n, theta):
+        m = grid_n * grid_n
+        if grid_n not in outs:
+            outs[grid_n] = {"map": torch.empty(m, dtype=torch.float64, device="cuda"),
+                            "snr": torch.empty(m, dtype=torch.float64, device="cuda"),
+                            "n_in": torch.empty(m, dtype=torch.int32, device="cuda")}
+        pc.pc_aperture_mass(dcat, synth.field_grid(side, grid_n), theta, synth.PAPER_DENSITY, out=outs[grid_n],
+                            stream=stream)
+        return pc.pc_debug_last_aperture()
+
+    G, TH = 2048, 32.0
+    pc.pc_debug_set_timing(True)
+    for k in range(args.warmup):
+        run(G, TH)
+        log(f"warmup {k + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    kern = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        info = run(G, TH)
+        kern.append(info["kernel_ms"])
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pairs = info["pairs_in"]
+    kern_s = float(np.mean(kern)) / 1e3
+    achieved = pairs * AP_FLOPS_PER_PAIR / kern_s / 1e12
+    table = []
+    for gn in AP_GRIDS:
+        for ti, th in enumerate(AP_THETAS):
+            run(gn, th)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            inf = run(gn, th)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter() - t1
+            table.append({"grid": gn, "theta_arcmin": th, "ms": t1 * 1e3, "kernel_ms": inf["kernel_ms"],
+                          "pairs_in": inf["pairs_in"], "pairs_tested": inf["pairs_tested"],
+                          "roofline_frac": inf["pairs_in"] * AP_FLOPS_PER_PAIR / (inf["kernel_ms"] / 1e3) / 1e12
+                          / PEAK_FP32_VECTOR_TFLOPS,
+                          "paper_m2070_s": AP_PAPER_GPU_S[gn][ti], "paper_cpu_core_s": AP_PAPER_CPU_S[gn][ti]})
+            log(f"grid {gn}^2 theta {th}': {t1 * 1e3:.2f} ms (kernel {inf['kernel_ms']:.2f} ms)")
+    pc.pc_debug_set_timing(False)
+    out = {
+        "metric": "aperture-mass map: galaxy-point pairs inside the filter radius per second",
+        "value": pairs * args.steps / dt / 1e9, "unit": "Gpairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "shear_1M_35_per_arcmin2_grid2048_theta32arcmin", "galaxies": int(cat[0].size),
+                   "field_arcmin": side, "grid": [G, G], "theta_max_arcmin": TH, "filter": "NFW (Eq. 4)",
+                   "pairs_in_aperture": pairs},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None, "kernel_ms": kern_s * 1e3,
+                     "work_per_pair": AP_FLOPS_PER_PAIR, "pairs_tested": info["pairs_tested"],
+                     "cell_side_arcmin": info["cell_side"]},
+        "table": table,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline (oracle)")
+        g = synth.field_grid(side, G)
+        rng = np.random.default_rng(18)
+        npts, spent, pin = 8, 0.0, 0
+        while True:
+            pick = rng.integers(0, G * G, npts)
+            t = time.perf_counter()
+            r = oracle.aperture_points(cat, g[0] + (pick % G) * g[2], g[1] + (pick // G) * g[3], TH,
+                                       synth.PAPER_DENSITY)
+            spent = time.perf_counter() - t
+            pin = int(r["n_in"].sum())
+            if spent >= 0.6 * args.cpu_seconds or npts >= 4096:
+                break
+            npts = max(npts + 1, min(4096, int(npts * args.cpu_seconds / max(spent, 1e-3))))
+        out["cpu_baseline"] = {"value": pin / spent / 1e9, "unit": "Gpairs/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{npts} seeded points of the {G}^2 x {TH:g}' map, each against all "
+                                         f"{cat[0].size} galaxies ({pin:.3e} pairs inside, {spent:.1f} s)"}
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(c, target_s: float):
@@ -177,9 +292,10 @@ def main():
     ap.add_argument("--tune-cache", default=None, metavar="PATH",
                     help="tuned launch parameters: use the entries in PATH if it exists (no tuning run), "
                          "else tune and write them there")
-    ap.add_argument("--workload", choices=["1m", "batched", "large", "paper"], default="1m",
+    ap.add_argument("--workload", choices=["1m", "batched", "large", "paper", "aperture"], default="1m",
                     help="1m: 1M clustered + 1M random (default); batched: 256 mocks x shared 1M random; "
-                         "large: 4M + 8M full sky; paper: DR of 1M + 1M uniform, 254 log bins")
+                         "large: 4M + 8M full sky; paper: DR of 1M + 1M uniform, 254 log bins; "
+                         "aperture: aperture-mass maps of 1M galaxies (Sec. 3)")
     ap.add_argument("--per-job-launches", action="store_true",
                     help="also time the same jobs with one launch each")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -196,6 +312,10 @@ def main():
               "tile-pair ranges would split across GPUs with one all-reduce of the histograms",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "aperture":
+        aperture_main(args)
+        return
 
     import numpy as np
     import torch

@@ -42,12 +42,27 @@ class pc_job(ctypes.Structure):
                 ("row_end", ctypes.c_int64), ("counts", ctypes.c_void_p)]
 
 
+class pc_shear_catalog(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("e1", ctypes.c_void_p), ("e2", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("on_device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pc_grid(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
 _lib = None
 
 _i32, _i64, _u64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
 _PCAT = ctypes.POINTER(pc_catalog)
 
 _SIGNATURES = {
+    "pc_aperture_mass": ([ctypes.POINTER(pc_shear_catalog), ctypes.POINTER(pc_grid), ctypes.c_double, ctypes.c_double,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p],
+                         ctypes.c_int),
+    "pc_debug_last_aperture": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
+                                ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "pc_count": ([_PCAT, _PCAT, _vp, _i32, _i32, _vp, _vp], ctypes.c_int),
     "pc_count_ex": ([_PCAT, _PCAT, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp], ctypes.c_int),
     "pc_count_batch": ([ctypes.POINTER(pc_job), _i32, _i32, _vp], ctypes.c_int),
@@ -78,6 +93,19 @@ _SIGNATURES = {
 }
 
 
+def _torch_runtime_first():
+    """PyTorch ships its own HIP runtime beside the system one libpc.so links.
+    Both can drive the GPU in one process, but only when PyTorch's starts
+    first (the other order leaves PyTorch without a device), so initialise it
+    before loading the library whenever PyTorch and a GPU are present."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def lib():
     """The loaded libpc.so.  Raises ImportError when it has not been built:
     there is no fallback implementation."""
@@ -86,6 +114,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1208_3658_amd.build` "
                               "(or __graft_entry__.build()); there is no CPU fallback")
+        _torch_runtime_first()
         L = ctypes.CDLL(LIB_PATH)
         for name, (argt, rest) in _SIGNATURES.items():
             f = getattr(L, name)
@@ -364,6 +393,63 @@ def pc_debug_last_pruning() -> dict:
                                        ctypes.byref(few), ctypes.byref(gram)))
     return {"survivors": int(surv.value), "pairs_computed": int(comp.value), "pairs_total": int(tot.value),
             "mfma_items": int(mf.value), "few_items": int(few.value), "gram_items": int(gram.value)}
+
+
+# ------------------------------------------------------------ aperture mass
+
+def pc_aperture_mass(cat, grid, theta_max: float, n_gal: float, out=None, stream=None) -> dict:
+    """Aperture mass (Eq. 3), SNR (Eq. 5) and aperture occupancy on a grid
+    (include/pc_aperture.h).  cat = (x, y, e1, e2): float64 torch CUDA
+    tensors (device catalogue) or arrays (host).  grid = (x0, y0, dx, dy, nx,
+    ny): point (ix, iy) at (x0 + ix*dx, y0 + iy*dy), index iy*nx + ix.
+    out = None: returns numpy arrays {map, snr, n_in}; otherwise a dict of
+    contiguous torch CUDA tensors map (float64), snr (float64 or None) and
+    n_in (int32 or None) of nx*ny entries, written on the device."""
+    x, y, e1, e2 = cat
+    if _is_torch(x) and x.is_cuda:
+        arrs = [a.contiguous() for a in (x, y, e1, e2)]
+        if any(str(a.dtype) != "torch.float64" or not a.is_cuda for a in arrs):
+            raise TypeError("shear catalogue tensors must be float64 CUDA tensors")
+        on_dev = 1
+        ptrs = [a.data_ptr() for a in arrs]
+    else:
+        arrs = [np.ascontiguousarray(a.numpy() if _is_torch(a) else a, dtype=np.float64) for a in (x, y, e1, e2)]
+        on_dev = 0
+        ptrs = [a.ctypes.data for a in arrs]
+    n = arrs[0].numel() if on_dev else arrs[0].size
+    for a in arrs[1:]:
+        if (a.numel() if on_dev else a.size) != n:
+            raise ValueError("x, y, e1 and e2 differ in length")
+    c = pc_shear_catalog(*ptrs, n, on_dev, 0)
+    x0, y0, dx, dy, nx, ny = grid
+    g = pc_grid(float(x0), float(y0), float(dx), float(dy), int(nx), int(ny))
+    m = int(nx) * int(ny)
+    if out is None:
+        alloc = m if 0 <= m < 2 ** 31 else 1  # sizes out of range are the library's to reject
+        res = {"map": np.empty(alloc), "snr": np.empty(alloc), "n_in": np.empty(alloc, dtype=np.uint32)}
+        _check(lib().pc_aperture_mass(ctypes.byref(c), ctypes.byref(g), float(theta_max), float(n_gal),
+                                      res["map"].ctypes.data, res["snr"].ctypes.data, res["n_in"].ctypes.data, 0,
+                                      _stream(stream)))
+        return res
+    ptr = lambda k: out[k].data_ptr() if out.get(k) is not None else None
+    for k, dt, sz in (("map", "torch.float64", 8), ("snr", "torch.float64", 8), ("n_in", "torch.int32", 4)):
+        t = out.get(k)
+        if t is not None and (str(t.dtype) != dt or not t.is_cuda or not t.is_contiguous() or t.numel() != m):
+            raise TypeError(f"out[{k!r}] must be a contiguous {dt} CUDA tensor of {m} entries")
+    _check(lib().pc_aperture_mass(ctypes.byref(c), ctypes.byref(g), float(theta_max), float(n_gal), ptr("map"),
+                                  ptr("snr"), ptr("n_in"), 1, _stream(stream)))
+    return out
+
+
+def pc_debug_last_aperture() -> dict:
+    ms = ctypes.c_double(0)
+    tested = ctypes.c_uint64(0)
+    inside = ctypes.c_uint64(0)
+    cell = ctypes.c_double(0)
+    _check(lib().pc_debug_last_aperture(ctypes.byref(ms), ctypes.byref(tested), ctypes.byref(inside),
+                                        ctypes.byref(cell)))
+    return {"kernel_ms": ms.value, "pairs_tested": int(tested.value), "pairs_in": int(inside.value),
+            "cell_side": cell.value}
 
 
 # ------------------------------------------------------------------ serving

@@ -1,0 +1,523 @@
+// pc_aperture.hip -- aperture-mass maps (Sec. 3, Eq. 3-5) on gfx950.
+//
+// The paper's GPU method gives each reconstruction point its own thread,
+// which loops over the galaxies near that point.  Here a wavefront owns an
+// 8 x 8 block of grid points (one per lane) and streams the galaxies near the
+// block through scalar loads: every galaxy is wave-uniform, so it reaches all
+// 64 lanes from SGPRs with no LDS and no vector memory traffic.  Galaxies are
+// first ordered by the cell of a square search lattice; the galaxies a block
+// can see lie, row of cells by row of cells, in one contiguous range each,
+// trimmed to the filter disc around the block.
+//
+// Arithmetic per (point, galaxy) pair:
+//   - the aperture cut in binary64, exactly as the definition states it
+//     (dx, dy, |d|^2 = dx*dx + dy*dy, 0 < |d|^2 < theta_max^2, no fused
+//     multiply-add), so the set of galaxies in each aperture is exact;
+//   - for galaxies inside, the filter Q (Eq. 4) and the tangential
+//     ellipticity in binary32 from dx, dy rounded to binary32: one
+//     reciprocal square root, three base-2 exponentials and one reciprocal;
+//   - the products Q eps_t and Q^2 |eps|^2 summed in binary32 over at most 64
+//     galaxies and then in binary64.
+#include <float.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pc_aperture.h"
+#include "pc_runtime.hpp"
+
+namespace pc {
+
+hipError_t launch_zero_u32(uint32_t *p, int64_t m, hipStream_t st);
+hipError_t launch_exclusive_scan(uint32_t *a, int64_t m, uint32_t *sums, hipStream_t st);
+size_t scan_sums_words(int64_t m);
+
+namespace {
+
+constexpr int kApSide = 8;             // grid points per wave along each axis
+constexpr int kApFlush = 64;           // galaxies summed in binary32 before the binary64 add
+constexpr uint32_t kNoCell = 0xFFFFFFFFu;
+constexpr int64_t kMaxCells = int64_t(1) << 22;
+
+// One galaxy as the map kernel reads it (32 bytes, one scalar load).
+struct alignas(32) ApGal {
+    double x, y;  // position
+    float a;      // -e1
+    float b;      // -2 e2
+    float ee;     // e1^2 + e2^2 (binary64, rounded once)
+    float pad;
+};
+
+// Square search lattice: cell (cx, cy) covers [ox + cx s, ox + (cx+1) s) x ...
+struct Lattice {
+    double ox, oy;
+    double s, inv_s;
+    int32_t ncx, ncy;
+};
+
+struct ApParams {
+    const ApGal *gal;
+    const uint32_t *start;  // ncx * ncy + 1 cell starts
+    Lattice lat;
+    double x0, y0, gdx, gdy;
+    int32_t nx, ny, tiles_x, n_tiles, per_xcd;
+    double theta;     // filter radius
+    double r2;        // theta^2 (binary64), the cut
+    double reach;     // theta with a relative margin for the cell search
+    float k_a, c_a;   // exp(6 - 150 x)  = 2^(k_a r + c_a), x = r / theta
+    float k_b, c_b;   // exp(-47 + 50 x) = 2^(k_b r + c_b)
+    float k_e;        // exp(2u) = 2^(k_e r), u = x / 0.15
+    float k_u;        // u = k_u r
+    double n_gal;
+    double *map;
+    double *snr;
+    uint32_t *n_in;
+    unsigned long long *stats;  // [pairs tested, pairs inside]
+};
+
+__device__ __forceinline__ int32_t cell_index(double v, double o, double inv_s, int32_t n) {
+    const double t = floor((v - o) * inv_s);
+    if (!(t >= 0.0)) return 0;
+    return t >= static_cast<double>(n) ? n - 1 : static_cast<int32_t>(t);
+}
+
+// ----------------------------------------------------------- cell ordering
+
+__global__ void __launch_bounds__(256) k_ap_keys(const double *__restrict__ X, const double *__restrict__ Y,
+                                                 const double *__restrict__ E1, const double *__restrict__ E2,
+                                                 int64_t n, Lattice lat, uint32_t *__restrict__ keys,
+                                                 uint32_t *__restrict__ count, uint32_t *__restrict__ flag) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = X[i], y = Y[i], e1 = E1[i], e2 = E2[i];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(e1) || !isfinite(e2)) {
+        atomicOr(flag, 1u);
+        keys[i] = kNoCell;
+        return;
+    }
+    const double tx = (x - lat.ox) * lat.inv_s;
+    const double ty = (y - lat.oy) * lat.inv_s;
+    // outside the lattice: farther than theta_max + one cell from every grid point
+    if (!(tx >= 0.0 && tx < static_cast<double>(lat.ncx) && ty >= 0.0 && ty < static_cast<double>(lat.ncy))) {
+        keys[i] = kNoCell;
+        return;
+    }
+    const uint32_t key = static_cast<uint32_t>(static_cast<int32_t>(floor(ty))) * static_cast<uint32_t>(lat.ncx) +
+                         static_cast<uint32_t>(static_cast<int32_t>(floor(tx)));
+    keys[i] = key;
+    atomicAdd(count + key, 1u);
+}
+
+__global__ void __launch_bounds__(256) k_ap_scatter(const uint32_t *__restrict__ keys, int64_t n,
+                                                    uint32_t *__restrict__ cursor, uint32_t *__restrict__ idx) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t key = keys[i];
+    if (key == kNoCell) return;
+    idx[atomicAdd(cursor + key, 1u)] = static_cast<uint32_t>(i);
+}
+
+// The scatter leaves each cell's galaxies in arbitrary order; place each one
+// at its rank by catalogue index inside the cell, so the summation order of
+// the map kernel, and with it every output bit, is reproducible.
+__global__ void __launch_bounds__(256) k_ap_place(const double *__restrict__ X, const double *__restrict__ Y,
+                                                  const double *__restrict__ E1, const double *__restrict__ E2,
+                                                  const uint32_t *__restrict__ keys, const uint32_t *__restrict__ idx,
+                                                  const uint32_t *__restrict__ start, int64_t n_cells, int64_t n,
+                                                  ApGal *__restrict__ gal) {
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n || p >= static_cast<int64_t>(start[n_cells])) return;
+    const uint32_t i = idx[p];
+    const uint32_t key = keys[i];
+    const uint32_t lo = start[key], hi = start[key + 1];
+    uint32_t rank = 0;
+    for (uint32_t q = lo; q < hi; ++q) rank += idx[q] < i ? 1u : 0u;
+    const double e1 = E1[i], e2 = E2[i];
+    ApGal g;
+    g.x = X[i];
+    g.y = Y[i];
+    g.a = static_cast<float>(-e1);
+    g.b = static_cast<float>(-2.0 * e2);
+    g.ee = static_cast<float>(e1 * e1 + e2 * e2);
+    g.pad = 0.0f;
+    gal[lo + rank] = g;
+}
+
+// ------------------------------------------------------------------ map
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Filter constants held in VGPRs (an instruction reads at most one SGPR).
+struct ApConsts {
+    float k_a, c_a, k_b, c_b, k_e, k_u;
+};
+
+// One (grid point, galaxy) pair: the exact cut, then Eq. 4 and the
+// tangential ellipticity, accumulated into the binary32 partial sums.
+__device__ __forceinline__ void ap_pair(const ApGal &G, double xg, double yg, double r2, const ApConsts &K,
+                                        uint32_t &cnt, float &a1, float &a2) {
+    const double ddx = G.x - xg;
+    const double ddy = G.y - yg;
+    const double d2 = ddx * ddx + ddy * ddy;
+    if (d2 < r2 && d2 > 0.0) {
+        cnt += 1u;
+        const float fx = static_cast<float>(ddx), fy = static_cast<float>(ddy);
+        const float f2 = fmaxf(static_cast<float>(d2), FLT_MIN);
+        const float rinv = __builtin_amdgcn_rsqf(f2);
+        const float r = f2 * rinv;
+        const float ea = __builtin_amdgcn_exp2f(fmaf(r, K.k_a, K.c_a));
+        const float eb = __builtin_amdgcn_exp2f(fmaf(r, K.k_b, K.c_b));
+        const float e2u = __builtin_amdgcn_exp2f(r * K.k_e);
+        const float u = r * K.k_u;
+        const float D = (1.0f + ea) + eb;
+        // tanh(u)/u = (e^2u - 1) / ((e^2u + 1) u); near u = 0 its series
+        // 1 - u^2/3 + 2u^4/15 (next term below 4e-9 there)
+        float num = e2u - 1.0f;
+        float den = ((e2u + 1.0f) * u) * D;
+        if (u < 0.0625f) {
+            const float u2 = u * u;
+            num = fmaf(u2, fmaf(u2, 0.133333333f, -0.333333333f), 1.0f);
+            den = D;
+        }
+        const float q = num * __builtin_amdgcn_rcpf(den);
+        // cos 2phi and sin 2phi from the unit direction
+        const float ux = fx * rinv, uy = fy * rinv;
+        const float c2 = fmaf(-uy, uy, ux * ux);
+        const float s2 = ux * uy;
+        const float et = fmaf(G.a, c2, G.b * s2);
+        a1 = fmaf(q, et, a1);
+        a2 = fmaf(q * q, G.ee, a2);
+    }
+}
+
+// One wave per 8 x 8 block of grid points.  Blocks are dealt to the eight
+// XCDs in contiguous strips (the hardware assigns workgroup b to XCD b mod 8),
+// so neighbouring blocks, which read mostly the same galaxies, share an L2.
+__global__ void __launch_bounds__(64) k_ap_map(const ApParams p) {
+    const int lane = static_cast<int>(threadIdx.x);
+    const int b = static_cast<int>(blockIdx.x);
+    const int tile = (b & 7) * p.per_xcd + (b >> 3);
+    if (tile >= p.n_tiles) return;
+    const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+    const int ix0 = tx * kApSide, iy0 = ty * kApSide;
+    const int ix1 = min(ix0 + kApSide - 1, p.nx - 1), iy1 = min(iy0 + kApSide - 1, p.ny - 1);
+    const int ixl = ix0 + (lane & (kApSide - 1)), iyl = iy0 + lane / kApSide;
+    const bool valid = ixl <= ix1 && iyl <= iy1;
+    const int ix = min(ixl, ix1), iy = min(iyl, iy1);  // lanes past the grid edge repeat a point
+    const double xg = p.x0 + static_cast<double>(ix) * p.gdx;
+    const double yg = p.y0 + static_cast<double>(iy) * p.gdy;
+    const double gxl = p.x0 + static_cast<double>(ix0) * p.gdx, gxh = p.x0 + static_cast<double>(ix1) * p.gdx;
+    const double gyl = p.y0 + static_cast<double>(iy0) * p.gdy, gyh = p.y0 + static_cast<double>(iy1) * p.gdy;
+    const Lattice L = p.lat;
+    ApConsts K{p.k_a, p.c_a, p.k_b, p.c_b, p.k_e, p.k_u};
+    asm("" : "+v"(K.k_a), "+v"(K.c_a), "+v"(K.k_b), "+v"(K.c_b), "+v"(K.k_e), "+v"(K.k_u));
+    const double slack = L.s * 1e-9;  // covers rounding of the cell coordinates
+
+    double S1 = 0.0, S2 = 0.0;
+    uint32_t cnt = 0;
+    uint64_t tested = 0;
+    const int cy0 = cell_index(gyl - p.reach - slack, L.oy, L.inv_s, L.ncy);
+    const int cy1 = cell_index(gyh + p.reach + slack, L.oy, L.inv_s, L.ncy);
+    for (int cy = cy0; cy <= cy1; ++cy) {
+        // vertical gap between this row of cells and the block; the row's
+        // galaxies within reach of the block lie within w of it horizontally
+        const double rlo = L.oy + static_cast<double>(cy) * L.s;
+        const double dv = fmax(0.0, fmax(rlo - gyh, gyl - (rlo + L.s)) - slack);
+        const double w2 = p.reach * p.reach - dv * dv;
+        if (!(w2 > 0.0)) continue;
+        const double w = sqrt(w2) + slack;
+        const int cx0 = cell_index(gxl - w, L.ox, L.inv_s, L.ncx);
+        const int cx1 = cell_index(gxh + w, L.ox, L.inv_s, L.ncx);
+        const uint32_t row = static_cast<uint32_t>(cy) * static_cast<uint32_t>(L.ncx);
+        const uint32_t g_begin = p.start[row + static_cast<uint32_t>(cx0)];
+        const uint32_t g_end = p.start[row + static_cast<uint32_t>(cx1) + 1u];
+        tested += g_end - g_begin;
+        for (uint32_t c0 = g_begin; c0 < g_end; c0 += kApFlush) {
+            const uint32_t c1 = min(c0 + static_cast<uint32_t>(kApFlush), g_end);
+            float a1 = 0.0f, a2 = 0.0f;
+            for (uint32_t g = c0; g < c1; ++g) ap_pair(p.gal[g], xg, yg, p.r2, K, cnt, a1, a2);
+            S1 += static_cast<double>(a1);
+            S2 += static_cast<double>(a2);
+        }
+    }
+    if (valid) {
+        const int64_t o = static_cast<int64_t>(iy) * p.nx + ix;
+        p.map[o] = S1 / p.n_gal;
+        if (p.snr) p.snr[o] = S2 > 0.0 ? (1.4142135623730951 * S1) / sqrt(S2) : __builtin_nan("");
+        if (p.n_in) p.n_in[o] = cnt;
+    }
+    if (p.stats) {
+        const uint32_t in_wave = wave_sum_u32(valid ? cnt : 0u);
+        const uint32_t lanes = wave_sum_u32(valid ? 1u : 0u);
+        if (lane == 0) {
+            atomicAdd(p.stats + 0, static_cast<unsigned long long>(tested) * lanes);
+            atomicAdd(p.stats + 1, static_cast<unsigned long long>(in_wave));
+        }
+    }
+}
+
+// ------------------------------------------------------------------- host
+
+struct ApLast {
+    double kernel_ms = -1.0;
+    uint64_t tested = 0;
+    uint64_t in = 0;
+    double cell = 0.0;
+};
+thread_local ApLast t_ap;
+
+struct DevMem {
+    void *mem = nullptr;
+    hipStream_t st = nullptr;
+    ~DevMem() {
+        if (mem) (void)hipFreeAsync(mem, st);
+    }
+};
+
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+size_t take(size_t *size, size_t bytes) {
+    const size_t o = (*size + 255) & ~size_t(255);
+    *size = o + bytes;
+    return o;
+}
+
+#define AP_HIP(call, what)                                 \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, (what)); \
+    } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_args(const pc_shear_catalog *cat, const pc_grid *grid, double theta_max, double n_gal, const double *map) {
+    if (!cat || !grid || !map) return fail(PC_ERR_INVALID, "NULL catalogue, grid or map");
+    if (cat->n < 0 || cat->n >= (int64_t(1) << 31)) return fail(PC_ERR_INVALID, "catalogue n outside [0, 2^31)");
+    if (cat->n > 0 && (!cat->x || !cat->y || !cat->e1 || !cat->e2))
+        return fail(PC_ERR_INVALID, "catalogue has NULL arrays");
+    if (!finite_pos(theta_max)) return fail(PC_ERR_INVALID, "theta_max must be finite and > 0");
+    if (!finite_pos(n_gal)) return fail(PC_ERR_INVALID, "n_gal must be finite and > 0");
+    if (!std::isfinite(grid->x0) || !std::isfinite(grid->y0) || !finite_pos(grid->dx) || !finite_pos(grid->dy))
+        return fail(PC_ERR_INVALID, "grid origin must be finite and spacings finite and > 0");
+    if (grid->nx < 0 || grid->ny < 0 || int64_t(grid->nx) * grid->ny >= (int64_t(1) << 31))
+        return fail(PC_ERR_INVALID, "grid size outside [0, 2^31)");
+    const double span_x = (grid->nx > 0 ? grid->nx - 1 : 0) * grid->dx, span_y = (grid->ny > 0 ? grid->ny - 1 : 0) * grid->dy;
+    if (!std::isfinite(grid->x0 + span_x) || !std::isfinite(grid->y0 + span_y))
+        return fail(PC_ERR_INVALID, "grid extent overflows");
+    if (!cat->on_device) {
+        for (int64_t i = 0; i < cat->n; ++i)
+            if (!std::isfinite(cat->x[i]) || !std::isfinite(cat->y[i]) || !std::isfinite(cat->e1[i]) ||
+                !std::isfinite(cat->e2[i]))
+                return fail(PC_ERR_INVALID, "non-finite galaxy position or ellipticity (index " +
+                                                std::to_string(i) + ")");
+    }
+    return PC_OK;
+}
+
+// Cell side theta/16 (coarser if the lattice would exceed kMaxCells), one
+// spare cell beyond theta on every side of the grid.
+int make_lattice(const pc_grid *g, double theta, Lattice *L) {
+    const double span_x = (g->nx - 1) * g->dx + 2.0 * theta;
+    const double span_y = (g->ny - 1) * g->dy + 2.0 * theta;
+    double s = theta / 16.0;
+    for (int it = 0; it < 200; ++it) {
+        const double cx = std::ceil(span_x / s) + 3.0, cy = std::ceil(span_y / s) + 3.0;
+        if (cx * cy <= static_cast<double>(kMaxCells)) {
+            L->s = s;
+            L->inv_s = 1.0 / s;
+            L->ncx = static_cast<int32_t>(cx);
+            L->ncy = static_cast<int32_t>(cy);
+            L->ox = g->x0 - theta - s;
+            L->oy = g->y0 - theta - s;
+            return PC_OK;
+        }
+        s *= 2.0;
+    }
+    return fail(PC_ERR_INVALID, "grid extent too large for the search lattice");
+}
+
+}  // namespace
+}  // namespace pc
+
+using namespace pc;
+
+extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid, double theta_max, double n_gal,
+                                double *map, double *snr, uint32_t *n_in, int32_t out_on_device, void *stream) {
+    clear_error();
+    int rc = check_args(cat, grid, theta_max, n_gal, map);
+    if (rc) return rc;
+    DeviceInfo *di = nullptr;
+    rc = device_info(&di);
+    if (rc) return rc;
+    const int64_t n = cat->n;
+    const int64_t m = int64_t(grid->nx) * grid->ny;
+    t_ap = ApLast();
+    if (m == 0) return PC_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    Lattice L;
+    rc = make_lattice(grid, theta_max, &L);
+    if (rc) return rc;
+    const int64_t n_cells = int64_t(L.ncx) * L.ncy;
+
+    // work space
+    const bool host_in = !cat->on_device, host_out = !out_on_device;
+    const size_t nn = static_cast<size_t>(n > 0 ? n : 1);
+    size_t size = 0;
+    const size_t o_in = host_in ? take(&size, 4 * sizeof(double) * nn) : 0;
+    const size_t o_keys = take(&size, sizeof(uint32_t) * nn);
+    const size_t o_idx = take(&size, sizeof(uint32_t) * nn);
+    const size_t o_gal = take(&size, sizeof(ApGal) * nn);
+    const size_t o_start = take(&size, sizeof(uint32_t) * static_cast<size_t>(n_cells + 1));
+    const size_t o_cursor = take(&size, sizeof(uint32_t) * static_cast<size_t>(n_cells));
+    const size_t o_sums = take(&size, sizeof(uint32_t) * scan_sums_words(n_cells + 1));
+    const size_t o_flag = take(&size, 4 * sizeof(uint32_t));
+    const size_t o_stats = take(&size, 2 * sizeof(unsigned long long));
+    const size_t o_out = host_out ? take(&size, (2 * sizeof(double) + sizeof(uint32_t)) * static_cast<size_t>(m)) : 0;
+    DevMem ws;
+    ws.st = st;
+    AP_HIP(hipMallocAsync(&ws.mem, size, st), "hipMallocAsync(aperture work space)");
+    char *base = static_cast<char *>(ws.mem);
+
+    const double *X = cat->x, *Y = cat->y, *E1 = cat->e1, *E2 = cat->e2;
+    if (host_in && n > 0) {
+        double *d = reinterpret_cast<double *>(base + o_in);
+        const size_t b = sizeof(double) * static_cast<size_t>(n);
+        AP_HIP(hipMemcpyAsync(d, cat->x, b, hipMemcpyHostToDevice, st), "H2D x");
+        AP_HIP(hipMemcpyAsync(d + n, cat->y, b, hipMemcpyHostToDevice, st), "H2D y");
+        AP_HIP(hipMemcpyAsync(d + 2 * n, cat->e1, b, hipMemcpyHostToDevice, st), "H2D e1");
+        AP_HIP(hipMemcpyAsync(d + 3 * n, cat->e2, b, hipMemcpyHostToDevice, st), "H2D e2");
+        X = d;
+        Y = d + n;
+        E1 = d + 2 * n;
+        E2 = d + 3 * n;
+    }
+    uint32_t *keys = reinterpret_cast<uint32_t *>(base + o_keys);
+    uint32_t *idx = reinterpret_cast<uint32_t *>(base + o_idx);
+    ApGal *gal = reinterpret_cast<ApGal *>(base + o_gal);
+    uint32_t *start = reinterpret_cast<uint32_t *>(base + o_start);
+    uint32_t *cursor = reinterpret_cast<uint32_t *>(base + o_cursor);
+    uint32_t *sums = reinterpret_cast<uint32_t *>(base + o_sums);
+    uint32_t *flag = reinterpret_cast<uint32_t *>(base + o_flag);
+    unsigned long long *stats = reinterpret_cast<unsigned long long *>(base + o_stats);
+
+    // order the galaxies by cell
+    AP_HIP(launch_zero_u32(start, n_cells + 1, st), "zero cell counts");
+    AP_HIP(launch_zero_u32(flag, 4, st), "zero flags");
+    AP_HIP(launch_zero_u32(reinterpret_cast<uint32_t *>(stats), 4, st), "zero stats");
+    if (n > 0) {
+        const uint32_t gn = static_cast<uint32_t>((n + 255) / 256);
+        k_ap_keys<<<dim3(gn), dim3(256), 0, st>>>(X, Y, E1, E2, n, L, keys, start, flag);
+        AP_HIP(hipGetLastError(), "k_ap_keys");
+        AP_HIP(launch_exclusive_scan(start, n_cells + 1, sums, st), "cell scan");
+        AP_HIP(hipMemcpyAsync(cursor, start, sizeof(uint32_t) * static_cast<size_t>(n_cells),
+                              hipMemcpyDeviceToDevice, st),
+               "cell cursors");
+        k_ap_scatter<<<dim3(gn), dim3(256), 0, st>>>(keys, n, cursor, idx);
+        AP_HIP(hipGetLastError(), "k_ap_scatter");
+        k_ap_place<<<dim3(gn), dim3(256), 0, st>>>(X, Y, E1, E2, keys, idx, start, n_cells, n, gal);
+        AP_HIP(hipGetLastError(), "k_ap_place");
+    }
+    uint32_t h_flag = 0;
+    AP_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st), "D2H flag");
+    AP_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (h_flag) return fail(PC_ERR_INVALID, "non-finite galaxy position or ellipticity in the device catalogue");
+
+    double *d_map = map, *d_snr = snr;
+    uint32_t *d_nin = n_in;
+    if (host_out) {
+        d_map = reinterpret_cast<double *>(base + o_out);
+        d_snr = d_map + m;
+        d_nin = reinterpret_cast<uint32_t *>(d_snr + m);
+    }
+    ApParams p;
+    p.gal = gal;
+    p.start = start;
+    p.lat = L;
+    p.x0 = grid->x0;
+    p.y0 = grid->y0;
+    p.gdx = grid->dx;
+    p.gdy = grid->dy;
+    p.nx = grid->nx;
+    p.ny = grid->ny;
+    p.tiles_x = (grid->nx + kApSide - 1) / kApSide;
+    const int tiles_y = (grid->ny + kApSide - 1) / kApSide;
+    p.n_tiles = p.tiles_x * tiles_y;
+    p.per_xcd = (p.n_tiles + 7) / 8;
+    p.theta = theta_max;
+    p.r2 = theta_max * theta_max;
+    p.reach = theta_max * (1.0 + 1e-9);
+    const double log2e = 1.4426950408889634;
+    p.k_a = static_cast<float>(-150.0 * log2e / theta_max);
+    p.c_a = static_cast<float>(6.0 * log2e);
+    p.k_b = static_cast<float>(50.0 * log2e / theta_max);
+    p.c_b = static_cast<float>(-47.0 * log2e);
+    p.k_e = static_cast<float>(2.0 * log2e / (0.15 * theta_max));
+    p.k_u = static_cast<float>(1.0 / (0.15 * theta_max));
+    p.n_gal = n_gal;
+    p.map = d_map;
+    p.snr = (snr || host_out) ? d_snr : nullptr;
+    p.n_in = (n_in || host_out) ? d_nin : nullptr;
+    p.stats = stats;
+
+    Events ev;
+    const bool timing = thread_timing();
+    if (timing) {
+        AP_HIP(hipEventCreate(&ev.a), "hipEventCreate");
+        AP_HIP(hipEventCreate(&ev.b), "hipEventCreate");
+        AP_HIP(hipEventRecord(ev.a, st), "hipEventRecord");
+    }
+    k_ap_map<<<dim3(static_cast<uint32_t>(8 * p.per_xcd)), dim3(64), 0, st>>>(p);
+    AP_HIP(hipGetLastError(), "k_ap_map");
+    if (timing) AP_HIP(hipEventRecord(ev.b, st), "hipEventRecord");
+
+    unsigned long long h_stats[2] = {0, 0};
+    AP_HIP(hipMemcpyAsync(h_stats, stats, sizeof(h_stats), hipMemcpyDeviceToHost, st), "D2H stats");
+    if (host_out) {
+        AP_HIP(hipMemcpyAsync(map, d_map, sizeof(double) * static_cast<size_t>(m), hipMemcpyDeviceToHost, st),
+               "D2H map");
+        if (snr)
+            AP_HIP(hipMemcpyAsync(snr, d_snr, sizeof(double) * static_cast<size_t>(m), hipMemcpyDeviceToHost, st),
+                   "D2H snr");
+        if (n_in)
+            AP_HIP(hipMemcpyAsync(n_in, d_nin, sizeof(uint32_t) * static_cast<size_t>(m), hipMemcpyDeviceToHost,
+                                  st),
+                   "D2H n_in");
+    }
+    AP_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    ApLast last;
+    if (timing) {
+        float ms = 0.0f;
+        AP_HIP(hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
+        last.kernel_ms = ms;
+    }
+    last.tested = h_stats[0];
+    last.in = h_stats[1];
+    last.cell = L.s;
+    t_ap = last;
+    return PC_OK;
+}
+
+extern "C" int pc_debug_last_aperture(double *kernel_ms, uint64_t *pairs_tested, uint64_t *pairs_in,
+                                      double *cell_side) {
+    clear_error();
+    if (kernel_ms) *kernel_ms = t_ap.kernel_ms;
+    if (pairs_tested) *pairs_tested = t_ap.tested;
+    if (pairs_in) *pairs_in = t_ap.in;
+    if (cell_side) *cell_side = t_ap.cell;
+    return PC_OK;
+}

@@ -481,6 +481,24 @@ size_t sort_scratch_words(int64_t n) {
     return static_cast<size_t>(n + m + (m + kScanChunk - 1) / kScanChunk + 64);
 }
 
+size_t scan_sums_words(int64_t m) { return static_cast<size_t>((m + kScanChunk - 1) / kScanChunk); }
+
+hipError_t launch_zero_u32(uint32_t *p, int64_t m, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    k_zero_u32<<<dim3(static_cast<uint32_t>((m + 255) / 256)), dim3(256), 0, st>>>(p, m);
+    return hipGetLastError();
+}
+
+// In-place exclusive prefix sum of a[0, m); sums: scan_sums_words(m) words.
+hipError_t launch_exclusive_scan(uint32_t *a, int64_t m, uint32_t *sums, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
+    k_scan_local<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(a, m, sums);
+    k_scan_sums<<<dim3(1), dim3(kScanBlock), 0, st>>>(sums, nb);
+    k_scan_add<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(a, m, sums);
+    return hipGetLastError();
+}
+
 // Spatially ordered copy of src[base, base+n) into a64s/a32s, and the tile
 // bounds.  scratch: sort_scratch_words(n) uint32 words.
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,

@@ -371,3 +371,36 @@ def test_tuning_cache_file_is_validated(tmp_path):
     with pytest.raises(pc.PcError):
         pc.pc_autotune_load(tmp_path / "missing.jsonl")
 
+
+
+@pytest.mark.parametrize("change,fragment", [
+    ({"theta": 0.0}, "theta_max"),
+    ({"theta": float("nan")}, "theta_max"),
+    ({"n_gal": -1.0}, "n_gal"),
+    ({"grid": (0.0, 0.0, 0.0, 1.0, 4, 4)}, "spacings"),
+    ({"grid": (0.0, float("inf"), 1.0, 1.0, 4, 4)}, "grid origin"),
+    ({"grid": (0.0, 0.0, 1.0, 1.0, -1, 4)}, "grid size"),
+    ({"grid": (0.0, 0.0, 1.0, 1.0, 65536, 65536)}, "grid size"),
+    ({"nan_at": 3}, "non-finite"),
+])
+def test_aperture_arguments_rejected_before_any_device_work(change, fragment):
+    x = np.linspace(0.0, 5.0, 10)
+    cat = [x, x[::-1].copy(), np.full(10, 0.1), np.full(10, -0.1)]
+    if "nan_at" in change:
+        cat[1][change["nan_at"]] = np.nan
+    grid = change.get("grid", (0.0, 0.0, 1.0, 1.0, 4, 4))
+    with pytest.raises(pc.PcError) as ei:
+        pc.pc_aperture_mass(tuple(cat), grid, change.get("theta", 2.0), change.get("n_gal", 35.0))
+    assert ei.value.code == pc.PC_ERR_INVALID
+    assert fragment in str(ei.value)
+
+
+def test_shear_catalogue_recipe():
+    (x, y, e1, e2), side = synth.shear_catalog(20000, density=35.0, config=9)
+    assert side == pytest.approx((20000 / 35.0) ** 0.5)
+    assert x.min() >= 0.0 and x.max() < side and y.min() >= 0.0 and y.max() < side
+    assert np.all(np.isfinite(e1)) and np.all(np.isfinite(e2))
+    again = synth.shear_catalog(20000, density=35.0, config=9)[0]
+    assert all(np.array_equal(a, b) for a, b in zip((x, y, e1, e2), again))
+    g = synth.field_grid(side, 64)
+    assert g[4] == g[5] == 64 and g[0] == pytest.approx(0.5 * side / 64)
