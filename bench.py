@@ -38,13 +38,13 @@ def work_per_pair(n_bins: int) -> int:
     return 8 + math.ceil(math.log2(n_bins + 2))
 
 
-def recorded_traffic(mode: str):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+def recorded_traffic(record: str, source: str):
+    """HBM bytes per launch from a committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     record, if it was taken on the kernel source as it is now; else None."""
     import hashlib
-    rec = os.path.join(ROOT, "profiles", "k_count_mixed_1M_traffic.json")
-    src = os.path.join(ROOT, "paper_1208_3658_amd", "csrc", "pc_kernels.hip")
-    if mode != "mixed" or not os.path.exists(rec):
+    rec = os.path.join(ROOT, "profiles", record)
+    src = os.path.join(ROOT, "paper_1208_3658_amd", "csrc", source)
+    if not os.path.exists(rec):
         return None
     with open(rec) as f:
         r = json.load(f)
@@ -111,7 +111,7 @@ def aperture_main(args):
     kern_s = float(np.mean(kern)) / 1e3
     achieved = pairs * AP_FLOPS_PER_PAIR / kern_s / 1e12
     table = []
-    for gn in AP_GRIDS:
+    for gn in (AP_GRIDS if not args.no_table else ()):
         for ti, th in enumerate(AP_THETAS):
             run(gn, th)
             torch.cuda.synchronize()
@@ -135,11 +135,14 @@ def aperture_main(args):
                    "field_arcmin": side, "grid": [G, G], "theta_max_arcmin": TH, "filter": "NFW (Eq. 4)",
                    "pairs_in_aperture": pairs},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None, "kernel_ms": kern_s * 1e3,
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": recorded_traffic("k_ap_map_shear1M_grid2048_theta32_traffic.json", "pc_aperture.hip"),
+                     "kernel_ms": kern_s * 1e3,
                      "work_per_pair": AP_FLOPS_PER_PAIR, "pairs_tested": info["pairs_tested"],
                      "cell_side_arcmin": info["cell_side"]},
-        "table": table,
     }
+    if table:
+        out["table"] = table
     if not args.no_cpu_baseline:
         import oracle
         log("cpu baseline (oracle)")
@@ -153,9 +156,9 @@ def aperture_main(args):
                                        synth.PAPER_DENSITY)
             spent = time.perf_counter() - t
             pin = int(r["n_in"].sum())
-            if spent >= 0.6 * args.cpu_seconds or npts >= 4096:
+            if spent >= 0.6 * args.cpu_seconds or npts >= 65536:
                 break
-            npts = max(npts + 1, min(4096, int(npts * args.cpu_seconds / max(spent, 1e-3))))
+            npts = max(npts + 1, min(65536, int(npts * args.cpu_seconds / max(spent, 1e-3))))
         out["cpu_baseline"] = {"value": pin / spent / 1e9, "unit": "Gpairs/s", "cores": oracle.num_threads(),
                                "kind": "oracle",
                                "sample": f"{npts} seeded points of the {G}^2 x {TH:g}' map, each against all "
@@ -296,6 +299,8 @@ def main():
                     help="1m: 1M clustered + 1M random (default); batched: 256 mocks x shared 1M random; "
                          "large: 4M + 8M full sky; paper: DR of 1M + 1M uniform, 254 log bins; "
                          "aperture: aperture-mass maps of 1M galaxies (Sec. 3)")
+    ap.add_argument("--no-table", action="store_true",
+                    help="aperture workload: time only the 2048^2 x 32 arcmin map, not the grid/radius table")
     ap.add_argument("--per-job-launches", action="store_true",
                     help="also time the same jobs with one launch each")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -389,7 +394,8 @@ def main():
                    + ("+tuned" if mode & pc.PC_TUNED else "")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": recorded_traffic(args.mode) if args.workload == "1m" else None,
+                     "traffic": recorded_traffic("k_count_mixed_1M_traffic.json", "pc_kernels.hip")
+                     if args.workload == "1m" and args.mode == "mixed" else None,
                      "kernel_ms": kern_s * 1e3, "work_per_pair": W, "grid": launch["grid"],
                      "lds_bytes": launch["lds_bytes"], "items": launch["items"],
                      "pairs_computed": prn["pairs_computed"], "survivor_items": prn["survivors"],

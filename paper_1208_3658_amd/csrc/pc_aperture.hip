@@ -173,16 +173,18 @@ __device__ __forceinline__ void ap_pair(const ApGal &G, double xg, double yg, do
         const float f2 = fmaxf(static_cast<float>(d2), FLT_MIN);
         const float rinv = __builtin_amdgcn_rsqf(f2);
         const float r = f2 * rinv;
-        const float ea = __builtin_amdgcn_exp2f(fmaf(r, K.k_a, K.c_a));
-        const float eb = __builtin_amdgcn_exp2f(fmaf(r, K.k_b, K.c_b));
         const float e2u = __builtin_amdgcn_exp2f(r * K.k_e);
         const float u = r * K.k_u;
+        const float ea = __builtin_amdgcn_exp2f(fmaf(r, K.k_a, K.c_a));
+        const float eb = __builtin_amdgcn_exp2f(fmaf(r, K.k_b, K.c_b));
         const float D = (1.0f + ea) + eb;
         // tanh(u)/u = (e^2u - 1) / ((e^2u + 1) u); near u = 0 its series
-        // 1 - u^2/3 + 2u^4/15 (next term below 4e-9 there)
+        // 1 - u^2/3 + 2u^4/15 (next term below 4e-9 there).  The series is
+        // needed only within 0.0094 theta_max of the point, so it is a branch
+        // that is almost never taken rather than selects every pair pays for.
         float num = e2u - 1.0f;
         float den = ((e2u + 1.0f) * u) * D;
-        if (u < 0.0625f) {
+        if (__builtin_expect(u < 0.0625f, 0)) {
             const float u2 = u * u;
             num = fmaf(u2, fmaf(u2, 0.133333333f, -0.333333333f), 1.0f);
             den = D;
@@ -462,12 +464,12 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     p.r2 = theta_max * theta_max;
     p.reach = theta_max * (1.0 + 1e-9);
     const double log2e = 1.4426950408889634;
+    p.k_e = static_cast<float>(2.0 * log2e / (0.15 * theta_max));
+    p.k_u = static_cast<float>(1.0 / (0.15 * theta_max));
     p.k_a = static_cast<float>(-150.0 * log2e / theta_max);
     p.c_a = static_cast<float>(6.0 * log2e);
     p.k_b = static_cast<float>(50.0 * log2e / theta_max);
     p.c_b = static_cast<float>(-47.0 * log2e);
-    p.k_e = static_cast<float>(2.0 * log2e / (0.15 * theta_max));
-    p.k_u = static_cast<float>(1.0 / (0.15 * theta_max));
     p.n_gal = n_gal;
     p.map = d_map;
     p.snr = (snr || host_out) ? d_snr : nullptr;
