@@ -57,14 +57,18 @@ int pc_debug_last_launch(double *kernel_ms, uint64_t *items, int32_t *grid, uint
 /*
  * pc_debug_last_pruning -- the calling thread's last counting launch: work
  * items (tile pairs) left for the pair kernel after whole-tile-pair binning,
- * pairs visited one by one, all pairs counted, how many of the left items went
- * through the matrix cores, how many had at most 3 edges inside their chord
- * interval (binned by comparing with those edges alone), and how many of the
- * vector path's items formed their chords in tile-centred Gram form.  Any
- * pointer may be NULL.
+ * pairs visited one by one, all pairs counted, and how many of the left items
+ * went through the matrix cores.  A left item of the mixed mode may be split:
+ * the j-tile's four sub-blocks of 64 points are looked at one by one, some
+ * binned whole, the others visited with their own edges (split_items counts
+ * those items).  few_items counts the work units (items, or open sub-blocks
+ * of split items) with at most 2 edges inside their chord interval (binned by
+ * comparing with those edges alone), gram_items those whose vector-path
+ * chords are formed in tile-centred Gram form.  Any pointer may be NULL.
  */
 int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_t *pairs_total,
-                          uint64_t *mfma_items, uint64_t *few_items, uint64_t *gram_items);
+                          uint64_t *mfma_items, uint64_t *few_items, uint64_t *gram_items,
+                          uint64_t *split_items);
 
 #ifdef __cplusplus
 }

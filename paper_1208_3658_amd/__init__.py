@@ -81,7 +81,7 @@ _SIGNATURES = {
     "pc_debug_lut32": ([_vp, _i32, _vp, _vp, _i64], ctypes.c_int),
     "pc_debug_set_timing": ([_i32], ctypes.c_int),
     "pc_debug_last_launch": ([_vp, _vp, _vp, _vp], ctypes.c_int),
-    "pc_debug_last_pruning": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "pc_debug_last_pruning": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "pc_debug_guard_band_gram": ([_vp, _i32, _vp, _vp], ctypes.c_int),
     "pc_server_create": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
     "pc_server_set_random": ([_vp, _i32, _PCAT], ctypes.c_int),
@@ -383,16 +383,10 @@ def pc_debug_last_launch() -> dict:
 
 
 def pc_debug_last_pruning() -> dict:
-    surv = _u64(0)
-    comp = _u64(0)
-    tot = _u64(0)
-    mf = _u64(0)
-    few = _u64(0)
-    gram = _u64(0)
-    _check(lib().pc_debug_last_pruning(ctypes.byref(surv), ctypes.byref(comp), ctypes.byref(tot), ctypes.byref(mf),
-                                       ctypes.byref(few), ctypes.byref(gram)))
-    return {"survivors": int(surv.value), "pairs_computed": int(comp.value), "pairs_total": int(tot.value),
-            "mfma_items": int(mf.value), "few_items": int(few.value), "gram_items": int(gram.value)}
+    vals = [_u64(0) for _ in range(7)]
+    _check(lib().pc_debug_last_pruning(*(ctypes.byref(v) for v in vals)))
+    keys = ("survivors", "pairs_computed", "pairs_total", "mfma_items", "few_items", "gram_items", "split_items")
+    return {k: int(v.value) for k, v in zip(keys, vals)}
 
 
 # ------------------------------------------------------------ aperture mass

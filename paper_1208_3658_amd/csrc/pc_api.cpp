@@ -25,16 +25,21 @@ hipError_t launch_convert(const double *ra, const double *dec, int64_t n, double
                           int *err, hipStream_t st);
 hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st);
 hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
-                        const uint64_t *items, const unsigned long long *n_items, uint64_t total_items,
-                        uint32_t lut_lds_off, uint32_t stage_lds_off,
+                        const uint64_t *items, const unsigned long long *n_items, const uint64_t *sub,
+                        uint64_t total_items, uint32_t lut_lds_off, uint32_t stage_lds_off,
                         unsigned long long *queue, int chunk, uint32_t lds_bytes, int grid, hipStream_t st);
 size_t sort_scratch_words(int64_t n);
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
                        float4 *a32s, float4 *g32s, double4 *bounds, hipStream_t st);
 hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, int64_t total_rows,
-                        uint64_t *survivors, unsigned long long *meta, int32_t mfma_ok, hipStream_t st);
+                        uint64_t *survivors, uint64_t *sub, unsigned long long *meta, int32_t mfma_ok,
+                        int32_t split_ok, hipStream_t st);
 hipError_t count_occupancy(bool fp64, bool mc, uint32_t lds_bytes, int *blocks_per_cu);
 hipError_t set_max_lds(uint32_t bytes);
+
+#ifndef PC_SPLIT
+#define PC_SPLIT 1  // split surviving tile pairs into j sub-blocks in the prune pass
+#endif
 
 // ------------------------------------------------------------------ errors
 
@@ -397,7 +402,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             // binary32 copies padded: the kernel reads a step of j-points ahead
             v.o_a32s = ar.take(sizeof(float4) * static_cast<size_t>(n + kJPad));
             v.o_g32s = ar.take(sizeof(float4) * static_cast<size_t>(n + kJPad));
-            v.o_bounds = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(n)));
+            v.o_bounds = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(n) * (1 + kSubs)));
             max_sort_n = std::max(max_sort_n, n);
         }
         const int id = static_cast<int>(views.size());
@@ -496,6 +501,10 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     // meta[0..5]: pruning results; meta[8..15]: the counting kernel's work queue
     const size_t o_meta = ar.take(sizeof(unsigned long long) * 16);
     const size_t o_surv = ar.take(sizeof(uint64_t) * std::max<uint64_t>(prune ? items : 1, 1));
+    // split survivors: the prune pass looks at the j-tile's sub-blocks too
+    // (mixed mode); their descriptions sit beside the survivors
+    const bool split = PC_SPLIT && prune && !fp64;
+    const size_t o_sub = ar.take(sizeof(uint64_t) * std::max<uint64_t>(split ? items : 1, 1));
 
     // ---- allocate the workspace
     Workspace ws;
@@ -534,6 +543,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         const float4 *a32s = nullptr;
         const float4 *g32s = nullptr;
         const double4 *bounds = nullptr;
+        const double4 *sub_bounds = nullptr;  // kSubs per tile, after the tiles' own
     };
     std::vector<ViewPtrs> vp(views.size());
     for (size_t v = 0; v < views.size(); ++v) {
@@ -544,6 +554,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             vp[v].a32s = r.a32s;
             vp[v].g32s = r.g32s;
             vp[v].bounds = r.bounds;
+            vp[v].sub_bounds = r.bounds + n_tiles(r.n);
             continue;
         }
         const int64_t n = vw.e - vw.b;
@@ -559,6 +570,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         vp[v].a32s = a32s;
         vp[v].g32s = g32s;
         vp[v].bounds = bnd;
+        vp[v].sub_bounds = bnd + n_tiles(n);
     }
 
     // ---- descriptors
@@ -573,6 +585,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         sd.j64 = vp[vj].a64s;
         sd.jb = vp[vj].bounds;
         sd.jg = vp[vj].g32s;
+        sd.jb_sub = vp[vj].sub_bounds;
         sd.counts = reinterpret_cast<unsigned long long *>(W + plan[static_cast<size_t>(sd.job)].o_counts);
     }
     std::vector<TableDesc> tds;
@@ -607,11 +620,12 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     const SegDesc *d_segs = reinterpret_cast<const SegDesc *>(W + o_segs);
     const TableDesc *d_tabs = reinterpret_cast<const TableDesc *>(W + o_tabs);
     uint64_t *surv = reinterpret_cast<uint64_t *>(W + o_surv);
+    uint64_t *sub_words = reinterpret_cast<uint64_t *>(W + o_sub);
     int grid = 0;
     if (items > 0) {
         if (prune)
-            PC_HIP(launch_prune(d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune_rows, surv, meta, mc ? 1 : 0,
-                                st),
+            PC_HIP(launch_prune(d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune_rows, surv,
+                                split ? sub_words : nullptr, meta, mc ? 1 : 0, split ? 1 : 0, st),
                    "prune");
         int per_cu = 0;
         PC_HIP(count_occupancy(fp64, mc, lds_bytes, &per_cu), "occupancy");
@@ -629,7 +643,8 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             PC_HIP(hipEventRecord(t_ev0, st), "hipEventRecord");
         }
         PC_HIP(launch_count(fp64, mc, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
-                            prune ? meta : nullptr, items, lut_off, stage_off, meta + 8, lt.chunk, lds_bytes, grid, st),
+                            prune ? meta : nullptr, split ? sub_words : nullptr, items, lut_off, stage_off, meta + 8,
+                            lt.chunk, lds_bytes, grid, st),
                "count kernel");
         if (timed) PC_HIP(hipEventRecord(t_ev1, st), "hipEventRecord");
     }
@@ -644,7 +659,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     }
     std::vector<int> flags(std::max<size_t>(srcs.size(), 1), 0);
     PC_HIP(hipMemcpyAsync(flags.data(), W + o_err, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, st), "D2H flags");
-    unsigned long long hmeta[6] = {0, 0, 0, 0, 0, 0};
+    unsigned long long hmeta[7] = {0, 0, 0, 0, 0, 0, 0};
     PC_HIP(hipMemcpyAsync(hmeta, meta, sizeof(hmeta), hipMemcpyDeviceToHost, st), "D2H meta");
     PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
     for (size_t k = 0; k < srcs.size(); ++k)
@@ -669,6 +684,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     t_last.mfma_items = prune ? hmeta[3] : 0;
     t_last.few_items = prune ? hmeta[4] : 0;
     t_last.gram_items = prune ? hmeta[5] : 0;
+    t_last.split_items = prune ? hmeta[6] : 0;
     if (t_timing && items > 0) {
         float ms = 0.0f;
         PC_HIP(hipEventElapsedTime(&ms, t_ev0, t_ev1), "hipEventElapsedTime");
@@ -695,7 +711,7 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
     const size_t o64s = ar.take(sizeof(double4) * n);
     const size_t o32s = ar.take(sizeof(float4) * (n + kJPad));  // padded as in run_batch
     const size_t og32s = ar.take(sizeof(float4) * (n + kJPad));
-    const size_t ob = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(static_cast<int64_t>(n))));
+    const size_t ob = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(static_cast<int64_t>(n)) * (1 + kSubs)));
     const size_t oerr = ar.take(sizeof(int));
     const size_t osc = ar.take(sizeof(uint32_t) * sort_scratch_words(static_cast<int64_t>(n)));
     size_t ora = 0, odec = 0;
@@ -955,8 +971,10 @@ extern "C" int pc_debug_set_timing(int32_t on) {
 }
 
 extern "C" int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_t *pairs_total,
-                                     uint64_t *mfma_items, uint64_t *few_items, uint64_t *gram_items) {
+                                     uint64_t *mfma_items, uint64_t *few_items, uint64_t *gram_items,
+                                     uint64_t *split_items) {
     clear_error();
+    if (split_items) *split_items = t_last.split_items;
     if (gram_items) *gram_items = t_last.gram_items;
     if (few_items) *few_items = t_last.few_items;
     if (mfma_items) *mfma_items = t_last.mfma_items;

@@ -74,6 +74,8 @@ struct TableDesc {
 //   bits  0..39  item number within the launch
 //   bits 40..50  k0: edges at or below the item's whole chord interval
 //   bits 51..52  m: edges inside the interval when at most kFewMax, else 0
+//   bit  53      split: the j-tile is visited as kSubs blocks of kSub points,
+//                each described by 16 bits of the item's sub-block word
 //   bit  61      vector path, chords in Gram form centred on the j-tile
 //   bit  62      matrix-core path centred on the j-tile
 //   bit  63      matrix-core path
@@ -83,6 +85,23 @@ constexpr int kFewMax = 3;  // at most 3: m has two bits
 #define PC_FEWCUT 2         // items with at most this many edges use few-edge binning (<= kFewMax)
 #endif
 constexpr uint64_t kItemMask = (1ull << kItemBits) - 1;
+constexpr int kSplitBit = 53;
+
+// Sub-blocks of a split item.  A full, off-diagonal tile pair that the prune
+// pass cannot bin whole is looked at again as kSubs pairs (i-tile, 64 points
+// of the j-tile), each with its own chord interval: some of them fall in one
+// bin and are binned whole, the others often meet fewer edges than the whole
+// tile pair.  Sub-block s of an item is described by bits 16s..16s+15 of the
+// item's sub-block word:
+//   bits  0..10  k0: edges at or below its chord interval (its bin if whole)
+//   bits 11..12  m: edges inside when at most PC_FEWCUT, else 0 (cell table)
+//   bit  13      binned whole by the prune pass (the kernel skips it)
+//   bit  14      vector path with Gram-form chords centred on the j-tile
+constexpr int kSub = 64;
+constexpr int kSubs = kTile / kSub;
+static_assert(kSubs == 4, "four 16-bit sub-block fields per 64-bit word");
+constexpr uint32_t kSubWhole = 1u << 13;
+constexpr uint32_t kSubGram = 1u << 14;
 
 // A binary32 cell table (see pc_tables.cpp).
 struct Lut32 {
@@ -101,6 +120,7 @@ struct SegDesc {
     const double4 *ib, *jb;           // tile bounds (centre, radius) of each side
     const float4 *jg;                 // j side in Gram form, centred on its own tile
                                       // (-2 b'_x, -2 b'_y, -2 b'_z, |b'|^2)
+    const double4 *jb_sub;            // bounds of the j side's sub-blocks, kSubs per tile
     int64_t i0, ni, j0, nj;
     int64_t tiles_i, tiles_j;
     int64_t prow0;          // first row of the segment in the prune pass's row space

@@ -26,6 +26,7 @@ struct KParams {
     const TableDesc *tabs;
     const uint64_t *items;                 // work items to visit (survivors), or null: all items
     const unsigned long long *n_items;     // device count of `items`
+    const uint64_t *sub;                   // sub-block words beside `items` (split items), or null
     uint64_t total_items;                  // number of items when `items` is null
     int32_t n_segs;
     uint32_t lut_lds_off;   // byte offset of the cell table in LDS (after the histogram)
@@ -90,6 +91,11 @@ __device__ __forceinline__ double4 ld_const(const double4 *p) {
     using CD = const __attribute__((address_space(4))) double;
     CD *q = (CD *)(p);
     return make_double4(q[0], q[1], q[2], q[3]);
+}
+
+__device__ __forceinline__ uint64_t ld_const(const uint64_t *p) {
+    using CU = const __attribute__((address_space(4))) unsigned long long;
+    return static_cast<uint64_t>(*(CU *)(p));
 }
 
 // A descriptor read through the constant address space (scalar loads), so
@@ -584,26 +590,36 @@ __device__ __forceinline__ void step32_gram(unsigned char *lds, const float4 (&b
     }
 }
 
-template <int M>
-__device__ __forceinline__ void tile32_gram(unsigned char *lds, const float4 *__restrict__ Jg,
-                                            const double4 *__restrict__ J64t, int32_t jn,
-                                            const double4 *__restrict__ I64, int64_t ibeg, int32_t i_lim,
-                                            double ox, double oy, double oz, const TileCtx &k, const FewCtx &f) {
-    const int32_t lane = static_cast<int32_t>(threadIdx.x);
+// The lane's i-points centred on the j-tile's centre o, in binary32, with
+// |a'|^2; slots past a ragged end get NaN so their pairs count nowhere.
+struct GramI {
     float ax[kR], ay[kR], az[kR], na[kR];
-    uint32_t valid = 0;
+    uint32_t valid;
+};
+
+__device__ __forceinline__ void centre_i_gram(GramI &g, const double4 (&pts)[kR], int32_t i_lim, double ox,
+                                              double oy, double oz) {
+    const int32_t lane = static_cast<int32_t>(threadIdx.x);
+    g.valid = 0;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int32_t ir = r * kWave + lane;
         const bool ok = ir < i_lim;
-        const double4 p = I64[ibeg + (ok ? ir : 0)];
-        ax[r] = static_cast<float>(p.x - ox);
-        ay[r] = static_cast<float>(p.y - oy);
-        az[r] = static_cast<float>(p.z - oz);
-        const float n2 = __builtin_fmaf(az[r], az[r], __builtin_fmaf(ay[r], ay[r], ax[r] * ax[r]));
-        na[r] = ok ? n2 : __builtin_nanf("");
-        valid += ok ? 1u : 0u;
+        const double4 p = pts[r];
+        g.ax[r] = static_cast<float>(p.x - ox);
+        g.ay[r] = static_cast<float>(p.y - oy);
+        g.az[r] = static_cast<float>(p.z - oz);
+        const float n2 = __builtin_fmaf(g.az[r], g.az[r], __builtin_fmaf(g.ay[r], g.ay[r], g.ax[r] * g.ax[r]));
+        g.na[r] = ok ? n2 : __builtin_nanf("");
+        g.valid += ok ? 1u : 0u;
     }
+}
+
+template <int M>
+__device__ __forceinline__ void tile32_gram(unsigned char *lds, const float4 *__restrict__ Jg,
+                                            const double4 *__restrict__ J64t, int32_t jn, const GramI &g,
+                                            const double4 *__restrict__ I64, int64_t ibeg, const TileCtx &k,
+                                            const FewCtx &f) {
     uint32_t ngt[M];
 #pragma unroll
     for (int t = 0; t < M; ++t) ngt[t] = 0u;
@@ -614,20 +630,20 @@ __device__ __forceinline__ void tile32_gram(unsigned char *lds, const float4 *__
     load_j<NJ>(Jg, b0);
     for (; jj + 2 * NJ <= jn; jj += 2 * NJ) {
         load_j<NJ>(Jg + jj + NJ, b1);
-        step32_gram<M, NJ>(lds, b0, J64t, jj, ax, ay, az, na, I64, ibeg, k, f, ngt);
+        step32_gram<M, NJ>(lds, b0, J64t, jj, g.ax, g.ay, g.az, g.na, I64, ibeg, k, f, ngt);
         load_j<NJ>(Jg + jj + 2 * NJ, b0);
-        step32_gram<M, NJ>(lds, b1, J64t, jj + NJ, ax, ay, az, na, I64, ibeg, k, f, ngt);
+        step32_gram<M, NJ>(lds, b1, J64t, jj + NJ, g.ax, g.ay, g.az, g.na, I64, ibeg, k, f, ngt);
     }
     if (jj + NJ <= jn) {
-        step32_gram<M, NJ>(lds, b0, J64t, jj, ax, ay, az, na, I64, ibeg, k, f, ngt);
+        step32_gram<M, NJ>(lds, b0, J64t, jj, g.ax, g.ay, g.az, g.na, I64, ibeg, k, f, ngt);
         jj += NJ;
     }
     for (; jj < jn; ++jj) {
         float4 bt[1];
         load_j<1>(Jg + jj, bt);
-        step32_gram<M, 1>(lds, bt, J64t, jj, ax, ay, az, na, I64, ibeg, k, f, ngt);
+        step32_gram<M, 1>(lds, bt, J64t, jj, g.ax, g.ay, g.az, g.na, I64, ibeg, k, f, ngt);
     }
-    few_flush<M>(lds, ngt, valid * static_cast<uint32_t>(jn), f, k);
+    few_flush<M>(lds, ngt, g.valid * static_cast<uint32_t>(jn), f, k);
 }
 
 // ----------------------------------------------------------- matrix cores
@@ -817,10 +833,18 @@ __device__ __forceinline__ void tile64(unsigned char *lds, const double4 *__rest
 
 // ------------------------------------------------------- persistent kernel
 
+// Waves per SIMD asked of the register allocator.  The counting loops wait
+// on scalar loads of j-points, LDS and the i-point loads of each item, and
+// more resident waves hide that: on the 1M workload 3, 4, 5, 6 and 7 waves
+// per SIMD give 73, 61, 57, 54 and 53 ms.  At 6 (80 VGPRs) the allocator
+// spills a few values of the rarely taken re-check branches; at 7 the
+// spills reach the counting loops.  The matrix-core instance keeps 3.
 #ifdef PC_WAVES_PER_EU
 #define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PC_WAVES_PER_EU)))
-#else
+#elif defined(PC_NO_OCCUPANCY_HINT)
 #define PC_OCCUPANCY
+#else
+#define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MC ? 3 : 6)))
 #endif
 
 // MC: tile pairs marked by the prune pass go through the matrix cores (a
@@ -844,18 +868,17 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     uint32_t xs = 0;
     uint64_t wi = 0, end = 0;
 
+    // Carried from item to item: the queue position, the segment index and
+    // the histogram's owner (table, job, counters, words to clear, items
+    // since the last flush).  Everything else -- the segment and table
+    // descriptors and what derives from them -- is reloaded from constant
+    // memory for each item, so it does not hold registers while the pairs
+    // are counted.
     int s = 0;
-    SegDesc sd = ld_const_struct(p.segs);
     int cur_tab = -1, cur_job = -1;
-    int32_t n_edges = 0, cols = 64, clear_words = 0;
-    uint32_t row_bytes = 0, lane_off = 0;
+    int32_t clear_words = 0;
     unsigned long long *cur_counts = nullptr;
-    uint32_t clo = 0, chi = 0, shift = 0, lut_base = 0, trash_off = 0;
-    bool search = false;
-    const double *e64 = nullptr;
-    const float *band = nullptr, *band_g = nullptr;
-    uint64_t since_flush = 0, flush_every = 1;
-
+    uint64_t since_flush = 0;
 
     for (;; ++wi) {
         if (wi >= end) {
@@ -882,35 +905,41 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         const bool gram_j = !FP64 && ((raw >> 61) & 1u) != 0;
         const uint32_t few_m = FP64 ? 0u : static_cast<uint32_t>((raw >> (kItemBits + 11)) & 3u);
         const uint32_t few_k0 = static_cast<uint32_t>((raw >> kItemBits) & 2047u);
+#ifndef PC_SPLIT
+#define PC_SPLIT 1
+#endif
+        const bool split = PC_SPLIT && !FP64 && ((raw >> kSplitBit) & 1u) != 0;
+        // a split item's sub-block word, and the chord form of the item: a
+        // split item takes the Gram form when every open part allows it
+        const uint64_t sub = split ? ld_const(p.sub + wi) : 0ull;
+        bool gram_all = true;
+#pragma unroll
+        for (int q = 0; q < kSubs; ++q) {
+            const uint32_t w = static_cast<uint32_t>(sub >> (16 * q)) & 0xFFFFu;
+            if (!(w & kSubWhole) && !(w & kSubGram)) gram_all = false;
+        }
+        const bool use_gram = !FP64 && !(MC && to_mfma) && (split ? gram_all : (gram_j && few_m != 0u));
         const uint64_t it = raw & kItemMask;
+        SegDesc sd = ld_const_struct(p.segs + s);
         if (it < sd.item0 || it >= sd.item0 + sd.n_items) {
             s = find_seg(p.segs, p.n_segs, it);
             sd = ld_const_struct(p.segs + s);
         }
+        const TableDesc td = ld_const_struct(p.tabs + sd.tab);
+        const int32_t n_edges = td.n_edges;
+        const int32_t cols = td.cols;
         // a lane adds at most kTile * kR per item to a word it shares with
         // kWave / cols - 1 other lanes: flush before a 32-bit word can wrap
+        const uint64_t flush_every = 0xFFFFFFFFull / (static_cast<uint64_t>(kTile) * kR * static_cast<uint64_t>(kWave / cols));
         if (sd.tab != cur_tab || sd.job != cur_job || since_flush >= flush_every) {
-            if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);
+            if (cur_job >= 0) {
+                // the histogram holds the previous owner's rows, in its table's layout
+                const TableDesc tc = sd.tab == cur_tab ? td : ld_const_struct(p.tabs + cur_tab);
+                flush_hist(lds, tc.n_edges + 1, tc.cols, clear_words, cur_counts);
+            }
             if (sd.tab != cur_tab) {
-                const TableDesc td = ld_const_struct(p.tabs + sd.tab);
-                n_edges = td.n_edges;
-                band = td.band;
-                band_g = td.band_g;
-                clo = td.clamp_lo;
-                chi = td.clamp_hi;
-                shift = td.shift;
-                search = td.search != 0;
-                e64 = td.e64;
-                cols = td.cols;
-                flush_every = 0xFFFFFFFFull / (static_cast<uint64_t>(kTile) * kR * static_cast<uint64_t>(kWave / cols));
-                row_bytes = static_cast<uint32_t>(cols) * 4u;
-                // absolute LDS addresses: histogram at lds0, cell table at lds0 + lut_lds_off
-                lane_off = lds0 + (lane & static_cast<uint32_t>(cols - 1)) * 4u;
-                trash_off = static_cast<uint32_t>(n_edges + 1) * row_bytes + lane_off;
-                lut_base = lds0 + p.lut_lds_off - (td.key0 << 4);
                 // copy the cell table (or, for a search table, the edges) into LDS
-                if (FP64 && search) {
-                    lut_base = lds0 + p.lut_lds_off;
+                if (FP64 && td.search != 0) {
                     double *dst = reinterpret_cast<double *>(lds + p.lut_lds_off);
                     for (int32_t k = lane; k < n_edges; k += kWave) dst[k] = td.e64[k];
                 } else {
@@ -932,18 +961,35 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
             since_flush = 0;
         }
         ++since_flush;
+        // this table's layout: absolute LDS addresses, histogram at lds0,
+        // cell table (or edges) at lds0 + lut_lds_off
+        const bool search = td.search != 0;
+        const float *band = td.band, *band_g = td.band_g;
+        const uint32_t clo = td.clamp_lo, chi = td.clamp_hi;
+        const uint32_t row_bytes = static_cast<uint32_t>(cols) * 4u;
+        const uint32_t lane_off = lds0 + (lane & static_cast<uint32_t>(cols - 1)) * 4u;
+        const uint32_t trash_off = static_cast<uint32_t>(n_edges + 1) * row_bytes + lane_off;
+        const uint32_t lut_base = (FP64 && search) ? lds0 + p.lut_lds_off : lds0 + p.lut_lds_off - (td.key0 << 4);
 
         int64_t t, u;
         map_item(sd, it - sd.item0, t, u);
         const int64_t iend = sd.i0 + sd.ni;
         const int64_t ibeg = sd.i0 + t * kTile;
         const int32_t i_lim = static_cast<int32_t>(uniform(static_cast<uint32_t>(min<int64_t>(kTile, iend - ibeg))));
-        // the lane's i-points, reloaded per item (4 loads against 1024
-        // pairs; keeping them across items would hold registers in the
-        // matrix-core path too)
-        float fx[kR], fy[kR], fz[kR];
+        // the lane's i-points, reloaded per item (4 loads against 1024 pairs)
+        // and issued first, so that their latency passes while the item is
+        // set up: binary64 for that kernel and for the Gram form (centred on
+        // the j-tile once the loads are in), binary32 for the difference form
         double dx[kR], dy[kR], dz[kR];
-        if (FP64 || !((MC && to_mfma) || gram_j)) {
+        float fx[kR], fy[kR], fz[kR];
+        double4 gi[kR];
+        if (use_gram) {
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                const int32_t ir = r * kWave + static_cast<int32_t>(lane);
+                gi[r] = sd.i64[ibeg + (ir < i_lim ? ir : 0)];
+            }
+        } else if (FP64 || !(MC && to_mfma)) {
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 const int32_t ir = r * kWave + static_cast<int32_t>(lane);
@@ -968,7 +1014,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         const int32_t j_rel = static_cast<int32_t>(uniform(static_cast<uint32_t>(jbeg - ibeg)));
         const double4 *J64t = uniform_ptr(sd.j64 + jbeg);
         TileCtx k;
-        k.shift = shift;
+        k.shift = td.shift;
         k.lut_base = lut_base;
         k.lane_off = lane_off;
         k.trash_off = trash_off;
@@ -976,7 +1022,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         k.klo = __uint_as_float(clo);
         k.khi = __uint_as_float(chi);
         k.n_edges = n_edges;
-        k.e64 = e64;
+        k.e64 = td.e64;
         if (FP64) {
             if (search) {
                 if (masked)
@@ -989,13 +1035,29 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 else
                     tile64<false, false>(lds, J64t, jn, dx, dy, dz, i_lim, j_rel, diag, clo, chi, k);
             }
-        } else {
-            // bands of the few-edge item's edges k0 .. k0+m-1 (the matrix-core
-            // path's own bands there)
+        } else if (MC && to_mfma) {
+            // the prune pass marks only few-edge items for the matrix cores
+            FewCtx f;
+            f.k0 = few_k0;
+#pragma unroll
+            for (int q = 0; q < kFewMax; ++q) {
+                const uint32_t e = min(few_k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
+                const float2 v = ld_const_f2(band_g + 2u * e);
+                f.lo[q] = v.x;
+                f.hi[q] = v.y;
+            }
+            const double4 o = ld_const(centre_j ? sd.jb + u : sd.ib + t);
+            const double4 *I64t = uniform_ptr(sd.i64 + ibeg);
+            const uint32_t st = lds0 + p.stage_lds_off;
+            if (few_m == 1) tile_mfma<1>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
+            else if (few_m == 2) tile_mfma<2>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
+            else tile_mfma<3>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
+        } else if (!split) {
+            // one part: the whole j-tile with the item's own edges
             FewCtx f;
             f.k0 = few_k0;
             if (few_m) {
-                const float *bd = ((MC && to_mfma) || gram_j) ? band_g : band;
+                const float *bd = gram_j ? band_g : band;
 #pragma unroll
                 for (int q = 0; q < kFewMax; ++q) {
                     const uint32_t e = min(few_k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
@@ -1004,22 +1066,15 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                     f.hi[q] = v.y;
                 }
             }
-            if (MC && to_mfma) {
-                const double4 o = ld_const(centre_j ? sd.jb + u : sd.ib + t);
-                const double4 *I64t = uniform_ptr(sd.i64 + ibeg);
-                const uint32_t st = lds0 + p.stage_lds_off;
-                // the prune pass marks only few-edge items for the matrix cores
-                if (few_m == 1) tile_mfma<1>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
-                else if (few_m == 2) tile_mfma<2>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
-                else tile_mfma<3>(lds, st, I64t, J64t, o.x, o.y, o.z, k, f);
-            } else if (gram_j && few_m) {
+            if (use_gram) {
                 // not a diagonal tile; i slots past a ragged end are NaN
                 const double4 o = ld_const(sd.jb + u);
+                GramI g;
+                centre_i_gram(g, gi, i_lim, o.x, o.y, o.z);
                 const float4 *Jg = uniform_ptr(sd.jg + jbeg);
-                const double4 *I64 = sd.i64;
-                if (few_m == 1) tile32_gram<1>(lds, Jg, J64t, jn, I64, ibeg, i_lim, o.x, o.y, o.z, k, f);
-                else if (few_m == 2) tile32_gram<2>(lds, Jg, J64t, jn, I64, ibeg, i_lim, o.x, o.y, o.z, k, f);
-                else tile32_gram<3>(lds, Jg, J64t, jn, I64, ibeg, i_lim, o.x, o.y, o.z, k, f);
+                if (few_m == 1) tile32_gram<1>(lds, Jg, J64t, jn, g, sd.i64, ibeg, k, f);
+                else if (few_m == 2) tile32_gram<2>(lds, Jg, J64t, jn, g, sd.i64, ibeg, k, f);
+                else tile32_gram<3>(lds, Jg, J64t, jn, g, sd.i64, ibeg, k, f);
             } else {
                 const float4 *Jt = uniform_ptr(sd.j32 + jbeg);
                 if (masked) {
@@ -1034,9 +1089,82 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                     else tile32<false>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
                 }
             }
+        } else {
+            // A split item (full, off-diagonal) visits its open sub-blocks of
+            // kSub j-points, each with its own edges.  The lane's i-points
+            // are loaded once, in one chord form for all its parts: Gram form
+            // when every part allows it, else the difference form (its guard
+            // band holds for any pair, so a Gram-eligible part may use it too).
+            // the next run of parts from `part` on: consecutive open parts
+            // with the same description go in one call; its edges
+            // k0 .. k0+m-1 (m = 0: cell table) and j range.  False when no
+            // part is left (the prune pass binned the rest whole).
+            auto next_run = [&](int &part, uint32_t &m, uint32_t &k0, int64_t &jb, int32_t &nj) -> bool {
+                uint32_t w = 0;
+                for (; part < kSubs; ++part) {
+                    w = static_cast<uint32_t>(sub >> (16 * part)) & 0xFFFFu;
+                    if (!(w & kSubWhole)) break;
+                }
+                if (part >= kSubs) return false;
+                int len = 1;
+                while (part + len < kSubs && (static_cast<uint32_t>(sub >> (16 * (part + len))) & 0xFFFFu) == w) ++len;
+                k0 = w & 2047u;
+                m = (w >> 11) & 3u;
+                jb = jbeg + part * kSub;
+                nj = len * kSub;
+                part += len;
+                return true;
+            };
+            auto bands = [&](FewCtx &f, uint32_t m, uint32_t k0, const float *bd) {
+                f.k0 = k0;
+                if (m) {
+#pragma unroll
+                    for (int q = 0; q < kFewMax; ++q) {
+                        const uint32_t e = min(k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
+                        const float2 v = ld_const_f2(bd + 2u * e);
+                        f.lo[q] = v.x;
+                        f.hi[q] = v.y;
+                    }
+                }
+            };
+            if (use_gram) {
+                // not a diagonal tile; i slots past a ragged end are NaN
+                const double4 o = ld_const(sd.jb + u);
+                GramI g;
+                centre_i_gram(g, gi, i_lim, o.x, o.y, o.z);
+                uint32_t m, k0;
+                int64_t jb;
+                int32_t nj;
+                for (int part = 0; next_run(part, m, k0, jb, nj);) {
+                    FewCtx f;
+                    bands(f, m, k0, band_g);
+                    const float4 *Jg = uniform_ptr(sd.jg + jb);
+                    const double4 *J64p = uniform_ptr(sd.j64 + jb);
+                    if (m == 1) tile32_gram<1>(lds, Jg, J64p, nj, g, sd.i64, ibeg, k, f);
+                    else if (m == 2) tile32_gram<2>(lds, Jg, J64p, nj, g, sd.i64, ibeg, k, f);
+                    else tile32_gram<3>(lds, Jg, J64p, nj, g, sd.i64, ibeg, k, f);
+                }
+            } else {
+                uint32_t m, k0;
+                int64_t jb;
+                int32_t nj;
+                for (int part = 0; next_run(part, m, k0, jb, nj);) {
+                    FewCtx f;
+                    bands(f, m, k0, band);
+                    const float4 *Jt = uniform_ptr(sd.j32 + jb);
+                    const double4 *J64p = uniform_ptr(sd.j64 + jb);
+                    if (m == 1) tile32_few<false, 1>(lds, Jt, J64p, nj, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, false, k, f);
+                    else if (m == 2) tile32_few<false, 2>(lds, Jt, J64p, nj, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, false, k, f);
+                    else if (m == 3) tile32_few<false, 3>(lds, Jt, J64p, nj, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, false, k, f);
+                    else tile32<false>(lds, Jt, J64p, nj, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, false, k);
+                }
+            }
         }
     }
-    if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);
+    if (cur_job >= 0) {
+        const TableDesc tc = ld_const_struct(p.tabs + cur_tab);
+        flush_hist(lds, tc.n_edges + 1, tc.cols, clear_words, cur_counts);
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1057,8 +1185,8 @@ hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
-                        const uint64_t *items, const unsigned long long *n_items, uint64_t total_items,
-                        uint32_t lut_lds_off, uint32_t stage_lds_off,
+                        const uint64_t *items, const unsigned long long *n_items, const uint64_t *sub,
+                        uint64_t total_items, uint32_t lut_lds_off, uint32_t stage_lds_off,
                         unsigned long long *queue, int chunk, uint32_t lds_bytes, int grid, hipStream_t st) {
     KParams p;
     p.queue = queue;
@@ -1067,6 +1195,7 @@ hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs,
     p.tabs = tabs;
     p.items = items;
     p.n_items = n_items;
+    p.sub = sub;
     p.total_items = total_items;
     p.n_segs = n_segs;
     p.lut_lds_off = lut_lds_off;

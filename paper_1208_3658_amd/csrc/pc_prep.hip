@@ -169,32 +169,14 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // One wave per tile of kTile sorted points: centre = normalised mean, radius
 // = largest distance from the centre, rounded outward.  Written as
-// (cx, cy, cz, r).  Each point is also written in Gram form centred on that
-// centre: b' = RN32(b - c) (difference in binary64), (-2 b'_x, -2 b'_y,
-// -2 b'_z, |b'|^2) with |b'|^2 formed in binary32 as z*z + (y*y + x*x) by
-// fused multiply-adds.
-__global__ void __launch_bounds__(kWave) k_bounds(const double4 *__restrict__ a64s, int64_t n,
-                                                  double4 *__restrict__ bounds, float4 *__restrict__ g32s) {
-    const int64_t t = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int64_t b = t * kTile;
-    double sx = 0, sy = 0, sz = 0;
-    double4 p[kR];
-    bool ok[kR];
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-        const int64_t i = b + r * kWave + lane;
-        ok[r] = i < n;
-        p[r] = a64s[ok[r] ? i : b];
-        if (ok[r]) {
-            sx += p[r].x;
-            sy += p[r].y;
-            sz += p[r].z;
-        }
-    }
-    sx = wave_sum(sx);
-    sy = wave_sum(sy);
-    sz = wave_sum(sz);
+// (cx, cy, cz, r).  The same for each of the tile's kSubs sub-blocks of kSub
+// points (the r-th point of every lane: sub-block r), into sub[kSubs t + r].
+// Each point is also written in Gram form centred on the tile's centre:
+// b' = RN32(b - c) (difference in binary64), (-2 b'_x, -2 b'_y, -2 b'_z,
+// |b'|^2) with |b'|^2 formed in binary32 as z*z + (y*y + x*x) by fused
+// multiply-adds.
+__device__ __forceinline__ double4 ball_of(const double4 *p, const bool *ok, int rows, double sx, double sy,
+                                           double sz, double4 fallback) {
     const double norm = sqrt(sx * sx + sy * sy + sz * sz);
     double cx, cy, cz;
     if (norm > 1e-6) {
@@ -202,21 +184,56 @@ __global__ void __launch_bounds__(kWave) k_bounds(const double4 *__restrict__ a6
         cy = sy / norm;
         cz = sz / norm;
     } else {
-        const double4 f = a64s[b];
-        cx = f.x;
-        cy = f.y;
-        cz = f.z;
+        cx = fallback.x;
+        cy = fallback.y;
+        cz = fallback.z;
     }
     double m = 0.0;
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
+    for (int r = 0; r < rows; ++r) {
         if (ok[r]) {
             const double dx = p[r].x - cx, dy = p[r].y - cy, dz = p[r].z - cz;
             m = fmax(m, dx * dx + dy * dy + dz * dz);
         }
     }
     m = wave_max(m);
-    if (lane == 0) bounds[t] = make_double4(cx, cy, cz, sqrt(m) * (1.0 + 0x1p-40) + 0x1p-60);
+    return make_double4(cx, cy, cz, sqrt(m) * (1.0 + 0x1p-40) + 0x1p-60);
+}
+
+__global__ void __launch_bounds__(kWave) k_bounds(const double4 *__restrict__ a64s, int64_t n,
+                                                  double4 *__restrict__ bounds, double4 *__restrict__ sub,
+                                                  float4 *__restrict__ g32s) {
+    static_assert(kSub == kWave, "a sub-block is one point per lane");
+    const int64_t t = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t b = t * kTile;
+    double sx = 0, sy = 0, sz = 0;
+    double4 p[kR];
+    bool ok[kR];
+    double4 rs[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int64_t i = b + r * kWave + lane;
+        ok[r] = i < n;
+        p[r] = a64s[ok[r] ? i : b];
+        // every lane takes part in the reductions; lanes past the end add 0
+        rs[r] = make_double4(wave_sum(ok[r] ? p[r].x : 0.0), wave_sum(ok[r] ? p[r].y : 0.0),
+                             wave_sum(ok[r] ? p[r].z : 0.0), 0.0);
+        sx += rs[r].x;
+        sy += rs[r].y;
+        sz += rs[r].z;
+    }
+    const double4 first = a64s[b];
+    const double4 tb = ball_of(p, ok, kR, sx, sy, sz, first);
+    if (lane == 0) bounds[t] = tb;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        // an empty sub-block (past a ragged end) gets the tile's ball; it is
+        // never split from
+        const bool any = __ballot(ok[r]) != 0ull;
+        const double4 sb = any ? ball_of(&p[r], &ok[r], 1, rs[r].x, rs[r].y, rs[r].z, first) : tb;
+        if (lane == 0) sub[t * kSubs + r] = sb;
+    }
+    const double cx = tb.x, cy = tb.y, cz = tb.z;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         if (ok[r]) {
@@ -255,28 +272,38 @@ struct PruneOut {
     int32_t bin;
     uint64_t pairs;
     uint64_t tags;  // bits 40..63 of the survivor entry
+    uint64_t sub;   // sub-block word of a split item, else 0
 };
 
-template <typename P>
-__device__ __forceinline__ PruneOut prune_item(const SegDesc &sd, int64_t t, int64_t u, P e, int32_t n_edges,
-                                               int32_t mfma_ok) {
-    PruneOut o;
-    const int64_t ni = min<int64_t>(kTile, sd.ni - t * kTile);
-    const int64_t nj = min<int64_t>(kTile, sd.nj - u * kTile);
-    const bool diag = sd.tri && t == u;
-    o.pairs = diag ? static_cast<uint64_t>(ni * (ni - 1) / 2) : static_cast<uint64_t>(ni * nj);
-    const double4 bi = sd.ib[t];
-    const double4 bj = sd.jb[u];
+// Squared-chord interval of the pairs between two balls (centre, radius):
+// [c_lo, c_hi], and the chord lower bound lo.
+__device__ __forceinline__ void chord_interval(const double4 &bi, const double4 &bj, double &lo, double &c_lo,
+                                               double &c_hi) {
     // outward-rounded bounds: distance of the centres (+-2^-45 relative),
     // radii (+2^-45), absolute 2^-50 for the subtraction, then the squared
     // chord interval widened by 1e-12 relative and 1e-300 absolute
     const double dx = bi.x - bj.x, dy = bi.y - bj.y, dz = bi.z - bj.z;
     const double d = sqrt(dx * dx + dy * dy + dz * dz);
     const double rs = (bi.w + bj.w) * (1.0 + 0x1p-45);
-    const double lo = fmax(0.0, d * (1.0 - 0x1p-45) - rs - 0x1p-50);
+    lo = fmax(0.0, d * (1.0 - 0x1p-45) - rs - 0x1p-50);
     const double hi = d * (1.0 + 0x1p-45) + rs + 0x1p-50;
-    const double c_lo = lo * lo * (1.0 - 1e-12) - 1e-300;
-    const double c_hi = hi * hi * (1.0 + 1e-12) + 1e-300;
+    c_lo = lo * lo * (1.0 - 1e-12) - 1e-300;
+    c_hi = hi * hi * (1.0 + 1e-12) + 1e-300;
+}
+
+template <typename P>
+__device__ __forceinline__ PruneOut prune_item(const SegDesc &sd, int64_t t, int64_t u, P e, int32_t n_edges,
+                                               int32_t mfma_ok, int32_t split_ok) {
+    PruneOut o;
+    o.sub = 0;
+    const int64_t ni = min<int64_t>(kTile, sd.ni - t * kTile);
+    const int64_t nj = min<int64_t>(kTile, sd.nj - u * kTile);
+    const bool diag = sd.tri && t == u;
+    o.pairs = diag ? static_cast<uint64_t>(ni * (ni - 1) / 2) : static_cast<uint64_t>(ni * nj);
+    const double4 bi = sd.ib[t];
+    const double4 bj = sd.jb[u];
+    double lo, c_lo, c_hi;
+    chord_interval(bi, bj, lo, c_lo, c_hi);
     const uint32_t k_lo = count_le(e, n_edges, c_lo);
     const uint32_t k_hi = count_le(e, n_edges, c_hi);
     if (k_lo == k_hi) {
@@ -295,12 +322,46 @@ __device__ __forceinline__ PruneOut prune_item(const SegDesc &sd, int64_t t, int
     // centred on the j-tile when that one is smaller (bit 62); otherwise the
     // vector path forms Gram chords centred on the j-tile (bit 61) under the
     // same condition on the j radius
-    const bool mfma = mfma_ok && is_few && !diag && ni == kTile && nj == kTile && 2.0 * fmin(bi.w, bj.w) <= lo;
+    const bool full = ni == kTile && nj == kTile;
+    const bool mfma = mfma_ok && is_few && !diag && full && 2.0 * fmin(bi.w, bj.w) <= lo;
     const bool gram_j = !mfma && is_few && !diag && 2.0 * bj.w <= lo;
     o.tags = (static_cast<uint64_t>(k_lo) << kItemBits) |
              (static_cast<uint64_t>(is_few ? m : 0u) << (kItemBits + 11)) | (mfma ? (1ull << 63) : 0ull) |
              ((mfma && bj.w < bi.w) ? (1ull << 62) : 0ull) | (gram_j ? (1ull << 61) : 0ull);
+    if (split_ok && !mfma && !diag && full) {
+        // the same decision for each sub-block of the j-tile; the Gram form
+        // stays centred on the whole j-tile, so its condition keeps the
+        // j-tile's radius against the sub-block's chord lower bound
+        uint64_t w = 0;
+#pragma unroll
+        for (int s = 0; s < kSubs; ++s) {
+            const double4 bs = sd.jb_sub[u * kSubs + s];
+            double lo_s, cl, ch;
+            chord_interval(bi, bs, lo_s, cl, ch);
+            const uint32_t kl = count_le(e, n_edges, cl);
+            const uint32_t kh = count_le(e, n_edges, ch);
+            uint32_t f;
+            if (kl == kh) {
+                f = kl | kSubWhole;
+            } else {
+                const uint32_t ms = kh - kl;
+                const bool few = ms <= static_cast<uint32_t>(PC_FEWCUT);
+                f = kl | ((few ? ms : 0u) << 11) | ((few && 2.0 * bj.w <= lo_s) ? kSubGram : 0u);
+            }
+            w |= static_cast<uint64_t>(f) << (16 * s);
+        }
+        o.sub = w;
+        o.tags |= 1ull << kSplitBit;
+    }
     return o;
+}
+
+// Sub-blocks of a split item left for the counting kernel.
+__device__ __forceinline__ uint32_t open_subs(uint64_t w) {
+    uint32_t n = 0;
+#pragma unroll
+    for (int s = 0; s < kSubs; ++s) n += (((w >> (16 * s)) & kSubWhole) == 0u) ? 1u : 0u;
+    return n;
 }
 
 // (t, u) and item number of column c of prune row r (map_item's fold for a
@@ -335,15 +396,17 @@ __device__ __forceinline__ bool row_item(const SegDesc &sd, int64_t r, int64_t c
 // global atomics on a few shared counters would otherwise serialise the pass.
 __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs, int32_t n_segs,
                                                const TableDesc *__restrict__ tabs,
-                                               uint64_t *__restrict__ survivors,
-                                               unsigned long long *__restrict__ meta, int32_t mfma_ok) {
-    // meta[0] = survivors, meta[1] = pairs in survivors, meta[2] = pairs binned
-    // whole, meta[3] = survivors marked for the matrix cores, meta[4] =
-    // survivors with at most kFewMax edges in their chord interval, meta[5] =
-    // survivors whose vector-path chords are formed in Gram form
+                                               uint64_t *__restrict__ survivors, uint64_t *__restrict__ sub_out,
+                                               unsigned long long *__restrict__ meta, int32_t mfma_ok,
+                                               int32_t split_ok) {
+    // meta[0] = survivors, meta[1] = pairs left for the counting kernel,
+    // meta[2] = pairs binned whole, meta[3] = survivors marked for the matrix
+    // cores; work units (a survivor, or an open sub-block of a split one):
+    // meta[4] with at most PC_FEWCUT edges in their chord interval, meta[5]
+    // with vector-path chords in Gram form; meta[6] = split survivors
     __shared__ double e_lds[kMaxEdges];
     __shared__ unsigned long long h_lds[kMaxEdges + 1];
-    __shared__ unsigned long long s_stat[5];  // survivors, pairs, matrix-core, few-edge, Gram
+    __shared__ unsigned long long s_stat[6];  // survivors, pairs, matrix-core, few-edge, Gram, split
     __shared__ unsigned long long s_base, s_whole;
     __shared__ unsigned int s_cursor;
     const int64_t row_g = blockIdx.x;
@@ -364,7 +427,7 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
     const int lane = tid & (kWave - 1);
     for (int32_t k = tid; k < n_edges; k += blockDim.x) e_lds[k] = td.e64[k];
     for (int32_t k = tid; k <= n_edges; k += blockDim.x) h_lds[k] = 0ull;
-    if (tid < 5) s_stat[tid] = 0ull;
+    if (tid < 6) s_stat[tid] = 0ull;
     if (tid == 0) {
         s_whole = 0ull;
         s_cursor = 0u;
@@ -372,37 +435,60 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
     __syncthreads();
     const int64_t r = row_g - sd.prow0;
     const int64_t cols = sd.tri ? sd.tiles_i + 1 : sd.tiles_j;
+    constexpr unsigned long long kSubPairs = static_cast<unsigned long long>(kTile) * kSub;
 
-    // pass 1: histogram of whole tile pairs, statistics of survivors
+    // pass 1: histogram of whole tile pairs and sub-blocks, statistics of survivors
     for (int64_t c0 = 0; c0 < cols; c0 += blockDim.x) {
         int64_t t, u;
         uint64_t q;
         const bool valid = row_item(sd, r, c0 + tid, t, u, q);
         bool survive = false;
-        uint64_t pairs = 0, tags = 0;
+        unsigned long long pairs = 0, few_u = 0, gram_u = 0;
+        uint64_t tags = 0, sub = 0;
         if (valid) {
-            const PruneOut o = prune_item(sd, t, u, e_lds, n_edges, mfma_ok);
-            if (o.bin >= 0) atomicAdd(&h_lds[o.bin], static_cast<unsigned long long>(o.pairs));
-            else {
+            const PruneOut o = prune_item(sd, t, u, e_lds, n_edges, mfma_ok, split_ok);
+            if (o.bin >= 0) {
+                atomicAdd(&h_lds[o.bin], static_cast<unsigned long long>(o.pairs));
+            } else if (o.sub) {
+                sub = o.sub;
+                tags = o.tags;
+#pragma unroll
+                for (int k = 0; k < kSubs; ++k) {
+                    const uint32_t f = static_cast<uint32_t>(o.sub >> (16 * k)) & 0xFFFFu;
+                    if (f & kSubWhole) {
+                        atomicAdd(&h_lds[f & 2047u], kSubPairs);
+                    } else {
+                        pairs += kSubPairs;
+                        few_u += ((f >> 11) & 3u) != 0u ? 1ull : 0ull;
+                        gram_u += (f & kSubGram) != 0u ? 1ull : 0ull;
+                    }
+                }
+                survive = pairs != 0;
+            } else {
                 survive = true;
                 pairs = o.pairs;
                 tags = o.tags;
+                few_u = ((tags >> (kItemBits + 11)) & 3u) != 0 ? 1ull : 0ull;
+                gram_u = ((tags >> 61) & 1u) != 0 ? 1ull : 0ull;
             }
         }
         const uint64_t sm = __ballot(survive);
         if (sm) {
-            unsigned long long p = survive ? pairs : 0ull;
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
+            for (int o = 32; o > 0; o >>= 1) {
+                pairs += __shfl_xor(pairs, o, kWave);
+                few_u += __shfl_xor(few_u, o, kWave);
+                gram_u += __shfl_xor(gram_u, o, kWave);
+            }
             const uint64_t mm = __ballot(survive && (tags >> 63) != 0);
-            const uint64_t mf = __ballot(survive && ((tags >> (kItemBits + 11)) & 3u) != 0);
-            const uint64_t mg = __ballot(survive && ((tags >> 61) & 1u) != 0);
+            const uint64_t ms = __ballot(survive && sub != 0);
             if (lane == 0) {
                 atomicAdd(&s_stat[0], static_cast<unsigned long long>(__popcll(sm)));
-                atomicAdd(&s_stat[1], p);
+                atomicAdd(&s_stat[1], pairs);
                 atomicAdd(&s_stat[2], static_cast<unsigned long long>(__popcll(mm)));
-                atomicAdd(&s_stat[3], static_cast<unsigned long long>(__popcll(mf)));
-                atomicAdd(&s_stat[4], static_cast<unsigned long long>(__popcll(mg)));
+                atomicAdd(&s_stat[3], few_u);
+                atomicAdd(&s_stat[4], gram_u);
+                atomicAdd(&s_stat[5], static_cast<unsigned long long>(__popcll(ms)));
             }
         }
     }
@@ -417,11 +503,12 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
             uint64_t q;
             const bool valid = row_item(sd, r, c0 + tid, t, u, q);
             bool survive = false;
-            uint64_t tags = 0;
+            uint64_t tags = 0, sub = 0;
             if (valid) {
-                const PruneOut o = prune_item(sd, t, u, e_lds, n_edges, mfma_ok);
-                survive = o.bin < 0;
+                const PruneOut o = prune_item(sd, t, u, e_lds, n_edges, mfma_ok, split_ok);
+                survive = o.bin < 0 && (o.sub == 0 || open_subs(o.sub) != 0);
                 tags = o.tags;
+                sub = o.sub;
             }
             const uint64_t sm = __ballot(survive);
             if (sm) {
@@ -430,7 +517,11 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                 if (lane == __ffsll(static_cast<long long>(sm)) - 1)
                     at = atomicAdd(&s_cursor, static_cast<unsigned int>(__popcll(sm)));
                 at = __shfl(at, __ffsll(static_cast<long long>(sm)) - 1, kWave);
-                if (survive) survivors[s_base + at + __popcll(below)] = (sd.item0 + q) | tags;
+                if (survive) {
+                    const uint64_t slot = s_base + at + __popcll(below);
+                    survivors[slot] = (sd.item0 + q) | tags;
+                    if (sub_out) sub_out[slot] = sub;
+                }
             }
         }
     }
@@ -455,6 +546,7 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
             if (s_stat[2]) atomicAdd(meta + 3, s_stat[2]);
             if (s_stat[3]) atomicAdd(meta + 4, s_stat[3]);
             if (s_stat[4]) atomicAdd(meta + 5, s_stat[4]);
+            if (s_stat[5]) atomicAdd(meta + 6, s_stat[5]);
         }
     }
 }
@@ -500,7 +592,8 @@ hipError_t launch_exclusive_scan(uint32_t *a, int64_t m, uint32_t *sums, hipStre
 }
 
 // Spatially ordered copy of src[base, base+n) into a64s/a32s, and the tile
-// bounds.  scratch: sort_scratch_words(n) uint32 words.
+// bounds: bounds[0, T) for the T tiles, then bounds[T, T + kSubs T) for their
+// sub-blocks.  scratch: sort_scratch_words(n) uint32 words.
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
                        float4 *a32s, float4 *g32s, double4 *bounds, hipStream_t st) {
     if (n <= 0) return hipSuccess;
@@ -518,16 +611,17 @@ hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *sc
     k_scan_add<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(hist, m, sums);
     k_scatter<<<dim3(gn), dim3(256), 0, st>>>(src, base, n, keys, hist, a64s, a32s);
     const int64_t tiles = (n + kTile - 1) / kTile;
-    k_bounds<<<dim3(static_cast<uint32_t>(tiles)), dim3(kWave), 0, st>>>(a64s, n, bounds, g32s);
+    k_bounds<<<dim3(static_cast<uint32_t>(tiles)), dim3(kWave), 0, st>>>(a64s, n, bounds, bounds + tiles, g32s);
     return hipGetLastError();
 }
 
 hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, int64_t total_rows,
-                        uint64_t *survivors, unsigned long long *meta, int32_t mfma_ok, hipStream_t st) {
+                        uint64_t *survivors, uint64_t *sub, unsigned long long *meta, int32_t mfma_ok,
+                        int32_t split_ok, hipStream_t st) {
     if (total_rows <= 0) return hipSuccess;
     if (total_rows > 0x7FFFFFFF) return hipErrorInvalidValue;
-    k_prune<<<dim3(static_cast<uint32_t>(total_rows)), dim3(256), 0, st>>>(segs, n_segs, tabs, survivors, meta,
-                                                                          mfma_ok);
+    k_prune<<<dim3(static_cast<uint32_t>(total_rows)), dim3(256), 0, st>>>(segs, n_segs, tabs, survivors, sub, meta,
+                                                                          mfma_ok, split_ok);
     return hipGetLastError();
 }
 

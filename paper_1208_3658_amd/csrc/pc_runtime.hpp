@@ -83,8 +83,9 @@ struct BatchStats {
     uint64_t pairs_total = 0;     // pairs counted by the launch
     uint64_t pairs_computed = 0;  // pairs visited one by one
     uint64_t mfma_items = 0;      // of the survivors, tile pairs done on the matrix cores
-    uint64_t few_items = 0;       // of the survivors, tile pairs with at most kFewMax edges inside
-    uint64_t gram_items = 0;      // of the survivors, tile pairs with Gram-form chords on the vector path
+    uint64_t few_items = 0;       // work units (survivors, or open sub-blocks of split ones) with few edges inside
+    uint64_t gram_items = 0;      // work units with Gram-form chords on the vector path
+    uint64_t split_items = 0;     // survivors visited as sub-blocks of the j-tile
 };
 
 // Launch parameters a tuner may choose (all give the same counts):
