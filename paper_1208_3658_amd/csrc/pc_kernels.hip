@@ -70,6 +70,13 @@ __global__ void __launch_bounds__(256) k_zero_u64(unsigned long long *p, int64_t
     if (i < n) p[i] = 0ull;
 }
 
+#ifndef PC_SPLIT
+#define PC_SPLIT 1  // split items (sub-blocks of the j-tile) from the prune pass
+#endif
+#ifndef PC_EARLY_GRAM
+#define PC_EARLY_GRAM 0  // 1: Gram-form items load their binary64 i-points first too (more registers)
+#endif
+
 // ------------------------------------------------------------ helpers
 
 // Loads through the constant address space: the addresses below are the
@@ -835,16 +842,16 @@ __device__ __forceinline__ void tile64(unsigned char *lds, const double4 *__rest
 
 // Waves per SIMD asked of the register allocator.  The counting loops wait
 // on scalar loads of j-points, LDS and the i-point loads of each item, and
-// more resident waves hide that: on the 1M workload 3, 4, 5, 6 and 7 waves
-// per SIMD give 73, 61, 57, 54 and 53 ms.  At 6 (80 VGPRs) the allocator
-// spills a few values of the rarely taken re-check branches; at 7 the
-// spills reach the counting loops.  The matrix-core instance keeps 3.
+// more resident waves hide that: on the 1M workload 3, 4, 5, 6, 7 and 8 waves
+// per SIMD give 73, 61, 57, 53, 52 and 56 ms.  At 7 (72 VGPRs) the
+// allocator spills to scratch, mostly around the rarely taken binary64
+// re-check branches.  The matrix-core instance keeps 3.
 #ifdef PC_WAVES_PER_EU
 #define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PC_WAVES_PER_EU)))
 #elif defined(PC_NO_OCCUPANCY_HINT)
 #define PC_OCCUPANCY
 #else
-#define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MC ? 3 : 6)))
+#define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MC ? 3 : 7)))
 #endif
 
 // MC: tile pairs marked by the prune pass go through the matrix cores (a
@@ -868,17 +875,21 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     uint32_t xs = 0;
     uint64_t wi = 0, end = 0;
 
-    // Carried from item to item: the queue position, the segment index and
-    // the histogram's owner (table, job, counters, words to clear, items
-    // since the last flush).  Everything else -- the segment and table
-    // descriptors and what derives from them -- is reloaded from constant
-    // memory for each item, so it does not hold registers while the pairs
-    // are counted.
+    // Carried from item to item: the queue position, the current segment's
+    // descriptor, the histogram's owner (table, job, counters, words to
+    // clear, items since the last flush) and the table's layout.
     int s = 0;
     int cur_tab = -1, cur_job = -1;
     int32_t clear_words = 0;
     unsigned long long *cur_counts = nullptr;
     uint64_t since_flush = 0;
+    SegDesc sd = ld_const_struct(p.segs);
+    int32_t n_edges = 0, cols = 64;
+    uint32_t row_bytes = 0, lane_off = 0, clo = 0, chi = 0, shift = 0, lut_base = 0, trash_off = 0;
+    bool search = false;
+    const double *e64 = nullptr;
+    const float *band = nullptr, *band_g = nullptr;
+    uint64_t flush_every = 1;
 
     for (;; ++wi) {
         if (wi >= end) {
@@ -905,9 +916,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         const bool gram_j = !FP64 && ((raw >> 61) & 1u) != 0;
         const uint32_t few_m = FP64 ? 0u : static_cast<uint32_t>((raw >> (kItemBits + 11)) & 3u);
         const uint32_t few_k0 = static_cast<uint32_t>((raw >> kItemBits) & 2047u);
-#ifndef PC_SPLIT
-#define PC_SPLIT 1
-#endif
+
         const bool split = PC_SPLIT && !FP64 && ((raw >> kSplitBit) & 1u) != 0;
         // a split item's sub-block word, and the chord form of the item: a
         // split item takes the Gram form when every open part allows it
@@ -920,26 +929,32 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         }
         const bool use_gram = !FP64 && !(MC && to_mfma) && (split ? gram_all : (gram_j && few_m != 0u));
         const uint64_t it = raw & kItemMask;
-        SegDesc sd = ld_const_struct(p.segs + s);
         if (it < sd.item0 || it >= sd.item0 + sd.n_items) {
             s = find_seg(p.segs, p.n_segs, it);
             sd = ld_const_struct(p.segs + s);
         }
-        const TableDesc td = ld_const_struct(p.tabs + sd.tab);
-        const int32_t n_edges = td.n_edges;
-        const int32_t cols = td.cols;
         // a lane adds at most kTile * kR per item to a word it shares with
         // kWave / cols - 1 other lanes: flush before a 32-bit word can wrap
-        const uint64_t flush_every = 0xFFFFFFFFull / (static_cast<uint64_t>(kTile) * kR * static_cast<uint64_t>(kWave / cols));
         if (sd.tab != cur_tab || sd.job != cur_job || since_flush >= flush_every) {
-            if (cur_job >= 0) {
-                // the histogram holds the previous owner's rows, in its table's layout
-                const TableDesc tc = sd.tab == cur_tab ? td : ld_const_struct(p.tabs + cur_tab);
-                flush_hist(lds, tc.n_edges + 1, tc.cols, clear_words, cur_counts);
-            }
+            if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);
             if (sd.tab != cur_tab) {
+                const TableDesc td = ld_const_struct(p.tabs + sd.tab);
+                n_edges = td.n_edges;
+                band = td.band;
+                band_g = td.band_g;
+                clo = td.clamp_lo;
+                chi = td.clamp_hi;
+                shift = td.shift;
+                search = td.search != 0;
+                e64 = td.e64;
+                cols = td.cols;
+                flush_every = 0xFFFFFFFFull / (static_cast<uint64_t>(kTile) * kR * static_cast<uint64_t>(kWave / cols));
+                row_bytes = static_cast<uint32_t>(cols) * 4u;
+                lane_off = lds0 + (lane & static_cast<uint32_t>(cols - 1)) * 4u;
+                trash_off = static_cast<uint32_t>(n_edges + 1) * row_bytes + lane_off;
+                lut_base = (FP64 && search) ? lds0 + p.lut_lds_off : lds0 + p.lut_lds_off - (td.key0 << 4);
                 // copy the cell table (or, for a search table, the edges) into LDS
-                if (FP64 && td.search != 0) {
+                if (FP64 && search) {
                     double *dst = reinterpret_cast<double *>(lds + p.lut_lds_off);
                     for (int32_t k = lane; k < n_edges; k += kWave) dst[k] = td.e64[k];
                 } else {
@@ -947,8 +962,6 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                     uint4 *dst = reinterpret_cast<uint4 *>(lds + p.lut_lds_off);
                     for (int32_t k = lane; k < td.n_cells; k += kWave) dst[k] = src[k];
                 }
-                // histogram words this table uses; anything beyond what was
-                // cleared before is cleared now
                 const int32_t words = (n_edges + 2) * cols;
                 uint32_t *h = reinterpret_cast<uint32_t *>(lds);
                 for (int32_t x = lane + (cur_job < 0 ? 0 : clear_words); x < words; x += kWave) h[x] = 0u;
@@ -961,16 +974,6 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
             since_flush = 0;
         }
         ++since_flush;
-        // this table's layout: absolute LDS addresses, histogram at lds0,
-        // cell table (or edges) at lds0 + lut_lds_off
-        const bool search = td.search != 0;
-        const float *band = td.band, *band_g = td.band_g;
-        const uint32_t clo = td.clamp_lo, chi = td.clamp_hi;
-        const uint32_t row_bytes = static_cast<uint32_t>(cols) * 4u;
-        const uint32_t lane_off = lds0 + (lane & static_cast<uint32_t>(cols - 1)) * 4u;
-        const uint32_t trash_off = static_cast<uint32_t>(n_edges + 1) * row_bytes + lane_off;
-        const uint32_t lut_base = (FP64 && search) ? lds0 + p.lut_lds_off : lds0 + p.lut_lds_off - (td.key0 << 4);
-
         int64_t t, u;
         map_item(sd, it - sd.item0, t, u);
         const int64_t iend = sd.i0 + sd.ni;
@@ -983,12 +986,15 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         double dx[kR], dy[kR], dz[kR];
         float fx[kR], fy[kR], fz[kR];
         double4 gi[kR];
-        if (use_gram) {
+        auto load_gi = [&]() {
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 const int32_t ir = r * kWave + static_cast<int32_t>(lane);
                 gi[r] = sd.i64[ibeg + (ir < i_lim ? ir : 0)];
             }
+        };
+        if (use_gram) {
+            if (PC_EARLY_GRAM) load_gi();
         } else if (FP64 || !(MC && to_mfma)) {
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
@@ -1014,7 +1020,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         const int32_t j_rel = static_cast<int32_t>(uniform(static_cast<uint32_t>(jbeg - ibeg)));
         const double4 *J64t = uniform_ptr(sd.j64 + jbeg);
         TileCtx k;
-        k.shift = td.shift;
+        k.shift = shift;
         k.lut_base = lut_base;
         k.lane_off = lane_off;
         k.trash_off = trash_off;
@@ -1022,7 +1028,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         k.klo = __uint_as_float(clo);
         k.khi = __uint_as_float(chi);
         k.n_edges = n_edges;
-        k.e64 = td.e64;
+        k.e64 = e64;
         if (FP64) {
             if (search) {
                 if (masked)
@@ -1070,6 +1076,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 // not a diagonal tile; i slots past a ragged end are NaN
                 const double4 o = ld_const(sd.jb + u);
                 GramI g;
+                if (!PC_EARLY_GRAM) load_gi();
                 centre_i_gram(g, gi, i_lim, o.x, o.y, o.z);
                 const float4 *Jg = uniform_ptr(sd.jg + jbeg);
                 if (few_m == 1) tile32_gram<1>(lds, Jg, J64t, jn, g, sd.i64, ibeg, k, f);
@@ -1131,6 +1138,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 // not a diagonal tile; i slots past a ragged end are NaN
                 const double4 o = ld_const(sd.jb + u);
                 GramI g;
+                if (!PC_EARLY_GRAM) load_gi();
                 centre_i_gram(g, gi, i_lim, o.x, o.y, o.z);
                 uint32_t m, k0;
                 int64_t jb;
@@ -1161,10 +1169,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
             }
         }
     }
-    if (cur_job >= 0) {
-        const TableDesc tc = ld_const_struct(p.tabs + cur_tab);
-        flush_hist(lds, tc.n_edges + 1, tc.cols, clear_words, cur_counts);
-    }
+    if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);
 }
 
 // ---------------------------------------------------------------- launchers
