@@ -193,13 +193,14 @@ def cpu_baseline(c, target_s: float):
             "sample": f"DD, DR and RR over the first {r} rows of the 1M workload ({pairs:.3e} pairs, {dt:.1f} s)"}
 
 
-def serve_run(pc, n_req: int, seed_config: int = 5):
+def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: bool = True):
     """Stream of w(theta) requests (config: N log-uniform 1e3..2e6, clustered
     on one of 4 pool patches of side 5-50 deg, 10-50 log bins).  The server's
     capacity on this stream is measured first (every request submitted at
-    once); then Poisson arrivals at 0.7 x that capacity give the latencies of
-    the mixed-precision batched server, and the same arrivals are replayed
-    against a binary64 server that runs one request per launch."""
+    once); then Poisson arrivals at each load (fraction of that capacity) give
+    the latencies of the mixed-precision batched server; at 0.7 the same
+    arrivals are also replayed against a binary64 server that runs one
+    request per launch."""
     import numpy as np
     import synth
     from synth.catalogs import pool_random, request_catalog
@@ -230,15 +231,26 @@ def serve_run(pc, n_req: int, seed_config: int = 5):
 
     mixed_cfg = {"streams": 2, "max_inflight": 64}
     closed, _ = run(np.zeros(n_req), mixed_cfg)
-    rate = 0.7 * n_req / closed["wall_s"]
-    gaps = np.random.Generator(np.random.PCG64(1000 * seed_config + 4)).exponential(1.0 / rate, n_req)
-    arrivals = np.cumsum(gaps)
-    log(f"serve: capacity {n_req / closed['wall_s']:.2f} requests/s on this stream; Poisson at {rate:.2f}/s")
-    mixed, res_m = run(arrivals, mixed_cfg)
-    single64, res_f = run(arrivals, {"streams": 1, "max_inflight": 64, "max_batch_pairs": 1, "mode": pc.PC_FP64_PLAIN})
-    same = all(a[k].tolist() == b[k].tolist() for a, b in zip(res_m, res_f) for k in ("DD", "DR", "RR"))
-    return {"requests": n_req, "rate_hz": rate, "capacity_rps": n_req / closed["wall_s"], **mixed,
-            "fp64_one_request_per_launch": single64, "identical_counts": same}
+    capacity = n_req / closed["wall_s"]
+    unit_gaps = np.random.Generator(np.random.PCG64(1000 * seed_config + 4)).exponential(1.0, n_req)
+    log(f"serve: capacity {capacity:.2f} requests/s on this stream")
+    out = {"requests": n_req, "capacity_rps": capacity}
+    for load in loads:
+        rate = load * capacity
+        arrivals = np.cumsum(unit_gaps / rate)
+        mixed, res_m = run(arrivals, mixed_cfg)
+        log(f"serve at {load:.1f} x capacity ({rate:.2f}/s): p50 {mixed['p50_s']:.3f} s, p99 {mixed['p99_s']:.3f} s")
+        if abs(load - 0.7) < 1e-9:
+            out.update({"rate_hz": rate, **mixed})
+            if fp64_compare:
+                single64, res_f = run(arrivals, {"streams": 1, "max_inflight": 64, "max_batch_pairs": 1,
+                                                 "mode": pc.PC_FP64_PLAIN})
+                out["fp64_one_request_per_launch"] = single64
+                out["identical_counts"] = all(a[k].tolist() == b[k].tolist() for a, b in zip(res_m, res_f)
+                                              for k in ("DD", "DR", "RR"))
+        else:
+            out.setdefault("load_sweep", []).append({"load": load, "rate_hz": rate, **mixed})
+    return out
 
 
 def build_workload(name, torch, pc):
@@ -309,6 +321,10 @@ def main():
     ap.add_argument("--no-prune-compare", action="store_true",
                     help="skip the extra step that visits every pair")
     ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-loads", default="0.7", metavar="F,F,...",
+                    help="Poisson arrival rates as fractions of the measured capacity (0.7 is always reported)")
+    ap.add_argument("--no-serve-fp64-compare", action="store_true",
+                    help="skip the replay against one binary64 launch per request")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (for scaling HBM counters) and exit")
     args = ap.parse_args()
@@ -459,10 +475,11 @@ def main():
                                    "identical_counts": all(a.tolist() == b.tolist() for a, b in zip(counts, single))}
         log(f"one launch per job: {t1 * 1e3:.1f} ms")
     if args.serve_requests > 0 and args.workload == "1m":
-        out["serve"] = serve_run(pc, args.serve_requests)
-        log(f"serve: p50 {out['serve']['p50_s']:.3f} s, p99 {out['serve']['p99_s']:.3f} s; binary64 one per launch: "
-            f"p50 {out['serve']['fp64_one_request_per_launch']['p50_s']:.3f} s, "
-            f"p99 {out['serve']['fp64_one_request_per_launch']['p99_s']:.3f} s")
+        loads = sorted({0.7, *(float(x) for x in args.serve_loads.split(",") if x.strip())})
+        out["serve"] = serve_run(pc, args.serve_requests, loads=loads, fp64_compare=not args.no_serve_fp64_compare)
+        if "fp64_one_request_per_launch" in out["serve"]:
+            log(f"serve: binary64 one per launch: p50 {out['serve']['fp64_one_request_per_launch']['p50_s']:.3f} s, "
+                f"p99 {out['serve']['fp64_one_request_per_launch']['p99_s']:.3f} s")
     if not args.no_cpu_baseline and args.workload == "1m":
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds)
