@@ -318,6 +318,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-host-compare", action="store_true",
+                    help="skip the extra step from host-memory catalogues (upload included)")
     ap.add_argument("--no-prune-compare", action="store_true",
                     help="skip the extra step that visits every pair")
     ap.add_argument("--serve-requests", type=int, default=40)
@@ -417,7 +419,9 @@ def main():
                      "pairs_computed": prn["pairs_computed"], "survivor_items": prn["survivors"],
                      "few_edge_items": prn["few_items"], "gram_form_items": prn["gram_items"],
                      "matrix_core_items": prn["mfma_items"],
-                     "computed_gpairs_s": prn["pairs_computed"] / kern_s / 1e9},
+                     "computed_gpairs_s": prn["pairs_computed"] / kern_s / 1e9,
+                     # the chord alone (8 flops per pair), for comparison with the full count W
+                     "chord_only_frac": prn["pairs_computed"] * 8 / kern_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS},
         "pairs_binned_whole": pairs - prn["pairs_computed"],
         "launch_tuning": tuned,
     }
@@ -465,6 +469,20 @@ def main():
         same = all(a.tolist() == b.tolist() for a, b in zip(counts, counts2))
         out["fp64_plain"] = {"value": pairs / t64 / 1e9, "ms_per_step": t64 * 1e3, "identical_counts": same}
         log(f"fp64 plain step {t64 * 1e3:.1f} ms, identical counts: {same}")
+    if args.workload == "1m" and not args.no_host_compare:
+        # the same step from catalogues in host memory: the upload (2 x 16 MB
+        # of binary64 RA/Dec) is inside the timed call, as in the paper's times
+        hjobs = [{"A": c["D"], "edges": c["edges"]}, {"A": c["D"], "B": c["R"], "edges": c["edges"], "auto": False},
+                 {"A": c["R"], "edges": c["edges"]}]
+        pc.pc_count_batch(hjobs, mode=mode, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hcounts = pc.pc_count_batch(hjobs, mode=mode, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t1
+        out["host_inputs"] = {"value": pairs / t1 / 1e9, "ms_per_step": t1 * 1e3,
+                              "identical_counts": all(a.tolist() == b.tolist() for a, b in zip(counts, hcounts))}
+        log(f"host-input step {t1 * 1e3:.1f} ms")
     if args.per_job_launches:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
