@@ -285,3 +285,21 @@ def test_matrix_core_path_far_clusters_and_edge_pairs(mode):
             assert st["gram_items"] > 0 and stc["gram_items"] > 0
         elif not mode & pc.PC_MATRIX_CORES:
             assert st["mfma_items"] == 0 and stc["mfma_items"] == 0
+
+
+@pytest.mark.parametrize("mode", [pc.PC_MIXED, pc.PC_MIXED | pc.PC_MATRIX_CORES])
+def test_split_items_match_oracle(mode):
+    """Clustered points on a 10-degree patch with 30 log bins: most surviving
+    tile pairs are split into 64-point j sub-blocks (some binned whole by the
+    prune pass, the rest counted with their own edges); DD and DR must equal
+    the oracle, and the run that visits every pair, exactly."""
+    c = synth.config_small(scale=0.5)
+    D, R, e = c["D"], c["R"], c["edges"]
+    dd = pc.pc_count_ex(dev(D), e, mode=mode)
+    st = pc.pc_debug_last_pruning()
+    assert st["split_items"] > 0
+    assert dd.tolist() == oracle.count(D, e).tolist()
+    assert dd.tolist() == pc.pc_count_ex(dev(D), e, mode=pc.PC_MIXED | pc.PC_NO_PRUNE).tolist()
+    dr = pc.pc_count_ex(dev(D), e, B=dev(R), auto=False, mode=mode)
+    assert pc.pc_debug_last_pruning()["split_items"] > 0
+    assert dr.tolist() == oracle.count(D, e, B=R, auto=False).tolist()
