@@ -260,6 +260,15 @@ int pc_guard_band(const double *theta_edges_deg, int32_t n_edges, float *lo, flo
  *   "streams"           number of streams (default 2)
  *   "max_batch_pairs"   pairs packed into one launch (default 2e12)
  *   "mode"              0 mixed, 1 fp64 plain
+ *   "max_queue"         requests waiting at once (default 2^20)
+ *   "deadline_s"        a request still waiting for admission this many
+ *                       seconds after submission fails with PC_ERR_CANCELLED
+ *                       (default 0: no deadline)
+ * Admission is first come, first served: requests enter in submission order
+ * while max_inflight, the free device memory minus the budget and the bytes
+ * held by running batches (128 bytes per point + 1 MiB each), and
+ * max_batch_pairs per launch allow.  A request that could not fit even on an
+ * empty device fails with PC_ERR_NOMEM.
  */
 int pc_server_create(const char *json_cfg, void **server);
 
@@ -281,6 +290,15 @@ int pc_server_submit(void *server, const pc_catalog *data, int32_t patch_id,
  */
 int pc_server_poll(void *server, uint64_t job_id, int32_t *done, uint64_t *DD, uint64_t *DR,
                    uint64_t *RR, double *w, double *latency_s);
+
+/*
+ * Cancel a request.  *cancelled = 1 when the request will report
+ * PC_ERR_CANCELLED from pc_server_poll: a waiting request leaves the queue at
+ * once; a running one finishes its launch and its answer is discarded.
+ * *cancelled = 0 when it had already finished (its answer stays pollable).
+ * PC_ERR_INVALID for an unknown (or already polled) id.
+ */
+int pc_server_cancel(void *server, uint64_t job_id, int32_t *cancelled);
 
 /* Block until every submitted request has finished. */
 int pc_server_drain(void *server);

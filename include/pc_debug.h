@@ -3,7 +3,8 @@
  *
  * They expose the host-built tables that the mixed-precision kernel uses to
  * place a binary32 squared chord into a bin, so that the table logic can be
- * checked on a CPU against the binary64 definition.
+ * checked on a CPU against the binary64 definition, facts about the last
+ * launches, and the server's admission policy.
  */
 #ifndef PC_DEBUG_H
 #define PC_DEBUG_H
@@ -69,6 +70,27 @@ int pc_debug_last_launch(double *kernel_ms, uint64_t *items, int32_t *grid, uint
 int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_t *pairs_total,
                           uint64_t *mfma_items, uint64_t *few_items, uint64_t *gram_items,
                           uint64_t *split_items);
+
+/*
+ * pc_debug_admission_plan -- the w(theta) server's admission policy applied to
+ * a queue described by the caller, with no device involved (the server applies
+ * the same function to its own queue and to the free and total device memory
+ * it reads).
+ *   need_bytes, pairs, age_s   host arrays of n: device bytes each queued
+ *                  request needs, the pairs it counts, seconds since it was
+ *                  submitted; index 0 is the front of the queue.
+ *   free_bytes, total_bytes    device memory figures to decide with.
+ *   reserved_bytes bytes held by batches already running.
+ *   inflight       requests already on the device.
+ *   json_cfg       server configuration as for pc_server_create (may be NULL).
+ *   outcome        host int32[n], written: 0 admitted into the next batch,
+ *                  1 fails (can never fit: PC_ERR_NOMEM), 2 fails (queueing
+ *                  deadline passed: PC_ERR_CANCELLED), 3 keeps waiting.
+ * Returns PC_OK, or PC_ERR_INVALID (NULL arrays with n > 0, n < 0, bad config).
+ */
+int pc_debug_admission_plan(const uint64_t *need_bytes, const double *pairs, const double *age_s, int32_t n,
+                            uint64_t free_bytes, uint64_t total_bytes, uint64_t reserved_bytes,
+                            int32_t inflight, const char *json_cfg, int32_t *outcome);
 
 #ifdef __cplusplus
 }

@@ -52,6 +52,8 @@ def lib():
         L.oracle_aperture_grid.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -193,3 +195,8 @@ def aperture_grid(cat, grid, theta_max: float, n_gal: float) -> dict:
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Number of OpenMP threads the oracle's counting loops use from now on."""
+    lib().oracle_set_num_threads(int(n))

@@ -276,3 +276,16 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the number of threads later calls use (n >= 1); a no-op without OpenMP.
+ * Used to time the oracle on one core, the comparison the paper's speed-ups
+ * are quoted against (Sec. 4, Table 1). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

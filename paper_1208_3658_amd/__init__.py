@@ -63,6 +63,8 @@ _SIGNATURES = {
                          ctypes.c_int),
     "pc_debug_last_aperture": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "pc_debug_admission_plan": ([_vp, _vp, _vp, _i32, _u64, _u64, _u64, _i32, ctypes.c_char_p, _vp],
+                                ctypes.c_int),
     "pc_count": ([_PCAT, _PCAT, _vp, _i32, _i32, _vp, _vp], ctypes.c_int),
     "pc_count_ex": ([_PCAT, _PCAT, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp], ctypes.c_int),
     "pc_count_batch": ([ctypes.POINTER(pc_job), _i32, _i32, _vp], ctypes.c_int),
@@ -87,6 +89,7 @@ _SIGNATURES = {
     "pc_server_set_random": ([_vp, _i32, _PCAT], ctypes.c_int),
     "pc_server_submit": ([_vp, _PCAT, _i32, _vp, _i32, ctypes.POINTER(_u64)], ctypes.c_int),
     "pc_server_poll": ([_vp, _u64, ctypes.POINTER(_i32), _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "pc_server_cancel": ([_vp, _u64, ctypes.POINTER(_i32)], ctypes.c_int),
     "pc_server_drain": ([_vp], ctypes.c_int),
     "pc_server_stats": ([_vp], ctypes.c_char_p),
     "pc_server_destroy": ([_vp], ctypes.c_int),
@@ -446,6 +449,26 @@ def pc_debug_last_aperture() -> dict:
             "cell_side": cell.value}
 
 
+ADMIT, NEVER_FITS, EXPIRED, WAIT = range(4)
+
+
+def pc_debug_admission_plan(need_bytes, pairs, age_s, free_bytes: int, total_bytes: int,
+                            reserved_bytes: int = 0, inflight: int = 0, config: dict | None = None):
+    """The server's admission decision for a described queue (front first):
+    int32 array of ADMIT, NEVER_FITS, EXPIRED or WAIT.  No device involved."""
+    need = np.ascontiguousarray(need_bytes, dtype=np.uint64)
+    prs = np.ascontiguousarray(pairs, dtype=np.float64)
+    age = np.ascontiguousarray(age_s, dtype=np.float64)
+    if not (need.ndim == prs.ndim == age.ndim == 1 and need.size == prs.size == age.size):
+        raise ValueError("need_bytes, pairs and age_s must be 1-D arrays of one length")
+    out = np.full(max(need.size, 1), -1, dtype=np.int32)
+    cfg = None if config is None else json.dumps(config).encode()
+    _check(lib().pc_debug_admission_plan(need.ctypes.data, prs.ctypes.data, age.ctypes.data, need.size,
+                                         int(free_bytes), int(total_bytes), int(reserved_bytes), int(inflight),
+                                         cfg, out.ctypes.data))
+    return out[: need.size]
+
+
 # ------------------------------------------------------------------ serving
 
 class Server:
@@ -485,6 +508,13 @@ class Server:
         del self._keep[job_id]
         _check(rc)
         return {"DD": DD, "DR": DR, "RR": RR, "w": w[: ne - 1], "latency_s": lat.value}
+
+    def cancel(self, job_id: int) -> bool:
+        """True when the request will report PC_ERR_CANCELLED from poll; False
+        when it had already finished (its answer stays pollable)."""
+        c = _i32(0)
+        _check(lib().pc_server_cancel(self._h, int(job_id), ctypes.byref(c)))
+        return bool(c.value)
 
     def drain(self):
         _check(lib().pc_server_drain(self._h))

@@ -19,6 +19,9 @@
 //  * Random catalogues are converted once per patch and stay resident; RR is
 //    cached per (patch, edge set), so a patch's RR is counted once.
 //  * Latency = submit -> answer ready, per request; the stats report p50/p99.
+//  * A request can be cancelled (queued: dropped at once; running: its batch
+//    finishes and its answer is discarded), and an optional queueing deadline
+//    fails requests still waiting for admission after that many seconds.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -51,6 +54,7 @@ struct ServerCfg {
     double max_batch_pairs = 2e12;
     int mode = PC_MIXED;
     int max_queue = 1 << 20;
+    double deadline_s = 0;  // 0: no queueing deadline
 };
 
 // minimal reader for flat {"key": number, ...} objects
@@ -78,12 +82,13 @@ bool parse_cfg(const char *s, ServerCfg &c, std::string &err) {
         const double v = strtod(j.c_str() + p, &end);
         if (end == j.c_str() + p) { err = "config: value of " + key + " must be a number"; return false; }
         p = static_cast<size_t>(end - j.c_str());
-        if (key == "hbm_budget_bytes") c.hbm_budget = static_cast<uint64_t>(std::max(0.0, v));
+        if (key == "hbm_budget_bytes") c.hbm_budget = static_cast<uint64_t>(std::min(std::max(0.0, v), 0x1p63));
         else if (key == "max_inflight") c.max_inflight = std::max(1, static_cast<int>(v));
         else if (key == "streams") c.streams = std::min(8, std::max(1, static_cast<int>(v)));
         else if (key == "max_batch_pairs") c.max_batch_pairs = std::max(1.0, v);
         else if (key == "mode") c.mode = static_cast<int>(v);
         else if (key == "max_queue") c.max_queue = std::max(1, static_cast<int>(v));
+        else if (key == "deadline_s") c.deadline_s = std::max(0.0, v);
         else { err = "config: unknown key " + key; return false; }
         skip();
         if (p < j.size() && j[p] == ',') { ++p; continue; }
@@ -104,6 +109,8 @@ struct Request {
     Clock::time_point t_submit;
     uint64_t need_bytes = 0;
     double pairs = 0;
+    bool running = false;    // admitted: its batch is on the device
+    bool cancelled = false;  // cancelled while running: answer discarded
     // results
     int status = PC_OK;
     std::string error;
@@ -117,6 +124,65 @@ struct Patch {
     uint64_t handle = 0;
     int64_t n = 0;
 };
+
+// Admission decision for one queued request.
+enum AdmitOutcome : int32_t { kAdmit = 0, kNeverFits = 1, kExpired = 2, kWait = 3 };
+
+struct QueuedView {
+    uint64_t need;  // device bytes the request needs while it runs
+    double pairs;   // pairs its DD and DR jobs count
+    double age_s;   // seconds since submission
+};
+
+// The admission policy, free of device calls (the server feeds it the free
+// and total device memory it reads; tests feed it chosen figures).  Walks
+// the queue from the front:
+//  * a request that cannot fit even on an empty device (need + budget >
+//    total) fails, wherever it stands;
+//  * a request past the queueing deadline fails, wherever it stands;
+//  * otherwise requests are admitted in order while the in-flight limit, the
+//    free memory (free - budget - bytes reserved by running batches) and the
+//    pairs per launch allow (the first request of a batch is exempt from the
+//    pairs limit); the first that does not fit ends admission, and it and
+//    every later request wait (first come, first served).
+// Returns the number admitted; *memory_blocked says whether admission ended
+// on free memory.
+int plan_admission(const QueuedView *q, int n, uint64_t free_b, uint64_t total_b, uint64_t reserved,
+                   int inflight, const ServerCfg &cfg, int32_t *outcome, bool *memory_blocked) {
+    const uint64_t held = cfg.hbm_budget + std::min<uint64_t>(reserved, UINT64_MAX - cfg.hbm_budget);
+    const uint64_t avail = free_b > held ? free_b - held : 0;
+    uint64_t bytes = 0;
+    double pairs = 0;
+    int admitted = 0;
+    bool open = true;
+    *memory_blocked = false;
+    for (int i = 0; i < n; ++i) {
+        if (q[i].need > total_b || cfg.hbm_budget > total_b - q[i].need) {
+            outcome[i] = kNeverFits;
+            continue;
+        }
+        if (cfg.deadline_s > 0 && q[i].age_s > cfg.deadline_s) {
+            outcome[i] = kExpired;
+            continue;
+        }
+        if (open) {
+            const bool slot = inflight + admitted < cfg.max_inflight;
+            const bool mem = q[i].need <= avail - bytes;  // bytes <= avail: only fitting requests add to it
+            const bool fits_launch = admitted == 0 || pairs + q[i].pairs <= cfg.max_batch_pairs;
+            if (slot && mem && fits_launch) {
+                outcome[i] = kAdmit;
+                bytes += q[i].need;
+                pairs += q[i].pairs;
+                ++admitted;
+                continue;
+            }
+            open = false;
+            *memory_blocked = slot && !mem;
+        }
+        outcome[i] = kWait;
+    }
+    return admitted;
+}
 
 std::string edge_key(int32_t patch, const std::vector<double> &e) {
     std::string k(reinterpret_cast<const char *>(&patch), sizeof(patch));
@@ -143,6 +209,8 @@ struct Server {
     std::vector<hipStream_t> streams;
     // stats
     uint64_t n_submitted = 0, n_done = 0, n_failed = 0, n_batches = 0, n_admit_waits = 0;
+    uint64_t n_cancelled = 0, n_expired = 0;
+    int running_batches = 0, max_running_batches = 0;
     double pairs_done = 0, busy_s = 0;
     std::vector<double> latencies;
     Clock::time_point t0 = Clock::now();
@@ -150,41 +218,65 @@ struct Server {
 
     void worker(int k);
     int take_batch(std::vector<std::shared_ptr<Request>> &out, uint64_t &bytes);
+    void finish_unrun(Request &r, int status, const std::string &msg);  // mu held
 };
 
+void Server::finish_unrun(Request &r, int status, const std::string &msg) {
+    r.status = status;
+    r.error = msg;
+    r.latency = std::chrono::duration<double>(Clock::now() - r.t_submit).count();
+    r.done = true;
+    std::vector<double>().swap(r.ra);
+    std::vector<double>().swap(r.dec);
+    ++n_failed;
+    if (status == PC_ERR_CANCELLED) ++n_cancelled;
+}
+
 int Server::take_batch(std::vector<std::shared_ptr<Request>> &out, uint64_t &bytes) {
-    // called with mu held; admits from the front of the queue
+    // called with mu held
     size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
-    double pairs = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = total_b = 0;
     bytes = 0;
-    while (!queue.empty() && inflight < cfg.max_inflight) {
-        auto &r = queue.front();
-        if (r->need_bytes + cfg.hbm_budget > total_b) {
-            // can never fit
-            r->status = PC_ERR_NOMEM;
-            r->error = "request needs " + std::to_string(r->need_bytes) + " bytes; device has " +
-                       std::to_string(total_b) + " with a budget of " + std::to_string(cfg.hbm_budget);
-            r->latency = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
-            r->done = true;
-            ++n_failed;
-            queue.pop_front();
-            cv_done.notify_all();
-            continue;
+    if (queue.empty()) return 0;
+    const auto now = Clock::now();
+    std::vector<QueuedView> view(queue.size());
+    std::vector<int32_t> outcome(queue.size());
+    for (size_t i = 0; i < queue.size(); ++i)
+        view[i] = {queue[i]->need_bytes, queue[i]->pairs,
+                   std::chrono::duration<double>(now - queue[i]->t_submit).count()};
+    bool mem_blocked = false;
+    plan_admission(view.data(), static_cast<int>(view.size()), free_b, total_b, reserved, inflight, cfg,
+                   outcome.data(), &mem_blocked);
+    if (mem_blocked) ++n_admit_waits;
+    std::deque<std::shared_ptr<Request>> keep;
+    bool failed = false;
+    for (size_t i = 0; i < queue.size(); ++i) {
+        auto &r = queue[i];
+        switch (outcome[i]) {
+            case kAdmit:
+                r->running = true;
+                bytes += r->need_bytes;
+                ++inflight;
+                out.push_back(r);
+                break;
+            case kNeverFits:
+                finish_unrun(*r, PC_ERR_NOMEM,
+                             "request needs " + std::to_string(r->need_bytes) + " bytes; device has " +
+                                 std::to_string(total_b) + " with a budget of " + std::to_string(cfg.hbm_budget));
+                failed = true;
+                break;
+            case kExpired:
+                ++n_expired;
+                finish_unrun(*r, PC_ERR_CANCELLED, "queueing deadline passed before admission");
+                failed = true;
+                break;
+            default:
+                keep.push_back(r);
         }
-        const uint64_t avail = free_b > cfg.hbm_budget + reserved ? free_b - cfg.hbm_budget - reserved : 0;
-        if (r->need_bytes + bytes > avail) {
-            ++n_admit_waits;
-            break;
-        }
-        if (!out.empty() && pairs + r->pairs > cfg.max_batch_pairs) break;
-        pairs += r->pairs;
-        bytes += r->need_bytes;
-        ++inflight;
-        out.push_back(r);
-        queue.pop_front();
     }
+    queue.swap(keep);
     reserved += bytes;
+    if (failed) cv_done.notify_all();
     return static_cast<int>(out.size());
 }
 
@@ -208,6 +300,7 @@ void Server::worker(int k) {
                 cv_work.wait_for(lk, std::chrono::milliseconds(2));
                 continue;
             }
+            max_running_batches = std::max(max_running_batches, ++running_batches);
         }
         // build the jobs: DD, DR, and RR where not cached
         std::vector<pc_catalog> cats(batch.size());
@@ -288,7 +381,12 @@ void Server::worker(int k) {
                 for (size_t s = 0; s < rr_keys.size(); ++s) rr_cache.emplace(rr_keys[s], rr_store[s]);
             for (size_t q = 0; q < batch.size(); ++q) {
                 Request &r = *batch[q];
-                if (rc == PC_OK) {
+                if (r.cancelled) {
+                    r.status = PC_ERR_CANCELLED;
+                    r.error = "request cancelled";
+                    ++n_failed;
+                    ++n_cancelled;
+                } else if (rc == PC_OK) {
                     if (rr_job[q] >= 0) r.RR = rr_store[rr_job[q]];
                     const int32_t nb = static_cast<int32_t>(r.edges.size()) - 1;
                     r.w.assign(nb, 0.0);
@@ -305,13 +403,15 @@ void Server::worker(int k) {
                     ++n_failed;
                 }
                 r.latency = std::chrono::duration<double>(Clock::now() - r.t_submit).count();
-                if (rc == PC_OK) latencies.push_back(r.latency);
+                if (r.status == PC_OK) latencies.push_back(r.latency);
+                r.running = false;
                 r.done = true;
                 std::vector<double>().swap(r.ra);
                 std::vector<double>().swap(r.dec);
                 --inflight;
             }
             reserved -= bytes;
+            --running_batches;
             ++n_batches;
             pairs_done += pairs;
             busy_s += dt;
@@ -440,7 +540,18 @@ int pc_server_poll(void *server, uint64_t job_id, int32_t *done, uint64_t *DD, u
         std::lock_guard<std::mutex> lk(s->mu);
         auto it = s->jobs.find(job_id);
         if (it == s->jobs.end()) return fail(PC_ERR_INVALID, "unknown job id");
-        if (!it->second->done) {
+        Request &q = *it->second;
+        if (!q.done && !q.running && s->cfg.deadline_s > 0 &&
+            std::chrono::duration<double>(Clock::now() - q.t_submit).count() > s->cfg.deadline_s) {
+            auto pos = std::find(s->queue.begin(), s->queue.end(), it->second);
+            if (pos != s->queue.end()) {
+                s->queue.erase(pos);
+                ++s->n_expired;
+                s->finish_unrun(q, PC_ERR_CANCELLED, "queueing deadline passed before admission");
+                s->cv_done.notify_all();
+            }
+        }
+        if (!q.done) {
             *done = 0;
             return PC_OK;
         }
@@ -458,6 +569,28 @@ int pc_server_poll(void *server, uint64_t job_id, int32_t *done, uint64_t *DD, u
     if (DR) memcpy(DR, r->DR.data(), sizeof(uint64_t) * (ne + 1));
     if (RR) memcpy(RR, r->RR.data(), sizeof(uint64_t) * (ne + 1));
     if (w) memcpy(w, r->w.data(), sizeof(double) * (ne - 1));
+    return PC_OK;
+}
+
+int pc_server_cancel(void *server, uint64_t job_id, int32_t *cancelled) {
+    clear_error();
+    auto *s = static_cast<Server *>(server);
+    if (!s || !cancelled) return fail(PC_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end()) return fail(PC_ERR_INVALID, "unknown job id");
+    Request &r = *it->second;
+    *cancelled = 0;
+    if (r.done) return PC_OK;  // finished first: its answer stays pollable
+    *cancelled = 1;
+    if (r.running) {
+        r.cancelled = true;    // the batch runs on; the answer is discarded
+        return PC_OK;
+    }
+    auto pos = std::find(s->queue.begin(), s->queue.end(), it->second);
+    if (pos != s->queue.end()) s->queue.erase(pos);
+    s->finish_unrun(r, PC_ERR_CANCELLED, "request cancelled");
+    s->cv_done.notify_all();
     return PC_OK;
 }
 
@@ -494,7 +627,9 @@ const char *pc_server_stats(void *server) {
       << ", \"admission_waits\": " << s->n_admit_waits << ", \"pairs\": " << s->pairs_done
       << ", \"busy_s\": " << s->busy_s << ", \"wall_s\": " << wall << ", \"p50_s\": " << pct(0.50)
       << ", \"p99_s\": " << pct(0.99) << ", \"max_s\": " << (l.empty() ? 0.0 : l.back())
-      << ", \"rr_cached\": " << s->rr_cache.size() << ", \"streams\": " << s->cfg.streams << "}";
+      << ", \"rr_cached\": " << s->rr_cache.size() << ", \"streams\": " << s->cfg.streams
+      << ", \"cancelled\": " << s->n_cancelled << ", \"expired\": " << s->n_expired
+      << ", \"max_concurrent_batches\": " << s->max_running_batches << "}";
     buf = o.str();
     return buf.c_str();
 }
@@ -513,6 +648,23 @@ int pc_server_destroy(void *server) {
     for (auto &p : s->patches) release_catalog(p.second.handle);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
     delete s;
+    return PC_OK;
+}
+
+int pc_debug_admission_plan(const uint64_t *need_bytes, const double *pairs, const double *age_s, int32_t n,
+                            uint64_t free_bytes, uint64_t total_bytes, uint64_t reserved_bytes, int32_t inflight,
+                            const char *json_cfg, int32_t *outcome) {
+    clear_error();
+    if (n < 0) return fail(PC_ERR_INVALID, "n must be >= 0");
+    if (n > 0 && (!need_bytes || !pairs || !age_s || !outcome)) return fail(PC_ERR_INVALID, "NULL argument");
+    if (inflight < 0) return fail(PC_ERR_INVALID, "inflight must be >= 0");
+    ServerCfg cfg;
+    std::string err;
+    if (!parse_cfg(json_cfg, cfg, err)) return fail(PC_ERR_INVALID, err);
+    std::vector<QueuedView> q(static_cast<size_t>(n));
+    for (int32_t i = 0; i < n; ++i) q[i] = {need_bytes[i], pairs[i], age_s[i]};
+    bool mem_blocked = false;
+    plan_admission(q.data(), n, free_bytes, total_bytes, reserved_bytes, inflight, cfg, outcome, &mem_blocked);
     return PC_OK;
 }
 

@@ -100,3 +100,97 @@ def test_server_config_errors():
         pc.Server({"no_such_key": 1})
     with pytest.raises(pc.PcError):
         pc.Server({"mode": 7})
+
+
+def _big_and_small(seed):
+    rng = np.random.default_rng(seed)
+    patch = synth.centred_patch(50.0)
+    R = synth.uniform_patch(1_000_000, patch, rng)
+    big = synth.uniform_patch(1_000_000, patch, rng)           # tens of ms on the device
+    small = [synth.uniform_patch(n, patch, rng) for n in (1500, 2500)]
+    return R, big, small, synth.log_edges(0.01, 10.0, 20)
+
+
+def _alone(cat, R, e):
+    return pc.pc_count_batch([{"A": cat, "edges": e}, {"A": cat, "B": R, "edges": e, "auto": False},
+                              {"A": R, "edges": e}])
+
+
+def test_cancel_queued_running_and_finished_requests():
+    R, big, (s1, s2), e = _big_and_small(41)
+    srv = pc.Server({"streams": 1, "max_inflight": 1})
+    try:
+        srv.set_random(0, R)
+        a = srv.submit(big, 0, e)
+        b = srv.submit(s1, 0, e)        # queued behind a (one request on the device at a time)
+        c = srv.submit(s2, 0, e)
+        assert srv.cancel(b) is True
+        with pytest.raises(pc.PcError) as ex:
+            srv.poll(b)
+        assert ex.value.code == pc.PC_ERR_CANCELLED
+        with pytest.raises(pc.PcError) as ex:
+            srv.cancel(b)               # already polled: unknown now
+        assert ex.value.code == pc.PC_ERR_INVALID
+        srv.drain()
+        assert srv.cancel(a) is False   # finished first: the answer stays
+        for jid, cat in ((a, big), (c, s2)):
+            res = srv.poll(jid)
+            dd, dr, rr = _alone(cat, R, e)
+            assert res["DD"].tolist() == dd.tolist() and res["DR"].tolist() == dr.tolist()
+            assert res["RR"].tolist() == rr.tolist()
+        # cancelling a running request discards its answer
+        d = srv.submit(big, 0, e)
+        while srv.stats()["inflight"] == 0 and srv.stats()["completed"] < 3:
+            time.sleep(0.0005)
+        was_running = srv.cancel(d)
+        srv.drain()
+        st = srv.stats()
+        if was_running:
+            with pytest.raises(pc.PcError) as ex:
+                srv.poll(d)
+            assert ex.value.code == pc.PC_ERR_CANCELLED and st["cancelled"] == 2
+        else:                               # it finished before the cancel arrived
+            assert srv.poll(d)["DD"].tolist() == _alone(big, R, e)[0].tolist() and st["cancelled"] == 1
+    finally:
+        srv.close()
+
+
+def test_queueing_deadline_fails_requests_that_wait_too_long():
+    R, big, (s1, _), e = _big_and_small(42)
+    srv = pc.Server({"streams": 1, "max_inflight": 1, "deadline_s": 0.005})
+    try:
+        srv.set_random(0, R)
+        a = srv.submit(big, 0, e)
+        b = srv.submit(s1, 0, e)        # waits for a (> 5 ms) and expires
+        srv.drain()
+        assert srv.poll(a)["DD"].sum() == big[0].size * (big[0].size - 1) // 2
+        with pytest.raises(pc.PcError) as ex:
+            srv.poll(b)
+        assert ex.value.code == pc.PC_ERR_CANCELLED
+        st = srv.stats()
+        assert st["expired"] == 1 and st["completed"] == 1
+    finally:
+        srv.close()
+
+
+def test_two_streams_run_two_batches_at_once():
+    # one request per launch; the second arrives while the first runs and is
+    # taken by the other stream's worker: two batches on the device together
+    R, big, (s1, _), e = _big_and_small(43)
+    srv = pc.Server({"streams": 2, "max_batch_pairs": 1})
+    try:
+        srv.set_random(0, R)
+        srv.submit(R, 0, e)             # RR of the patch counted (and cached) first
+        srv.drain()
+        a = srv.submit(big, 0, e)
+        b = srv.submit(big, 0, e)
+        srv.drain()
+        st = srv.stats()
+        assert st["max_concurrent_batches"] == 2
+        ra, rb = srv.poll(a), srv.poll(b)
+        dd, dr, rr = _alone(big, R, e)
+        for res in (ra, rb):
+            assert res["DD"].tolist() == dd.tolist() and res["DR"].tolist() == dr.tolist()
+            assert res["RR"].tolist() == rr.tolist()
+    finally:
+        srv.close()
