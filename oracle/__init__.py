@@ -21,12 +21,17 @@ _u32p = ctypes.POINTER(ctypes.c_uint32)
 
 
 def lib():
+    """The oracle library: oracle/libpc_oracle.so (rebuilt when a source is
+    newer), or the build named by PC_ORACLE_LIB (variant builds in tests)."""
     global _lib
     if _lib is None:
-        srcs = [os.path.join(os.path.dirname(LIB), f) for f in ("pc_oracle.c", "ap_oracle.c")]
-        if not os.path.exists(LIB) or any(os.path.getmtime(f) > os.path.getmtime(LIB) for f in srcs):
-            build()
-        L = ctypes.CDLL(LIB)
+        path = os.environ.get("PC_ORACLE_LIB")
+        if not path:
+            path = LIB
+            srcs = [os.path.join(os.path.dirname(LIB), f) for f in ("pc_oracle.c", "ap_oracle.c")]
+            if not os.path.exists(LIB) or any(os.path.getmtime(f) > os.path.getmtime(LIB) for f in srcs):
+                build()
+        L = ctypes.CDLL(path)
         L.oracle_sincosd.argtypes = [ctypes.c_double, _dp, _dp]
         L.oracle_sincosd.restype = None
         L.oracle_unit_vectors.argtypes = [_i64, _dp, _dp, _dp]

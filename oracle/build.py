@@ -17,13 +17,17 @@ FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
          "-ffp-contract=off", "-fno-fast-math", "-fno-unsafe-math-optimizations"]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", *FLAGS, *SRCS, "-o", LIB + ".tmp", "-lm"]
+def build(verbose: bool = False, out: str = LIB, opt=("-O2",)) -> str:
+    """Builds the oracle into `out`; `opt` replaces the optimisation flags
+    (tests build -O0, -march=native and sanitizer variants to check that the
+    results do not depend on them)."""
+    flags = [f for f in FLAGS if f != "-O2"]
+    cmd = ["gcc", *opt, *flags, *SRCS, "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":
