@@ -93,6 +93,12 @@ typedef struct {
  *                   The entries sum to n(n-1)/2 (auto) or n_A*n_B (cross).
  *   stream          hipStream_t or NULL.
  * n = 0 or 1 (auto) gives all-zero counts.  Mode PC_MIXED.
+ * Limits (PC_ERR_INVALID beyond them): n_edges <= 1024; n <= 2^40 points per
+ * catalogue; at most 2^40 - 1 tile pairs of 256 points in one call (one auto
+ * job of up to ~3.8e8 points, or the sum over a batch's jobs).  Device memory:
+ * about 100-130 bytes per point plus 16 bytes per tile pair; PC_ERR_NOMEM
+ * when it is not available.  Returns PC_OK, PC_ERR_INVALID (bad argument; nothing
+ * launched), PC_ERR_NOMEM or PC_ERR_DEVICE (pc_last_error() has the text).
  */
 int pc_count(const pc_catalog *A, const pc_catalog *B, const double *theta_edges_deg,
              int32_t n_edges, int32_t auto_flag, uint64_t *counts, void *stream);
