@@ -461,6 +461,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     // ---- segments
     std::vector<SegDesc> segs;
     uint64_t items = 0;
+    bool items_overflow = false;  // more tile pairs than an item number holds
     int64_t prune_rows = 0;
     auto view_n = [&](int v) { return views[v].e - views[v].b; };
     for (size_t q = 0; q < jobs.size(); ++q) {
@@ -476,10 +477,14 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             sd.nj = nj;
             sd.tiles_i = n_tiles(ni);
             sd.tiles_j = n_tiles(nj);
-            sd.n_items = tri ? static_cast<uint64_t>(sd.tiles_i) * static_cast<uint64_t>(sd.tiles_i + 1) / 2
-                             : static_cast<uint64_t>(sd.tiles_i) * static_cast<uint64_t>(sd.tiles_j);
+            // in 128 bits: up to 2^32 tiles per side, whose products pass 2^64
+            const unsigned __int128 n_items =
+                tri ? static_cast<unsigned __int128>(sd.tiles_i) * static_cast<unsigned __int128>(sd.tiles_i + 1) / 2
+                    : static_cast<unsigned __int128>(sd.tiles_i) * static_cast<unsigned __int128>(sd.tiles_j);
+            if (n_items > kItemMask || items + static_cast<uint64_t>(n_items) > kItemMask) items_overflow = true;
+            sd.n_items = static_cast<uint64_t>(std::min<unsigned __int128>(n_items, kItemMask));
             sd.item0 = items;
-            items += sd.n_items;
+            items = std::min<uint64_t>(items + sd.n_items, kItemMask + 1);
             // rows of the prune pass (see k_prune)
             sd.prow0 = prune_rows;
             prune_rows += tri ? (sd.tiles_i + 1) / 2 : sd.tiles_i;
@@ -493,8 +498,8 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         if (plan[q].vi_tri >= 0) add(true, plan[q].vi_tri, plan[q].vi_tri);
         if (plan[q].vi_rect >= 0 && plan[q].vj_rect >= 0) add(false, plan[q].vi_rect, plan[q].vj_rect);
     }
-    if (items > kItemMask)
-        return fail(PC_ERR_INVALID, "too many tile pairs in one call (" + std::to_string(items) +
+    if (items_overflow || items > kItemMask)
+        return fail(PC_ERR_INVALID, "too many tile pairs in one call (more than " + std::to_string(kItemMask) +
                                         "); split the catalogues into row ranges");
     const size_t o_segs = ar.take(sizeof(SegDesc) * std::max<size_t>(segs.size(), 1));
     const size_t o_tabs = ar.take(sizeof(TableDesc) * tabs.size());
