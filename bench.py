@@ -424,6 +424,7 @@ def main():
         kern.append(pc.pc_debug_last_launch()["kernel_ms"])
         log(f"step {k + 1}/{args.steps} done")
     prn = pc.pc_debug_last_pruning()
+    rechecked = pc.pc_debug_last_rechecks()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     launch = pc.pc_debug_last_launch()
@@ -458,6 +459,9 @@ def main():
                      # the chord alone (8 flops per pair), for comparison with the full count W
                      "chord_only_frac": prn["pairs_computed"] * 8 / kern_s / 1e12 / peak},
         "pairs_binned_whole": pairs - prn["pairs_computed"],
+        # pairs whose binary32 chord fell in an edge's guard band (re-checked in binary64)
+        "rechecks": {"pairs": rechecked, "of_computed": rechecked / max(prn["pairs_computed"], 1),
+                     "of_all": rechecked / pairs},
         "launch_tuning": tuned,
     }
     pc.pc_debug_set_timing(False)

@@ -72,6 +72,15 @@ int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_
                           uint64_t *split_items);
 
 /*
+ * pc_debug_last_rechecks -- the calling thread's last counting launch: how many
+ * pairs had a binary32 squared chord inside the guard band of an edge and were
+ * recomputed in binary64 (Appendix A separation; the mixed kernel only: the
+ * binary64 kernel and whole-binned tile pairs report none).  Counted on the
+ * device in a histogram row of its own.  PC_ERR_INVALID for NULL.
+ */
+int pc_debug_last_rechecks(uint64_t *pairs_rechecked);
+
+/*
  * pc_debug_admission_plan -- the w(theta) server's admission policy applied to
  * a queue described by the caller, with no device involved (the server applies
  * the same function to its own queue and to the free and total device memory

@@ -65,6 +65,7 @@ _SIGNATURES = {
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "pc_debug_admission_plan": ([_vp, _vp, _vp, _i32, _u64, _u64, _u64, _i32, ctypes.c_char_p, _vp],
                                 ctypes.c_int),
+    "pc_debug_last_rechecks": ([ctypes.POINTER(_u64)], ctypes.c_int),
     "pc_count": ([_PCAT, _PCAT, _vp, _i32, _i32, _vp, _vp], ctypes.c_int),
     "pc_count_ex": ([_PCAT, _PCAT, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp], ctypes.c_int),
     "pc_count_batch": ([ctypes.POINTER(pc_job), _i32, _i32, _vp], ctypes.c_int),
@@ -390,6 +391,14 @@ def pc_debug_last_pruning() -> dict:
     _check(lib().pc_debug_last_pruning(*(ctypes.byref(v) for v in vals)))
     keys = ("survivors", "pairs_computed", "pairs_total", "mfma_items", "few_items", "gram_items", "split_items")
     return {k: int(v.value) for k, v in zip(keys, vals)}
+
+
+def pc_debug_last_rechecks() -> int:
+    """Pairs of the calling thread's last counting launch that were re-checked
+    in binary64 (binary32 chord inside an edge's guard band)."""
+    v = _u64(0)
+    _check(lib().pc_debug_last_rechecks(ctypes.byref(v)))
+    return int(v.value)
 
 
 # ------------------------------------------------------------ aperture mass

@@ -27,7 +27,8 @@ hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st);
 hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
                         const uint64_t *items, const unsigned long long *n_items, const uint64_t *sub,
                         uint64_t total_items, uint32_t lut_lds_off, uint32_t stage_lds_off,
-                        unsigned long long *queue, int chunk, uint32_t lds_bytes, int grid, hipStream_t st);
+                        unsigned long long *queue, unsigned long long *rechecked, int chunk, uint32_t lds_bytes,
+                        int grid, hipStream_t st);
 size_t sort_scratch_words(int64_t n);
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
                        float4 *a32s, float4 *g32s, double4 *bounds, hipStream_t st);
@@ -216,7 +217,7 @@ TableDesc table_desc(const DevTable &t, bool fp64) {
 // then (mixed) the matrix-core path's cell table
 static void table_lds(const DevTable &t, bool fp64, uint32_t *hist, uint32_t *lut) {
     const HostTable &h = t.host;
-    *hist = static_cast<uint32_t>(h.e64.size() + 2) * (fp64 ? h.row_bytes64 : h.row_bytes32);
+    *hist = static_cast<uint32_t>(h.e64.size() + 3) * (fp64 ? h.row_bytes64 : h.row_bytes32);
     if (fp64) {
         *lut = h.search64 ? static_cast<uint32_t>(8 * h.e64.size())
                           : static_cast<uint32_t>(16 * h.lut64.size());
@@ -649,7 +650,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         }
         PC_HIP(launch_count(fp64, mc, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
                             prune ? meta : nullptr, split ? sub_words : nullptr, items, lut_off, stage_off, meta + 8,
-                            lt.chunk, lds_bytes, grid, st),
+                            meta + 7, lt.chunk, lds_bytes, grid, st),
                "count kernel");
         if (timed) PC_HIP(hipEventRecord(t_ev1, st), "hipEventRecord");
     }
@@ -664,7 +665,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     }
     std::vector<int> flags(std::max<size_t>(srcs.size(), 1), 0);
     PC_HIP(hipMemcpyAsync(flags.data(), W + o_err, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, st), "D2H flags");
-    unsigned long long hmeta[7] = {0, 0, 0, 0, 0, 0, 0};
+    unsigned long long hmeta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     PC_HIP(hipMemcpyAsync(hmeta, meta, sizeof(hmeta), hipMemcpyDeviceToHost, st), "D2H meta");
     PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
     for (size_t k = 0; k < srcs.size(); ++k)
@@ -690,6 +691,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     t_last.few_items = prune ? hmeta[4] : 0;
     t_last.gram_items = prune ? hmeta[5] : 0;
     t_last.split_items = prune ? hmeta[6] : 0;
+    t_last.rechecked = hmeta[7];
     if (t_timing && items > 0) {
         float ms = 0.0f;
         PC_HIP(hipEventElapsedTime(&ms, t_ev0, t_ev1), "hipEventElapsedTime");
@@ -986,6 +988,13 @@ extern "C" int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_comput
     if (survivors) *survivors = t_last.survivors;
     if (pairs_computed) *pairs_computed = t_last.pairs_computed;
     if (pairs_total) *pairs_total = t_last.pairs_total;
+    return PC_OK;
+}
+
+extern "C" int pc_debug_last_rechecks(uint64_t *pairs_rechecked) {
+    clear_error();
+    if (!pairs_rechecked) return fail(PC_ERR_INVALID, "pairs_rechecked is NULL");
+    *pairs_rechecked = t_last.rechecked;
     return PC_OK;
 }
 

@@ -27,8 +27,9 @@ constexpr int kJPad = 16;               // readable points past the end of an or
 constexpr int kMaxLutCells = 1024;        // per table, 16 bytes each
 constexpr uint32_t kLdsTarget = 16 * 1024;  // per-wave histogram bytes aimed for at most
 
-// Histogram layout in LDS: n_edges + 2 rows (under/overflow bins and one
-// discard row for masked pairs) of `cols` lane columns.  Lane l adds to column
+// Histogram layout in LDS: n_edges + 3 rows (under/overflow bins, one
+// discard row for masked pairs, and one row tallying the pairs re-checked in
+// binary64) of `cols` lane columns.  Lane l adds to column
 // l & (cols - 1), so with cols = 64 no two lanes of a wave share a word, and
 // since a row is exactly `cols` words the word of lane l sits in bank l (mod
 // the bank count) whatever its row: the adds are free of bank conflicts.

@@ -32,6 +32,7 @@ struct KParams {
     uint32_t lut_lds_off;   // byte offset of the cell table in LDS (after the histogram)
     uint32_t stage_lds_off; // byte offset of the matrix-core path's A-operand block (16 x 64 floats)
     unsigned long long *queue;  // 8 zeroed chunk counters, one per slice of the items
+    unsigned long long *rechecked;  // zeroed; pairs re-checked in binary64 are added here
     uint32_t chunk;             // items taken from the queue at a time
 };
 
@@ -178,11 +179,12 @@ __device__ __forceinline__ uint32_t umed3(uint32_t x, uint32_t lo, uint32_t hi) 
 }
 
 // Sum the histogram rows [0, n_rows) over the lane columns into the job's
-// 64-bit counters, then clear every row (including the discard row).  Lane r
-// sums row r, visiting the columns in a lane-rotated order so that the lanes
-// of one read touch distinct banks.
+// 64-bit counters and the re-check tally row (row n_rows + 1, after the
+// discard row) into *rechecked, then clear every row.  Lane r sums row r,
+// visiting the columns in a lane-rotated order so that the lanes of one read
+// touch distinct banks.
 __device__ void flush_hist(unsigned char *lds, int32_t n_rows, int32_t cols, int32_t clear_words,
-                           unsigned long long *counts) {
+                           unsigned long long *counts, unsigned long long *rechecked) {
     __syncthreads();
     const uint32_t lane = threadIdx.x;
     uint32_t *h = reinterpret_cast<uint32_t *>(lds);
@@ -191,6 +193,12 @@ __device__ void flush_hist(unsigned char *lds, int32_t n_rows, int32_t cols, int
         const uint32_t *row = h + r * cols;
         for (int c = 0; c < cols; ++c) s += row[(c + r) & (cols - 1)];
         if (s) atomicAdd(counts + r, s);
+    }
+    if (lane == kWave - 1) {
+        unsigned long long s = 0;
+        const uint32_t *row = h + (n_rows + 1) * cols;
+        for (int c = 0; c < cols; ++c) s += row[c];
+        if (s) atomicAdd(rechecked, s);
     }
     __syncthreads();
     for (int32_t w = lane; w < clear_words; w += kWave) h[w] = 0u;
@@ -353,6 +361,7 @@ __device__ __forceinline__ void step32(unsigned char *lds, const float4 (&b)[NJ]
                     const double c64 = chord2_64(a64.x, a64.y, a64.z, b64.x, b64.y, b64.z);
                     const uint32_t exact = bin_search(k.e64, k.n_edges, c64) * k.row_bytes + k.lane_off;
                     const uint32_t prov = en.x + k.lane_off;
+                    lds_add(lds, k.trash_off + k.row_bytes, 1u);  // re-check tally row
                     if (exact != prov) {
                         lds_add(lds, exact, 1u);
                         lds_add(lds, prov, 0xFFFFFFFFu);
@@ -455,6 +464,7 @@ __device__ __forceinline__ void few_recheck(unsigned char *lds, float c, const d
     for (int t = 0; t < M; ++t) prov += c > f.hi[t] ? 1u : 0u;
     const double c64 = chord2_64(a64.x, a64.y, a64.z, b64.x, b64.y, b64.z);
     const uint32_t exact = bin_search(k.e64, k.n_edges, c64);
+    lds_add(lds, k.trash_off + k.row_bytes, 1u);  // re-check tally row
     if (exact != prov) {
         lds_add(lds, exact * k.row_bytes + k.lane_off, 1u);
         lds_add(lds, prov * k.row_bytes + k.lane_off, 0xFFFFFFFFu);
@@ -936,7 +946,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         // a lane adds at most kTile * kR per item to a word it shares with
         // kWave / cols - 1 other lanes: flush before a 32-bit word can wrap
         if (sd.tab != cur_tab || sd.job != cur_job || since_flush >= flush_every) {
-            if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);
+            if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts, p.rechecked);
             if (sd.tab != cur_tab) {
                 const TableDesc td = ld_const_struct(p.tabs + sd.tab);
                 n_edges = td.n_edges;
@@ -962,7 +972,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                     uint4 *dst = reinterpret_cast<uint4 *>(lds + p.lut_lds_off);
                     for (int32_t k = lane; k < td.n_cells; k += kWave) dst[k] = src[k];
                 }
-                const int32_t words = (n_edges + 2) * cols;
+                const int32_t words = (n_edges + 3) * cols;
                 uint32_t *h = reinterpret_cast<uint32_t *>(lds);
                 for (int32_t x = lane + (cur_job < 0 ? 0 : clear_words); x < words; x += kWave) h[x] = 0u;
                 clear_words = max(clear_words, words);
@@ -1169,7 +1179,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
             }
         }
     }
-    if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts);
+    if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts, p.rechecked);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1192,9 +1202,11 @@ hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st) {
 hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
                         const uint64_t *items, const unsigned long long *n_items, const uint64_t *sub,
                         uint64_t total_items, uint32_t lut_lds_off, uint32_t stage_lds_off,
-                        unsigned long long *queue, int chunk, uint32_t lds_bytes, int grid, hipStream_t st) {
+                        unsigned long long *queue, unsigned long long *rechecked, int chunk, uint32_t lds_bytes,
+                        int grid, hipStream_t st) {
     KParams p;
     p.queue = queue;
+    p.rechecked = rechecked;
     p.chunk = static_cast<uint32_t>(chunk);
     p.segs = segs;
     p.tabs = tabs;

@@ -86,6 +86,7 @@ struct BatchStats {
     uint64_t few_items = 0;       // work units (survivors, or open sub-blocks of split ones) with few edges inside
     uint64_t gram_items = 0;      // work units with Gram-form chords on the vector path
     uint64_t split_items = 0;     // survivors visited as sub-blocks of the j-tile
+    uint64_t rechecked = 0;       // pairs whose binary32 chord fell in a guard band (re-checked in binary64)
 };
 
 // Launch parameters a tuner may choose (all give the same counts):

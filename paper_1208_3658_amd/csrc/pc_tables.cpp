@@ -319,7 +319,7 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
     // waves share a CU
     auto pick = [&](int widest) {
         for (int c = widest; c > 8; c >>= 1)
-            if (static_cast<uint64_t>(n_edges + 2) * row_bytes_for(c) <= kLdsTarget) return c;
+            if (static_cast<uint64_t>(n_edges + 3) * row_bytes_for(c) <= kLdsTarget) return c;
         return 8;
     };
     if (cols32 != 0 && (cols32 < 8 || cols32 > 64 || (cols32 & (cols32 - 1)) != 0)) {

@@ -136,6 +136,14 @@ def test_adversarial_near_edge_pairs_exact(mode):
         A = _near_edge_catalogue(theta)
         got = pc.pc_count_ex(dev(A), theta, mode=mode)
         assert got.tolist() == oracle.count(A, theta).tolist()
+        # pairs placed at the edges land in the guard bands: the mixed kernel
+        # re-checks them in binary64; the binary64 kernel has nothing to re-check
+        rk = pc.pc_debug_last_rechecks()
+        n = A[0].size
+        if mode == pc.PC_FP64_PLAIN:
+            assert rk == 0
+        else:
+            assert 0 < rk <= n * (n - 1) // 2
 
 
 def test_antipodes_poles_duplicates_full_sky():
@@ -247,8 +255,11 @@ def test_pruning_skips_most_pairs_on_the_1m_shape():
     D, R, e = dev(c["D"]), dev(c["R"]), c["edges"]
     got = pc.pc_count_ex(D, e, B=R, auto=False)
     st = pc.pc_debug_last_pruning()
+    rk = pc.pc_debug_last_rechecks()
     assert st["pairs_total"] == 100_000 * 100_000
     assert st["pairs_computed"] < 0.35 * st["pairs_total"]
+    # guard-band re-checks: a small fraction of the computed pairs, but some
+    assert 0 < rk < 1e-3 * st["pairs_computed"]
     # few-edge work units: survivors, or open sub-blocks of split survivors
     assert 0 < st["few_items"] <= 4 * st["survivors"]
     assert 0 < st["split_items"] <= st["survivors"]
