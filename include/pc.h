@@ -270,6 +270,13 @@ int pc_guard_band(const double *theta_edges_deg, int32_t n_edges, float *lo, flo
  *   "deadline_s"        a request still waiting for admission this many
  *                       seconds after submission fails with PC_ERR_CANCELLED
  *                       (default 0: no deadline)
+ *   "log_path"          (a string) file to which one JSON line per finished
+ *                       request is appended: id, patch, n, n_edges, pairs,
+ *                       status, error, batch (-1 if it never ran), submit_s
+ *                       (since the server started), latency_s.  Lines are
+ *                       written after each launch and by pc_server_drain.
+ * The environment variable PC_HBM_BUDGET_BYTES, if set, replaces the default
+ * of "hbm_budget_bytes" (the key still wins).
  * Admission is first come, first served: requests enter in submission order
  * while max_inflight, the free device memory minus the budget and the bytes
  * held by running batches (128 bytes per point + 1 MiB each), and

@@ -55,10 +55,17 @@ struct ServerCfg {
     int mode = PC_MIXED;
     int max_queue = 1 << 20;
     double deadline_s = 0;  // 0: no queueing deadline
+    std::string log_path;   // one JSON line per finished request is appended here (empty: none)
 };
 
 // minimal reader for flat {"key": number, ...} objects
 bool parse_cfg(const char *s, ServerCfg &c, std::string &err) {
+    if (const char *env = getenv("PC_HBM_BUDGET_BYTES")) {
+        char *end = nullptr;
+        const double v = strtod(env, &end);
+        if (end == env || !(v >= 0.0)) { err = "PC_HBM_BUDGET_BYTES must be a number >= 0"; return false; }
+        c.hbm_budget = static_cast<uint64_t>(std::min(v, 0x1p63));
+    }
     if (!s) return true;
     std::string j(s);
     size_t p = 0;
@@ -78,6 +85,18 @@ bool parse_cfg(const char *s, ServerCfg &c, std::string &err) {
         if (p >= j.size() || j[p] != ':') { err = "config: expected ':'"; return false; }
         ++p;
         skip();
+        if (key == "log_path") {
+            if (p >= j.size() || j[p] != '"') { err = "config: log_path must be a string"; return false; }
+            const size_t q2 = j.find('"', p + 1);
+            if (q2 == std::string::npos) { err = "config: bad log_path"; return false; }
+            c.log_path = j.substr(p + 1, q2 - p - 1);
+            p = q2 + 1;
+            skip();
+            if (p < j.size() && j[p] == ',') { ++p; continue; }
+            if (p < j.size() && j[p] == '}') break;
+            err = "config: expected ',' or '}'";
+            return false;
+        }
         char *end = nullptr;
         const double v = strtod(j.c_str() + p, &end);
         if (end == j.c_str() + p) { err = "config: value of " + key + " must be a number"; return false; }
@@ -107,6 +126,7 @@ struct Request {
     std::vector<double> ra, dec;
     std::vector<double> edges;
     Clock::time_point t_submit;
+    int64_t n_points = 0;
     uint64_t need_bytes = 0;
     double pairs = 0;
     bool running = false;    // admitted: its batch is on the device
@@ -215,11 +235,47 @@ struct Server {
     std::vector<double> latencies;
     Clock::time_point t0 = Clock::now();
     std::string stats_buf;
+    std::vector<std::string> log_pending;  // request log lines not yet written (mu)
+    std::mutex log_mu;                     // serialises appends to cfg.log_path
 
     void worker(int k);
     int take_batch(std::vector<std::shared_ptr<Request>> &out, uint64_t &bytes);
     void finish_unrun(Request &r, int status, const std::string &msg);  // mu held
+    void log_request(const Request &r, int64_t batch);                  // mu held
+    void write_log();                                                    // mu not held
 };
+
+void Server::log_request(const Request &r, int64_t batch) {
+    if (cfg.log_path.empty()) return;
+    std::string err;
+    for (char ch : r.error) {
+        if (ch == '"' || ch == '\\') err += '\\';
+        if (static_cast<unsigned char>(ch) >= 0x20) err += ch;
+    }
+    std::ostringstream o;
+    o.precision(9);
+    o << "{\"id\": " << r.id << ", \"patch\": " << r.patch << ", \"n\": " << r.n_points
+      << ", \"n_edges\": " << r.edges.size() << ", \"pairs\": " << r.pairs << ", \"status\": " << r.status
+      << ", \"error\": \"" << err << "\", \"batch\": " << batch
+      << ", \"submit_s\": " << std::chrono::duration<double>(r.t_submit - t0).count()
+      << ", \"latency_s\": " << r.latency << "}\n";
+    log_pending.push_back(o.str());
+}
+
+void Server::write_log() {
+    if (cfg.log_path.empty()) return;
+    std::vector<std::string> lines;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        lines.swap(log_pending);
+    }
+    if (lines.empty()) return;
+    std::lock_guard<std::mutex> lk(log_mu);
+    if (FILE *f = fopen(cfg.log_path.c_str(), "a")) {
+        for (const auto &l : lines) fwrite(l.data(), 1, l.size(), f);
+        fclose(f);
+    }
+}
 
 void Server::finish_unrun(Request &r, int status, const std::string &msg) {
     r.status = status;
@@ -230,6 +286,7 @@ void Server::finish_unrun(Request &r, int status, const std::string &msg) {
     std::vector<double>().swap(r.dec);
     ++n_failed;
     if (status == PC_ERR_CANCELLED) ++n_cancelled;
+    log_request(r, -1);
 }
 
 int Server::take_batch(std::vector<std::shared_ptr<Request>> &out, uint64_t &bytes) {
@@ -406,6 +463,7 @@ void Server::worker(int k) {
                 if (r.status == PC_OK) latencies.push_back(r.latency);
                 r.running = false;
                 r.done = true;
+                log_request(r, static_cast<int64_t>(n_batches));
                 std::vector<double>().swap(r.ra);
                 std::vector<double>().swap(r.dec);
                 --inflight;
@@ -416,6 +474,7 @@ void Server::worker(int k) {
             pairs_done += pairs;
             busy_s += dt;
         }
+        write_log();
         cv_done.notify_all();
         cv_work.notify_all();
     }
@@ -514,6 +573,7 @@ int pc_server_submit(void *server, const pc_catalog *data, int32_t patch_id, con
         }
     }
     r->need_bytes = 128ull * std::max<size_t>(n, 1) + (1u << 20);
+    r->n_points = static_cast<int64_t>(n);
     std::lock_guard<std::mutex> lk(s->mu);
     auto pit = s->patches.find(patch_id);
     if (pit == s->patches.end()) return fail(PC_ERR_INVALID, "no random catalogue registered for this patch");
@@ -598,8 +658,11 @@ int pc_server_drain(void *server) {
     clear_error();
     auto *s = static_cast<Server *>(server);
     if (!s) return fail(PC_ERR_INVALID, "server is NULL");
-    std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_done.wait(lk, [&] { return s->queue.empty() && s->inflight == 0; });
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_done.wait(lk, [&] { return s->queue.empty() && s->inflight == 0; });
+    }
+    s->write_log();
     return PC_OK;
 }
 
@@ -644,6 +707,7 @@ int pc_server_destroy(void *server) {
     }
     s->cv_work.notify_all();
     for (auto &t : s->workers) t.join();
+    s->write_log();
     (void)hipSetDevice(s->device);
     for (auto &p : s->patches) release_catalog(p.second.handle);
     for (auto st : s->streams) (void)hipStreamDestroy(st);

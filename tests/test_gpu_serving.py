@@ -194,3 +194,24 @@ def test_two_streams_run_two_batches_at_once():
             assert res["RR"].tolist() == rr.tolist()
     finally:
         srv.close()
+
+
+def test_request_log_has_one_line_per_finished_request(tmp_path):
+    import json
+    log = tmp_path / "requests.jsonl"
+    patches, reqs, rands, cats = _patches_and_requests(6, n_max=5_000, n_random=5_000)
+    srv = pc.Server({"streams": 2, "log_path": str(log)})
+    try:
+        for p, R in enumerate(rands):
+            srv.set_random(p, R)
+        ids = [srv.submit(cat, r["patch"], r["edges"]) for r, cat in zip(reqs, cats)]
+        srv.drain()
+        lines = [json.loads(l) for l in log.read_text().splitlines()]
+        assert sorted(l["id"] for l in lines) == sorted(ids)
+        for l, r, cat in zip(sorted(lines, key=lambda l: l["id"]), reqs, cats):
+            assert l["status"] == 0 and l["error"] == "" and l["batch"] >= 0
+            assert l["n"] == cat[0].size and l["n_edges"] == len(r["edges"]) and l["latency_s"] > 0
+        for jid in ids:
+            srv.poll(jid)
+    finally:
+        srv.close()

@@ -167,3 +167,20 @@ def test_fake_executor_burst_expires_late_requests():
     first_expired = status.index("expired")
     assert all(s == "ok" for s in status[:first_expired]) and all(s == "expired" for s in status[first_expired:])
     assert all(len(b) == 1 for _, b in log)
+
+
+def test_budget_from_environment_and_string_keys(monkeypatch):
+    need, pairs, age = [int(3 * GB)], [1e9], [0.0]
+    # default budget 4 GiB: 3 GiB fits in 8 GiB free
+    assert pc.pc_debug_admission_plan(need, pairs, age, 8 * GB, 288 * GB).tolist() == [A]
+    monkeypatch.setenv("PC_HBM_BUDGET_BYTES", str(6 * GB))
+    assert pc.pc_debug_admission_plan(need, pairs, age, 8 * GB, 288 * GB).tolist() == [W]
+    # an explicit key wins over the environment
+    assert pc.pc_debug_admission_plan(need, pairs, age, 8 * GB, 288 * GB, config={"hbm_budget_bytes": 0}).tolist() == [A]
+    monkeypatch.setenv("PC_HBM_BUDGET_BYTES", "lots")
+    with pytest.raises(pc.PcError):
+        pc.pc_debug_admission_plan(need, pairs, age, 8 * GB, 288 * GB)
+    monkeypatch.delenv("PC_HBM_BUDGET_BYTES")
+    assert pc.pc_debug_admission_plan(need, pairs, age, 8 * GB, 288 * GB, config={"log_path": "/tmp/x.jsonl"}).tolist() == [A]
+    with pytest.raises(pc.PcError):
+        pc.pc_debug_admission_plan(need, pairs, age, 8 * GB, 288 * GB, config={"log_path": 3})
