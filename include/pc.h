@@ -286,7 +286,10 @@ int pc_guard_band(const double *theta_edges_deg, int32_t n_edges, float *lo, flo
 int pc_server_create(const char *json_cfg, void **server);
 
 /* Register the random catalogue of sky patch `patch_id` (converted and kept
- * resident; copied, so the caller may free its arrays afterwards). */
+ * resident; copied, so the caller may free its arrays afterwards).  Replacing
+ * a patch's catalogue drops its cached RR counts; launches already running
+ * keep using the old copy, which is released when none runs; requests not yet
+ * launched use the new one. */
 int pc_server_set_random(void *server, int32_t patch_id, const pc_catalog *randoms);
 
 /* Submit a request.  The data arrays are copied before return.  *job_id
@@ -320,6 +323,9 @@ int pc_server_drain(void *server);
  * next call on this thread). */
 const char *pc_server_stats(void *server);
 
+/* Stop the server: requests still waiting for admission are dropped, running
+ * launches finish, then the streams and resident catalogues are released.
+ * Unpolled answers are lost. */
 int pc_server_destroy(void *server);
 
 #ifdef __cplusplus

@@ -204,8 +204,10 @@ int plan_admission(const QueuedView *q, int n, uint64_t free_b, uint64_t total_b
     return admitted;
 }
 
-std::string edge_key(int32_t patch, const std::vector<double> &e) {
-    std::string k(reinterpret_cast<const char *>(&patch), sizeof(patch));
+// RR cache key: the random catalogue's handle (unique per upload, so counts
+// of a replaced catalogue never match) and the edges.
+std::string rr_key(uint64_t random_handle, const std::vector<double> &e) {
+    std::string k(reinterpret_cast<const char *>(&random_handle), sizeof(random_handle));
     k.append(reinterpret_cast<const char *>(e.data()), sizeof(double) * e.size());
     return k;
 }
@@ -221,6 +223,7 @@ struct Server {
     std::unordered_map<uint64_t, std::shared_ptr<Request>> jobs;  // submitted, not yet polled
     std::map<int32_t, Patch> patches;
     std::map<std::string, std::vector<uint64_t>> rr_cache;
+    std::vector<uint64_t> retired;  // replaced random catalogues, released once no launch runs
     uint64_t next_id = 1;
     int inflight = 0;
     uint64_t reserved = 0;
@@ -396,7 +399,7 @@ void Server::worker(int k) {
             dr.auto_flag = 0;
             dr.counts = r.DR.data();
             jobs.push_back(dr);
-            const std::string key = edge_key(r.patch, r.edges);
+            const std::string key = rr_key(pinfo[q].handle, r.edges);
             bool cached;
             {
                 std::lock_guard<std::mutex> lk(mu);
@@ -435,7 +438,15 @@ void Server::worker(int k) {
         {
             std::lock_guard<std::mutex> lk(mu);
             if (rc == PC_OK)
-                for (size_t s = 0; s < rr_keys.size(); ++s) rr_cache.emplace(rr_keys[s], rr_store[s]);
+                for (size_t s = 0; s < rr_keys.size(); ++s) {
+                    uint64_t h;
+                    memcpy(&h, rr_keys[s].data(), sizeof(h));
+                    const bool current = std::any_of(patches.begin(), patches.end(),
+                                                     [&](const std::pair<const int32_t, Patch> &pp) {
+                                                         return pp.second.handle == h;
+                                                     });
+                    if (current) rr_cache.emplace(rr_keys[s], rr_store[s]);
+                }
             for (size_t q = 0; q < batch.size(); ++q) {
                 Request &r = *batch[q];
                 if (r.cancelled) {
@@ -471,6 +482,11 @@ void Server::worker(int k) {
             reserved -= bytes;
             --running_batches;
             ++n_batches;
+            if (running_batches == 0) {
+                // no launch can still use a replaced random catalogue
+                for (uint64_t h : retired) release_catalog(h);
+                retired.clear();
+            }
             pairs_done += pairs;
             busy_s += dt;
         }
@@ -524,12 +540,15 @@ int pc_server_set_random(void *server, int32_t patch_id, const pc_catalog *rando
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->patches.find(patch_id);
     if (it != s->patches.end()) {
-        release_catalog(it->second.handle);
-        // drop cached RR of this patch
+        const uint64_t old = it->second.handle;
+        // a running launch may still read the old catalogue: release it once
+        // none runs; its cached RR counts are dropped now
+        if (s->running_batches == 0) release_catalog(old);
+        else s->retired.push_back(old);
         for (auto c = s->rr_cache.begin(); c != s->rr_cache.end();) {
-            int32_t p;
-            memcpy(&p, c->first.data(), sizeof(p));
-            if (p == patch_id) c = s->rr_cache.erase(c);
+            uint64_t h;
+            memcpy(&h, c->first.data(), sizeof(h));
+            if (h == old) c = s->rr_cache.erase(c);
             else ++c;
         }
     }
@@ -702,14 +721,20 @@ int pc_server_destroy(void *server) {
     auto *s = static_cast<Server *>(server);
     if (!s) return PC_OK;
     {
+        // nobody can poll after this call: requests still waiting are dropped,
+        // launches already running finish
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
+        for (auto &r : s->queue) s->finish_unrun(*r, PC_ERR_CANCELLED, "server destroyed before admission");
+        s->queue.clear();
     }
     s->cv_work.notify_all();
+    s->cv_done.notify_all();
     for (auto &t : s->workers) t.join();
     s->write_log();
     (void)hipSetDevice(s->device);
     for (auto &p : s->patches) release_catalog(p.second.handle);
+    for (uint64_t h : s->retired) release_catalog(h);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
     delete s;
     return PC_OK;

@@ -215,3 +215,41 @@ def test_request_log_has_one_line_per_finished_request(tmp_path):
             srv.poll(jid)
     finally:
         srv.close()
+
+
+def test_replacing_a_patch_random_catalogue_mid_stream():
+    R1, big, (s1, s2), e = _big_and_small(44)
+    R2 = synth.uniform_patch(300_000, synth.centred_patch(50.0), np.random.default_rng(45))
+    srv = pc.Server({"streams": 2, "max_batch_pairs": 1})
+    try:
+        srv.set_random(0, R1)
+        a = srv.submit(big, 0, e)           # long: still running when the patch is replaced
+        b = srv.submit(s1, 0, e)
+        srv.set_random(0, R2)
+        c = srv.submit(s2, 0, e)            # submitted after the replacement: uses R2
+        srv.drain()
+        res = {j: srv.poll(j) for j in (a, b, c)}
+        dd, dr, rr = _alone(s2, R2, e)
+        assert res[c]["DR"].tolist() == dr.tolist() and res[c]["RR"].tolist() == rr.tolist()
+        # the earlier requests: DR, RR and w all from one and the same random catalogue
+        for j, cat in ((a, big), (b, s1)):
+            matches = []
+            for R in (R1, R2):
+                dd, dr, rr = _alone(cat, R, e)
+                w = pc.pc_wtheta(dd[1:-1], dr[1:-1], rr[1:-1], cat[0].size, R[0].size)
+                matches.append(res[j]["DR"].tolist() == dr.tolist() and res[j]["RR"].tolist() == rr.tolist()
+                               and np.array_equal(res[j]["w"], w, equal_nan=True))
+            assert any(matches)
+    finally:
+        srv.close()
+
+
+def test_destroy_drops_waiting_requests_and_returns():
+    R, big, (s1, _), e = _big_and_small(46)
+    srv = pc.Server({"streams": 1, "max_inflight": 1})
+    srv.set_random(0, R)
+    for _ in range(3):
+        srv.submit(big, 0, e)               # one runs, the others wait
+    t0 = time.perf_counter()
+    srv.close()
+    assert time.perf_counter() - t0 < 30.0
