@@ -114,7 +114,17 @@ struct TableKey {
 };
 
 static std::mutex g_tab_mu;
-static std::map<TableKey, std::shared_ptr<DevTable>> g_tabs;
+// Device tables by (device, cols, edges), least recently used dropped past
+// kMaxCachedTables (a launch holds its own references, so dropping an entry
+// never frees a table in use).  A server with a new edge set per request
+// would otherwise keep every table.
+constexpr size_t kMaxCachedTables = 256;
+struct CachedTable {
+    std::shared_ptr<DevTable> t;
+    uint64_t last_use = 0;
+};
+static std::map<TableKey, CachedTable> g_tabs;
+static uint64_t g_tab_tick = 0;
 
 DevTable::~DevTable() {
     if (d_mem) (void)hipFree(d_mem);
@@ -135,7 +145,8 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
         std::lock_guard<std::mutex> lk(g_tab_mu);
         auto it = g_tabs.find(key);
         if (it != g_tabs.end()) {
-            *out = it->second;
+            it->second.last_use = ++g_tab_tick;
+            *out = it->second.t;
             return PC_OK;
         }
     }
@@ -175,10 +186,17 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
     std::lock_guard<std::mutex> lk(g_tab_mu);
     auto it = g_tabs.find(key);
     if (it != g_tabs.end()) {
-        *out = it->second;  // another thread won; ours is freed
+        it->second.last_use = ++g_tab_tick;
+        *out = it->second.t;  // another thread won; ours is freed
         return PC_OK;
     }
-    g_tabs.emplace(key, t);
+    if (g_tabs.size() >= kMaxCachedTables) {
+        auto lru = g_tabs.begin();
+        for (auto c = g_tabs.begin(); c != g_tabs.end(); ++c)
+            if (c->second.last_use < lru->second.last_use) lru = c;
+        g_tabs.erase(lru);
+    }
+    g_tabs.emplace(key, CachedTable{t, ++g_tab_tick});
     *out = t;
     return PC_OK;
 }

@@ -314,3 +314,18 @@ def test_split_items_match_oracle(mode):
     dr = pc.pc_count_ex(dev(D), e, B=dev(R), auto=False, mode=mode)
     assert pc.pc_debug_last_pruning()["split_items"] > 0
     assert dr.tolist() == oracle.count(D, e, B=R, auto=False).tolist()
+
+
+def test_many_edge_sets_cycle_the_table_cache():
+    # more distinct edge sets than the library keeps device tables for: old
+    # tables are dropped and rebuilt when they come back; counts stay exact
+    rng = np.random.default_rng(47)
+    A = synth.uniform_patch(400, synth.centred_patch(20.0), rng)
+    Ad = dev(A)
+    sets = [synth.log_edges(0.05 + 0.001 * k, 10.0 + 0.01 * k, 10 + k % 20) for k in range(300)]
+    for k, e in enumerate(sets + sets[:5]):
+        got = pc.pc_count_ex(Ad, e)
+        if k % 37 == 0 or k >= 300:
+            assert got.tolist() == oracle.count(A, e).tolist(), k
+        else:
+            assert int(got.sum()) == 400 * 399 // 2
