@@ -461,7 +461,6 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             tabs.push_back(t);
         }
         plan[q].tab = it->second;
-        plan[q].o_counts = ar.take(sizeof(unsigned long long) * static_cast<size_t>(j.n_edges + 1));
         if (j.auto_flag) {
             // pairs i<j with i in [r0, r1): triangle on [r0, r1) + rectangle [r0, r1) x [r1, n)
             plan[q].vi_tri = add_view(sa, r0, r1);
@@ -474,7 +473,22 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             plan[q].vj_rect = add_view(sb, 0, srcs[sb].n);
         }
     }
-    const size_t o_err = ar.take(sizeof(int) * std::max<size_t>(srcs.size(), 1));
+    // results block, read back with one copy: meta[16] | each job's counts | conversion flags
+    // (meta[0..6]: pruning figures, meta[7]: re-check tally, meta[8..15]: the
+    // counting kernel's work queue)
+    size_t res_words = 16;
+    for (size_t q = 0; q < jobs.size(); ++q) res_words += static_cast<size_t>(jobs[q].n_edges + 1);
+    const size_t err_words = (std::max<size_t>(srcs.size(), 1) + 1) / 2;
+    const size_t o_res = ar.take(sizeof(unsigned long long) * (res_words + err_words));
+    {
+        size_t w = 16;
+        for (size_t q = 0; q < jobs.size(); ++q) {
+            plan[q].o_counts = o_res + sizeof(unsigned long long) * w;
+            w += static_cast<size_t>(jobs[q].n_edges + 1);
+        }
+    }
+    const size_t o_err = o_res + sizeof(unsigned long long) * res_words;
+    const size_t o_meta = o_res;
     const size_t o_scratch = ar.take(sizeof(uint32_t) * (max_sort_n > 0 ? sort_scratch_words(max_sort_n) : 1));
 
     // ---- segments
@@ -522,8 +536,6 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
                                         "); split the catalogues into row ranges");
     const size_t o_segs = ar.take(sizeof(SegDesc) * std::max<size_t>(segs.size(), 1));
     const size_t o_tabs = ar.take(sizeof(TableDesc) * tabs.size());
-    // meta[0..5]: pruning results; meta[8..15]: the counting kernel's work queue
-    const size_t o_meta = ar.take(sizeof(unsigned long long) * 16);
     const size_t o_surv = ar.take(sizeof(uint64_t) * std::max<uint64_t>(prune ? items : 1, 1));
     // split survivors: the prune pass looks at the j-tile's sub-blocks too
     // (mixed mode); their descriptions sit beside the survivors
@@ -537,7 +549,8 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     unsigned char *W = static_cast<unsigned char *>(ws.mem);
 
     // ---- convert the sources (validity flags read back at the end)
-    PC_HIP(hipMemsetAsync(W + o_err, 0, sizeof(int) * std::max<size_t>(srcs.size(), 1), st), "hipMemsetAsync(err)");
+    PC_HIP(launch_zero(reinterpret_cast<unsigned long long *>(W + o_res), static_cast<int64_t>(res_words + err_words), st),
+           "zero results");
     std::vector<const double4 *> src_a64(srcs.size(), nullptr);
     for (size_t k = 0; k < srcs.size(); ++k) {
         if (srcs[k].res) {
@@ -634,11 +647,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
                "H2D segments");
     PC_HIP(hipMemcpyAsync(W + o_tabs, tds.data(), sizeof(TableDesc) * tds.size(), hipMemcpyHostToDevice, st),
            "H2D tables");
-    for (size_t q = 0; q < jobs.size(); ++q)
-        PC_HIP(launch_zero(reinterpret_cast<unsigned long long *>(W + plan[q].o_counts), jobs[q].n_edges + 1, st),
-               "zero counts");
     unsigned long long *meta = reinterpret_cast<unsigned long long *>(W + o_meta);
-    PC_HIP(launch_zero(meta, 16, st), "zero meta");
 
     // ---- whole-tile-pair binning, then the counting kernel over the rest
     const SegDesc *d_segs = reinterpret_cast<const SegDesc *>(W + o_segs);
@@ -674,22 +683,17 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     }
 
     // ---- results: counts, validity flags and pruning figures under one sync
-    std::vector<std::vector<uint64_t>> host_counts(jobs.size());
-    for (size_t q = 0; q < jobs.size(); ++q) {
-        host_counts[q].resize(static_cast<size_t>(jobs[q].n_edges + 1));
-        PC_HIP(hipMemcpyAsync(host_counts[q].data(), W + plan[q].o_counts, sizeof(uint64_t) * host_counts[q].size(),
-                              hipMemcpyDeviceToHost, st),
-               "D2H counts");
-    }
-    std::vector<int> flags(std::max<size_t>(srcs.size(), 1), 0);
-    PC_HIP(hipMemcpyAsync(flags.data(), W + o_err, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, st), "D2H flags");
-    unsigned long long hmeta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    PC_HIP(hipMemcpyAsync(hmeta, meta, sizeof(hmeta), hipMemcpyDeviceToHost, st), "D2H meta");
+    std::vector<unsigned long long> hres(res_words + err_words, 0ull);
+    PC_HIP(hipMemcpyAsync(hres.data(), W + o_res, sizeof(unsigned long long) * hres.size(), hipMemcpyDeviceToHost, st),
+           "D2H results");
     PC_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    const int *flags = reinterpret_cast<const int *>(hres.data() + res_words);
     for (size_t k = 0; k < srcs.size(); ++k)
         if (flags[k]) return fail(PC_ERR_INVALID, "catalogue has non-finite RA/Dec or |Dec| > 90");
     for (size_t q = 0; q < jobs.size(); ++q)
-        memcpy(jobs[q].counts, host_counts[q].data(), sizeof(uint64_t) * host_counts[q].size());
+        memcpy(jobs[q].counts, hres.data() + (plan[q].o_counts - o_res) / sizeof(unsigned long long),
+               sizeof(uint64_t) * static_cast<size_t>(jobs[q].n_edges + 1));
+    const unsigned long long *hmeta = hres.data();
 
     uint64_t total_pairs = 0;
     for (const SegDesc &sd : segs) {
