@@ -329,3 +329,45 @@ def test_many_edge_sets_cycle_the_table_cache():
             assert got.tolist() == oracle.count(A, e).tolist(), k
         else:
             assert int(got.sum()) == 400 * 399 // 2
+
+
+def test_concurrent_calls_on_distinct_streams():
+    # the C ABI is thread-safe on distinct streams: four host threads count
+    # different catalogues and edge sets at once; each result equals the
+    # same call made alone
+    import threading
+    rng = np.random.default_rng(48)
+    cases = []
+    for k in range(4):
+        A = synth.neyman_scott(60 + 20 * k, 20, 0.3, synth.centred_patch(30.0), rng)
+        B = synth.uniform_patch(3000 + 500 * k, synth.centred_patch(30.0), rng)
+        e = synth.log_edges(0.02 * (k + 1), 15.0, 12 + 6 * k)
+        cases.append((dev(A), dev(B), e, A, B))
+    torch.cuda.synchronize()
+    alone = [(pc.pc_count_ex(a, e), pc.pc_count_ex(a, e, B=b, auto=False)) for a, b, e, _, _ in cases]
+    streams = [torch.cuda.Stream() for _ in cases]
+    got = [None] * len(cases)
+    errors = []
+
+    def work(k):
+        try:
+            a, b, e, _, _ = cases[k]
+            out = []
+            for _ in range(5):
+                out.append((pc.pc_count_ex(a, e, stream=streams[k]),
+                            pc.pc_count_ex(a, e, B=b, auto=False, stream=streams[k])))
+            got[k] = out
+        except Exception as ex:  # reported below
+            errors.append(repr(ex))
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(len(cases))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(120)
+    assert not errors, errors
+    for k, (dd, dr) in enumerate(alone):
+        for gdd, gdr in got[k]:
+            assert gdd.tolist() == dd.tolist() and gdr.tolist() == dr.tolist(), k
+    a, b, e, A, B = cases[0]
+    assert alone[0][1].tolist() == oracle.count(A, e, B=B, auto=False).tolist()
