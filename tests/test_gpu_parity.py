@@ -184,11 +184,16 @@ def test_invalid_device_input_reported():
 
 
 def test_repeatable_counts():
+    # 20 runs cycling through the kernels and work distributions (mixed,
+    # matrix cores, every pair visited, binary64; the tuner's 18 launch
+    # shapes are compared inside pc_autotune): integer counts, so any race
+    # between waves would show as a difference
     c = synth.config_small(scale=0.5)
     D, e = dev(c["D"]), c["edges"]
     first = pc.pc_count(D, e)
-    for _ in range(5):
-        assert pc.pc_count(D, e).tolist() == first.tolist()
+    modes = [pc.PC_MIXED, pc.PC_MIXED | pc.PC_MATRIX_CORES, pc.PC_MIXED | pc.PC_NO_PRUNE, pc.PC_FP64_PLAIN]
+    for k in range(20):
+        assert pc.pc_count_ex(D, e, mode=modes[k % 4]).tolist() == first.tolist(), k
 
 
 def test_1m_config_sampled_rows_and_decompositions():
