@@ -170,21 +170,31 @@ __device__ __forceinline__ void ap_pair(const ApGal &G, double xg, double yg, do
     if (d2 < r2 && d2 > 0.0) {
         cnt += 1u;
         const float fx = static_cast<float>(ddx), fy = static_cast<float>(ddy);
-        const float f2 = fmaxf(static_cast<float>(d2), FLT_MIN);
-        const float rinv = __builtin_amdgcn_rsqf(f2);
-        const float r = f2 * rinv;
+        const float f2 = static_cast<float>(d2);  // 0 only if |d| < ~1e-19 (then r is NaN below)
+        float rinv = __builtin_amdgcn_rsqf(f2);
+        float r = f2 * rinv;
         const float e2u = __builtin_amdgcn_exp2f(r * K.k_e);
-        const float u = r * K.k_u;
-        const float ea = __builtin_amdgcn_exp2f(fmaf(r, K.k_a, K.c_a));
-        const float eb = __builtin_amdgcn_exp2f(fmaf(r, K.k_b, K.c_b));
-        const float D = (1.0f + ea) + eb;
+        float u = r * K.k_u;
+        float ea = __builtin_amdgcn_exp2f(fmaf(r, K.k_a, K.c_a));
+        float eb = __builtin_amdgcn_exp2f(fmaf(r, K.k_b, K.c_b));
+        float D = (1.0f + ea) + eb;
         // tanh(u)/u = (e^2u - 1) / ((e^2u + 1) u); near u = 0 its series
         // 1 - u^2/3 + 2u^4/15 (next term below 4e-9 there).  The series is
         // needed only within 0.0094 theta_max of the point, so it is a branch
         // that is almost never taken rather than selects every pair pays for.
+        // The same branch catches a squared distance that rounded to zero in
+        // binary32 (u is NaN then): it redoes the filter from |d|^2 raised to
+        // the smallest normal binary32 value.
         float num = e2u - 1.0f;
         float den = ((e2u + 1.0f) * u) * D;
-        if (__builtin_expect(u < 0.0625f, 0)) {
+        if (__builtin_expect(!(u >= 0.0625f), 0)) {
+            const float f2c = fmaxf(f2, FLT_MIN);
+            rinv = __builtin_amdgcn_rsqf(f2c);
+            r = f2c * rinv;
+            u = r * K.k_u;
+            ea = __builtin_amdgcn_exp2f(fmaf(r, K.k_a, K.c_a));
+            eb = __builtin_amdgcn_exp2f(fmaf(r, K.k_b, K.c_b));
+            D = (1.0f + ea) + eb;
             const float u2 = u * u;
             num = fmaf(u2, fmaf(u2, 0.133333333f, -0.333333333f), 1.0f);
             den = D;
