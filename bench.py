@@ -226,7 +226,7 @@ def cpu_baseline(c, target_s: float):
     return out
 
 
-def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: bool = True):
+def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: bool = True, server_cfg=None):
     """Stream of w(theta) requests (config: N log-uniform 1e3..2e6, clustered
     on one of 4 pool patches of side 5-50 deg, 10-50 log bins).  The server's
     capacity on this stream is measured first (every request submitted at
@@ -262,7 +262,7 @@ def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: 
                 "gpairs_s": st["pairs"] / wall / 1e9, "wall_s": wall, "batches": st["batches"],
                 "rr_cached": st["rr_cached"]}, res
 
-    mixed_cfg = {"streams": 2, "max_inflight": 64}
+    mixed_cfg = {"streams": 2, "max_inflight": 64, **(server_cfg or {})}
     closed, _ = run(np.zeros(n_req), mixed_cfg)
     capacity = n_req / closed["wall_s"]
     unit_gaps = np.random.Generator(np.random.PCG64(1000 * seed_config + 4)).exponential(1.0, n_req)
@@ -356,6 +356,8 @@ def main():
     ap.add_argument("--no-prune-compare", action="store_true",
                     help="skip the extra step that visits every pair")
     ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-config", default="",
+                    help="JSON object of pc_server_create keys overriding the mixed server's (e.g. streams)")
     ap.add_argument("--serve-loads", default="0.7", metavar="F,F,...",
                     help="Poisson arrival rates as fractions of the measured capacity (0.7 is always reported)")
     ap.add_argument("--no-serve-fp64-compare", action="store_true",
@@ -541,7 +543,10 @@ def main():
         log(f"one launch per job: {t1 * 1e3:.1f} ms")
     if args.serve_requests > 0 and args.workload == "1m":
         loads = sorted({0.7, *(float(x) for x in args.serve_loads.split(",") if x.strip())})
-        out["serve"] = serve_run(pc, args.serve_requests, loads=loads, fp64_compare=not args.no_serve_fp64_compare)
+        out["serve"] = serve_run(pc, args.serve_requests, loads=loads, fp64_compare=not args.no_serve_fp64_compare,
+                                 server_cfg=json.loads(args.serve_config) if args.serve_config else None)
+        if args.serve_config:
+            out["serve"]["server_config"] = json.loads(args.serve_config)
         if "fp64_one_request_per_launch" in out["serve"]:
             log(f"serve: binary64 one per launch: p50 {out['serve']['fp64_one_request_per_launch']['p50_s']:.3f} s, "
                 f"p99 {out['serve']['fp64_one_request_per_launch']['p99_s']:.3f} s")
