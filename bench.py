@@ -39,19 +39,29 @@ def work_per_pair(n_bins: int) -> int:
     return 8 + math.ceil(math.log2(n_bins + 2))
 
 
+def code_fingerprint(path: str) -> str:
+    """SHA-256 of a source file's code: comments removed and whitespace
+    collapsed, so that editing a comment does not retire a profile record."""
+    import hashlib
+    import re
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
 def recorded_traffic(record: str, source: str):
     """HBM bytes per launch from a committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    record, if it was taken on the kernel source as it is now; else None."""
-    import hashlib
+    record, if it was taken on the kernel code as it is now; else None."""
     rec = os.path.join(ROOT, "profiles", record)
     src = os.path.join(ROOT, "paper_1208_3658_amd", "csrc", source)
     if not os.path.exists(rec):
         return None
     with open(rec) as f:
         r = json.load(f)
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    return r["traffic_bytes_per_launch"] if r.get("kernel_source_sha256") == sha else None
+    return r["traffic_bytes_per_launch"] if r.get("kernel_code_sha256") == code_fingerprint(src) else None
 
 
 # Aperture mass (Sec. 3): algorithmic flops per galaxy-point pair inside the

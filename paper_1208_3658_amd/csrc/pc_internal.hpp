@@ -30,9 +30,9 @@ constexpr uint32_t kLdsTarget = 16 * 1024;  // per-wave histogram bytes aimed fo
 // Histogram layout in LDS: n_edges + 3 rows (under/overflow bins, one
 // discard row for masked pairs, and one row tallying the pairs re-checked in
 // binary64) of `cols` lane columns.  Lane l adds to column
-// l & (cols - 1), so with cols = 64 no two lanes of a wave share a word, and
-// since a row is exactly `cols` words the word of lane l sits in bank l (mod
-// the bank count) whatever its row: the adds are free of bank conflicts.
+// l & (cols - 1); a row is exactly `cols` words, so the columns of one add sit
+// in distinct banks whatever their rows, and only the 64 / cols lanes that
+// share a column meet on a word (with cols = 64, none).
 inline uint32_t row_bytes_for(int cols) { return static_cast<uint32_t>(cols) * 4u; }
 
 // Cell lookup entry of the mixed (binary32) kernel.  For a squared chord c in

@@ -12,10 +12,12 @@
 //     tile only i < j: every unordered pair exactly once, no self-pairs
 //     (Sec. 2, n(n-1)/2 pairs); cross pairs use every tile pair (n_A n_B);
 //   * each workgroup is a single wave that owns its LDS: a private cell
-//     table for the current edge set and a histogram with one column per lane
-//     (no two lanes ever add to the same LDS word, so the paper's same-bin
-//     atomic contention, Sec. 2.1, cannot arise), flushed into 64-bit global
-//     counters when the job changes and at the end.
+//     table for the current edge set and a histogram of `cols` lane columns
+//     (8 to 64: only the 64 / cols lanes of one wave that share a column can
+//     meet on a word, never lanes of other waves, so the paper's same-bin
+//     atomic contention across threads, Sec. 2.1, is bounded), flushed into
+//     64-bit global counters when the job changes and at the end; the
+//     few-edge paths count in registers and touch LDS once per item.
 #include "pc_internal.hpp"
 #include "pc_math.h"
 
