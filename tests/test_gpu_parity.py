@@ -376,3 +376,21 @@ def test_concurrent_calls_on_distinct_streams():
             assert gdd.tolist() == dd.tolist() and gdr.tolist() == dr.tolist(), k
     a, b, e, A, B = cases[0]
     assert alone[0][1].tolist() == oracle.count(A, e, B=B, auto=False).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_largest_edge_set(mode):
+    # 1024 edges, the most a call takes: the widest histograms and cell
+    # tables in LDS, pairs spread over every bin
+    rng = np.random.default_rng(49)
+    A = synth.uniform_patch(1500, synth.centred_patch(60.0), rng)
+    B = synth.uniform_patch(900, synth.centred_patch(60.0), rng)
+    e = synth.log_edges(0.05, 80.0, 1023)
+    assert e.size == 1024
+    got = pc.pc_count_ex(dev(A), e, mode=mode)
+    assert got.tolist() == oracle.count(A, e).tolist()
+    got = pc.pc_count_ex(dev(A), e, B=dev(B), auto=False, mode=mode)
+    assert got.tolist() == oracle.count(A, e, B=B, auto=False).tolist()
+    lin = synth.linear_edges(0.0, 180.0, 1023)
+    got = pc.pc_count_ex(dev(A), lin, mode=mode)
+    assert got.tolist() == oracle.count(A, lin).tolist()

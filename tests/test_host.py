@@ -326,6 +326,7 @@ def test_estimators_match_oracle_bitwise():
     (((np.zeros(3), np.zeros(3)), [1.0]), ">= 2"),
     (((np.zeros(3), np.zeros(3)), [1.0, 181.0]), "[0, 180]"),
     (((np.zeros(3), np.zeros(3)), [-1.0, 1.0]), "[0, 180]"),
+    (((np.zeros(3), np.zeros(3)), list(np.linspace(0.0, 90.0, 1025))), "<= 1024"),
 ])
 def test_invalid_arguments_rejected_before_any_device_work(args, fragment):
     with pytest.raises(pc.PcError) as ex:
