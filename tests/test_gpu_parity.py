@@ -394,3 +394,34 @@ def test_largest_edge_set(mode):
     lin = synth.linear_edges(0.0, 180.0, 1023)
     got = pc.pc_count_ex(dev(A), lin, mode=mode)
     assert got.tolist() == oracle.count(A, lin).tolist()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_seeded_random_configurations(seed):
+    # random shapes drawn from a seed: patch size, clustering, sizes (ragged),
+    # edge sets (log or linear, 1..300 bins, zero edge or not), kernel, auto
+    # or cross, row range; every result against the oracle
+    rng = np.random.default_rng(1000 + seed)
+    side = float(rng.choice([2.0, 10.0, 45.0, 120.0]))
+    patch = synth.centred_patch(side) if side < 120 else synth.FULL_SKY
+    nA, nB = int(rng.integers(0, 2600)), int(rng.integers(1, 1800))
+    if rng.random() < 0.5 and nA >= 20:
+        A = synth.neyman_scott(max(1, nA // 20), 20, float(rng.uniform(0.01, 0.5)), patch, rng)
+    else:
+        A = synth.uniform_patch(nA, patch, rng) if nA else (np.zeros(0), np.zeros(0))
+    B = synth.uniform_patch(nB, patch, rng)
+    nbins = int(rng.integers(1, 300))
+    if rng.random() < 0.5:
+        lo = float(10 ** rng.uniform(-3, 0))
+        e = synth.log_edges(lo, float(min(180.0, lo * 10 ** rng.uniform(0.5, 4))), nbins)
+    else:
+        e = synth.linear_edges(0.0 if rng.random() < 0.5 else float(rng.uniform(0, 5)), float(rng.uniform(5, 180)), nbins)
+    mode = MODES[int(rng.integers(0, len(MODES)))]
+    n = A[0].size
+    r0 = int(rng.integers(0, n + 1))
+    r1 = int(rng.integers(r0, n + 1))
+    Ad = dev(A) if n else A
+    got = pc.pc_count_ex(Ad, e, mode=mode, rows=(r0, r1))
+    assert got.tolist() == oracle.count(A, e, rows=(r0, r1)).tolist(), (seed, n, nbins, mode, r0, r1)
+    got = pc.pc_count_ex(Ad, e, B=dev(B), auto=False, mode=mode)
+    assert got.tolist() == oracle.count(A, e, B=B, auto=False).tolist(), (seed, n, nB, nbins, mode)
