@@ -170,3 +170,20 @@ def test_paper_workload_sampled(grid_n, theta):
     info = pc.pc_debug_last_aperture()
     print(f"{grid_n}^2 theta={theta}: worst {worst:.3g} of tolerance; {info}")
     assert info["pairs_in"] == int(out["n_in"].sum().item())
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_seeded_random_maps(seed):
+    # random catalogue size and density, filter radius, grid shape, spacing
+    # and offset (grids partly off the field), against the oracle
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(0, 20000))
+    density = float(rng.uniform(5.0, 60.0))
+    cat, side = synth.shear_catalog(n, density=density, config=30 + seed)
+    theta = float(10 ** rng.uniform(-0.7, 1.0))
+    nx, ny = int(rng.integers(1, 70)), int(rng.integers(1, 70))
+    grid = (float(rng.uniform(-0.2, 0.5)) * side, float(rng.uniform(-0.2, 0.5)) * side,
+            float(rng.uniform(0.2, 1.5)) * side / nx, float(rng.uniform(0.2, 1.5)) * side / ny, nx, ny)
+    gpu = pc.pc_aperture_mass(cat, grid, theta, density)
+    ref = oracle.aperture_grid(cat, grid, theta, density)
+    _check(gpu, ref, density, f"seed {seed}: n={n} theta={theta:.3g} grid={nx}x{ny}")
