@@ -425,3 +425,31 @@ def test_seeded_random_configurations(seed):
     assert got.tolist() == oracle.count(A, e, rows=(r0, r1)).tolist(), (seed, n, nbins, mode, r0, r1)
     got = pc.pc_count_ex(Ad, e, B=dev(B), auto=False, mode=mode)
     assert got.tolist() == oracle.count(A, e, B=B, auto=False).tolist(), (seed, n, nB, nbins, mode)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_seeded_random_batches(seed):
+    # 3..12 jobs in one launch: shared and distinct catalogues, auto and
+    # cross, row ranges, several edge sets; each job against the oracle
+    rng = np.random.default_rng(3000 + seed)
+    patch = synth.centred_patch(float(rng.choice([5.0, 30.0, 90.0])))
+    cats = [synth.uniform_patch(int(rng.integers(1, 1500)), patch, rng) for _ in range(4)]
+    devs = [dev(c) for c in cats]
+    sets = [synth.log_edges(0.01, 20.0, int(rng.integers(2, 60))), synth.linear_edges(0.0, 90.0, int(rng.integers(1, 40)))]
+    jobs, want = [], []
+    for _ in range(int(rng.integers(3, 13))):
+        a, b = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+        e = sets[int(rng.integers(0, 2))]
+        if rng.random() < 0.5:
+            n = cats[a][0].size
+            r0 = int(rng.integers(0, n + 1))
+            r1 = int(rng.integers(r0, n + 1))
+            jobs.append({"A": devs[a], "edges": e, "rows": (r0, r1)})
+            want.append(oracle.count(cats[a], e, rows=(r0, r1)))
+        else:
+            jobs.append({"A": devs[a], "B": devs[b], "edges": e, "auto": False})
+            want.append(oracle.count(cats[a], e, B=cats[b], auto=False))
+    mode = MODES[seed % len(MODES)]
+    got = pc.pc_count_batch(jobs, mode=mode)
+    for k, (g, w) in enumerate(zip(got, want)):
+        assert g.tolist() == w.tolist(), (seed, k)
