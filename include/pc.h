@@ -270,6 +270,10 @@ int pc_guard_band(const double *theta_edges_deg, int32_t n_edges, float *lo, flo
  *   "deadline_s"        a request still waiting for admission this many
  *                       seconds after submission fails with PC_ERR_CANCELLED
  *                       (default 0: no deadline)
+ *   "policy"            0 (default): first come, first served; 1: requests
+ *                       waiting at least "aging_s" seconds (default 1) go
+ *                       first, oldest first, then the others with the fewest
+ *                       pairs first
  *   "log_path"          (a string) file to which one JSON line per finished
  *                       request is appended: id, patch, n, n_edges, pairs,
  *                       status, error, batch (-1 if it never ran), submit_s
@@ -277,7 +281,7 @@ int pc_guard_band(const double *theta_edges_deg, int32_t n_edges, float *lo, flo
  *                       written after each launch and by pc_server_drain.
  * The environment variable PC_HBM_BUDGET_BYTES, if set, replaces the default
  * of "hbm_budget_bytes" (the key still wins).
- * Admission is first come, first served: requests enter in submission order
+ * Admission (policy 0) is first come, first served: requests enter in submission order
  * while max_inflight, the free device memory minus the budget and the bytes
  * held by running batches (128 bytes per point + 1 MiB each), and
  * max_batch_pairs per launch allow.  A request that could not fit even on an

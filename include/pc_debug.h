@@ -92,7 +92,7 @@ int pc_debug_last_rechecks(uint64_t *pairs_rechecked);
  *   reserved_bytes bytes held by batches already running.
  *   inflight       requests already on the device.
  *   json_cfg       server configuration as for pc_server_create (may be NULL).
- *   outcome        host int32[n], written: 0 admitted into the next batch,
+ *   outcome        host int32[n] (in queue order), written: 0 admitted into the next batch,
  *                  1 fails (can never fit: PC_ERR_NOMEM), 2 fails (queueing
  *                  deadline passed: PC_ERR_CANCELLED), 3 keeps waiting.
  * Returns PC_OK, or PC_ERR_INVALID (NULL arrays with n > 0, n < 0, bad config).

@@ -55,6 +55,8 @@ struct ServerCfg {
     int mode = PC_MIXED;
     int max_queue = 1 << 20;
     double deadline_s = 0;  // 0: no queueing deadline
+    int policy = 0;         // 0: first come first served; 1: fewest pairs first, with ageing
+    double aging_s = 1.0;   // policy 1: requests waiting this long go first, oldest first
     std::string log_path;   // one JSON line per finished request is appended here (empty: none)
 };
 
@@ -108,6 +110,8 @@ bool parse_cfg(const char *s, ServerCfg &c, std::string &err) {
         else if (key == "mode") c.mode = static_cast<int>(v);
         else if (key == "max_queue") c.max_queue = std::max(1, static_cast<int>(v));
         else if (key == "deadline_s") c.deadline_s = std::max(0.0, v);
+        else if (key == "policy") c.policy = static_cast<int>(v);
+        else if (key == "aging_s") c.aging_s = std::max(0.0, v);
         else { err = "config: unknown key " + key; return false; }
         skip();
         if (p < j.size() && j[p] == ',') { ++p; continue; }
@@ -117,6 +121,7 @@ bool parse_cfg(const char *s, ServerCfg &c, std::string &err) {
         return false;
     }
     if (c.mode != PC_MIXED && c.mode != PC_FP64_PLAIN) { err = "config: mode must be 0 or 1"; return false; }
+    if (c.policy != 0 && c.policy != 1) { err = "config: policy must be 0 or 1"; return false; }
     return true;
 }
 
@@ -156,7 +161,8 @@ struct QueuedView {
 
 // The admission policy, free of device calls (the server feeds it the free
 // and total device memory it reads; tests feed it chosen figures).  Walks
-// the queue from the front:
+// the queue from the front (policy 0; policy 1 visits aged requests first,
+// then the rest by fewest pairs):
 //  * a request that cannot fit even on an empty device (need + budget >
 //    total) fails, wherever it stands;
 //  * a request past the queueing deadline fails, wherever it stands;
@@ -176,7 +182,20 @@ int plan_admission(const QueuedView *q, int n, uint64_t free_b, uint64_t total_b
     int admitted = 0;
     bool open = true;
     *memory_blocked = false;
-    for (int i = 0; i < n; ++i) {
+    // visiting order: the queue's, or (policy 1) requests past the ageing
+    // limit first, oldest first, then the rest by pairs, fewest first (ties in
+    // queue order)
+    std::vector<int> order(static_cast<size_t>(n));
+    for (int i = 0; i < n; ++i) order[static_cast<size_t>(i)] = i;
+    if (cfg.policy == 1)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const bool oa = q[a].age_s >= cfg.aging_s, ob = q[b].age_s >= cfg.aging_s;
+            if (oa != ob) return oa;
+            if (oa) return false;  // both aged: queue order (stable)
+            return q[a].pairs < q[b].pairs;
+        });
+    for (int k = 0; k < n; ++k) {
+        const int i = order[static_cast<size_t>(k)];
         if (q[i].need > total_b || cfg.hbm_budget > total_b - q[i].need) {
             outcome[i] = kNeverFits;
             continue;

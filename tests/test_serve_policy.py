@@ -184,3 +184,33 @@ def test_budget_from_environment_and_string_keys(monkeypatch):
     assert pc.pc_debug_admission_plan(need, pairs, age, 8 * GB, 288 * GB, config={"log_path": "/tmp/x.jsonl"}).tolist() == [A]
     with pytest.raises(pc.PcError):
         pc.pc_debug_admission_plan(need, pairs, age, 8 * GB, 288 * GB, config={"log_path": 3})
+
+
+def test_smallest_first_policy_with_ageing():
+    pairs = [3e12, 1e9, 5e11]
+    # fewest pairs first: the two small requests share a launch, the big one waits
+    assert plan([3, 1, 2], free_gb=100, pairs=pairs, policy=1, max_batch_pairs=2e12) == [W, A, A]
+    # a request past the ageing limit goes first whatever its size
+    assert plan([3, 1, 2], free_gb=100, pairs=pairs, age=[2.0, 0.0, 0.0], policy=1, aging_s=1.0,
+                max_batch_pairs=2e12) == [A, W, W]
+    # first come, first served by default
+    assert plan([3, 1, 2], free_gb=100, pairs=pairs, max_batch_pairs=2e12) == [A, W, W]
+    with pytest.raises(pc.PcError):
+        plan([1], free_gb=100, policy=2)
+
+
+def test_fake_executor_smallest_first_serves_everyone():
+    rng = np.random.default_rng(33)
+    n = 300
+    t = np.cumsum(rng.exponential(0.004, n))
+    npts = np.exp(rng.uniform(np.log(1e3), np.log(2e6), n))
+    need = (128 * npts + (1 << 20)).astype(np.int64)
+    pairs = npts ** 2 / 2
+    cfg = {"hbm_budget_bytes": 4 * GB, "max_inflight": 16, "streams": 2, "max_batch_pairs": 2e12,
+           "policy": 1, "aging_s": 0.5}
+    res, log = _simulate(list(zip(t, need, pairs)), 64 * GB, 288 * GB, cfg)
+    assert all(res[i][2] == "ok" for i in range(n))               # nobody starves
+    waits = np.array([res[i][0] - t[i] for i in range(n)])
+    fifo, _ = _simulate(list(zip(t, need, pairs)), 64 * GB, 288 * GB, {**cfg, "policy": 0})
+    fifo_waits = np.array([fifo[i][0] - t[i] for i in range(n)])
+    assert np.median(waits) <= np.median(fifo_waits) + 1e-12
