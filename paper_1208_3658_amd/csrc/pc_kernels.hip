@@ -854,16 +854,16 @@ __device__ __forceinline__ void tile64(unsigned char *lds, const double4 *__rest
 
 // Waves per SIMD asked of the register allocator.  The counting loops wait
 // on scalar loads of j-points, LDS and the i-point loads of each item, and
-// more resident waves hide that: on the 1M workload 3, 4, 5, 6, 7 and 8 waves
-// per SIMD give 73, 61, 57, 53, 52 and 56 ms.  At 7 (72 VGPRs) the
+// more resident waves hide that: on the 1M workload the mixed instance takes
+// 52.8, 51.3 and 50.7 ms at 6, 7 and 8 waves per SIMD.  At 8 (64 VGPRs) the
 // allocator spills to scratch, mostly around the rarely taken binary64
-// re-check branches.  The matrix-core instance keeps 3.
+// re-check branches.  The binary64 instance keeps 7, the matrix-core one 3.
 #ifdef PC_WAVES_PER_EU
 #define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PC_WAVES_PER_EU)))
 #elif defined(PC_NO_OCCUPANCY_HINT)
 #define PC_OCCUPANCY
 #else
-#define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MC ? 3 : 7)))
+#define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MC ? 3 : (FP64 ? 7 : 8))))
 #endif
 
 // MC: tile pairs marked by the prune pass go through the matrix cores (a
