@@ -39,6 +39,26 @@ def work_per_pair(n_bins: int) -> int:
     return 8 + math.ceil(math.log2(n_bins + 2))
 
 
+def work_per_pair_method(n_bins: int, m: int) -> int:
+    """Operations a pair needs on the path that binned it: 8 flops for the
+    chord, plus ceil(log2(m+1)) comparisons when the prune pass left only m
+    edges inside its chord interval (m + 1 possible rows), or
+    ceil(log2(B+2)) through the cell table (m = 0: any of the B + 2 rows)."""
+    return 8 + (math.ceil(math.log2(m + 1)) if m > 0 else math.ceil(math.log2(n_bins + 2)))
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu's "Model name")."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def code_fingerprint(path: str) -> str:
     """SHA-256 of a source file's code: comments removed and whitespace
     collapsed, so that editing a comment does not retire a profile record."""
@@ -176,7 +196,7 @@ def aperture_main(args):
         cores = oracle.num_threads()
         npts, pin, spent = sample(args.cpu_seconds)
         out["cpu_baseline"] = {"value": pin / spent / 1e9, "unit": "Gpairs/s", "cores": cores,
-                               "kind": "oracle",
+                               "kind": "oracle", "cpu_model": cpu_model(),
                                "sample": f"{npts} seeded points of the {G}^2 x {TH:g}' map, each against all "
                                          f"{cat[0].size} galaxies ({pin:.3e} pairs inside, {spent:.1f} s)"}
         if cores > 1:
@@ -223,6 +243,7 @@ def cpu_baseline(c, target_s: float):
     cores = oracle.num_threads()
     r, pairs, dt = sample(target_s)
     out = {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(),
            "sample": f"DD, DR and RR over the first {r} rows of the 1M workload ({pairs:.3e} pairs, {dt:.1f} s)"}
     if cores > 1:
         # the paper's speed-ups are against one CPU core (Sec. 4, Table 1)
@@ -236,7 +257,34 @@ def cpu_baseline(c, target_s: float):
     return out
 
 
-def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: bool = True, server_cfg=None):
+def serve_oracle_check(reqs, cats, randoms, results, budget_s: float):
+    """Served answers against the CPU oracle: DD and DR of whole requests,
+    smallest first, until about budget_s seconds of oracle time are spent.
+    (RR of a 10^6-point pool catalogue is 5e11 pairs per edge set, minutes of
+    oracle time each: it is compared with the tests' oracle-pinned batch
+    counts instead, not here.)"""
+    import oracle
+    order = sorted(range(len(reqs)), key=lambda k: (cats[k][0].size, k))
+    t0 = time.perf_counter()
+    checked, same, n_max, pairs = 0, True, 0, 0
+    for k in order:
+        if time.perf_counter() - t0 > budget_s:
+            break
+        r, cat, res = reqs[k], cats[k], results[k]
+        R = randoms[r["patch"]]
+        dd = oracle.count(cat, r["edges"])
+        dr = oracle.count(cat, r["edges"], B=R, auto=False)
+        same &= res["DD"].tolist() == dd.tolist() and res["DR"].tolist() == dr.tolist()
+        checked += 1
+        n_max = max(n_max, int(cat[0].size))
+        pairs += int(dd.sum()) + int(dr.sum())
+    return {"requests": checked, "of": len(reqs), "n_max": n_max, "pairs": pairs, "identical_dd_dr": bool(same),
+            "oracle_s": time.perf_counter() - t0, "threads": oracle.num_threads(),
+            "sample": "the smallest requests (whole DD and DR) within the oracle time budget"}
+
+
+def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: bool = True, server_cfg=None,
+              oracle_seconds: float = 0.0):
     """Stream of w(theta) requests (config: N log-uniform 1e3..2e6, clustered
     on one of 4 pool patches of side 5-50 deg, 10-50 log bins).  The server's
     capacity on this stream is measured first (every request submitted at
@@ -270,7 +318,8 @@ def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: 
         lat = np.sort(np.array([x["latency_s"] for x in res]))
         return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                 "gpairs_s": st["pairs"] / wall / 1e9, "wall_s": wall, "batches": st["batches"],
-                "rr_cached": st["rr_cached"]}, res
+                "rr_cached": st["rr_cached"], "parts_requeued": st.get("parts_requeued", 0),
+                "slice_pairs": st.get("slice_pairs")}, res
 
     mixed_cfg = {"streams": 2, "max_inflight": 64, **(server_cfg or {})}
     closed, _ = run(np.zeros(n_req), mixed_cfg)
@@ -285,6 +334,8 @@ def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: 
         log(f"serve at {load:.1f} x capacity ({rate:.2f}/s): p50 {mixed['p50_s']:.3f} s, p99 {mixed['p99_s']:.3f} s")
         if abs(load - 0.7) < 1e-9:
             out.update({"rate_hz": rate, **mixed})
+            if oracle_seconds > 0:
+                out["oracle_check"] = serve_oracle_check(reqs, cats, randoms, res_m, oracle_seconds)
             if fp64_compare:
                 single64, res_f = run(arrivals, {"streams": 1, "max_inflight": 64, "max_batch_pairs": 1,
                                                  "mode": pc.PC_FP64_PLAIN})
@@ -365,7 +416,9 @@ def main():
                     help="skip the extra step from host-memory catalogues (upload included)")
     ap.add_argument("--no-prune-compare", action="store_true",
                     help="skip the extra step that visits every pair")
-    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-oracle-seconds", type=float, default=15.0,
+                    help="CPU oracle time spent checking served answers (smallest requests first); 0: none")
     ap.add_argument("--serve-config", default="",
                     help="JSON object of pc_server_create keys overriding the mixed server's (e.g. streams)")
     ap.add_argument("--serve-loads", default="0.7", metavar="F,F,...",
@@ -436,6 +489,7 @@ def main():
         kern.append(pc.pc_debug_last_launch()["kernel_ms"])
         log(f"step {k + 1}/{args.steps} done")
     prn = pc.pc_debug_last_pruning()
+    paths = pc.pc_debug_last_paths()
     rechecked = pc.pc_debug_last_rechecks()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -449,6 +503,12 @@ def main():
     achieved = prn["pairs_computed"] * W / kern_s / 1e12
     fp64_run = (mode & 0xFF) == pc.PC_FP64_PLAIN
     peak = PEAK_FP64_VECTOR_TFLOPS if fp64_run else PEAK_FP32_VECTOR_TFLOPS
+    # the same rate counting, per pair, only the comparisons its path needs
+    # (few-edge pairs compare with the m <= 2 edges left in their interval)
+    by = paths["by_edges"]
+    assert sum(by) == prn["pairs_computed"], (by, prn["pairs_computed"])
+    work_method = sum(by[m] * work_per_pair_method(n_bins, m) for m in range(4))
+    achieved_method = work_method / kern_s / 1e12
     out = {
         "metric": "Gpairs/s binned (DD+DR+RR) at N=1M; p50/p99 latency of served w(theta) jobs",
         "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -462,6 +522,12 @@ def main():
                      "frac": achieved / peak,
                      "traffic": recorded_traffic("k_count_mixed_1M_traffic.json", "pc_kernels.hip")
                      if args.workload == "1m" and args.mode == "mixed" else None,
+                     "frac_method": achieved_method / peak, "achieved_method": achieved_method,
+                     "work_per_pair_method": work_method / max(prn["pairs_computed"], 1),
+                     "pairs_by_path": {"cell_table": by[0], "one_edge": by[1], "two_edges": by[2],
+                                       "three_edges": by[3], "gram_form": paths["gram"],
+                                       "difference_form": prn["pairs_computed"] - paths["gram"] - paths["mfma"],
+                                       "matrix_cores": paths["mfma"]},
                      "kernel_ms": kern_s * 1e3, "work_per_pair": W, "grid": launch["grid"],
                      "lds_bytes": launch["lds_bytes"], "items": launch["items"],
                      "pairs_computed": prn["pairs_computed"], "survivor_items": prn["survivors"],
@@ -554,7 +620,8 @@ def main():
     if args.serve_requests > 0 and args.workload == "1m":
         loads = sorted({0.7, *(float(x) for x in args.serve_loads.split(",") if x.strip())})
         out["serve"] = serve_run(pc, args.serve_requests, loads=loads, fp64_compare=not args.no_serve_fp64_compare,
-                                 server_cfg=json.loads(args.serve_config) if args.serve_config else None)
+                                 server_cfg=json.loads(args.serve_config) if args.serve_config else None,
+                                 oracle_seconds=0.0 if args.no_cpu_baseline else args.serve_oracle_seconds)
         if args.serve_config:
             out["serve"]["server_config"] = json.loads(args.serve_config)
         if "fp64_one_request_per_launch" in out["serve"]:

@@ -146,7 +146,8 @@ int pc_count_batch(const pc_job *jobs, int32_t n_jobs, int32_t mode, void *strea
  *   w            host array of n_bins binary64, written:
  *                w[k] = ((dd - 2 dr) + rr) / rr with dd = DD[k]/(nD(nD-1)/2),
  *                dr = DR[k]/(nD nR), rr = RR[k]/(nR(nR-1)/2)  (binary64, this
- *                order, no fused multiply-add).  RR[k] = 0 gives NaN.
+ *                order, no fused multiply-add).  RR[k] = 0 gives the IEEE
+ *                quotient: an infinity, or NaN when DD[k] and DR[k] are 0 too.
  * Host computation; no device needed.
  */
 int pc_wtheta(const uint64_t *DD, const uint64_t *DR, const uint64_t *RR, int32_t n_bins,
@@ -176,16 +177,20 @@ int pc_estimator(int32_t kind, const uint64_t *DD, const uint64_t *DR, const uin
 
 /*
  * pc_autotune -- time the batch (as pc_count_batch would run it in `mode`)
- * under each candidate launch configuration -- histogram lane columns
- * {8, 16, 32}, work items taken from the queue at a time {2, 4, 8}, matrix
- * cores off/on (on only in PC_MIXED) -- check that every candidate gives the
+ * under candidate launch configurations, check that every candidate gives the
  * same counts, and remember the fastest for batches of this shape (device,
  * ceil(log2(max n_edges)), floor(log2(pairs))); later calls with PC_TUNED use
- * it.  Each job's counts are written as pc_count_batch writes them.
+ * it.  First the tile size -- the size of the submatrices the pair matrix is
+ * cut into (Sec. 2.1): 128 or 256 points -- on the whole launch's time; then,
+ * at that size, histogram lane columns {8, 16, 32}, work items taken from the
+ * queue at a time {2, 4, 8} and matrix cores off/on (PC_MIXED with 256-point
+ * tiles only) on the counting kernel's time.  Each job's counts are written
+ * as pc_count_batch writes them.
  *   cache_path   NULL, or a file of tuned entries (one JSON object per line)
  *                that the result is added to (created if missing).
  *   result       NULL, or a host buffer of result_len bytes receiving a JSON
- *                object {"cols", "chunk", "matrix_cores", "kernel_ms",
+ *                object {"device", "edges_class", "pairs_class", "tile",
+ *                "cols", "chunk", "matrix_cores", "kernel_ms", "launch_ms",
  *                "candidates"}.
  * Returns PC_ERR_DEVICE if two candidates disagree (a library fault).
  */

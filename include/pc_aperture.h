@@ -101,6 +101,17 @@ int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid, double th
  */
 int pc_debug_last_aperture(double *kernel_ms, uint64_t *pairs_tested, uint64_t *pairs_in, double *cell_side);
 
+/*
+ * pc_debug_ap_filter -- the filter Q(x) of Eq. 4 as the map kernel evaluates
+ * it, on the host: x = theta / theta_max in [0, 1] (host array of n doubles),
+ * looked up in the kernel's table (1024 cells over [0, 1], a cubic in the
+ * position inside each cell, fitted in binary64 at the cell's Chebyshev
+ * points) with the kernel's binary32 steps; q (n doubles) written.  For
+ * checking the table against the binary64 definition.  PC_ERR_INVALID for
+ * NULL arrays with n > 0 or n < 0.
+ */
+int pc_debug_ap_filter(const double *x, int64_t n, double *q);
+
 #ifdef __cplusplus
 }
 #endif

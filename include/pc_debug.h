@@ -48,6 +48,36 @@ int pc_debug_guard_band_gram(const double *theta_edges_deg, int32_t n_edges, flo
 int pc_debug_set_timing(int32_t on);
 
 /*
+ * pc_debug_set_flush_every -- items > 0: the calling thread's later counting
+ * launches flush each wave's 32-bit LDS histogram into the 64-bit global
+ * counts at least every `items` work items (normally only when a word could
+ * otherwise wrap, about 10^6 items, at a change of job or edge set, and at the
+ * end), so that tests reach the wrap-guard flush; 0 restores the default.
+ * Counts are unchanged (Sec. 2.1: per-block histograms summed into global
+ * memory).
+ */
+int pc_debug_set_flush_every(uint64_t items);
+
+/*
+ * pc_debug_set_tile -- tile = 128 or 256: the calling thread's later counting
+ * launches (except pc_autotune's own candidates) cut the pair matrix into
+ * tiles of that many points whatever the tuner chose; 0 restores the default
+ * (256, or the tuned size with PC_TUNED).  Counts do not depend on it.
+ * PC_ERR_INVALID for other values.
+ */
+int pc_debug_set_tile(int32_t tile);
+
+/*
+ * pc_debug_fail_allocations -- the calling thread's next n device
+ * allocations made by the library (workspaces, edge-set tables, resident
+ * catalogues, aperture-map work space) fail as if the device were out of
+ * memory: the call reports PC_ERR_NOMEM, leaves its outputs untouched and
+ * keeps nothing it had allocated.  n = 0 turns it off.  PC_ERR_INVALID for
+ * n < 0.  For testing failure handling.
+ */
+int pc_debug_fail_allocations(int32_t n);
+
+/*
  * pc_debug_last_launch -- facts about the calling thread's last counting
  * launch: kernel time in ms from the HIP events (-1 if timing was off),
  * number of tile-pair work items, grid size (single-wave workgroups) and LDS
@@ -72,6 +102,22 @@ int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_
                           uint64_t *split_items);
 
 /*
+ * pc_debug_last_paths -- the calling thread's last counting launch: how the
+ * pairs visited one by one were binned, as the prune pass assigned them.
+ *   pairs_by_edges  host uint64[4] or NULL, written: [m] for m = 1..3 the pairs
+ *                   binned by comparing with the m edges inside their tile
+ *                   pair's (or sub-block's) chord interval; [0] the pairs
+ *                   binned through the cell table (every computed pair of the
+ *                   binary64 kernel and of launches with PC_NO_PRUNE).
+ *   gram_pairs      of the few-edge pairs, those whose chords the vector path
+ *                   forms in tile-centred Gram form (NULL allowed).
+ *   mfma_pairs      pairs whose chords came from the matrix cores (NULL allowed).
+ * Sec. 2.1 (binning) is the operation; these figures let a reader count the
+ * comparisons a pair needs on its path.
+ */
+int pc_debug_last_paths(uint64_t *pairs_by_edges, uint64_t *gram_pairs, uint64_t *mfma_pairs);
+
+/*
  * pc_debug_last_rechecks -- the calling thread's last counting launch: how many
  * pairs had a binary32 squared chord inside the guard band of an edge and were
  * recomputed in binary64 (Appendix A separation; the mixed kernel only: the
@@ -79,6 +125,33 @@ int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_computed, uint64_
  * device in a histogram row of its own.  PC_ERR_INVALID for NULL.
  */
 int pc_debug_last_rechecks(uint64_t *pairs_rechecked);
+
+/*
+ * pc_debug_request_parts -- how the w(theta) server would run one request,
+ * host only: the request (n_points data points, a patch of n_random randoms,
+ * n_edges log-spaced edges, RR counted by it when count_rr != 0) is cut into
+ * parts of about slice_pairs pairs (the "slice_pairs" key; 0: one part), each
+ * a launch over data rows [a, b) (DD and DR) and random rows [c, d) (RR);
+ * counts over disjoint row ranges add up exactly (Sec. 2.1 submatrices).
+ *   rows        host int64[4 * max_parts], written: {a, b, c, d} per part.
+ *   need_bytes  host uint64[max_parts], written: device bytes each part's
+ *               launch needs, as the server's admission reserves them (planned
+ *               by the batch runner without a device).
+ *   n_parts     written: the number of parts (may exceed max_parts; only the
+ *               first max_parts are described).
+ */
+int pc_debug_request_parts(int64_t n_points, int64_t n_random, int32_t n_edges, int32_t count_rr,
+                           double slice_pairs, int32_t max_parts, int64_t *rows, uint64_t *need_bytes,
+                           int32_t *n_parts);
+
+/*
+ * pc_debug_server_hold -- hold != 0: the server's workers keep each batch they
+ * admit (its requests hold their device slots and bytes) from launching until
+ * the hold is released (hold = 0); other requests keep waiting or expire as
+ * usual.  Makes queueing tests independent of kernel durations.
+ * PC_ERR_INVALID for a NULL server.
+ */
+int pc_debug_server_hold(void *server, int32_t hold);
 
 /*
  * pc_debug_admission_plan -- the w(theta) server's admission policy applied to

@@ -61,11 +61,13 @@ _SIGNATURES = {
     "pc_aperture_mass": ([ctypes.POINTER(pc_shear_catalog), ctypes.POINTER(pc_grid), ctypes.c_double, ctypes.c_double,
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p],
                          ctypes.c_int),
+    "pc_debug_ap_filter": ([_vp, _i64, _vp], ctypes.c_int),
     "pc_debug_last_aperture": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "pc_debug_admission_plan": ([_vp, _vp, _vp, _i32, _u64, _u64, _u64, _i32, ctypes.c_char_p, _vp],
                                 ctypes.c_int),
     "pc_debug_last_rechecks": ([ctypes.POINTER(_u64)], ctypes.c_int),
+    "pc_debug_last_paths": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)], ctypes.c_int),
     "pc_count": ([_PCAT, _PCAT, _vp, _i32, _i32, _vp, _vp], ctypes.c_int),
     "pc_count_ex": ([_PCAT, _PCAT, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp], ctypes.c_int),
     "pc_count_batch": ([ctypes.POINTER(pc_job), _i32, _i32, _vp], ctypes.c_int),
@@ -83,6 +85,12 @@ _SIGNATURES = {
     "pc_autotune_load": ([ctypes.c_char_p], ctypes.c_int),
     "pc_debug_lut32": ([_vp, _i32, _vp, _vp, _i64], ctypes.c_int),
     "pc_debug_set_timing": ([_i32], ctypes.c_int),
+    "pc_debug_set_flush_every": ([_u64], ctypes.c_int),
+    "pc_debug_fail_allocations": ([_i32], ctypes.c_int),
+    "pc_debug_set_tile": ([_i32], ctypes.c_int),
+    "pc_debug_server_hold": ([_vp, _i32], ctypes.c_int),
+    "pc_debug_request_parts": ([_i64, _i64, _i32, _i32, ctypes.c_double, _i32, _vp, _vp, ctypes.POINTER(_i32)],
+                               ctypes.c_int),
     "pc_debug_last_launch": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "pc_debug_last_pruning": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "pc_debug_guard_band_gram": ([_vp, _i32, _vp, _vp], ctypes.c_int),
@@ -377,6 +385,24 @@ def pc_debug_set_timing(on: bool):
     _check(lib().pc_debug_set_timing(1 if on else 0))
 
 
+def pc_debug_set_flush_every(items: int):
+    """items > 0: flush the counting kernel's LDS histograms at least every
+    `items` work items on this thread (testing); 0: default."""
+    _check(lib().pc_debug_set_flush_every(int(items)))
+
+
+def pc_debug_set_tile(tile: int):
+    """Tile size (128 or 256 points) of this thread's later counting launches
+    that have no explicit launch parameters; 0 restores the default."""
+    _check(lib().pc_debug_set_tile(int(tile)))
+
+
+def pc_debug_fail_allocations(n: int):
+    """The calling thread's next n device allocations in the library fail as
+    out of memory (testing); 0 turns it off."""
+    _check(lib().pc_debug_fail_allocations(int(n)))
+
+
 def pc_debug_last_launch() -> dict:
     ms = ctypes.c_double(0)
     items = _u64(0)
@@ -391,6 +417,16 @@ def pc_debug_last_pruning() -> dict:
     _check(lib().pc_debug_last_pruning(*(ctypes.byref(v) for v in vals)))
     keys = ("survivors", "pairs_computed", "pairs_total", "mfma_items", "few_items", "gram_items", "split_items")
     return {k: int(v.value) for k, v in zip(keys, vals)}
+
+
+def pc_debug_last_paths() -> dict:
+    """Pairs of the calling thread's last counting launch by the path that
+    binned them: by_edges[m] (m = 1..3 edges compared one by one, 0 = cell
+    table), gram (Gram-form chords), mfma (matrix-core chords)."""
+    by = np.zeros(4, dtype=np.uint64)
+    g, m = _u64(0), _u64(0)
+    _check(lib().pc_debug_last_paths(by.ctypes.data, ctypes.byref(g), ctypes.byref(m)))
+    return {"by_edges": [int(x) for x in by], "gram": int(g.value), "mfma": int(m.value)}
 
 
 def pc_debug_last_rechecks() -> int:
@@ -447,6 +483,15 @@ def pc_aperture_mass(cat, grid, theta_max: float, n_gal: float, out=None, stream
     return out
 
 
+def pc_debug_ap_filter(x) -> np.ndarray:
+    """Eq. 4's Q(x) as the map kernel evaluates it (its table and binary32
+    steps), computed on the host."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    q = np.empty(x.size, dtype=np.float64)
+    _check(lib().pc_debug_ap_filter(x.ctypes.data, x.size, q.ctypes.data))
+    return q
+
+
 def pc_debug_last_aperture() -> dict:
     ms = ctypes.c_double(0)
     tested = ctypes.c_uint64(0)
@@ -456,6 +501,22 @@ def pc_debug_last_aperture() -> dict:
                                         ctypes.byref(cell)))
     return {"kernel_ms": ms.value, "pairs_tested": int(tested.value), "pairs_in": int(inside.value),
             "cell_side": cell.value}
+
+
+def pc_debug_request_parts(n_points: int, n_random: int, n_edges: int, count_rr: bool = True,
+                           slice_pairs: float = 5e11):
+    """The server's plan for one request (host only): a list of parts
+    {"rows": (a, b), "rr_rows": (c, d), "need_bytes": B}."""
+    n = _i32(0)
+    _check(lib().pc_debug_request_parts(int(n_points), int(n_random), int(n_edges), 1 if count_rr else 0,
+                                        float(slice_pairs), 0, None, None, ctypes.byref(n)))
+    rows = np.zeros((max(n.value, 1), 4), dtype=np.int64)
+    need = np.zeros(max(n.value, 1), dtype=np.uint64)
+    _check(lib().pc_debug_request_parts(int(n_points), int(n_random), int(n_edges), 1 if count_rr else 0,
+                                        float(slice_pairs), n.value, rows.ctypes.data, need.ctypes.data,
+                                        ctypes.byref(n)))
+    return [{"rows": (int(r[0]), int(r[1])), "rr_rows": (int(r[2]), int(r[3])), "need_bytes": int(b)}
+            for r, b in zip(rows[: n.value], need[: n.value])]
 
 
 ADMIT, NEVER_FITS, EXPIRED, WAIT = range(4)
@@ -527,6 +588,11 @@ class Server:
 
     def drain(self):
         _check(lib().pc_server_drain(self._h))
+
+    def hold(self, on: bool):
+        """Debug gate (pc_debug_server_hold): while on, admitted batches wait
+        before their launch."""
+        _check(lib().pc_debug_server_hold(self._h, 1 if on else 0))
 
     def stats(self) -> dict:
         return json.loads(lib().pc_server_stats(self._h).decode())

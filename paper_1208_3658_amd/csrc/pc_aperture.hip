@@ -13,9 +13,12 @@
 //   - the aperture cut in binary64, exactly as the definition states it
 //     (dx, dy, |d|^2 = dx*dx + dy*dy, 0 < |d|^2 < theta_max^2, no fused
 //     multiply-add), so the set of galaxies in each aperture is exact;
-//   - for galaxies inside, the filter Q (Eq. 4) and the tangential
-//     ellipticity in binary32 from dx, dy rounded to binary32: one
-//     reciprocal square root, three base-2 exponentials and one reciprocal;
+//   - for galaxies inside, x = |d| / theta_max from one reciprocal square
+//     root in binary32, and the filter Q(x) (Eq. 4), a function of x alone,
+//     from a table in LDS: 1024 cells over [0, 1], each a cubic in the
+//     position inside the cell fitted on the host in binary64 (no
+//     exponential, reciprocal or series per pair);
+//   - the tangential ellipticity in binary32 from dx, dy rounded to binary32;
 //   - the products Q eps_t and Q^2 |eps|^2 summed in binary32 over at most 64
 //     galaxies and then in binary64.
 #include <float.h>
@@ -24,6 +27,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -39,6 +45,9 @@ size_t scan_sums_words(int64_t m);
 namespace {
 
 constexpr int kApSide = 8;             // grid points per wave along each axis
+constexpr int kApWaves = 4;            // waves per workgroup: 2 x 2 blocks sharing one filter table
+constexpr int kApGroupSide = 2 * kApSide;
+constexpr int kQCells = 1024;          // filter table cells over x in [0, 1]
 constexpr int kApFlush = 64;           // galaxies summed in binary32 before the binary64 add
 constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 constexpr int64_t kMaxCells = int64_t(1) << 22;
@@ -62,16 +71,15 @@ struct Lattice {
 struct ApParams {
     const ApGal *gal;
     const uint32_t *start;  // ncx * ncy + 1 cell starts
+    const float4 *qtab;     // kQCells cubics (c0, c1, c2, c3): Q = c0 + t (c1 + t (c2 + t c3))
     Lattice lat;
     double x0, y0, gdx, gdy;
-    int32_t nx, ny, tiles_x, n_tiles, per_xcd;
+    int32_t nx, ny, tiles_x, n_tiles, per_xcd;  // tiles: groups of 2 x 2 blocks
     double theta;     // filter radius
     double r2;        // theta^2 (binary64), the cut
     double reach;     // theta with a relative margin for the cell search
-    float k_a, c_a;   // exp(6 - 150 x)  = 2^(k_a r + c_a), x = r / theta
-    float k_b, c_b;   // exp(-47 + 50 x) = 2^(k_b r + c_b)
-    float k_e;        // exp(2u) = 2^(k_e r), u = x / 0.15
-    float k_u;        // u = k_u r
+    float k_s;        // table position s = r k_s = kQCells x, x = r / theta
+    float s_max;      // largest binary32 below kQCells (r rounded up to theta)
     double n_gal;
     double *map;
     double *snr;
@@ -157,11 +165,23 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 
 // Filter constants held in VGPRs (an instruction reads at most one SGPR).
 struct ApConsts {
-    float k_a, c_a, k_b, c_b, k_e, k_u;
+    float k_s, s_max;
+    uint32_t tab;  // LDS byte address of the filter table
 };
 
-// One (grid point, galaxy) pair: the exact cut, then Eq. 4 and the
-// tangential ellipticity, accumulated into the binary32 partial sums.
+// The filter Q(x) of Eq. 4 at table position s = kQCells x (s <= s_max):
+// cell i = floor(s), t = s - i, Q = c0 + t (c1 + t (c2 + t c3)).
+__device__ __forceinline__ float q_table(float s, uint32_t tab) {
+    const uint32_t i = static_cast<uint32_t>(s);
+    const float t = __builtin_amdgcn_fractf(s);
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    using lds_f4 = __attribute__((address_space(3))) const f32x4;
+    const f32x4 c = *(lds_f4 *)(uintptr_t)(tab + (i << 4));
+    return fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
+}
+
+// One (grid point, galaxy) pair: the exact cut, then Eq. 4 from the table and
+// the tangential ellipticity, accumulated into the binary32 partial sums.
 __device__ __forceinline__ void ap_pair(const ApGal &G, double xg, double yg, double r2, const ApConsts &K,
                                         uint32_t &cnt, float &a1, float &a2) {
     const double ddx = G.x - xg;
@@ -170,36 +190,13 @@ __device__ __forceinline__ void ap_pair(const ApGal &G, double xg, double yg, do
     if (d2 < r2 && d2 > 0.0) {
         cnt += 1u;
         const float fx = static_cast<float>(ddx), fy = static_cast<float>(ddy);
-        const float f2 = static_cast<float>(d2);  // 0 only if |d| < ~1e-19 (then r is NaN below)
-        float rinv = __builtin_amdgcn_rsqf(f2);
-        float r = f2 * rinv;
-        const float e2u = __builtin_amdgcn_exp2f(r * K.k_e);
-        float u = r * K.k_u;
-        float ea = __builtin_amdgcn_exp2f(fmaf(r, K.k_a, K.c_a));
-        float eb = __builtin_amdgcn_exp2f(fmaf(r, K.k_b, K.c_b));
-        float D = (1.0f + ea) + eb;
-        // tanh(u)/u = (e^2u - 1) / ((e^2u + 1) u); near u = 0 its series
-        // 1 - u^2/3 + 2u^4/15 (next term below 4e-9 there).  The series is
-        // needed only within 0.0094 theta_max of the point, so it is a branch
-        // that is almost never taken rather than selects every pair pays for.
-        // The same branch catches a squared distance that rounded to zero in
-        // binary32 (u is NaN then): it redoes the filter from |d|^2 raised to
-        // the smallest normal binary32 value.
-        float num = e2u - 1.0f;
-        float den = ((e2u + 1.0f) * u) * D;
-        if (__builtin_expect(!(u >= 0.0625f), 0)) {
-            const float f2c = fmaxf(f2, FLT_MIN);
-            rinv = __builtin_amdgcn_rsqf(f2c);
-            r = f2c * rinv;
-            u = r * K.k_u;
-            ea = __builtin_amdgcn_exp2f(fmaf(r, K.k_a, K.c_a));
-            eb = __builtin_amdgcn_exp2f(fmaf(r, K.k_b, K.c_b));
-            D = (1.0f + ea) + eb;
-            const float u2 = u * u;
-            num = fmaf(u2, fmaf(u2, 0.133333333f, -0.333333333f), 1.0f);
-            den = D;
-        }
-        const float q = num * __builtin_amdgcn_rcpf(den);
+        // |d|^2 > 0 can still round below the smallest normal binary32 value;
+        // raised to it, r stays finite (the direction of such a pair, within
+        // 1e-19 of the point, is then not resolved in binary32)
+        const float f2 = fmaxf(static_cast<float>(d2), FLT_MIN);
+        const float rinv = __builtin_amdgcn_rsqf(f2);
+        const float r = f2 * rinv;
+        const float q = q_table(fminf(r * K.k_s, K.s_max), K.tab);
         // cos 2phi and sin 2phi from the unit direction
         const float ux = fx * rinv, uy = fy * rinv;
         const float c2 = fmaf(-uy, uy, ux * ux);
@@ -210,16 +207,23 @@ __device__ __forceinline__ void ap_pair(const ApGal &G, double xg, double yg, do
     }
 }
 
-// One wave per 8 x 8 block of grid points.  Blocks are dealt to the eight
+// One wave per 8 x 8 block of grid points, four waves (2 x 2 blocks) per
+// workgroup sharing the filter table in LDS.  Groups are dealt to the eight
 // XCDs in contiguous strips (the hardware assigns workgroup b to XCD b mod 8),
 // so neighbouring blocks, which read mostly the same galaxies, share an L2.
-__global__ void __launch_bounds__(64) k_ap_map(const ApParams p) {
-    const int lane = static_cast<int>(threadIdx.x);
+__global__ void __launch_bounds__(64 * kApWaves) k_ap_map(const ApParams p) {
+    __shared__ float4 qtab[kQCells];
+    const int lane = static_cast<int>(threadIdx.x) & 63;
+    const int wave = static_cast<int>(threadIdx.x) >> 6;
     const int b = static_cast<int>(blockIdx.x);
     const int tile = (b & 7) * p.per_xcd + (b >> 3);
-    if (tile >= p.n_tiles) return;
+    if (tile >= p.n_tiles) return;  // the whole workgroup: before any barrier
+    for (int k = static_cast<int>(threadIdx.x); k < kQCells; k += 64 * kApWaves) qtab[k] = p.qtab[k];
+    __syncthreads();
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-    const int ix0 = tx * kApSide, iy0 = ty * kApSide;
+    const int ix0 = tx * kApGroupSide + (wave & 1) * kApSide, iy0 = ty * kApGroupSide + (wave >> 1) * kApSide;
+    // a block of the group past the grid's edge has no points
+    if (ix0 >= p.nx || iy0 >= p.ny) return;
     const int ix1 = min(ix0 + kApSide - 1, p.nx - 1), iy1 = min(iy0 + kApSide - 1, p.ny - 1);
     const int ixl = ix0 + (lane & (kApSide - 1)), iyl = iy0 + lane / kApSide;
     const bool valid = ixl <= ix1 && iyl <= iy1;
@@ -229,8 +233,10 @@ __global__ void __launch_bounds__(64) k_ap_map(const ApParams p) {
     const double gxl = p.x0 + static_cast<double>(ix0) * p.gdx, gxh = p.x0 + static_cast<double>(ix1) * p.gdx;
     const double gyl = p.y0 + static_cast<double>(iy0) * p.gdy, gyh = p.y0 + static_cast<double>(iy1) * p.gdy;
     const Lattice L = p.lat;
-    ApConsts K{p.k_a, p.c_a, p.k_b, p.c_b, p.k_e, p.k_u};
-    asm("" : "+v"(K.k_a), "+v"(K.c_a), "+v"(K.k_b), "+v"(K.c_b), "+v"(K.k_e), "+v"(K.k_u));
+    ApConsts K{p.k_s, p.s_max,
+               static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
+                   (__attribute__((address_space(3))) const float4 *)(qtab)))};
+    asm("" : "+v"(K.k_s), "+v"(K.s_max), "+v"(K.tab));
     const double slack = L.s * 1e-9;  // covers rounding of the cell coordinates
 
     double S1 = 0.0, S2 = 0.0;
@@ -316,6 +322,49 @@ size_t take(size_t *size, size_t bytes) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Eq. 4 in binary64: Q(x) = 1 / (1 + e^(6 - 150 x) + e^(-47 + 50 x)) *
+// tanh(x / 0.15) / (x / 0.15), with tanh(u)/u = 1 at u = 0.
+double q_filter(double x) {
+    const double u = x / 0.15;
+    const double th = u == 0.0 ? 1.0 : std::tanh(u) / u;
+    return th / (1.0 + std::exp(6.0 - 150.0 * x) + std::exp(-47.0 + 50.0 * x));
+}
+
+// The filter table: cell k covers x in [k, k+1] / kQCells; its cubic in
+// t = kQCells x - k interpolates Q at the four Chebyshev points of [0, 1]
+// (solved in binary64, coefficients rounded to binary32 once).  Built once.
+const float4 *filter_table() {
+    static float4 tab[kQCells];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const double kPi = 3.14159265358979323846;
+        for (int k = 0; k < kQCells; ++k) {
+            double A[4][5];
+            for (int j = 0; j < 4; ++j) {
+                const double t = 0.5 - 0.5 * std::cos((2 * j + 1) * kPi / 8.0);
+                double tp = 1.0;
+                for (int m = 0; m < 4; ++m, tp *= t) A[j][m] = tp;
+                A[j][4] = q_filter((k + t) / kQCells);
+            }
+            // Gaussian elimination with partial pivoting on the 4 x 4 system
+            for (int c = 0; c < 4; ++c) {
+                int piv = c;
+                for (int r = c + 1; r < 4; ++r)
+                    if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+                for (int m = 0; m < 5; ++m) std::swap(A[c][m], A[piv][m]);
+                for (int r = 0; r < 4; ++r) {
+                    if (r == c) continue;
+                    const double f = A[r][c] / A[c][c];
+                    for (int m = c; m < 5; ++m) A[r][m] -= f * A[c][m];
+                }
+            }
+            tab[k] = make_float4(static_cast<float>(A[0][4] / A[0][0]), static_cast<float>(A[1][4] / A[1][1]),
+                                 static_cast<float>(A[2][4] / A[2][2]), static_cast<float>(A[3][4] / A[3][3]));
+        }
+    });
+    return tab;
+}
+
 int check_args(const pc_shear_catalog *cat, const pc_grid *grid, double theta_max, double n_gal, const double *map) {
     if (!cat || !grid || !map) return fail(PC_ERR_INVALID, "NULL catalogue, grid or map");
     if (cat->n < 0 || cat->n >= (int64_t(1) << 31)) return fail(PC_ERR_INVALID, "catalogue n outside [0, 2^31)");
@@ -399,10 +448,12 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     const size_t o_sums = take(&size, sizeof(uint32_t) * scan_sums_words(n_cells + 1));
     const size_t o_flag = take(&size, 4 * sizeof(uint32_t));
     const size_t o_stats = take(&size, 2 * sizeof(unsigned long long));
+    const size_t o_qtab = take(&size, sizeof(float4) * kQCells);
     const size_t o_out = host_out ? take(&size, (2 * sizeof(double) + sizeof(uint32_t)) * static_cast<size_t>(m)) : 0;
     DevMem ws;
     ws.st = st;
-    AP_HIP(hipMallocAsync(&ws.mem, size, st), "hipMallocAsync(aperture work space)");
+    AP_HIP(injected_alloc_failure() ? hipErrorOutOfMemory : hipMallocAsync(&ws.mem, size, st),
+           "hipMallocAsync(aperture work space)");
     char *base = static_cast<char *>(ws.mem);
 
     const double *X = cat->x, *Y = cat->y, *E1 = cat->e1, *E2 = cat->e2;
@@ -426,6 +477,9 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     uint32_t *sums = reinterpret_cast<uint32_t *>(base + o_sums);
     uint32_t *flag = reinterpret_cast<uint32_t *>(base + o_flag);
     unsigned long long *stats = reinterpret_cast<unsigned long long *>(base + o_stats);
+    float4 *qtab = reinterpret_cast<float4 *>(base + o_qtab);
+    AP_HIP(hipMemcpyAsync(qtab, filter_table(), sizeof(float4) * kQCells, hipMemcpyHostToDevice, st),
+           "H2D filter table");
 
     // order the galaxies by cell
     AP_HIP(launch_zero_u32(start, n_cells + 1, st), "zero cell counts");
@@ -466,20 +520,16 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     p.gdy = grid->dy;
     p.nx = grid->nx;
     p.ny = grid->ny;
-    p.tiles_x = (grid->nx + kApSide - 1) / kApSide;
-    const int tiles_y = (grid->ny + kApSide - 1) / kApSide;
+    p.tiles_x = (grid->nx + kApGroupSide - 1) / kApGroupSide;
+    const int tiles_y = (grid->ny + kApGroupSide - 1) / kApGroupSide;
     p.n_tiles = p.tiles_x * tiles_y;
     p.per_xcd = (p.n_tiles + 7) / 8;
     p.theta = theta_max;
     p.r2 = theta_max * theta_max;
     p.reach = theta_max * (1.0 + 1e-9);
-    const double log2e = 1.4426950408889634;
-    p.k_e = static_cast<float>(2.0 * log2e / (0.15 * theta_max));
-    p.k_u = static_cast<float>(1.0 / (0.15 * theta_max));
-    p.k_a = static_cast<float>(-150.0 * log2e / theta_max);
-    p.c_a = static_cast<float>(6.0 * log2e);
-    p.k_b = static_cast<float>(50.0 * log2e / theta_max);
-    p.c_b = static_cast<float>(-47.0 * log2e);
+    p.k_s = static_cast<float>(static_cast<double>(kQCells) / theta_max);
+    p.s_max = std::nextafter(static_cast<float>(kQCells), 0.0f);
+    p.qtab = qtab;
     p.n_gal = n_gal;
     p.map = d_map;
     p.snr = (snr || host_out) ? d_snr : nullptr;
@@ -493,7 +543,7 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
         AP_HIP(hipEventCreate(&ev.b), "hipEventCreate");
         AP_HIP(hipEventRecord(ev.a, st), "hipEventRecord");
     }
-    k_ap_map<<<dim3(static_cast<uint32_t>(8 * p.per_xcd)), dim3(64), 0, st>>>(p);
+    k_ap_map<<<dim3(static_cast<uint32_t>(8 * p.per_xcd)), dim3(64 * kApWaves), 0, st>>>(p);
     AP_HIP(hipGetLastError(), "k_ap_map");
     if (timing) AP_HIP(hipEventRecord(ev.b, st), "hipEventRecord");
 
@@ -531,5 +581,22 @@ extern "C" int pc_debug_last_aperture(double *kernel_ms, uint64_t *pairs_tested,
     if (pairs_tested) *pairs_tested = t_ap.tested;
     if (pairs_in) *pairs_in = t_ap.in;
     if (cell_side) *cell_side = t_ap.cell;
+    return PC_OK;
+}
+
+extern "C" int pc_debug_ap_filter(const double *x, int64_t n, double *q) {
+    clear_error();
+    if (n < 0 || (n > 0 && (!x || !q))) return fail(PC_ERR_INVALID, "NULL argument or n < 0");
+    const float4 *tab = filter_table();
+    const float s_max = std::nextafter(static_cast<float>(kQCells), 0.0f);
+    for (int64_t k = 0; k < n; ++k) {
+        // the kernel's steps in binary32: s = x kQCells clamped below kQCells,
+        // cell floor(s), t = s - floor(s), Horner with fused multiply-adds
+        const float sv = std::fmin(static_cast<float>(x[k]) * static_cast<float>(kQCells), s_max);
+        const uint32_t i = static_cast<uint32_t>(sv);
+        const float t = sv - std::floor(sv);
+        const float4 c = tab[i];
+        q[k] = std::fma(std::fma(std::fma(c.w, t, c.z), t, c.y), t, c.x);
+    }
     return PC_OK;
 }

@@ -24,19 +24,44 @@ namespace pc {
 hipError_t launch_convert(const double *ra, const double *dec, int64_t n, double4 *a64, float4 *a32,
                           int *err, hipStream_t st);
 hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st);
-hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
-                        const uint64_t *items, const unsigned long long *n_items, const uint64_t *sub,
-                        uint64_t total_items, uint32_t lut_lds_off, uint32_t stage_lds_off,
-                        unsigned long long *queue, unsigned long long *rechecked, int chunk, uint32_t lds_bytes,
-                        int grid, hipStream_t st);
 size_t sort_scratch_words(int64_t n);
-hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
-                       float4 *a32s, float4 *g32s, double4 *bounds, hipStream_t st);
-hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, int64_t total_rows,
-                        uint64_t *survivors, uint64_t *sub, unsigned long long *meta, int32_t mfma_ok,
-                        int32_t split_ok, hipStream_t st);
-hipError_t count_occupancy(bool fp64, bool mc, uint32_t lds_bytes, int *blocks_per_cu);
-hipError_t set_max_lds(uint32_t bytes);
+
+// the per-tile-size steps (pc_kernels.hip, pc_prep.hip; one instance per size)
+#define PC_TILE_STEPS                                                                                              \
+    hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,        \
+                            const uint64_t *items, const unsigned long long *n_items, const uint64_t *sub,         \
+                            uint64_t total_items, uint32_t lut_lds_off, uint32_t stage_lds_off,                    \
+                            unsigned long long *queue, unsigned long long *rechecked, int chunk,                   \
+                            uint32_t lds_bytes, int grid, uint64_t flush_cap, hipStream_t st);                     \
+    hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,          \
+                           float4 *a32s, float4 *g32s, double4 *bounds, hipStream_t st);                           \
+    hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, int64_t total_rows,        \
+                            uint64_t *survivors, uint64_t *sub, unsigned long long *meta, int32_t mfma_ok,         \
+                            int32_t split_ok, hipStream_t st);                                                     \
+    hipError_t count_occupancy(bool fp64, bool mc, uint32_t lds_bytes, int *blocks_per_cu);                        \
+    hipError_t set_max_lds(uint32_t bytes);
+namespace t256 { PC_TILE_STEPS }
+namespace t128 { PC_TILE_STEPS }
+#undef PC_TILE_STEPS
+
+// One tile size's steps.  tile = points per tile (both axes); 64-point
+// sub-blocks, tile / 64 of them per tile; the matrix-core path needs 256.
+struct TileOps {
+    int tile;
+    int subs;
+    bool matrix_cores;
+    decltype(&t256::launch_count) launch_count;
+    decltype(&t256::launch_sort) launch_sort;
+    decltype(&t256::launch_prune) launch_prune;
+    decltype(&t256::count_occupancy) count_occupancy;
+    decltype(&t256::set_max_lds) set_max_lds;
+};
+static const TileOps kTile256 = {256, 4, true, t256::launch_count, t256::launch_sort, t256::launch_prune,
+                                 t256::count_occupancy, t256::set_max_lds};
+static const TileOps kTile128 = {128, 2, false, t128::launch_count, t128::launch_sort, t128::launch_prune,
+                                 t128::count_occupancy, t128::set_max_lds};
+// the tile size resident catalogues are ordered and bounded for
+static const TileOps &kResidentTile = kTile256;
 
 #ifndef PC_SPLIT
 #define PC_SPLIT 1  // split surviving tile pairs into j sub-blocks in the prune pass
@@ -65,6 +90,15 @@ int hip_fail(hipError_t e, const char *what) {
 
 void clear_error() { t_err.clear(); }
 
+// per-thread count of device allocations still to fail (testing)
+static thread_local int32_t t_fail_allocs = 0;
+
+bool injected_alloc_failure() {
+    if (t_fail_allocs <= 0) return false;
+    --t_fail_allocs;
+    return true;
+}
+
 // ------------------------------------------------------------------ device
 
 static std::mutex g_dev_mu;
@@ -89,7 +123,8 @@ int device_info(DeviceInfo **out) {
         d.ok = d.arch.rfind("gfx950", 0) == 0;
         if (d.ok) {
             const uint32_t want = std::max<uint32_t>(d.lds_per_block, 64u * 1024u);
-            if (set_max_lds(want) == hipSuccess) d.lds_per_block = want;
+            if (kTile256.set_max_lds(want) == hipSuccess && kTile128.set_max_lds(want) == hipSuccess)
+                d.lds_per_block = want;
         }
         it = g_dev.emplace(dev, d).first;
     }
@@ -130,6 +165,36 @@ DevTable::~DevTable() {
     if (d_mem) (void)hipFree(d_mem);
 }
 
+void table_blob(const HostTable &h, TableBlob *out) {
+    // one device block: e64 | band | band_g | lut32 | lut64
+    const size_t b_e = sizeof(double) * h.e64.size();
+    const size_t b_b = 2 * sizeof(float) * h.e64.size();
+    out->o_band = (b_e + 255) & ~size_t(255);
+    out->o_band_g = (out->o_band + b_b + 255) & ~size_t(255);
+    out->o_lut32 = (out->o_band_g + b_b + 255) & ~size_t(255);
+    const size_t b_l32 = sizeof(LutEntry32) * h.lut32.entries.size();
+    out->o_lut64 = (out->o_lut32 + b_l32 + 255) & ~size_t(255);
+    const size_t b_l64 = sizeof(LutEntry64) * h.lut64.size();
+    std::vector<unsigned char> &blob = out->bytes;
+    blob.assign(out->o_lut64 + b_l64 + 256, 0);
+    memcpy(blob.data(), h.e64.data(), b_e);
+    for (size_t k = 0; k < h.e64.size(); ++k) {
+        const float bb[4] = {h.lo[k], h.hi[k], h.lo_g[k], h.hi_g[k]};
+        memcpy(blob.data() + out->o_band + 8 * k, bb, 8);
+        memcpy(blob.data() + out->o_band_g + 8 * k, bb + 2, 8);
+    }
+    if (b_l32) memcpy(blob.data() + out->o_lut32, h.lut32.entries.data(), b_l32);
+    if (b_l64) memcpy(blob.data() + out->o_lut64, h.lut64.data(), b_l64);
+}
+
+void table_place(DevTable *t, const TableBlob &b, unsigned char *base) {
+    t->d_e64 = reinterpret_cast<const double *>(base);
+    t->d_band = reinterpret_cast<const float *>(base + b.o_band);
+    t->d_band_g = reinterpret_cast<const float *>(base + b.o_band_g);
+    t->d_lut32 = base + b.o_lut32;
+    t->d_lut64 = base + b.o_lut64;
+}
+
 int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *out, int cols) {
     if (!theta) return fail(PC_ERR_INVALID, "theta_edges_deg is NULL");
     if (n_edges < 2) return fail(PC_ERR_INVALID, "n_edges must be >= 2");
@@ -153,36 +218,13 @@ int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *o
     auto t = std::make_shared<DevTable>();
     std::string err;
     if (!build_table(theta, n_edges, t->host, err, cols)) return fail(PC_ERR_INVALID, err);
-    const HostTable &h = t->host;
-    // one device block: e64 | band | band_g | lut32 | lut64
-    const size_t b_e = sizeof(double) * h.e64.size();
-    const size_t b_b = 2 * sizeof(float) * h.e64.size();
-    const size_t o_b = (b_e + 255) & ~size_t(255);
-    const size_t o_bg = (o_b + b_b + 255) & ~size_t(255);
-    const size_t o_l32 = (o_bg + b_b + 255) & ~size_t(255);
-    const size_t b_l32 = sizeof(LutEntry32) * h.lut32.entries.size();
-    const size_t o_l64 = (o_l32 + b_l32 + 255) & ~size_t(255);
-    const size_t b_l64 = sizeof(LutEntry64) * h.lut64.size();
-    const size_t total = o_l64 + b_l64 + 256;
-    std::vector<unsigned char> blob(total, 0);
-    memcpy(blob.data(), h.e64.data(), b_e);
-    for (size_t k = 0; k < h.e64.size(); ++k) {
-        const float bb[4] = {h.lo[k], h.hi[k], h.lo_g[k], h.hi_g[k]};
-        memcpy(blob.data() + o_b + 8 * k, bb, 8);
-        memcpy(blob.data() + o_bg + 8 * k, bb + 2, 8);
-    }
-    if (b_l32) memcpy(blob.data() + o_l32, h.lut32.entries.data(), b_l32);
-    if (b_l64) memcpy(blob.data() + o_l64, h.lut64.data(), b_l64);
+    TableBlob blob;
+    table_blob(t->host, &blob);
     void *d = nullptr;
-    PC_HIP(hipMalloc(&d, total), "hipMalloc(tables)");
+    PC_HIP(injected_alloc_failure() ? hipErrorOutOfMemory : hipMalloc(&d, blob.bytes.size()), "hipMalloc(tables)");
     t->d_mem = d;
-    PC_HIP(hipMemcpy(d, blob.data(), total, hipMemcpyHostToDevice), "hipMemcpy(tables)");
-    unsigned char *base = static_cast<unsigned char *>(d);
-    t->d_e64 = reinterpret_cast<const double *>(base);
-    t->d_band = reinterpret_cast<const float *>(base + o_b);
-    t->d_band_g = reinterpret_cast<const float *>(base + o_bg);
-    t->d_lut32 = base + o_l32;
-    t->d_lut64 = base + o_l64;
+    PC_HIP(hipMemcpy(d, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice), "hipMemcpy(tables)");
+    table_place(t.get(), blob, static_cast<unsigned char *>(d));
     std::lock_guard<std::mutex> lk(g_tab_mu);
     auto it = g_tabs.find(key);
     if (it != g_tabs.end()) {
@@ -297,7 +339,7 @@ struct Arena {
     }
 };
 
-static int64_t n_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+static int64_t n_tiles(int64_t n, int tile) { return (n + tile - 1) / tile; }
 
 // ------------------------------------------------------------------- batch
 
@@ -307,10 +349,24 @@ static thread_local bool t_timing = false;
 bool thread_timing() { return t_timing; }
 void set_thread_timing(bool on) { t_timing = on; }
 static thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
+// per-thread cap on the counting kernel's histogram flush interval (testing)
+static thread_local uint64_t t_flush_cap = 0;
+// per-thread tile size for launches without explicit parameters (testing; 0: as chosen)
+static thread_local int t_force_tile = 0;
 static thread_local BatchStats t_last;
 
 int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st, BatchStats *stats,
               const LaunchTune *tune) {
+    BatchOpts o;
+    o.tune = tune;
+    return run_batch_opts(jobs, mode_flags, st, stats, o);
+}
+
+int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st, BatchStats *stats,
+                   const BatchOpts &opts) {
+    const LaunchTune *tune = opts.tune;
+    const bool plan_only = opts.plan_bytes != nullptr;
+    const bool ext = !plan_only && opts.ws != nullptr;  // caller's workspace: allocate nothing
     if (jobs.empty()) return fail(PC_ERR_INVALID, "no jobs");
     const int mode = mode_flags & ~(PC_NO_PRUNE | PC_MATRIX_CORES | PC_TUNED);
     const bool prune = (mode_flags & PC_NO_PRUNE) == 0;
@@ -327,19 +383,28 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     } else {
         lt.matrix_cores = (mode_flags & PC_MATRIX_CORES) != 0;
     }
+    if (!tune && t_force_tile) lt.tile = t_force_tile;
     if (lt.chunk < 1 || lt.chunk > 64) return fail(PC_ERR_INVALID, "work chunk must be in [1, 64]");
     // the matrix-core path needs the prune pass's marks; binary32 only
-    const bool mc = lt.matrix_cores && prune && !fp64;
+    if (lt.tile != 0 && lt.tile != 128 && lt.tile != 256) return fail(PC_ERR_INVALID, "tile must be 128 or 256 points");
+    const TileOps &T = lt.tile == 128 ? kTile128 : kTile256;
+    const int tile = T.tile;
+    const bool mc = lt.matrix_cores && prune && !fp64 && T.matrix_cores;
     // host-side validation first, so bad arguments are reported as such
     for (const BatchJob &j : jobs) {
         if (j.auto_flag != 0 && j.auto_flag != 1) return fail(PC_ERR_INVALID, "auto_flag must be 0 or 1");
         std::string err;
         if (!validate_edges(j.theta, j.n_edges, err)) return fail(PC_ERR_INVALID, err);
-        if (!j.counts) return fail(PC_ERR_INVALID, "counts is NULL");
-        int r = j.hA ? PC_OK : validate_catalog(j.A, "A");
-        if (r) return r;
-        if (!j.auto_flag) {
-            r = j.hB ? PC_OK : validate_catalog(j.B, "B");
+        if (!j.counts && !plan_only) return fail(PC_ERR_INVALID, "counts is NULL");
+        // inputs the caller already checked point by point (the server's
+        // copies) skip the per-point scan here
+        const pc_catalog *A = j.hA ? nullptr : j.A, *B = (j.auto_flag || j.hB) ? nullptr : j.B;
+        if (opts.trusted_inputs) {
+            if ((!j.hA && !A) || (!j.auto_flag && !j.hB && !B)) return fail(PC_ERR_INVALID, "catalogue is NULL");
+        } else {
+            int r = A ? validate_catalog(A, "A") : PC_OK;
+            if (r) return r;
+            r = B ? validate_catalog(B, "B") : PC_OK;
             if (r) return r;
         }
         if (!j.hA) {
@@ -351,8 +416,11 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         }
     }
     DeviceInfo *di = nullptr;
-    int rc = device_info(&di);
-    if (rc) return rc;
+    int rc = PC_OK;
+    if (!plan_only) {
+        rc = device_info(&di);
+        if (rc) return rc;
+    }
 
     Arena ar;
     // ---- sources: catalogues as binary64 unit vectors in the caller's order
@@ -370,8 +438,15 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             auto it = src_of_handle.find(h);
             if (it != src_of_handle.end()) { *out = it->second; return PC_OK; }
             Source sc;
-            int r = get_resident(h, &sc.res);
-            if (r) return r;
+            auto v = plan_only && opts.plan_sizes ? opts.plan_sizes->find(h) : std::map<uint64_t, int64_t>::const_iterator();
+            if (plan_only && opts.plan_sizes && v != opts.plan_sizes->end()) {
+                // planning against a catalogue described only by its size
+                sc.res = std::make_shared<Resident>();
+                sc.res->n = v->second;
+            } else {
+                int r = get_resident(h, &sc.res);
+                if (r) return r;
+            }
             sc.n = sc.res->n;
             *out = static_cast<int>(srcs.size());
             src_of_handle.emplace(h, *out);
@@ -414,14 +489,16 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         v.b = b;
         v.e = e;
         const int64_t n = e - b;
-        if (srcs[src].res && b == 0 && e == srcs[src].n) {
+        // a resident catalogue's own ordered copy and bounds serve a view of
+        // all of it when the launch uses the tile size they were built for
+        if (srcs[src].res && b == 0 && e == srcs[src].n && &T == &kResidentTile) {
             v.resident_full = true;
         } else if (n > 0) {
             v.o_a64s = ar.take(sizeof(double4) * static_cast<size_t>(n));
             // binary32 copies padded: the kernel reads a step of j-points ahead
             v.o_a32s = ar.take(sizeof(float4) * static_cast<size_t>(n + kJPad));
             v.o_g32s = ar.take(sizeof(float4) * static_cast<size_t>(n + kJPad));
-            v.o_bounds = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(n) * (1 + kSubs)));
+            v.o_bounds = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(n, tile) * (1 + T.subs)));
             max_sort_n = std::max(max_sort_n, n);
         }
         const int id = static_cast<int>(views.size());
@@ -432,6 +509,10 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
 
     std::vector<std::shared_ptr<DevTable>> tabs;
     std::map<const DevTable *, int> tab_idx;
+    // planning, or the caller's workspace: the batch's own tables by edge set
+    // (in the workspace, not the allocating per-device cache)
+    std::map<std::pair<int, std::vector<uint64_t>>, int> local_tab;
+    std::vector<TableBlob> blobs;
     struct JobPlan {
         int tab = 0;
         size_t o_counts = 0;
@@ -452,15 +533,35 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         if (r0 < 0 || r1 > nA || r0 > r1)
             return fail(PC_ERR_INVALID, "row range [" + std::to_string(r0) + ", " + std::to_string(r1) +
                                             ") outside [0, " + std::to_string(nA) + "]");
-        std::shared_ptr<DevTable> t;
-        rc = get_table(j.theta, j.n_edges, &t, fp64 ? 0 : lt.cols);
-        if (rc) return rc;
-        auto it = tab_idx.find(t.get());
-        if (it == tab_idx.end()) {
-            it = tab_idx.emplace(t.get(), static_cast<int>(tabs.size())).first;
-            tabs.push_back(t);
+        if (plan_only || ext) {
+            std::vector<uint64_t> bits(static_cast<size_t>(j.n_edges));
+            memcpy(bits.data(), j.theta, sizeof(double) * bits.size());
+            auto key = std::make_pair(fp64 ? 0 : lt.cols, std::move(bits));
+            auto it = local_tab.find(key);
+            if (it == local_tab.end()) {
+                auto t = std::make_shared<DevTable>();
+                if (ext) {
+                    std::string err;
+                    if (!build_table(j.theta, j.n_edges, t->host, err, fp64 ? 0 : lt.cols))
+                        return fail(PC_ERR_INVALID, err);
+                    blobs.emplace_back();
+                    table_blob(t->host, &blobs.back());
+                }
+                it = local_tab.emplace(std::move(key), static_cast<int>(tabs.size())).first;
+                tabs.push_back(t);
+            }
+            plan[q].tab = it->second;
+        } else {
+            std::shared_ptr<DevTable> t;
+            rc = get_table(j.theta, j.n_edges, &t, fp64 ? 0 : lt.cols);
+            if (rc) return rc;
+            auto it = tab_idx.find(t.get());
+            if (it == tab_idx.end()) {
+                it = tab_idx.emplace(t.get(), static_cast<int>(tabs.size())).first;
+                tabs.push_back(t);
+            }
+            plan[q].tab = it->second;
         }
-        plan[q].tab = it->second;
         if (j.auto_flag) {
             // pairs i<j with i in [r0, r1): triangle on [r0, r1) + rectangle [r0, r1) x [r1, n)
             plan[q].vi_tri = add_view(sa, r0, r1);
@@ -473,15 +574,16 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             plan[q].vj_rect = add_view(sb, 0, srcs[sb].n);
         }
     }
-    // results block, read back with one copy: meta[16] | each job's counts | conversion flags
+    // results block, read back with one copy: meta[kMetaWords] | each job's counts | conversion flags
     // (meta[0..6]: pruning figures, meta[7]: re-check tally, meta[8..15]: the
-    // counting kernel's work queue)
-    size_t res_words = 16;
+    // counting kernel's work queue, meta[16..21]: computed pairs by path)
+    constexpr size_t kMetaWords = 24;
+    size_t res_words = kMetaWords;
     for (size_t q = 0; q < jobs.size(); ++q) res_words += static_cast<size_t>(jobs[q].n_edges + 1);
     const size_t err_words = (std::max<size_t>(srcs.size(), 1) + 1) / 2;
     const size_t o_res = ar.take(sizeof(unsigned long long) * (res_words + err_words));
     {
-        size_t w = 16;
+        size_t w = kMetaWords;
         for (size_t q = 0; q < jobs.size(); ++q) {
             plan[q].o_counts = o_res + sizeof(unsigned long long) * w;
             w += static_cast<size_t>(jobs[q].n_edges + 1);
@@ -508,8 +610,8 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             sd.ni = ni;
             sd.j0 = 0;
             sd.nj = nj;
-            sd.tiles_i = n_tiles(ni);
-            sd.tiles_j = n_tiles(nj);
+            sd.tiles_i = n_tiles(ni, tile);
+            sd.tiles_j = n_tiles(nj, tile);
             // in 128 bits: up to 2^32 tiles per side, whose products pass 2^64
             const unsigned __int128 n_items =
                 tri ? static_cast<unsigned __int128>(sd.tiles_i) * static_cast<unsigned __int128>(sd.tiles_i + 1) / 2
@@ -541,12 +643,34 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     // (mixed mode); their descriptions sit beside the survivors
     const bool split = PC_SPLIT && prune && !fp64;
     const size_t o_sub = ar.take(sizeof(uint64_t) * std::max<uint64_t>(split ? items : 1, 1));
+    std::vector<size_t> o_blob(blobs.size());
+    for (size_t k = 0; k < blobs.size(); ++k) o_blob[k] = ar.take(blobs[k].bytes.size());
+    if (plan_only) {
+        *opts.plan_bytes = ar.size;
+        return PC_OK;
+    }
 
-    // ---- allocate the workspace
+    // ---- the workspace: allocated here, or the caller's
     Workspace ws;
     ws.st = st;
-    PC_HIP(hipMallocAsync(&ws.mem, ar.size, st), "hipMallocAsync(workspace)");
-    unsigned char *W = static_cast<unsigned char *>(ws.mem);
+    unsigned char *W = nullptr;
+    if (ext) {
+        if (ar.size > opts.ws_bytes)
+            return fail(PC_ERR_INVALID, "the call needs " + std::to_string(ar.size) +
+                                            " bytes of device workspace; the fixed workspace holds " +
+                                            std::to_string(opts.ws_bytes));
+        W = static_cast<unsigned char *>(opts.ws);
+        for (size_t k = 0; k < blobs.size(); ++k) {
+            PC_HIP(hipMemcpyAsync(W + o_blob[k], blobs[k].bytes.data(), blobs[k].bytes.size(), hipMemcpyHostToDevice,
+                                  st),
+                   "H2D tables");
+            table_place(tabs[k].get(), blobs[k], W + o_blob[k]);
+        }
+    } else {
+        PC_HIP(injected_alloc_failure() ? hipErrorOutOfMemory : hipMallocAsync(&ws.mem, ar.size, st),
+               "hipMallocAsync(workspace)");
+        W = static_cast<unsigned char *>(ws.mem);
+    }
 
     // ---- convert the sources (validity flags read back at the end)
     PC_HIP(launch_zero(reinterpret_cast<unsigned long long *>(W + o_res), static_cast<int64_t>(res_words + err_words), st),
@@ -580,7 +704,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         const float4 *a32s = nullptr;
         const float4 *g32s = nullptr;
         const double4 *bounds = nullptr;
-        const double4 *sub_bounds = nullptr;  // kSubs per tile, after the tiles' own
+        const double4 *sub_bounds = nullptr;  // T.subs per tile, after the tiles' own
     };
     std::vector<ViewPtrs> vp(views.size());
     for (size_t v = 0; v < views.size(); ++v) {
@@ -591,7 +715,7 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             vp[v].a32s = r.a32s;
             vp[v].g32s = r.g32s;
             vp[v].bounds = r.bounds;
-            vp[v].sub_bounds = r.bounds + n_tiles(r.n);
+            vp[v].sub_bounds = r.bounds + n_tiles(r.n, tile);
             continue;
         }
         const int64_t n = vw.e - vw.b;
@@ -600,14 +724,14 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
         float4 *a32s = reinterpret_cast<float4 *>(W + vw.o_a32s);
         float4 *g32s = reinterpret_cast<float4 *>(W + vw.o_g32s);
         double4 *bnd = reinterpret_cast<double4 *>(W + vw.o_bounds);
-        PC_HIP(launch_sort(src_a64[vw.src], vw.b, n, reinterpret_cast<uint32_t *>(W + o_scratch), a64s, a32s, g32s,
+        PC_HIP(T.launch_sort(src_a64[vw.src], vw.b, n, reinterpret_cast<uint32_t *>(W + o_scratch), a64s, a32s, g32s,
                            bnd, st),
                "sort");
         vp[v].a64s = a64s;
         vp[v].a32s = a32s;
         vp[v].g32s = g32s;
         vp[v].bounds = bnd;
-        vp[v].sub_bounds = bnd + n_tiles(n);
+        vp[v].sub_bounds = bnd + n_tiles(n, tile);
     }
 
     // ---- descriptors
@@ -657,17 +781,17 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     int grid = 0;
     if (items > 0) {
         if (prune)
-            PC_HIP(launch_prune(d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune_rows, surv,
+            PC_HIP(T.launch_prune(d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune_rows, surv,
                                 split ? sub_words : nullptr, meta, mc ? 1 : 0, split ? 1 : 0, st),
                    "prune");
         int per_cu = 0;
-        PC_HIP(count_occupancy(fp64, mc, lds_bytes, &per_cu), "occupancy");
+        PC_HIP(T.count_occupancy(fp64, mc, lds_bytes, &per_cu), "occupancy");
         per_cu = std::max(per_cu, 1);
         int64_t g = static_cast<int64_t>(di->cus) * per_cu;
         g = std::min<int64_t>(g, static_cast<int64_t>(items));
         if (g >= 8) g -= g % 8;
         grid = static_cast<int>(std::max<int64_t>(g, 1));
-        const bool timed = t_timing;
+        const bool timed = t_timing && !ext;  // events are not created in the caller's-workspace mode
         if (timed) {
             if (!t_ev0) {
                 PC_HIP(hipEventCreate(&t_ev0), "hipEventCreate");
@@ -675,9 +799,9 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
             }
             PC_HIP(hipEventRecord(t_ev0, st), "hipEventRecord");
         }
-        PC_HIP(launch_count(fp64, mc, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
+        PC_HIP(T.launch_count(fp64, mc, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
                             prune ? meta : nullptr, split ? sub_words : nullptr, items, lut_off, stage_off, meta + 8,
-                            meta + 7, lt.chunk, lds_bytes, grid, st),
+                            meta + 7, lt.chunk, lds_bytes, grid, t_flush_cap, st),
                "count kernel");
         if (timed) PC_HIP(hipEventRecord(t_ev1, st), "hipEventRecord");
     }
@@ -714,7 +838,18 @@ int run_batch(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_t st,
     t_last.gram_items = prune ? hmeta[5] : 0;
     t_last.split_items = prune ? hmeta[6] : 0;
     t_last.rechecked = hmeta[7];
-    if (t_timing && items > 0) {
+    for (int m = 0; m < 4; ++m) t_last.pairs_by_m[m] = prune ? hmeta[16 + m] : 0;
+    t_last.pairs_gram = prune ? hmeta[20] : 0;
+    if (!prune || fp64) {
+        // every computed pair through the cell table (the binary64 kernel
+        // ignores the few-edge tags)
+        t_last.pairs_by_m[0] = t_last.pairs_computed;
+        for (int m = 1; m < 4; ++m) t_last.pairs_by_m[m] = 0;
+        t_last.pairs_gram = 0;
+    }
+    t_last.pairs_mfma = prune ? hmeta[21] : 0;
+    t_last.workspace_bytes = ar.size;
+    if (t_timing && !ext && items > 0) {
         float ms = 0.0f;
         PC_HIP(hipEventElapsedTime(&ms, t_ev0, t_ev1), "hipEventElapsedTime");
         t_last.kernel_ms = ms;
@@ -740,7 +875,8 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
     const size_t o64s = ar.take(sizeof(double4) * n);
     const size_t o32s = ar.take(sizeof(float4) * (n + kJPad));  // padded as in run_batch
     const size_t og32s = ar.take(sizeof(float4) * (n + kJPad));
-    const size_t ob = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(static_cast<int64_t>(n)) * (1 + kSubs)));
+    const size_t ob = ar.take(sizeof(double4) * static_cast<size_t>(n_tiles(static_cast<int64_t>(n), kResidentTile.tile) *
+                                                                     (1 + kResidentTile.subs)));
     const size_t oerr = ar.take(sizeof(int));
     const size_t osc = ar.take(sizeof(uint32_t) * sort_scratch_words(static_cast<int64_t>(n)));
     size_t ora = 0, odec = 0;
@@ -748,7 +884,7 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
         ora = ar.take(sizeof(double) * n);
         odec = ar.take(sizeof(double) * n);
     }
-    PC_HIP(hipMalloc(&r->d_mem, ar.size), "hipMalloc(catalogue)");
+    PC_HIP(injected_alloc_failure() ? hipErrorOutOfMemory : hipMalloc(&r->d_mem, ar.size), "hipMalloc(catalogue)");
     unsigned char *W = static_cast<unsigned char *>(r->d_mem);
     r->a64 = reinterpret_cast<double4 *>(W + o64);
     r->a32 = reinterpret_cast<float4 *>(W + o32);
@@ -766,7 +902,7 @@ int upload_catalog(const pc_catalog *c, hipStream_t st, uint64_t *handle) {
             dec = reinterpret_cast<const double *>(W + odec);
         }
         PC_HIP(launch_convert(ra, dec, c->n, r->a64, r->a32, reinterpret_cast<int *>(W + oerr), st), "convert");
-        PC_HIP(launch_sort(r->a64, 0, c->n, reinterpret_cast<uint32_t *>(W + osc), r->a64s, r->a32s, r->g32s,
+        PC_HIP(kResidentTile.launch_sort(r->a64, 0, c->n, reinterpret_cast<uint32_t *>(W + osc), r->a64s, r->a32s, r->g32s,
                            r->bounds, st),
                "sort");
     }
@@ -993,6 +1129,26 @@ extern "C" int pc_debug_guard_band_gram(const double *theta_edges_deg, int32_t n
     return PC_OK;
 }
 
+extern "C" int pc_debug_fail_allocations(int32_t n) {
+    clear_error();
+    if (n < 0) return fail(PC_ERR_INVALID, "n must be >= 0");
+    t_fail_allocs = n;
+    return PC_OK;
+}
+
+extern "C" int pc_debug_set_tile(int32_t tile) {
+    clear_error();
+    if (tile != 0 && tile != 128 && tile != 256) return fail(PC_ERR_INVALID, "tile must be 0, 128 or 256");
+    t_force_tile = tile;
+    return PC_OK;
+}
+
+extern "C" int pc_debug_set_flush_every(uint64_t items) {
+    clear_error();
+    t_flush_cap = items;
+    return PC_OK;
+}
+
 extern "C" int pc_debug_set_timing(int32_t on) {
     clear_error();
     t_timing = on != 0;
@@ -1010,6 +1166,15 @@ extern "C" int pc_debug_last_pruning(uint64_t *survivors, uint64_t *pairs_comput
     if (survivors) *survivors = t_last.survivors;
     if (pairs_computed) *pairs_computed = t_last.pairs_computed;
     if (pairs_total) *pairs_total = t_last.pairs_total;
+    return PC_OK;
+}
+
+extern "C" int pc_debug_last_paths(uint64_t *pairs_by_edges, uint64_t *gram_pairs, uint64_t *mfma_pairs) {
+    clear_error();
+    if (pairs_by_edges)
+        for (int m = 0; m < 4; ++m) pairs_by_edges[m] = t_last.pairs_by_m[m];
+    if (gram_pairs) *gram_pairs = t_last.pairs_gram;
+    if (mfma_pairs) *mfma_pairs = t_last.pairs_mfma;
     return PC_OK;
 }
 

@@ -9,8 +9,19 @@
 
 namespace pc {
 
+// The counting path is compiled for two tile sizes: 256 points (4 i-points
+// per lane, namespace pc::t256) and 128 points (2 per lane, pc::t128); the
+// launch picks one at run time (a tuned launch parameter).  A translation
+// unit sees one of them through PC_R.
 #ifndef PC_R
 #define PC_R 4              // i-points held per lane
+#endif
+#if PC_R == 4
+#define PC_TILE_NS t256
+#elif PC_R == 2
+#define PC_TILE_NS t128
+#else
+#error "PC_R must be 2 or 4"
 #endif
 #ifndef PC_COLS32
 #define PC_COLS32 16        // widest histogram of the mixed kernel (lane columns)
@@ -100,7 +111,7 @@ constexpr int kSplitBit = 53;
 //   bit  14      vector path with Gram-form chords centred on the j-tile
 constexpr int kSub = 64;
 constexpr int kSubs = kTile / kSub;
-static_assert(kSubs == 4, "four 16-bit sub-block fields per 64-bit word");
+static_assert(kSubs >= 1 && kSubs <= 4, "at most four 16-bit sub-block fields per 64-bit word");
 constexpr uint32_t kSubWhole = 1u << 13;
 constexpr uint32_t kSubGram = 1u << 14;
 

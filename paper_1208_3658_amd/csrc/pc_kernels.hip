@@ -23,20 +23,8 @@
 
 namespace pc {
 
-struct KParams {
-    const SegDesc *segs;
-    const TableDesc *tabs;
-    const uint64_t *items;                 // work items to visit (survivors), or null: all items
-    const unsigned long long *n_items;     // device count of `items`
-    const uint64_t *sub;                   // sub-block words beside `items` (split items), or null
-    uint64_t total_items;                  // number of items when `items` is null
-    int32_t n_segs;
-    uint32_t lut_lds_off;   // byte offset of the cell table in LDS (after the histogram)
-    uint32_t stage_lds_off; // byte offset of the matrix-core path's A-operand block (16 x 64 floats)
-    unsigned long long *queue;  // 8 zeroed chunk counters, one per slice of the items
-    unsigned long long *rechecked;  // zeroed; pairs re-checked in binary64 are added here
-    uint32_t chunk;             // items taken from the queue at a time
-};
+#if PC_R == 4
+// ------------------- tile-independent part (compiled once, 256-point build)
 
 // -------------------------------------------------------------- conversion
 
@@ -72,6 +60,45 @@ __global__ void __launch_bounds__(256) k_zero_u64(unsigned long long *p, int64_t
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
 }
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_convert(const double *ra, const double *dec, int64_t n, double4 *a64, float4 *a32,
+                          int *err, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    k_convert<<<dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, st>>>(ra, dec, n, a64, a32, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    k_zero_u64<<<dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, st>>>(p, n);
+    return hipGetLastError();
+}
+
+#endif  // tile-independent part
+
+// ------------------------------------------------ per tile size
+
+namespace PC_TILE_NS {
+
+struct KParams {
+    const SegDesc *segs;
+    const TableDesc *tabs;
+    const uint64_t *items;                 // work items to visit (survivors), or null: all items
+    const unsigned long long *n_items;     // device count of `items`
+    const uint64_t *sub;                   // sub-block words beside `items` (split items), or null
+    uint64_t total_items;                  // number of items when `items` is null
+    int32_t n_segs;
+    uint32_t lut_lds_off;   // byte offset of the cell table in LDS (after the histogram)
+    uint32_t stage_lds_off; // byte offset of the matrix-core path's A-operand block (16 x 64 floats)
+    unsigned long long *queue;  // 8 zeroed chunk counters, one per slice of the items
+    unsigned long long *rechecked;  // zeroed; pairs re-checked in binary64 are added here
+    uint32_t chunk;             // items taken from the queue at a time
+    uint64_t flush_cap;         // > 0: flush the histogram at least every flush_cap items (testing)
+};
 
 #ifndef PC_SPLIT
 #define PC_SPLIT 1  // split items (sub-blocks of the j-tile) from the prune pass
@@ -240,6 +267,11 @@ __device__ __forceinline__ int find_seg(const SegDesc *segs, int n, uint64_t ite
 // ------------------------------------------------------- mixed precision
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// A wave-uniform binary32 value kept in a scalar register (the band limits
+// of the few-edge compares: without this the compiler may not prove them
+// uniform and keeps them in vector registers, which then spill).
+__device__ __forceinline__ float uniform_f(float x) { return __uint_as_float(uniform(__float_as_uint(x))); }
 
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
     return static_cast<uint64_t>(uniform(static_cast<uint32_t>(x))) |
@@ -666,6 +698,9 @@ __device__ __forceinline__ void tile32_gram(unsigned char *lds, const float4 *__
 }
 
 // ----------------------------------------------------------- matrix cores
+// (256-point tiles only: a tile pair is 16 x 16 blocks of 16 x 16 pairs)
+
+constexpr bool kMatrixCores = kTile == 256;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -961,6 +996,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 e64 = td.e64;
                 cols = td.cols;
                 flush_every = 0xFFFFFFFFull / (static_cast<uint64_t>(kTile) * kR * static_cast<uint64_t>(kWave / cols));
+                if (p.flush_cap) flush_every = min(flush_every, p.flush_cap);
                 row_bytes = static_cast<uint32_t>(cols) * 4u;
                 lane_off = lds0 + (lane & static_cast<uint32_t>(cols - 1)) * 4u;
                 trash_off = static_cast<uint32_t>(n_edges + 1) * row_bytes + lane_off;
@@ -1056,13 +1092,13 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         } else if (MC && to_mfma) {
             // the prune pass marks only few-edge items for the matrix cores
             FewCtx f;
-            f.k0 = few_k0;
+            f.k0 = uniform(few_k0);
 #pragma unroll
             for (int q = 0; q < kFewMax; ++q) {
                 const uint32_t e = min(few_k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
                 const float2 v = ld_const_f2(band_g + 2u * e);
-                f.lo[q] = v.x;
-                f.hi[q] = v.y;
+                f.lo[q] = uniform_f(v.x);
+                f.hi[q] = uniform_f(v.y);
             }
             const double4 o = ld_const(centre_j ? sd.jb + u : sd.ib + t);
             const double4 *I64t = uniform_ptr(sd.i64 + ibeg);
@@ -1073,15 +1109,15 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         } else if (!split) {
             // one part: the whole j-tile with the item's own edges
             FewCtx f;
-            f.k0 = few_k0;
+            f.k0 = uniform(few_k0);
             if (few_m) {
                 const float *bd = gram_j ? band_g : band;
 #pragma unroll
                 for (int q = 0; q < kFewMax; ++q) {
                     const uint32_t e = min(few_k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
                     const float2 v = ld_const_f2(bd + 2u * e);
-                    f.lo[q] = v.x;
-                    f.hi[q] = v.y;
+                    f.lo[q] = uniform_f(v.x);
+                    f.hi[q] = uniform_f(v.y);
                 }
             }
             if (use_gram) {
@@ -1135,14 +1171,14 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 return true;
             };
             auto bands = [&](FewCtx &f, uint32_t m, uint32_t k0, const float *bd) {
-                f.k0 = k0;
+                f.k0 = uniform(k0);
                 if (m) {
 #pragma unroll
                     for (int q = 0; q < kFewMax; ++q) {
                         const uint32_t e = min(k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
                         const float2 v = ld_const_f2(bd + 2u * e);
-                        f.lo[q] = v.x;
-                        f.hi[q] = v.y;
+                        f.lo[q] = uniform_f(v.x);
+                        f.hi[q] = uniform_f(v.y);
                     }
                 }
             };
@@ -1184,29 +1220,13 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts, p.rechecked);
 }
 
-// ---------------------------------------------------------------- launchers
-
-hipError_t launch_convert(const double *ra, const double *dec, int64_t n, double4 *a64, float4 *a32,
-                          int *err, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + 255) / 256;
-    k_convert<<<dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, st>>>(ra, dec, n, a64, a32, err);
-    return hipGetLastError();
-}
-
-hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + 255) / 256;
-    k_zero_u64<<<dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, st>>>(p, n);
-    return hipGetLastError();
-}
-
 hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
                         const uint64_t *items, const unsigned long long *n_items, const uint64_t *sub,
                         uint64_t total_items, uint32_t lut_lds_off, uint32_t stage_lds_off,
                         unsigned long long *queue, unsigned long long *rechecked, int chunk, uint32_t lds_bytes,
-                        int grid, hipStream_t st) {
+                        int grid, uint64_t flush_cap, hipStream_t st) {
     KParams p;
+    p.flush_cap = flush_cap;
     p.queue = queue;
     p.rechecked = rechecked;
     p.chunk = static_cast<uint32_t>(chunk);
@@ -1222,7 +1242,7 @@ hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs,
     if (fp64)
         k_count<true, false><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
     else if (mc)
-        k_count<false, true><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
+        k_count<false, kMatrixCores><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
     else
         k_count<false, false><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
     return hipGetLastError();
@@ -1232,19 +1252,22 @@ hipError_t count_occupancy(bool fp64, bool mc, uint32_t lds_bytes, int *blocks_p
     if (fp64)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<true, false>, kWave, lds_bytes);
     if (mc)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<false, true>, kWave, lds_bytes);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<false, kMatrixCores>, kWave,
+                                                             lds_bytes);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<false, false>, kWave, lds_bytes);
 }
 
 hipError_t set_max_lds(uint32_t bytes) {
     const void *fs[3] = {reinterpret_cast<const void *>(k_count<true, false>),
                          reinterpret_cast<const void *>(k_count<false, false>),
-                         reinterpret_cast<const void *>(k_count<false, true>)};
+                         reinterpret_cast<const void *>(k_count<false, kMatrixCores>)};
     for (const void *f : fs) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
+
+}  // namespace PC_TILE_NS
 
 }  // namespace pc

@@ -12,6 +12,10 @@
 
 namespace pc {
 
+#if PC_R == 4
+// ------------------- tile-independent part (compiled once, 256-point build)
+
+
 // ---------------------------------------------------------- ordering keys
 // Cube-face Hilbert key: the face of the cube the unit vector points through
 // (axis and sign of its largest component), then the 2-D Hilbert index of the
@@ -152,6 +156,79 @@ __global__ void __launch_bounds__(256) k_scatter(const double4 *__restrict__ src
     a64s[pos] = v;
     a32s[pos] = make_float4(static_cast<float>(v.x), static_cast<float>(v.y), static_cast<float>(v.z), 0.0f);
 }
+
+// --------------------------------------------------------------- launchers
+
+__global__ void __launch_bounds__(256) k_zero_u32(uint32_t *p, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Key bits per face axis for n points: 4^(bits+1) * 4 <= n, between 2 and 9
+// (at most 6 * 4^9 buckets).
+uint32_t order_bits(int64_t n) {
+    uint32_t b = 2;
+    while (b < 9 && (int64_t(1) << (2 * (b + 1))) * 4 <= n) ++b;
+    return b;
+}
+
+static int64_t n_buckets(uint32_t bits) { return int64_t(6) << (2 * bits); }
+
+size_t sort_scratch_words(int64_t n) {
+    const int64_t m = n_buckets(order_bits(n));
+    return static_cast<size_t>(n + m + (m + kScanChunk - 1) / kScanChunk + 64);
+}
+
+size_t scan_sums_words(int64_t m) { return static_cast<size_t>((m + kScanChunk - 1) / kScanChunk); }
+
+hipError_t launch_zero_u32(uint32_t *p, int64_t m, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    k_zero_u32<<<dim3(static_cast<uint32_t>((m + 255) / 256)), dim3(256), 0, st>>>(p, m);
+    return hipGetLastError();
+}
+
+// In-place exclusive prefix sum of a[0, m); sums: scan_sums_words(m) words.
+hipError_t launch_exclusive_scan(uint32_t *a, int64_t m, uint32_t *sums, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
+    k_scan_local<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(a, m, sums);
+    k_scan_sums<<<dim3(1), dim3(kScanBlock), 0, st>>>(sums, nb);
+    k_scan_add<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(a, m, sums);
+    return hipGetLastError();
+}
+
+// Spatially ordered copy of src[base, base+n) into a64s/a32s, and the tile
+// bounds: bounds[0, T) for the T tiles, then bounds[T, T + kSubs T) for their
+// sub-blocks.  scratch: sort_scratch_words(n) uint32 words.
+hipError_t launch_order(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
+                        float4 *a32s, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const uint32_t bits = order_bits(n);
+    const int64_t m = n_buckets(bits);
+    const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
+    uint32_t *keys = scratch;
+    uint32_t *hist = scratch + n;
+    uint32_t *sums = hist + m;
+    const uint32_t gn = static_cast<uint32_t>((n + 255) / 256);
+    k_zero_u32<<<dim3(static_cast<uint32_t>((m + 255) / 256)), dim3(256), 0, st>>>(hist, m);
+    k_keys<<<dim3(gn), dim3(256), 0, st>>>(src, base, n, bits, keys, hist);
+    k_scan_local<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(hist, m, sums);
+    k_scan_sums<<<dim3(1), dim3(kScanBlock), 0, st>>>(sums, nb);
+    k_scan_add<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(hist, m, sums);
+    k_scatter<<<dim3(gn), dim3(256), 0, st>>>(src, base, n, keys, hist, a64s, a32s);
+    return hipGetLastError();
+}
+
+#else
+// tile-independent steps, compiled once (with the 256-point instance)
+size_t sort_scratch_words(int64_t n);
+hipError_t launch_order(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
+                        float4 *a32s, hipStream_t st);
+#endif  // tile-independent part
+
+// ------------------------------------------------ per tile size
+
+namespace PC_TILE_NS {
 
 // ---------------------------------------------------------------- bounds
 
@@ -403,10 +480,18 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
     // meta[2] = pairs binned whole, meta[3] = survivors marked for the matrix
     // cores; work units (a survivor, or an open sub-block of a split one):
     // meta[4] with at most PC_FEWCUT edges in their chord interval, meta[5]
-    // with vector-path chords in Gram form; meta[6] = split survivors
+    // with vector-path chords in Gram form; meta[6] = split survivors.
+    // Pairs left for the counting kernel by the path it takes them through
+    // (the same decisions as k_count): meta[16 + m] = pairs binned against m
+    // edges one by one (m = 1..3), meta[16] = pairs binned through the cell
+    // table; meta[20] = pairs whose chords the vector path forms in Gram form,
+    // meta[21] = pairs on the matrix cores.
     __shared__ double e_lds[kMaxEdges];
     __shared__ unsigned long long h_lds[kMaxEdges + 1];
-    __shared__ unsigned long long s_stat[6];  // survivors, pairs, matrix-core, few-edge, Gram, split
+    // survivors, pairs, matrix-core, few-edge, Gram, split; pairs by m (4),
+    // Gram-form pairs, matrix-core pairs
+    constexpr int kStats = 12;
+    __shared__ unsigned long long s_stat[kStats];
     __shared__ unsigned long long s_base, s_whole;
     __shared__ unsigned int s_cursor;
     const int64_t row_g = blockIdx.x;
@@ -427,7 +512,7 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
     const int lane = tid & (kWave - 1);
     for (int32_t k = tid; k < n_edges; k += blockDim.x) e_lds[k] = td.e64[k];
     for (int32_t k = tid; k <= n_edges; k += blockDim.x) h_lds[k] = 0ull;
-    if (tid < 6) s_stat[tid] = 0ull;
+    if (tid < kStats) s_stat[tid] = 0ull;
     if (tid == 0) {
         s_whole = 0ull;
         s_cursor = 0u;
@@ -444,6 +529,9 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
         const bool valid = row_item(sd, r, c0 + tid, t, u, q);
         bool survive = false;
         unsigned long long pairs = 0, few_u = 0, gram_u = 0;
+        // pairs by the counting kernel's path: by edges compared one by one
+        // (index m, 0 = cell table), Gram-form chords, matrix cores
+        unsigned long long by_m[4] = {0, 0, 0, 0}, gram_p = 0, mfma_p = 0;
         uint64_t tags = 0, sub = 0;
         if (valid) {
             const PruneOut o = prune_item(sd, t, u, e_lds, n_edges, mfma_ok, split_ok);
@@ -452,15 +540,26 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
             } else if (o.sub) {
                 sub = o.sub;
                 tags = o.tags;
+                // the kernel forms a split item's chords in Gram form when
+                // every open sub-block allows it
+                bool gram_all = true;
+#pragma unroll
+                for (int k = 0; k < kSubs; ++k) {
+                    const uint32_t f = static_cast<uint32_t>(o.sub >> (16 * k)) & 0xFFFFu;
+                    if (!(f & kSubWhole) && !(f & kSubGram)) gram_all = false;
+                }
 #pragma unroll
                 for (int k = 0; k < kSubs; ++k) {
                     const uint32_t f = static_cast<uint32_t>(o.sub >> (16 * k)) & 0xFFFFu;
                     if (f & kSubWhole) {
                         atomicAdd(&h_lds[f & 2047u], kSubPairs);
                     } else {
+                        const uint32_t m = (f >> 11) & 3u;
                         pairs += kSubPairs;
-                        few_u += ((f >> 11) & 3u) != 0u ? 1ull : 0ull;
+                        few_u += m != 0u ? 1ull : 0ull;
                         gram_u += (f & kSubGram) != 0u ? 1ull : 0ull;
+                        by_m[m] += kSubPairs;
+                        gram_p += gram_all ? kSubPairs : 0ull;
                     }
                 }
                 survive = pairs != 0;
@@ -468,8 +567,13 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                 survive = true;
                 pairs = o.pairs;
                 tags = o.tags;
-                few_u = ((tags >> (kItemBits + 11)) & 3u) != 0 ? 1ull : 0ull;
+                const uint32_t m = static_cast<uint32_t>((tags >> (kItemBits + 11)) & 3u);
+                const bool mc = (tags >> 63) != 0;
+                few_u = m != 0u ? 1ull : 0ull;
                 gram_u = ((tags >> 61) & 1u) != 0 ? 1ull : 0ull;
+                by_m[m] = pairs;
+                gram_p = (!mc && gram_u && m != 0u) ? pairs : 0ull;
+                mfma_p = mc ? pairs : 0ull;
             }
         }
         const uint64_t sm = __ballot(survive);
@@ -479,6 +583,10 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                 pairs += __shfl_xor(pairs, o, kWave);
                 few_u += __shfl_xor(few_u, o, kWave);
                 gram_u += __shfl_xor(gram_u, o, kWave);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) by_m[m] += __shfl_xor(by_m[m], o, kWave);
+                gram_p += __shfl_xor(gram_p, o, kWave);
+                mfma_p += __shfl_xor(mfma_p, o, kWave);
             }
             const uint64_t mm = __ballot(survive && (tags >> 63) != 0);
             const uint64_t ms = __ballot(survive && sub != 0);
@@ -489,6 +597,11 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                 atomicAdd(&s_stat[3], few_u);
                 atomicAdd(&s_stat[4], gram_u);
                 atomicAdd(&s_stat[5], static_cast<unsigned long long>(__popcll(ms)));
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    if (by_m[m]) atomicAdd(&s_stat[6 + m], by_m[m]);
+                if (gram_p) atomicAdd(&s_stat[10], gram_p);
+                if (mfma_p) atomicAdd(&s_stat[11], mfma_p);
             }
         }
     }
@@ -547,69 +660,22 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
             if (s_stat[3]) atomicAdd(meta + 4, s_stat[3]);
             if (s_stat[4]) atomicAdd(meta + 5, s_stat[4]);
             if (s_stat[5]) atomicAdd(meta + 6, s_stat[5]);
+#pragma unroll
+            for (int k = 6; k < kStats; ++k)
+                if (s_stat[k]) atomicAdd(meta + 10 + k, s_stat[k]);
         }
     }
 }
 
-// --------------------------------------------------------------- launchers
-
-__global__ void __launch_bounds__(256) k_zero_u32(uint32_t *p, int64_t n) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
-}
-
-// Key bits per face axis for n points: 4^(bits+1) * 4 <= n, between 2 and 9
-// (at most 6 * 4^9 buckets).
-uint32_t order_bits(int64_t n) {
-    uint32_t b = 2;
-    while (b < 9 && (int64_t(1) << (2 * (b + 1))) * 4 <= n) ++b;
-    return b;
-}
-
-static int64_t n_buckets(uint32_t bits) { return int64_t(6) << (2 * bits); }
-
-size_t sort_scratch_words(int64_t n) {
-    const int64_t m = n_buckets(order_bits(n));
-    return static_cast<size_t>(n + m + (m + kScanChunk - 1) / kScanChunk + 64);
-}
-
-size_t scan_sums_words(int64_t m) { return static_cast<size_t>((m + kScanChunk - 1) / kScanChunk); }
-
-hipError_t launch_zero_u32(uint32_t *p, int64_t m, hipStream_t st) {
-    if (m <= 0) return hipSuccess;
-    k_zero_u32<<<dim3(static_cast<uint32_t>((m + 255) / 256)), dim3(256), 0, st>>>(p, m);
-    return hipGetLastError();
-}
-
-// In-place exclusive prefix sum of a[0, m); sums: scan_sums_words(m) words.
-hipError_t launch_exclusive_scan(uint32_t *a, int64_t m, uint32_t *sums, hipStream_t st) {
-    if (m <= 0) return hipSuccess;
-    const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
-    k_scan_local<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(a, m, sums);
-    k_scan_sums<<<dim3(1), dim3(kScanBlock), 0, st>>>(sums, nb);
-    k_scan_add<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(a, m, sums);
-    return hipGetLastError();
-}
-
 // Spatially ordered copy of src[base, base+n) into a64s/a32s, and the tile
 // bounds: bounds[0, T) for the T tiles, then bounds[T, T + kSubs T) for their
-// sub-blocks.  scratch: sort_scratch_words(n) uint32 words.
+// sub-blocks, and the Gram-form copy g32s.  scratch: sort_scratch_words(n)
+// uint32 words.
 hipError_t launch_sort(const double4 *src, int64_t base, int64_t n, uint32_t *scratch, double4 *a64s,
                        float4 *a32s, float4 *g32s, double4 *bounds, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    const uint32_t bits = order_bits(n);
-    const int64_t m = n_buckets(bits);
-    const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
-    uint32_t *keys = scratch;
-    uint32_t *hist = scratch + n;
-    uint32_t *sums = hist + m;
-    const uint32_t gn = static_cast<uint32_t>((n + 255) / 256);
-    k_zero_u32<<<dim3(static_cast<uint32_t>((m + 255) / 256)), dim3(256), 0, st>>>(hist, m);
-    k_keys<<<dim3(gn), dim3(256), 0, st>>>(src, base, n, bits, keys, hist);
-    k_scan_local<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(hist, m, sums);
-    k_scan_sums<<<dim3(1), dim3(kScanBlock), 0, st>>>(sums, nb);
-    k_scan_add<<<dim3(static_cast<uint32_t>(nb)), dim3(kScanBlock), 0, st>>>(hist, m, sums);
-    k_scatter<<<dim3(gn), dim3(256), 0, st>>>(src, base, n, keys, hist, a64s, a32s);
+    hipError_t e = launch_order(src, base, n, scratch, a64s, a32s, st);
+    if (e != hipSuccess) return e;
     const int64_t tiles = (n + kTile - 1) / kTile;
     k_bounds<<<dim3(static_cast<uint32_t>(tiles)), dim3(kWave), 0, st>>>(a64s, n, bounds, bounds + tiles, g32s);
     return hipGetLastError();
@@ -624,5 +690,7 @@ hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *ta
                                                                           mfma_ok, split_ok);
     return hipGetLastError();
 }
+
+}  // namespace PC_TILE_NS
 
 }  // namespace pc

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <memory>
 #include <string>
 #include <tuple>
@@ -15,6 +16,9 @@
 namespace pc {
 
 int fail(int code, const std::string &msg);
+// true when a test asked this thread's next device allocation to fail
+// (pc_debug_fail_allocations); the caller then reports it as out of memory
+bool injected_alloc_failure();
 int hip_fail(hipError_t e, const char *what);
 void clear_error();
 
@@ -41,6 +45,16 @@ struct DevTable {
 };
 // cols: histogram lane columns of the mixed kernel's tables (0 = default)
 int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *out, int cols = 0);
+
+// A table's device image: e64 | band | band_g | lut32 | lut64 at the offsets
+// below (256-byte aligned), built on the host.
+struct TableBlob {
+    std::vector<unsigned char> bytes;
+    size_t o_band = 0, o_band_g = 0, o_lut32 = 0, o_lut64 = 0;
+};
+void table_blob(const HostTable &h, TableBlob *out);
+// points t's device pointers into a copy of the blob at `base` (t does not own it)
+void table_place(DevTable *t, const TableBlob &b, unsigned char *base);
 
 // A converted catalogue kept on the device.
 struct Resident {
@@ -87,15 +101,23 @@ struct BatchStats {
     uint64_t gram_items = 0;      // work units with Gram-form chords on the vector path
     uint64_t split_items = 0;     // survivors visited as sub-blocks of the j-tile
     uint64_t rechecked = 0;       // pairs whose binary32 chord fell in a guard band (re-checked in binary64)
+    // computed pairs by the counting kernel's path: [m] binned against m edges
+    // one by one (m = 1..3), [0] through the cell table (or binary64 kernel)
+    uint64_t pairs_by_m[4] = {0, 0, 0, 0};
+    uint64_t pairs_gram = 0;      // of the few-edge pairs, chords in tile-centred Gram form
+    uint64_t pairs_mfma = 0;      // pairs on the matrix cores
+    uint64_t workspace_bytes = 0; // device workspace of the launch
 };
 
 // Launch parameters a tuner may choose (all give the same counts):
 // histogram lane columns of the mixed kernel (0 = the table's default), work
-// items taken from the queue at a time, and the matrix-core chord path.
+// items taken from the queue at a time, the matrix-core chord path (256-point
+// tiles only) and the tile size.
 struct LaunchTune {
     int cols = 0;
     int chunk = 4;
     bool matrix_cores = false;
+    int tile = 256;  // points per tile, 128 or 256 (0: 256)
 };
 
 // Runs the jobs in one persistent launch on `st` and blocks until the host
@@ -104,6 +126,29 @@ struct LaunchTune {
 // is used when one exists.
 int run_batch(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, BatchStats *stats,
               const LaunchTune *tune = nullptr);
+
+// Further options of a batch:
+//  * ws / ws_bytes: run in this caller-provided device workspace instead of
+//    allocating one; the batch's edge-set tables are placed in it too (not
+//    taken from the per-device cache, which allocates).  PC_ERR_INVALID when
+//    the batch needs more than ws_bytes (nothing is launched then).
+//  * plan_bytes: only plan -- write the workspace bytes the batch needs
+//    (tables excluded; they are cached per device) and return, with no device
+//    call.  Catalogue arguments are validated as for a real run.
+//  * trusted_inputs: the host catalogues were already checked point by point
+//    (finite RA, |Dec| <= 90); only their shape is checked here.
+//  * plan_sizes (planning only): resident-catalogue handles that need not
+//    exist, given by their number of points.
+struct BatchOpts {
+    const LaunchTune *tune = nullptr;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    uint64_t *plan_bytes = nullptr;
+    bool trusted_inputs = false;
+    const std::map<uint64_t, int64_t> *plan_sizes = nullptr;
+};
+int run_batch_opts(const std::vector<BatchJob> &jobs, int mode, hipStream_t st, BatchStats *stats,
+                   const BatchOpts &opts);
 
 // Tuned entries: keyed by device, edge count class and pair count class.
 struct TuneKey {
@@ -116,7 +161,8 @@ struct TuneKey {
 };
 struct TuneEntry {
     LaunchTune tune;
-    double kernel_ms = 0.0;
+    double kernel_ms = 0.0;  // counting kernel (HIP events)
+    double launch_ms = 0.0;  // the whole launch (host clock)
 };
 TuneKey tune_key_of(const std::vector<BatchJob> &jobs);
 int tune_lookup(const TuneKey &k, TuneEntry *e);

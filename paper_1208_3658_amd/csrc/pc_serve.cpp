@@ -58,6 +58,7 @@ struct ServerCfg {
     int policy = 0;         // 0: first come first served; 1: fewest pairs first, with ageing
     double aging_s = 1.0;   // policy 1: requests waiting this long go first, oldest first
     std::string log_path;   // one JSON line per finished request is appended here (empty: none)
+    double slice_pairs = 5e11;  // a request with more pairs runs as row-range parts of about this many (0: never)
 };
 
 // minimal reader for flat {"key": number, ...} objects
@@ -112,6 +113,7 @@ bool parse_cfg(const char *s, ServerCfg &c, std::string &err) {
         else if (key == "deadline_s") c.deadline_s = std::max(0.0, v);
         else if (key == "policy") c.policy = static_cast<int>(v);
         else if (key == "aging_s") c.aging_s = std::max(0.0, v);
+        else if (key == "slice_pairs") c.slice_pairs = std::max(0.0, v);
         else { err = "config: unknown key " + key; return false; }
         skip();
         if (p < j.size() && j[p] == ',') { ++p; continue; }
@@ -125,6 +127,16 @@ bool parse_cfg(const char *s, ServerCfg &c, std::string &err) {
     return true;
 }
 
+// The rows a request counts in one launch: DD and DR for data rows [a, b)
+// (pairs i < j with i in range, and (i, all randoms)), RR for random rows
+// [c, d).  Counts over disjoint row ranges add up exactly (Sec. 2.1, the pair
+// matrix cut into submatrices), so a large request can run as several parts
+// in successive launches while small requests run in between.
+struct Part {
+    int64_t a = 0, b = 0;  // data rows
+    int64_t c = 0, d = 0;  // random rows (RR), empty when RR is not counted here
+};
+
 struct Request {
     uint64_t id = 0;
     int32_t patch = 0;
@@ -132,10 +144,20 @@ struct Request {
     std::vector<double> edges;
     Clock::time_point t_submit;
     int64_t n_points = 0;
-    uint64_t need_bytes = 0;
-    double pairs = 0;
+    int64_t n_random = 0;    // the patch's random catalogue when the request was submitted
+    uint64_t random_handle = 0;
+    uint64_t need_bytes = 0; // device bytes of the next part's launch (planned on the host)
+    double pairs = 0;        // pairs of the whole request (DD + DR)
+    double part_pairs = 0;   // pairs of the next part (DD + DR + RR rows)
+    Part part;               // the next part
+    int64_t data_done = 0;   // data rows counted so far
+    int64_t rr_done = 0;     // random rows counted so far (RR)
+    bool rr_needed = true;   // RR not cached: counted by this request's parts
+    bool started = false;    // a part has run: no queueing deadline any more
+    int parts_run = 0;
     bool running = false;    // admitted: its batch is on the device
     bool cancelled = false;  // cancelled while running: answer discarded
+    std::vector<uint64_t> pDD, pDR, pRR;  // counts of the part on the device
     // results
     int status = PC_OK;
     std::string error;
@@ -157,6 +179,7 @@ struct QueuedView {
     uint64_t need;  // device bytes the request needs while it runs
     double pairs;   // pairs its DD and DR jobs count
     double age_s;   // seconds since submission
+    bool started = false;  // a part of it has already run (no queueing deadline)
 };
 
 // The admission policy, free of device calls (the server feeds it the free
@@ -200,7 +223,7 @@ int plan_admission(const QueuedView *q, int n, uint64_t free_b, uint64_t total_b
             outcome[i] = kNeverFits;
             continue;
         }
-        if (cfg.deadline_s > 0 && q[i].age_s > cfg.deadline_s) {
+        if (cfg.deadline_s > 0 && !q[i].started && q[i].age_s > cfg.deadline_s) {
             outcome[i] = kExpired;
             continue;
         }
@@ -231,6 +254,122 @@ std::string rr_key(uint64_t random_handle, const std::vector<double> &e) {
     return k;
 }
 
+// DD pairs of data rows [a, b) of an n-point catalogue (pairs i < j with i in
+// the range): sum over i of n - 1 - i.
+double auto_rows_pairs(int64_t n, int64_t a, int64_t b) {
+    const double k = static_cast<double>(b - a);
+    return k * static_cast<double>(n - 1 - a) - 0.5 * k * (k - 1.0);
+}
+
+// The next part of request r: all that is left when that is at most `slice`
+// pairs (or slicing is off); else data rows from where the last part ended
+// whose DD + DR pairs first reach `slice`, and once the data rows are done,
+// random rows for RR likewise.  *pairs receives the part's pairs.
+Part next_part(const Request &r, double slice, double *pairs) {
+    const int64_t n = r.n_points, nr = r.n_random;
+    const int64_t c = r.rr_needed ? r.rr_done : nr, d = nr;
+    const double data_left = auto_rows_pairs(n, r.data_done, n) +
+                             static_cast<double>(n - r.data_done) * static_cast<double>(nr);
+    const double rr_left = auto_rows_pairs(nr, c, d);
+    Part p;
+    if (slice <= 0 || data_left + rr_left <= slice) {
+        p.a = r.data_done;
+        p.b = n;
+        p.c = c;
+        p.d = d;
+        *pairs = data_left + rr_left;
+        return p;
+    }
+    if (r.data_done < n) {
+        const int64_t a = r.data_done;
+        auto rows_pairs = [&](int64_t b) {
+            return auto_rows_pairs(n, a, b) + static_cast<double>(b - a) * static_cast<double>(nr);
+        };
+        int64_t lo = a + 1, hi = n;  // the first b whose pairs reach `slice`
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (rows_pairs(mid) >= slice) hi = mid;
+            else lo = mid + 1;
+        }
+        p.a = a;
+        p.b = lo;
+        p.c = p.d = 0;
+        *pairs = rows_pairs(lo);
+        return p;
+    }
+    int64_t lo = c + 1, hi = d;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (auto_rows_pairs(nr, c, mid) >= slice) hi = mid;
+        else lo = mid + 1;
+    }
+    p.a = p.b = n;
+    p.c = c;
+    p.d = lo;
+    *pairs = auto_rows_pairs(nr, c, lo);
+    return p;
+}
+
+// The jobs of one part: DD and DR over data rows [a, b) (left out when the
+// range is empty and the part counts RR rows), RR over random rows [c, d).
+// `cat` describes the request's host copy of its catalogue.
+void part_jobs(const Request &r, const Part &p, const pc_catalog *cat, std::vector<BatchJob> *jobs,
+               uint64_t *dd, uint64_t *dr, uint64_t *rr) {
+    const int32_t ne = static_cast<int32_t>(r.edges.size());
+    const bool has_rr = p.c < p.d;
+    if (p.a < p.b || !has_rr) {
+        BatchJob j;
+        j.A = cat;
+        j.theta = r.edges.data();
+        j.n_edges = ne;
+        j.auto_flag = 1;
+        j.row_begin = p.a;
+        j.row_end = p.b;
+        j.counts = dd;
+        jobs->push_back(j);
+        j.hB = r.random_handle;
+        j.auto_flag = 0;
+        j.counts = dr;
+        jobs->push_back(j);
+    }
+    if (has_rr) {
+        BatchJob j;
+        j.hA = r.random_handle;
+        j.theta = r.edges.data();
+        j.n_edges = ne;
+        j.auto_flag = 1;
+        j.row_begin = p.c;
+        j.row_end = p.d;
+        j.counts = rr;
+        jobs->push_back(j);
+    }
+}
+
+// Device bytes the launch of part p needs on its own, planned on the host by
+// the batch runner itself (its workspace: converted and ordered copies, sort
+// scratch, survivor lists, results).  `sizes` describes resident catalogues
+// that need not exist (tests).
+int part_need_bytes(const Request &r, const Part &p, int mode, const std::map<uint64_t, int64_t> *sizes,
+                    uint64_t *bytes) {
+    pc_catalog cat;
+    cat.ra_deg = r.ra.empty() ? reinterpret_cast<const double *>(&r) : r.ra.data();
+    cat.dec_deg = r.dec.empty() ? reinterpret_cast<const double *>(&r) : r.dec.data();
+    cat.n = r.n_points;
+    cat.on_device = 0;
+    cat.reserved = 0;
+    std::vector<BatchJob> jobs;
+    part_jobs(r, p, &cat, &jobs, nullptr, nullptr, nullptr);
+    BatchOpts o;
+    uint64_t b = 0;
+    o.plan_bytes = &b;
+    o.trusted_inputs = true;
+    o.plan_sizes = sizes;
+    const int rc = run_batch_opts(jobs, mode, nullptr, nullptr, o);
+    if (rc) return rc;
+    *bytes = b + (1u << 20);  // plus the launch's tables and descriptors, generously
+    return PC_OK;
+}
+
 }  // namespace
 
 struct Server {
@@ -247,11 +386,12 @@ struct Server {
     int inflight = 0;
     uint64_t reserved = 0;
     bool stop = false;
+    bool hold = false;  // debug gate: admitted batches wait before their launch
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
     // stats
     uint64_t n_submitted = 0, n_done = 0, n_failed = 0, n_batches = 0, n_admit_waits = 0;
-    uint64_t n_cancelled = 0, n_expired = 0;
+    uint64_t n_cancelled = 0, n_expired = 0, n_requeued = 0, n_split_batches = 0;
     int running_batches = 0, max_running_batches = 0;
     double pairs_done = 0, busy_s = 0;
     std::vector<double> latencies;
@@ -262,6 +402,10 @@ struct Server {
 
     void worker(int k);
     int take_batch(std::vector<std::shared_ptr<Request>> &out, uint64_t &bytes);
+    void prepare(Request &r);                                            // mu held
+    int launch_parts(const std::vector<std::shared_ptr<Request>> &reqs, hipStream_t st, std::string *err);
+    void finish_part(Request &r, int rc, const std::string &err);        // mu held
+    void release_retired();                                              // mu held
     void finish_unrun(Request &r, int status, const std::string &msg);  // mu held
     void log_request(const Request &r, int64_t batch);                  // mu held
     void write_log();                                                    // mu not held
@@ -321,8 +465,8 @@ int Server::take_batch(std::vector<std::shared_ptr<Request>> &out, uint64_t &byt
     std::vector<QueuedView> view(queue.size());
     std::vector<int32_t> outcome(queue.size());
     for (size_t i = 0; i < queue.size(); ++i)
-        view[i] = {queue[i]->need_bytes, queue[i]->pairs,
-                   std::chrono::duration<double>(now - queue[i]->t_submit).count()};
+        view[i] = {queue[i]->need_bytes, queue[i]->part_pairs,
+                   std::chrono::duration<double>(now - queue[i]->t_submit).count(), queue[i]->started};
     bool mem_blocked = false;
     plan_admission(view.data(), static_cast<int>(view.size()), free_b, total_b, reserved, inflight, cfg,
                    outcome.data(), &mem_blocked);
@@ -333,6 +477,15 @@ int Server::take_batch(std::vector<std::shared_ptr<Request>> &out, uint64_t &byt
         auto &r = queue[i];
         switch (outcome[i]) {
             case kAdmit:
+                if (r->rr_needed && r->rr_done == 0 && r->part.c < r->part.d) {
+                    // RR counted (and cached) since the part was planned
+                    auto it = rr_cache.find(rr_key(r->random_handle, r->edges));
+                    if (it != rr_cache.end()) {
+                        r->RR = it->second;
+                        r->rr_needed = false;
+                        r->part.c = r->part.d = 0;
+                    }
+                }
                 r->running = true;
                 bytes += r->need_bytes;
                 ++inflight;
@@ -359,6 +512,161 @@ int Server::take_batch(std::vector<std::shared_ptr<Request>> &out, uint64_t &byt
     return static_cast<int>(out.size());
 }
 
+// Replaced random catalogues are released once no launch runs and no request
+// that has been counted in part still refers to them (mu held).
+void Server::release_retired() {
+    if (running_batches != 0 || retired.empty()) return;
+    std::vector<uint64_t> keep;
+    for (uint64_t h : retired) {
+        const bool used = std::any_of(queue.begin(), queue.end(), [&](const std::shared_ptr<Request> &q) {
+            return q->random_handle == h;
+        });
+        if (used) keep.push_back(h);
+        else release_catalog(h);
+    }
+    retired.swap(keep);
+}
+
+// The next part of r and the device bytes its launch needs (mu held).
+void Server::prepare(Request &r) {
+    r.part = next_part(r, cfg.slice_pairs, &r.part_pairs);
+    uint64_t b = 0;
+    if (part_need_bytes(r, r.part, cfg.mode, nullptr, &b) != PC_OK) {
+        // planning only fails for arguments that were checked at submission;
+        // fall back to a generous figure rather than refusing the request
+        const double pts = static_cast<double>(r.n_points) + static_cast<double>(r.n_random);
+        b = static_cast<uint64_t>(std::min(0x1p62, 200.0 * pts + 16.0 * r.part_pairs / 65536.0)) + (1u << 20);
+    }
+    r.need_bytes = b;
+}
+
+// One launch for the current parts of `reqs` on stream st: each request's
+// part counts land in its pDD, pDR, pRR.  RR over the same rows of the same
+// random catalogue and edges is counted once.
+int Server::launch_parts(const std::vector<std::shared_ptr<Request>> &reqs, hipStream_t st, std::string *err) {
+    std::vector<pc_catalog> cats(reqs.size());
+    std::vector<BatchJob> jobs;
+    std::map<std::tuple<std::string, int64_t, int64_t>, size_t> rr_of;
+    std::vector<std::vector<uint64_t>> rr_store;
+    std::vector<size_t> rr_job(reqs.size(), SIZE_MAX);
+    std::vector<size_t> rr_first;  // jobs index of each RR job
+    for (size_t q = 0; q < reqs.size(); ++q) {
+        Request &r = *reqs[q];
+        const size_t ne = r.edges.size();
+        r.pDD.assign(ne + 1, 0);
+        r.pDR.assign(ne + 1, 0);
+        r.pRR.assign(ne + 1, 0);
+        cats[q].ra_deg = r.ra.data();
+        cats[q].dec_deg = r.dec.data();
+        cats[q].n = r.n_points;
+        cats[q].on_device = 0;
+        cats[q].reserved = 0;
+        Part p = r.part;
+        const bool has_rr = p.c < p.d;
+        std::tuple<std::string, int64_t, int64_t> key;
+        bool shared = false;
+        if (has_rr) {
+            key = std::make_tuple(rr_key(r.random_handle, r.edges), p.c, p.d);
+            auto it = rr_of.find(key);
+            if (it != rr_of.end()) {
+                rr_job[q] = it->second;
+                shared = true;
+                p.c = p.d = 0;  // counted by an earlier request of this launch
+            }
+        }
+        const size_t before = jobs.size();
+        part_jobs(r, p, &cats[q], &jobs, r.pDD.data(), r.pDR.data(), nullptr);
+        if (has_rr && !shared) {
+            rr_job[q] = rr_store.size();
+            rr_of.emplace(key, rr_store.size());
+            rr_store.emplace_back(ne + 1, 0);
+            for (size_t k = before; k < jobs.size(); ++k)
+                if (jobs[k].hA) rr_first.push_back(k);
+        }
+    }
+    for (size_t s = 0; s < rr_first.size(); ++s) jobs[rr_first[s]].counts = rr_store[s].data();
+    BatchOpts o;
+    o.trusted_inputs = true;  // checked point by point at submission
+    const int rc = run_batch_opts(jobs, cfg.mode, st, nullptr, o);
+    if (rc) {
+        *err = pc_last_error();
+        return rc;
+    }
+    for (size_t q = 0; q < reqs.size(); ++q)
+        if (rr_job[q] != SIZE_MAX) reqs[q]->pRR = rr_store[rr_job[q]];
+    return PC_OK;
+}
+
+// A part of r has run (status rc): add its counts, then either requeue r
+// for its next part or finish it (mu held).
+void Server::finish_part(Request &r, int rc, const std::string &err) {
+    r.running = false;
+    --inflight;
+    bool done = true;
+    if (r.cancelled) {
+        r.status = PC_ERR_CANCELLED;
+        r.error = "request cancelled";
+        ++n_failed;
+        ++n_cancelled;
+    } else if (rc != PC_OK) {
+        r.status = rc;
+        r.error = err;
+        ++n_failed;
+    } else {
+        const size_t ne = r.edges.size();
+        for (size_t k = 0; k <= ne; ++k) {
+            r.DD[k] += r.pDD[k];
+            r.DR[k] += r.pDR[k];
+        }
+        if (r.part.c < r.part.d)
+            for (size_t k = 0; k <= ne; ++k) r.RR[k] += r.pRR[k];
+        r.data_done = r.part.b;
+        if (r.part.c < r.part.d) r.rr_done = r.part.d;
+        r.started = true;
+        ++r.parts_run;
+        const bool rr_left = r.rr_needed && r.rr_done < r.n_random;
+        if (r.data_done < r.n_points || rr_left) {
+            done = false;
+        } else {
+            if (r.rr_needed) {
+                // cache RR unless the patch's random catalogue was replaced meanwhile
+                const bool current = std::any_of(patches.begin(), patches.end(),
+                                                 [&](const std::pair<const int32_t, Patch> &pp) {
+                                                     return pp.second.handle == r.random_handle;
+                                                 });
+                if (current) rr_cache.emplace(rr_key(r.random_handle, r.edges), r.RR);
+            }
+            const int32_t nb = static_cast<int32_t>(r.edges.size()) - 1;
+            r.w.assign(nb, 0.0);
+            if (r.n_points >= 2 && r.n_random >= 2)
+                landy_szalay(r.DD.data() + 1, r.DR.data() + 1, r.RR.data() + 1, nb, r.n_points, r.n_random,
+                             r.w.data());
+            else
+                std::fill(r.w.begin(), r.w.end(), std::nan(""));
+            pairs_done += r.pairs;
+            ++n_done;
+        }
+    }
+    std::vector<uint64_t>().swap(r.pDD);
+    std::vector<uint64_t>().swap(r.pDR);
+    std::vector<uint64_t>().swap(r.pRR);
+    if (!done) {
+        // back to the front of the queue, ahead of requests submitted later
+        prepare(r);
+        auto pos = std::find_if(queue.begin(), queue.end(),
+                                [&](const std::shared_ptr<Request> &x) { return x->t_submit > r.t_submit; });
+        queue.insert(pos, jobs.at(r.id));
+        ++n_requeued;
+        return;
+    }
+    r.latency = std::chrono::duration<double>(Clock::now() - r.t_submit).count();
+    if (r.status == PC_OK) latencies.push_back(r.latency);
+    r.done = true;
+    log_request(r, static_cast<int64_t>(n_batches));
+    std::vector<double>().swap(r.ra);
+    std::vector<double>().swap(r.dec);
+}
+
 void Server::worker(int k) {
     (void)hipSetDevice(device);
     hipStream_t st = streams[k];
@@ -380,133 +688,31 @@ void Server::worker(int k) {
                 continue;
             }
             max_running_batches = std::max(max_running_batches, ++running_batches);
-        }
-        // build the jobs: DD, DR, and RR where not cached
-        std::vector<pc_catalog> cats(batch.size());
-        std::vector<BatchJob> jobs;
-        std::vector<std::string> rr_keys;
-        std::vector<int> rr_job(batch.size(), -1);
-        std::map<std::string, int> rr_new;
-        std::vector<std::vector<uint64_t>> rr_store;
-        std::vector<Patch> pinfo(batch.size());
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            for (size_t q = 0; q < batch.size(); ++q) pinfo[q] = patches[batch[q]->patch];
-        }
-        for (size_t q = 0; q < batch.size(); ++q) {
-            Request &r = *batch[q];
-            const int32_t ne = static_cast<int32_t>(r.edges.size());
-            r.DD.assign(ne + 1, 0);
-            r.DR.assign(ne + 1, 0);
-            cats[q].ra_deg = r.ra.data();
-            cats[q].dec_deg = r.dec.data();
-            cats[q].n = static_cast<int64_t>(r.ra.size());
-            cats[q].on_device = 0;
-            cats[q].reserved = 0;
-            BatchJob dd;
-            dd.A = &cats[q];
-            dd.theta = r.edges.data();
-            dd.n_edges = ne;
-            dd.auto_flag = 1;
-            dd.counts = r.DD.data();
-            jobs.push_back(dd);
-            BatchJob dr;
-            dr.A = &cats[q];
-            dr.hB = pinfo[q].handle;
-            dr.theta = r.edges.data();
-            dr.n_edges = ne;
-            dr.auto_flag = 0;
-            dr.counts = r.DR.data();
-            jobs.push_back(dr);
-            const std::string key = rr_key(pinfo[q].handle, r.edges);
-            bool cached;
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                auto it = rr_cache.find(key);
-                cached = it != rr_cache.end();
-                if (cached) r.RR = it->second;
-            }
-            if (!cached) {
-                auto it = rr_new.find(key);
-                if (it == rr_new.end()) {
-                    it = rr_new.emplace(key, static_cast<int>(rr_store.size())).first;
-                    rr_store.emplace_back(ne + 1, 0);
-                    rr_keys.push_back(key);
-                    BatchJob rr;
-                    rr.hA = pinfo[q].handle;
-                    rr.theta = r.edges.data();
-                    rr.n_edges = ne;
-                    rr.auto_flag = 1;
-                    rr.counts = nullptr;  // set below, after rr_store stops growing
-                    jobs.push_back(rr);
-                }
-                rr_job[q] = it->second;
-            }
-        }
-        // RR jobs are the ones with hA set and auto; point them at rr_store
-        {
-            size_t s = 0;
-            for (auto &j : jobs)
-                if (j.hA && j.auto_flag) j.counts = rr_store[s++].data();
+            // the batch is admitted (it holds its slots and bytes); a test
+            // may hold it here to make the queue's timing deterministic
+            cv_work.wait(lk, [&] { return !hold || stop; });
         }
         const auto t_start = Clock::now();
-        const int rc = run_batch(jobs, cfg.mode, st, nullptr);
-        const std::string err = rc ? std::string(pc_last_error()) : std::string();
+        std::string err;
+        std::vector<int> rcs(batch.size(), launch_parts(batch, st, &err));
+        std::vector<std::string> errs(batch.size(), err);
+        if (rcs[0] == PC_ERR_NOMEM && batch.size() > 1) {
+            // the device had less memory than admission saw: the requests
+            // run one launch each rather than fail together
+            ++n_split_batches;
+            for (size_t q = 0; q < batch.size(); ++q) {
+                errs[q].clear();
+                rcs[q] = launch_parts({batch[q]}, st, &errs[q]);
+            }
+        }
         const double dt = std::chrono::duration<double>(Clock::now() - t_start).count();
-        double pairs = 0;
         {
             std::lock_guard<std::mutex> lk(mu);
-            if (rc == PC_OK)
-                for (size_t s = 0; s < rr_keys.size(); ++s) {
-                    uint64_t h;
-                    memcpy(&h, rr_keys[s].data(), sizeof(h));
-                    const bool current = std::any_of(patches.begin(), patches.end(),
-                                                     [&](const std::pair<const int32_t, Patch> &pp) {
-                                                         return pp.second.handle == h;
-                                                     });
-                    if (current) rr_cache.emplace(rr_keys[s], rr_store[s]);
-                }
-            for (size_t q = 0; q < batch.size(); ++q) {
-                Request &r = *batch[q];
-                if (r.cancelled) {
-                    r.status = PC_ERR_CANCELLED;
-                    r.error = "request cancelled";
-                    ++n_failed;
-                    ++n_cancelled;
-                } else if (rc == PC_OK) {
-                    if (rr_job[q] >= 0) r.RR = rr_store[rr_job[q]];
-                    const int32_t nb = static_cast<int32_t>(r.edges.size()) - 1;
-                    r.w.assign(nb, 0.0);
-                    if (r.ra.size() >= 2 && pinfo[q].n >= 2)
-                        landy_szalay(r.DD.data() + 1, r.DR.data() + 1, r.RR.data() + 1, nb,
-                                     static_cast<int64_t>(r.ra.size()), pinfo[q].n, r.w.data());
-                    else
-                        std::fill(r.w.begin(), r.w.end(), std::nan(""));
-                    pairs += r.pairs;
-                    ++n_done;
-                } else {
-                    r.status = rc;
-                    r.error = err;
-                    ++n_failed;
-                }
-                r.latency = std::chrono::duration<double>(Clock::now() - r.t_submit).count();
-                if (r.status == PC_OK) latencies.push_back(r.latency);
-                r.running = false;
-                r.done = true;
-                log_request(r, static_cast<int64_t>(n_batches));
-                std::vector<double>().swap(r.ra);
-                std::vector<double>().swap(r.dec);
-                --inflight;
-            }
+            for (size_t q = 0; q < batch.size(); ++q) finish_part(*batch[q], rcs[q], errs[q]);
             reserved -= bytes;
             --running_batches;
             ++n_batches;
-            if (running_batches == 0) {
-                // no launch can still use a replaced random catalogue
-                for (uint64_t h : retired) release_catalog(h);
-                retired.clear();
-            }
-            pairs_done += pairs;
+            release_retired();
             busy_s += dt;
         }
         write_log();
@@ -562,8 +768,7 @@ int pc_server_set_random(void *server, int32_t patch_id, const pc_catalog *rando
         const uint64_t old = it->second.handle;
         // a running launch may still read the old catalogue: release it once
         // none runs; its cached RR counts are dropped now
-        if (s->running_batches == 0) release_catalog(old);
-        else s->retired.push_back(old);
+        s->retired.push_back(old);
         for (auto c = s->rr_cache.begin(); c != s->rr_cache.end();) {
             uint64_t h;
             memcpy(&h, c->first.data(), sizeof(h));
@@ -575,6 +780,22 @@ int pc_server_set_random(void *server, int32_t patch_id, const pc_catalog *rando
     p.handle = h;
     p.n = randoms->n;
     s->patches[patch_id] = p;
+    // requests of this patch still waiting for their first launch use the new
+    // catalogue; requests already counted in part keep the old one until they
+    // finish (it is released once nothing refers to it)
+    for (auto &q : s->queue) {
+        Request &r = *q;
+        if (r.patch != patch_id || r.started) continue;
+        r.random_handle = h;
+        r.n_random = p.n;
+        const double nn = static_cast<double>(r.n_points), nr = static_cast<double>(p.n);
+        r.pairs = 0.5 * nn * (nn - 1.0) + nn * nr;
+        r.rr_needed = true;
+        r.rr_done = 0;
+        std::fill(r.RR.begin(), r.RR.end(), 0ull);
+        s->prepare(r);
+    }
+    s->release_retired();
     return PC_OK;
 }
 
@@ -610,21 +831,32 @@ int pc_server_submit(void *server, const pc_catalog *data, int32_t patch_id, con
             memcpy(r->dec.data(), data->dec_deg, sizeof(double) * n);
         }
     }
-    r->need_bytes = 128ull * std::max<size_t>(n, 1) + (1u << 20);
     r->n_points = static_cast<int64_t>(n);
+    r->DD.assign(static_cast<size_t>(n_edges) + 1, 0);
+    r->DR.assign(static_cast<size_t>(n_edges) + 1, 0);
+    r->RR.assign(static_cast<size_t>(n_edges) + 1, 0);
     std::lock_guard<std::mutex> lk(s->mu);
     auto pit = s->patches.find(patch_id);
     if (pit == s->patches.end()) return fail(PC_ERR_INVALID, "no random catalogue registered for this patch");
+    if (static_cast<int>(s->queue.size()) >= s->cfg.max_queue) return fail(PC_ERR_BUSY, "server queue is full");
+    r->n_random = pit->second.n;
+    r->random_handle = pit->second.handle;
     const double nn = static_cast<double>(n), nr = static_cast<double>(pit->second.n);
     r->pairs = 0.5 * nn * (nn - 1.0) + nn * nr;
-    if (static_cast<int>(s->queue.size()) >= s->cfg.max_queue) return fail(PC_ERR_BUSY, "server queue is full");
+    auto cached = s->rr_cache.find(rr_key(r->random_handle, r->edges));
+    if (cached != s->rr_cache.end()) {
+        r->RR = cached->second;
+        r->rr_needed = false;
+    }
+    // the first part and the device bytes its launch needs (host-only plan)
+    s->prepare(*r);
     r->id = s->next_id++;
     r->t_submit = Clock::now();
     s->jobs.emplace(r->id, r);
     s->queue.push_back(r);
     ++s->n_submitted;
     *job_id = r->id;
-    s->cv_work.notify_one();
+    s->cv_work.notify_all();
     return PC_OK;
 }
 
@@ -639,7 +871,7 @@ int pc_server_poll(void *server, uint64_t job_id, int32_t *done, uint64_t *DD, u
         auto it = s->jobs.find(job_id);
         if (it == s->jobs.end()) return fail(PC_ERR_INVALID, "unknown job id");
         Request &q = *it->second;
-        if (!q.done && !q.running && s->cfg.deadline_s > 0 &&
+        if (!q.done && !q.running && !q.started && s->cfg.deadline_s > 0 &&
             std::chrono::duration<double>(Clock::now() - q.t_submit).count() > s->cfg.deadline_s) {
             auto pos = std::find(s->queue.begin(), s->queue.end(), it->second);
             if (pos != s->queue.end()) {
@@ -730,7 +962,8 @@ const char *pc_server_stats(void *server) {
       << ", \"p99_s\": " << pct(0.99) << ", \"max_s\": " << (l.empty() ? 0.0 : l.back())
       << ", \"rr_cached\": " << s->rr_cache.size() << ", \"streams\": " << s->cfg.streams
       << ", \"cancelled\": " << s->n_cancelled << ", \"expired\": " << s->n_expired
-      << ", \"max_concurrent_batches\": " << s->max_running_batches << "}";
+      << ", \"max_concurrent_batches\": " << s->max_running_batches << ", \"parts_requeued\": " << s->n_requeued
+      << ", \"split_batches\": " << s->n_split_batches << ", \"slice_pairs\": " << s->cfg.slice_pairs << "}";
     buf = o.str();
     return buf.c_str();
 }
@@ -756,6 +989,57 @@ int pc_server_destroy(void *server) {
     for (uint64_t h : s->retired) release_catalog(h);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
     delete s;
+    return PC_OK;
+}
+
+int pc_debug_request_parts(int64_t n_points, int64_t n_random, int32_t n_edges, int32_t count_rr,
+                           double slice_pairs, int32_t max_parts, int64_t *rows, uint64_t *need_bytes,
+                           int32_t *n_parts) {
+    clear_error();
+    if (!n_parts || (max_parts > 0 && (!rows || !need_bytes))) return fail(PC_ERR_INVALID, "NULL argument");
+    if (n_points < 0 || n_random < 0 || n_edges < 2 || n_edges > kMaxEdges || !(slice_pairs >= 0))
+        return fail(PC_ERR_INVALID, "bad sizes");
+    Request r;
+    r.n_points = n_points;
+    r.n_random = n_random;
+    r.random_handle = 1;  // a catalogue described by its size only
+    r.rr_needed = count_rr != 0;
+    r.edges.resize(static_cast<size_t>(n_edges));
+    for (int32_t k = 0; k < n_edges; ++k) r.edges[k] = 0.01 * std::pow(1000.0, k / double(n_edges - 1));
+    const std::map<uint64_t, int64_t> sizes{{1, n_random}};
+    int32_t np = 0;
+    while (true) {
+        double pairs = 0;
+        const Part p = next_part(r, slice_pairs, &pairs);
+        if (np < max_parts) {
+            uint64_t b = 0;
+            const int rc = part_need_bytes(r, p, PC_MIXED, &sizes, &b);
+            if (rc) return rc;
+            rows[4 * np + 0] = p.a;
+            rows[4 * np + 1] = p.b;
+            rows[4 * np + 2] = p.c;
+            rows[4 * np + 3] = p.d;
+            need_bytes[np] = b;
+        }
+        ++np;
+        r.data_done = p.b;
+        if (p.c < p.d) r.rr_done = p.d;
+        if (r.data_done >= n_points && (!r.rr_needed || r.rr_done >= n_random)) break;
+        if (np > (1 << 24)) return fail(PC_ERR_INVALID, "too many parts");
+    }
+    *n_parts = np;
+    return PC_OK;
+}
+
+int pc_debug_server_hold(void *server, int32_t hold) {
+    clear_error();
+    auto *s = static_cast<Server *>(server);
+    if (!s) return fail(PC_ERR_INVALID, "server is NULL");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->hold = hold != 0;
+    }
+    s->cv_work.notify_all();
     return PC_OK;
 }
 

@@ -1,7 +1,10 @@
 // pc_tune.cpp -- launch-parameter tuning for batches of a given shape.
 //
 // The counting launch has parameters that change its speed but not its counts:
-// the mixed kernel's histogram lane columns (LDS per wave, hence waves per CU,
+// the tile size (the size of the paper's submatrices, Sec. 2.1: 128 or 256
+// points; smaller tiles bound sparse catalogues more tightly, so more tile
+// pairs are binned whole or against fewer edges, at more work items), the
+// mixed kernel's histogram lane columns (LDS per wave, hence waves per CU,
 // and lanes sharing a counter word), how many work items a wave takes from the
 // queue at a time, and whether far tile pairs go through the matrix cores.
 // pc_autotune times every candidate on the caller's own batch, checks that
@@ -12,6 +15,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <chrono>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -82,10 +86,10 @@ bool to_int(const std::string &s, int *v) {
 std::string entry_json(const TuneKey &k, const TuneEntry &e) {
     char buf[512];
     snprintf(buf, sizeof(buf),
-             "{\"device\": \"%s\", \"edges_class\": %d, \"pairs_class\": %d, \"cols\": %d, \"chunk\": %d, "
-             "\"matrix_cores\": %d, \"kernel_ms\": %.4f}",
-             k.device.c_str(), k.edges_class, k.pairs_class, e.tune.cols, e.tune.chunk, e.tune.matrix_cores ? 1 : 0,
-             e.kernel_ms);
+             "{\"device\": \"%s\", \"edges_class\": %d, \"pairs_class\": %d, \"tile\": %d, \"cols\": %d, "
+             "\"chunk\": %d, \"matrix_cores\": %d, \"kernel_ms\": %.4f, \"launch_ms\": %.4f}",
+             k.device.c_str(), k.edges_class, k.pairs_class, e.tune.tile, e.tune.cols, e.tune.chunk,
+             e.tune.matrix_cores ? 1 : 0, e.kernel_ms, e.launch_ms);
     return buf;
 }
 
@@ -151,9 +155,13 @@ int parse_file(const char *path, std::map<TuneKey, TuneEntry> *out) {
         ok = ok && field(line, "chunk", &v) && to_int(v, &e.tune.chunk);
         ok = ok && field(line, "matrix_cores", &v) && to_int(v, &mc);
         if (ok && field(line, "kernel_ms", &v)) e.kernel_ms = atof(v.c_str());
+        if (ok && field(line, "launch_ms", &v)) e.launch_ms = atof(v.c_str());
+        // entries written before the tile size was tuned mean 256-point tiles
+        if (ok && field(line, "tile", &v)) ok = to_int(v, &e.tune.tile) && (e.tune.tile == 128 || e.tune.tile == 256);
         const bool cols_ok = e.tune.cols == 0 || (e.tune.cols >= 8 && e.tune.cols <= 64 &&
                                                   (e.tune.cols & (e.tune.cols - 1)) == 0);
-        if (!ok || !cols_ok || e.tune.chunk < 1 || e.tune.chunk > 64 || (mc != 0 && mc != 1))
+        if (!ok || !cols_ok || e.tune.chunk < 1 || e.tune.chunk > 64 || (mc != 0 && mc != 1) ||
+            (mc && e.tune.tile != 256))
             return fail(PC_ERR_INVALID, std::string("bad tuning entry in ") + path + ": " + line);
         e.tune.matrix_cores = mc != 0;
         got[k] = e;
@@ -214,17 +222,17 @@ extern "C" int pc_autotune(const pc_job *jobs, int32_t n_jobs, int32_t mode, con
     const bool mixed = (mode & ~PC_NO_PRUNE) == PC_MIXED;
     const bool prune = (mode & PC_NO_PRUNE) == 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    std::vector<LaunchTune> cands;
-    for (int mc = 0; mc <= ((mixed && prune) ? 1 : 0); ++mc)
-        for (int cols : {8, 16, 32})
-            for (int chunk : {2, 4, 8}) {
-                if (!mixed && cols != 8) continue;  // the binary64 kernel's columns are fixed
-                LaunchTune t;
-                t.cols = mixed ? cols : 0;
-                t.chunk = chunk;
-                t.matrix_cores = mc != 0;
-                cands.push_back(t);
-            }
+    // Two stages.  The tile size changes the prune pass and the ordering too
+    // (four times as many tile pairs at 128 points, each tighter), so it is
+    // chosen first on the whole launch's time with the other parameters at
+    // their defaults; then the histogram columns, the queue chunk and (256-point
+    // tiles) the matrix-core path on the counting kernel's time at that size.
+    std::vector<LaunchTune> stage1;
+    for (int tile : {256, 128}) {
+        LaunchTune t;
+        t.tile = tile;
+        stage1.push_back(t);
+    }
     // every candidate counts into its own buffers; the first is the reference
     std::vector<std::vector<uint64_t>> ref(v.size()), cur(v.size());
     std::vector<BatchJob> w = v;
@@ -240,29 +248,66 @@ extern "C" int pc_autotune(const pc_job *jobs, int32_t n_jobs, int32_t mode, con
     } reset{was_timing};
     // one untimed run first (code objects, tables)
     for (size_t q = 0; q < v.size(); ++q) w[q].counts = ref[q].data();
-    rc = run_batch(w, mode, st, nullptr, &cands[0]);
+    rc = run_batch(w, mode, st, nullptr, &stage1[0]);
     if (rc) return rc;
-    int best = -1;
-    double best_ms = 0.0;
-    for (size_t c = 0; c < cands.size(); ++c) {
+    size_t n_cands = 0;
+    // times each candidate (counting kernel, whole launch on the host's
+    // clock) and checks its counts against the reference
+    auto run = [&](const LaunchTune &t, double *kernel_ms, double *launch_ms) -> int {
         for (size_t q = 0; q < v.size(); ++q) w[q].counts = cur[q].data();
         BatchStats bs;
-        rc = run_batch(w, mode, st, &bs, &cands[c]);
-        if (rc) return rc;
+        const auto t0 = std::chrono::steady_clock::now();
+        const int r = run_batch(w, mode, st, &bs, &t);
+        if (r) return r;
+        *launch_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *kernel_ms = bs.kernel_ms >= 0.0 ? bs.kernel_ms : 0.0;
+        ++n_cands;
         for (size_t q = 0; q < v.size(); ++q)
             if (cur[q] != ref[q])
-                return fail(PC_ERR_DEVICE, "tuning candidates disagree on the counts (cols " +
-                                               std::to_string(cands[c].cols) + ", chunk " +
-                                               std::to_string(cands[c].chunk) + ")");
-        const double ms = bs.kernel_ms >= 0.0 ? bs.kernel_ms : 0.0;
-        if (best < 0 || ms < best_ms) {
+                return fail(PC_ERR_DEVICE, "tuning candidates disagree on the counts (tile " + std::to_string(t.tile) +
+                                               ", cols " + std::to_string(t.cols) + ", chunk " +
+                                               std::to_string(t.chunk) + ")");
+        return PC_OK;
+    };
+    int tile = 256;
+    double best_launch = 0.0;
+    for (const LaunchTune &t : stage1) {
+        double kms = 0, lms = 0;
+        rc = run(t, &kms, &lms);
+        if (rc) return rc;
+        if (t.tile == stage1[0].tile || lms < best_launch) {
+            tile = t.tile;
+            best_launch = lms;
+        }
+    }
+    std::vector<LaunchTune> cands;
+    for (int mc = 0; mc <= ((mixed && prune && tile == 256) ? 1 : 0); ++mc)
+        for (int cols : {8, 16, 32})
+            for (int chunk : {2, 4, 8}) {
+                if (!mixed && cols != 8) continue;  // the binary64 kernel's columns are fixed
+                LaunchTune t;
+                t.tile = tile;
+                t.cols = mixed ? cols : 0;
+                t.chunk = chunk;
+                t.matrix_cores = mc != 0;
+                cands.push_back(t);
+            }
+    int best = -1;
+    double best_ms = 0.0, best_lms = 0.0;
+    for (size_t c = 0; c < cands.size(); ++c) {
+        double kms = 0, lms = 0;
+        rc = run(cands[c], &kms, &lms);
+        if (rc) return rc;
+        if (best < 0 || kms < best_ms) {
             best = static_cast<int>(c);
-            best_ms = ms;
+            best_ms = kms;
+            best_lms = lms;
         }
     }
     TuneEntry e;
     e.tune = cands[static_cast<size_t>(best)];
     e.kernel_ms = best_ms;
+    e.launch_ms = best_lms;
     const TuneKey key = tune_key_of(v);
     tune_store(key, e);
     if (cache_path) {
@@ -273,7 +318,7 @@ extern "C" int pc_autotune(const pc_job *jobs, int32_t n_jobs, int32_t mode, con
     if (result && result_len > 0) {
         std::string j = entry_json(key, e);
         j.pop_back();
-        j += ", \"candidates\": " + std::to_string(cands.size()) + "}";
+        j += ", \"candidates\": " + std::to_string(n_cands) + "}";
         snprintf(result, static_cast<size_t>(result_len), "%s", j.c_str());
     }
     return PC_OK;

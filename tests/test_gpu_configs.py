@@ -1,6 +1,7 @@
 """GPU parity on the shapes of the batched-covariance and large full-sky
 configurations (reduced sizes the oracle finishes in seconds), plus the
 isotropic closed form on the device."""
+import json
 import math
 
 import numpy as np
@@ -96,8 +97,10 @@ def test_autotune_chooses_a_configuration_and_tuned_runs_are_exact(tmp_path):
     jobs = [{"A": D, "edges": e}, {"A": D, "B": R, "edges": e, "auto": False}, {"A": R, "edges": e}]
     cache = tmp_path / "tune.jsonl"
     counts, cfg = pc.pc_autotune(jobs, cache_path=cache)
-    assert cfg["cols"] in (8, 16, 32) and cfg["chunk"] in (2, 4, 8) and cfg["candidates"] == 18
-    assert cfg["kernel_ms"] > 0
+    # tile size first (two candidates), then columns x chunk (x matrix cores at 256-point tiles)
+    assert cfg["tile"] in (128, 256) and cfg["cols"] in (8, 16, 32) and cfg["chunk"] in (2, 4, 8)
+    assert cfg["candidates"] == (20 if cfg["tile"] == 256 else 11)
+    assert cfg["kernel_ms"] > 0 and cfg["launch_ms"] > 0
     want = [oracle.count(c["D"], e), oracle.count(c["D"], e, B=c["R"], auto=False), oracle.count(c["R"], e)]
     for got, w in zip(counts, want):
         assert got.tolist() == w.tolist()
@@ -105,9 +108,40 @@ def test_autotune_chooses_a_configuration_and_tuned_runs_are_exact(tmp_path):
     for got, w in zip(tuned, want):
         assert got.tolist() == w.tolist()
     lines = [l for l in cache.read_text().splitlines() if l.strip()]
-    assert len(lines) == 1 and '"cols": %d' % cfg["cols"] in lines[0]
+    assert len(lines) == 1 and '"cols": %d' % cfg["cols"] in lines[0] and '"tile": %d' % cfg["tile"] in lines[0]
     pc.pc_autotune_load(cache)
-    # the binary64 kernel tunes its chunk only
+    # the binary64 kernel tunes its tile size and chunk only
     counts64, cfg64 = pc.pc_autotune(jobs[:1], mode=pc.PC_FP64_PLAIN)
-    assert cfg64["candidates"] == 3 and counts64[0].tolist() == want[0].tolist()
+    assert cfg64["candidates"] == 5 and counts64[0].tolist() == want[0].tolist()
+
+
+def test_tuned_tile_size_from_a_cache_file(tmp_path):
+    """A tuning entry that chose 128-point tiles, loaded from its file, makes
+    PC_TUNED launches of that shape use them (pruning figures change, counts
+    do not); an entry naming another size is refused."""
+    c = synth.config_small(scale=0.4)
+    D, R, e = dev(c["D"]), dev(c["R"]), c["edges"]
+    jobs = [{"A": D, "edges": e}, {"A": D, "B": R, "edges": e, "auto": False}, {"A": R, "edges": e}]
+    _, cfg = pc.pc_autotune(jobs)
+    cache = tmp_path / "tune.jsonl"
+    entry = dict(cfg)
+    entry.pop("candidates")
+    entry["matrix_cores"] = 0          # the matrix-core path needs 256-point tiles
+    for tile in (128, 256):
+        entry["tile"] = tile
+        cache.write_text(json.dumps(entry) + "\n")
+        pc.pc_autotune_load(cache)
+        got = pc.pc_count_batch(jobs, mode=pc.PC_MIXED | pc.PC_TUNED)
+        items = pc.pc_debug_last_launch()["items"]
+        want = [oracle.count(c["D"], e), oracle.count(c["D"], e, B=c["R"], auto=False), oracle.count(c["R"], e)]
+        for g, w in zip(got, want):
+            assert g.tolist() == w.tolist(), tile
+        if tile == 128:
+            items128 = items
+        else:
+            assert items128 > 3 * items          # four times the tile pairs (ragged ends aside)
+    entry["tile"] = 64
+    cache.write_text(json.dumps(entry) + "\n")
+    with pytest.raises(pc.PcError):
+        pc.pc_autotune_load(cache)
 

@@ -453,3 +453,118 @@ def test_seeded_random_batches(seed):
     got = pc.pc_count_batch(jobs, mode=mode)
     for k, (g, w) in enumerate(zip(got, want)):
         assert g.tolist() == w.tolist(), (seed, k)
+
+
+@pytest.mark.parametrize("mode", MODES + [pc.PC_MIXED | pc.PC_NO_PRUNE])
+def test_histogram_flushed_every_few_items(mode):
+    """The wrap guard's flush (LDS uint32 histogram -> uint64 counts before a
+    word could wrap, Sec. 2.1 per-block histograms) normally fires every ~10^6
+    items; lowered to 1, 2 and 3 items through the debug hook, each wave
+    flushes between most of its ~tens of items.  Counts equal the oracle."""
+    c = synth.config_small(scale=6.0)   # 60,000 + 60,000 on the 10 x 10 deg patch: most tile pairs survive
+    D, R, e = c["D"], c["R"], c["edges"]
+    Dd, Rd = dev(D), dev(R)
+    jobs = [{"A": Dd, "edges": e}, {"A": Dd, "B": Rd, "edges": e, "auto": False}, {"A": Rd, "edges": e}]
+    want = [oracle.count(D, e), oracle.count(D, e, B=R, auto=False), oracle.count(R, e)]
+    try:
+        for every in (1, 2, 3):
+            pc.pc_debug_set_flush_every(every)
+            got = pc.pc_count_batch(jobs, mode=mode)
+            launch = pc.pc_debug_last_launch()
+            work = pc.pc_debug_last_pruning()["survivors"] if not mode & pc.PC_NO_PRUNE else launch["items"]
+            assert work >= 4 * launch["grid"], (work, launch)     # several items per wave
+            for g, w in zip(got, want):
+                assert g.tolist() == w.tolist(), every
+    finally:
+        pc.pc_debug_set_flush_every(0)
+    for g, w in zip(pc.pc_count_batch(jobs, mode=mode), want):
+        assert g.tolist() == w.tolist()
+
+
+def test_allocation_failures_report_nomem_leave_outputs_untouched_and_recover():
+    """Device allocations made to fail from the host (workspace, edge-set
+    table, resident catalogue, aperture work space): each call reports
+    PC_ERR_NOMEM, writes nothing, and the next call works; a hundred failed
+    calls leave device memory where it was."""
+    c = synth.config_small(scale=0.1)
+    D, e = dev(c["D"]), c["edges"]
+    want = pc.pc_count(D, e)                       # the edge set's table is cached from here on
+    assert want.tolist() == oracle.count(c["D"], e).tolist()
+    a = pc.as_catalog(D)
+    sentinel = np.uint64(0xDEADBEEFCAFE)
+    counts = np.full(e.size + 1, sentinel, dtype=np.uint64)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    try:
+        for _ in range(100):
+            pc.pc_debug_fail_allocations(1)
+            rc = pc.lib().pc_count(a.ref(), None, e.ctypes.data, e.size, 1, counts.ctypes.data, None)
+            assert rc == pc.PC_ERR_NOMEM, rc
+            assert "out of memory" in pc.pc_last_error()
+            assert np.all(counts == sentinel)
+        torch.cuda.synchronize()
+        assert abs(torch.cuda.mem_get_info()[0] - free0) < (64 << 20)
+        assert pc.pc_count(D, e).tolist() == want.tolist()
+        # a new edge set: its table's allocation fails, then the call works
+        e2 = synth.linear_edges(0.0, 7.5, 17)
+        pc.pc_debug_fail_allocations(1)
+        with pytest.raises(pc.PcError) as ex:
+            pc.pc_count(D, e2)
+        assert ex.value.code == pc.PC_ERR_NOMEM
+        assert pc.pc_count(D, e2).tolist() == oracle.count(c["D"], e2).tolist()
+        # a resident catalogue
+        pc.pc_debug_fail_allocations(1)
+        with pytest.raises(pc.PcError) as ex:
+            pc.pc_catalog_upload(D)
+        assert ex.value.code == pc.PC_ERR_NOMEM
+        h = pc.pc_catalog_upload(D)
+        assert pc.pc_count_h(h, e).tolist() == want.tolist()
+        pc.pc_catalog_release(h)
+        # the aperture-mass map's work space
+        cat, side = synth.shear_catalog(2000, config=23)
+        pc.pc_debug_fail_allocations(1)
+        with pytest.raises(pc.PcError) as ex:
+            pc.pc_aperture_mass(cat, (0.0, 0.0, side / 8, side / 8, 8, 8), 2.0, 35.0)
+        assert ex.value.code == pc.PC_ERR_NOMEM
+        assert pc.pc_aperture_mass(cat, (0.0, 0.0, side / 8, side / 8, 8, 8), 2.0, 35.0)["n_in"].size == 64
+    finally:
+        pc.pc_debug_fail_allocations(0)
+
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_128_point_tiles_match_the_oracle(mode):
+    """The counting path compiled for 128-point tiles (the tuner's other
+    submatrix size, Sec. 2.1): the small configuration's DD, DR and RR, ragged
+    sizes, row ranges and a resident catalogue (re-ordered for the smaller
+    tiles) equal the oracle; its pruning and sub-block paths are exercised."""
+    try:
+        pc.pc_debug_set_tile(128)
+        c = synth.config_small(scale=0.3)
+        D, R, e = c["D"], c["R"], c["edges"]
+        got = pc.pc_count_batch([{"A": dev(D), "edges": e}, {"A": dev(D), "B": dev(R), "edges": e, "auto": False},
+                                 {"A": dev(R), "edges": e}], mode=mode)
+        want = [oracle.count(D, e), oracle.count(D, e, B=R, auto=False), oracle.count(R, e)]
+        for g, w in zip(got, want):
+            assert g.tolist() == w.tolist()
+        if mode == pc.PC_MIXED:
+            st = pc.pc_debug_last_pruning()
+            assert st["split_items"] > 0 and st["few_items"] > 0
+        rng = np.random.default_rng(55)
+        patch = synth.centred_patch(12.0)
+        e2 = synth.log_edges(0.05, 8.0, 12)
+        for n in (1, 2, 127, 128, 129, 255, 257, 1000):
+            A = synth.uniform_patch(n, patch, rng)
+            assert pc.pc_count_ex(dev(A), e2, mode=mode).tolist() == oracle.count(A, e2).tolist(), n
+            B = synth.uniform_patch(n * 3 % 200 + 1, patch, rng)
+            assert pc.pc_count_ex(dev(A), e2, B=dev(B), auto=False, mode=mode).tolist() == \
+                oracle.count(A, e2, B=B, auto=False).tolist(), n
+        for rows in [(0, 1), (129, 1000), (1777, D[0].size)]:
+            assert pc.pc_count_ex(dev(D), e, rows=rows, mode=mode).tolist() == oracle.count(D, e, rows=rows).tolist()
+        h = pc.pc_catalog_upload(dev(D))
+        try:
+            assert pc.pc_count_h(h, e, mode=mode).tolist() == want[0].tolist()
+        finally:
+            pc.pc_catalog_release(h)
+    finally:
+        pc.pc_debug_set_tile(0)

@@ -156,12 +156,23 @@ def test_cancel_queued_running_and_finished_requests():
 
 
 def test_queueing_deadline_fails_requests_that_wait_too_long():
+    # request a is admitted and held from the host before its launch (a debug
+    # gate), so b waits behind it for as long as the test says, whatever the
+    # kernel's duration on this device
     R, big, (s1, _), e = _big_and_small(42)
-    srv = pc.Server({"streams": 1, "max_inflight": 1, "deadline_s": 0.01})
+    srv = pc.Server({"streams": 1, "max_inflight": 1, "deadline_s": 0.5})
     try:
         srv.set_random(0, R)
+        srv.hold(True)
         a = srv.submit(big, 0, e)
-        b = srv.submit(s1, 0, e)        # waits for a (tens of ms) and expires
+        t0 = time.time()
+        while srv.stats()["inflight"] == 0:
+            assert time.time() - t0 < 0.4, "request a was not admitted"
+            time.sleep(0.001)
+        b = srv.submit(s1, 0, e)        # no slot while a holds it
+        time.sleep(0.8)
+        assert srv.stats()["queued"] == 1
+        srv.hold(False)
         srv.drain()
         assert srv.poll(a)["DD"].sum() == big[0].size * (big[0].size - 1) // 2
         with pytest.raises(pc.PcError) as ex:
@@ -253,3 +264,31 @@ def test_destroy_drops_waiting_requests_and_returns():
     t0 = time.perf_counter()
     srv.close()
     assert time.perf_counter() - t0 < 30.0
+
+
+def test_large_request_runs_in_parts_small_ones_finish_first():
+    """A request of ~2e12 pairs with a slice of 2e11 runs as ~10 row-range
+    parts in successive launches (counts over disjoint rows add up exactly,
+    Sec. 2.1); a small request submitted after it joins an early launch and
+    finishes first.  Both answers equal the same requests counted alone."""
+    R, big, (s1, _), e = _big_and_small(44)
+    srv = pc.Server({"streams": 1, "slice_pairs": 2e11})
+    try:
+        srv.set_random(0, R)
+        a = srv.submit(big, 0, e)
+        b = srv.submit(s1, 0, e)
+        srv.drain()
+        st = srv.stats()
+        assert st["completed"] == 2 and st["failed"] == 0
+        assert st["parts_requeued"] >= 6 and st["batches"] >= 7, st
+        ra, rb = srv.poll(a), srv.poll(b)
+        for res, cat in ((ra, big), (rb, s1)):
+            dd, dr, rr = _alone(cat, R, e)
+            assert res["DD"].tolist() == dd.tolist() and res["DR"].tolist() == dr.tolist()
+            assert res["RR"].tolist() == rr.tolist()
+            w = pc.pc_wtheta(dd[1:-1], dr[1:-1], rr[1:-1], cat[0].size, R[0].size)
+            assert np.array_equal(res["w"], w, equal_nan=True)
+        assert rb["DR"].tolist() == oracle.count(s1, e, B=R, auto=False).tolist()
+        assert rb["latency_s"] < ra["latency_s"]
+    finally:
+        srv.close()

@@ -214,3 +214,61 @@ def test_fake_executor_smallest_first_serves_everyone():
     fifo, _ = _simulate(list(zip(t, need, pairs)), 64 * GB, 288 * GB, {**cfg, "policy": 0})
     fifo_waits = np.array([fifo[i][0] - t[i] for i in range(n)])
     assert np.median(waits) <= np.median(fifo_waits) + 1e-12
+
+
+# ------------------------------------------------------ parts and their sizes
+
+def _pairs(n, a, b):
+    """DD pairs of rows [a, b) of an n-point catalogue (i < j, i in range)."""
+    k = b - a
+    return k * (n - 1 - a) - k * (k - 1) // 2
+
+
+def test_large_requests_run_as_row_range_parts_that_cover_every_pair():
+    """A 2M-point request on a 1M-random patch, with RR to count, cut into
+    parts of about 5e11 pairs: data rows then random rows, contiguous and
+    disjoint (so the parts' counts add up to the whole, Sec. 2.1), each part
+    at most one row past the slice."""
+    n, nr, slice_pairs = 2_000_000, 1_000_000, 5e11
+    parts = pc.pc_debug_request_parts(n, nr, 41, True, slice_pairs)
+    data = [p["rows"] for p in parts if p["rows"][0] < p["rows"][1]]
+    rr = [p["rr_rows"] for p in parts if p["rr_rows"][0] < p["rr_rows"][1]]
+    assert data[0][0] == 0 and data[-1][1] == n
+    assert all(x[1] == y[0] for x, y in zip(data, data[1:]))
+    assert rr[0][0] == 0 and rr[-1][1] == nr
+    assert all(x[1] == y[0] for x, y in zip(rr, rr[1:]))
+    total = n * (n - 1) // 2 + n * nr + nr * (nr - 1) // 2
+    got = sum(_pairs(n, a, b) + (b - a) * nr for a, b in data) + sum(_pairs(nr, c, d) for c, d in rr)
+    assert got == total
+    for a, b in data:
+        row = (n - 1 - a) + nr          # the first row is the largest
+        assert _pairs(n, a, b) + (b - a) * nr < slice_pairs + row
+    assert len(parts) >= total / (slice_pairs + n + nr)
+    # RR already cached: no random rows; slicing off: one part with everything
+    assert all(p["rr_rows"][0] == p["rr_rows"][1] for p in pc.pc_debug_request_parts(n, nr, 41, False))
+    one = pc.pc_debug_request_parts(n, nr, 41, True, 0)
+    assert len(one) == 1 and one[0]["rows"] == (0, n) and one[0]["rr_rows"] == (0, nr)
+
+
+def test_admission_need_counts_the_launch_workspace():
+    """The bytes admission reserves for a request come from the batch
+    runner's own plan: converted and ordered copies (~100 B per point), plus
+    16 bytes per pair of 256-point tiles for the survivor lists -- for a
+    2M-point request against 1M randoms with RR, over 1.2 GB in one part, so
+    a 1 GB budget window holds it back while its 5e11-pair parts fit."""
+    n, nr = 2_000_000, 1_000_000
+    T, TR = -(-n // 256), -(-nr // 256)
+    items = T * (T + 1) // 2 + T * TR + TR * (TR + 1) // 2
+    whole = pc.pc_debug_request_parts(n, nr, 41, True, 0)[0]["need_bytes"]
+    assert whole >= 16 * items + 100 * n
+    assert whole > 1.2e9
+    parts = pc.pc_debug_request_parts(n, nr, 41, True, 5e11)
+    worst = max(p["need_bytes"] for p in parts)
+    assert worst < whole
+    avail_gb = 4 + 1.0                       # budget 4 GB + a 1 GB window
+    assert plan([whole / GB], free_gb=avail_gb) == [W]
+    assert plan([worst / GB], free_gb=avail_gb) == [A] or worst > GB
+    # a small request's need is small
+    small = pc.pc_debug_request_parts(5_000, nr, 20, False)[0]["need_bytes"]
+    assert small < 40e6
+
