@@ -140,6 +140,30 @@ typedef struct {
 int pc_count_batch(const pc_job *jobs, int32_t n_jobs, int32_t mode, void *stream);
 
 /*
+ * pc_bin_edges -- theta edges from the paper's binning presets (Sec. 2.1: the
+ * histogram's low and high limits and one of three preset bin widths),
+ * host only; the counting calls take the edges it writes.
+ *   preset      PC_BINS_EVEN (equal widths in theta), PC_BINS_LN (in ln theta)
+ *               or PC_BINS_LOG10 (in log10 theta; the same edges as PC_BINS_LN
+ *               for the same number of bins, up to rounding).
+ *   lo_deg, hi_deg  0 <= lo < hi <= 180 degrees (lo > 0 for the log presets);
+ *               the first and last edges are exactly lo and hi.
+ *   n_bins      > 0: that many bins of equal width in the preset's scale;
+ *               0: bins of `width` (in the preset's scale: degrees, natural
+ *               log or decades), the last one narrower when the range is not a
+ *               whole number of widths.
+ *   edges       host array of max_edges doubles, written with the n_edges
+ *               edges (may be NULL to ask only for *n_edges).
+ *   n_edges     written: number of edges (bins + 1, at most 1024).
+ * In the preset's scale F: edge k = F^-1(F(lo) + k w) in binary64 (libm),
+ * k = 1 .. n-1.  PC_ERR_INVALID for bad limits, a bad preset or width, more
+ * than 1023 bins, or a buffer that is too small.
+ */
+enum pc_bin_preset { PC_BINS_EVEN = 0, PC_BINS_LN = 1, PC_BINS_LOG10 = 2 };
+int pc_bin_edges(int32_t preset, double lo_deg, double hi_deg, int32_t n_bins, double width, int32_t max_edges,
+                 double *edges, int32_t *n_edges);
+
+/*
  * pc_wtheta -- Landy-Szalay estimator (Eq. 2) from in-range bin counts.
  *   DD, DR, RR   host arrays of n_bins uint64 (pass counts + 1 of pc_count).
  *   nD, nR       catalogue sizes, each >= 2.

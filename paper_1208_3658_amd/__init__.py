@@ -72,6 +72,8 @@ _SIGNATURES = {
     "pc_count_ex": ([_PCAT, _PCAT, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp], ctypes.c_int),
     "pc_count_batch": ([ctypes.POINTER(pc_job), _i32, _i32, _vp], ctypes.c_int),
     "pc_wtheta": ([_vp, _vp, _vp, _i32, _i64, _i64, _vp], ctypes.c_int),
+    "pc_bin_edges": ([_i32, ctypes.c_double, ctypes.c_double, _i32, ctypes.c_double, _i32, _vp,
+                      ctypes.POINTER(_i32)], ctypes.c_int),
     "pc_last_error": ([], ctypes.c_char_p),
     "pc_version": ([], ctypes.c_char_p),
     "pc_catalog_upload": ([_PCAT, _vp, ctypes.POINTER(_u64)], ctypes.c_int),
@@ -293,6 +295,22 @@ def pc_count_batch(jobs, mode: int = PC_MIXED, stream=None):
         outs.append(out)
     _check(lib().pc_count_batch(arr, len(jobs), int(mode), _stream(stream)))
     return outs
+
+
+PC_BINS_EVEN, PC_BINS_LN, PC_BINS_LOG10 = 0, 1, 2
+
+
+def pc_bin_edges(preset: int, lo_deg: float, hi_deg: float, n_bins: int = 0, width: float = 0.0) -> np.ndarray:
+    """Theta edges (degrees) from the paper's binning presets: limits lo, hi
+    and evenly spaced, natural-log or log10 bins, given as a number of bins
+    or as a width in the preset's scale (include/pc.h)."""
+    n = _i32(0)
+    _check(lib().pc_bin_edges(int(preset), float(lo_deg), float(hi_deg), int(n_bins), float(width), 0, None,
+                              ctypes.byref(n)))
+    e = np.empty(n.value, dtype=np.float64)
+    _check(lib().pc_bin_edges(int(preset), float(lo_deg), float(hi_deg), int(n_bins), float(width), e.size,
+                              e.ctypes.data, ctypes.byref(n)))
+    return e
 
 
 def pc_wtheta(DD, DR, RR, nD: int, nR: int) -> np.ndarray:

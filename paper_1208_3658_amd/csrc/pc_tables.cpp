@@ -33,9 +33,12 @@
 #include <algorithm>
 #include <cmath>
 #include <limits>
+#include <string>
+#include <vector>
 
 #include "pc_internal.hpp"
 #include "pc_math.h"
+#include "pc_runtime.hpp"
 
 namespace pc {
 
@@ -336,3 +339,54 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
 }
 
 }  // namespace pc
+
+// ------------------------------------------------------------- bin presets
+//
+// The paper's three preset bin widths (Sec. 2.1: the user sets the low and
+// high limits of the histogram and picks evenly spaced, natural-log or
+// base-10-log bins).  In the preset's scale F (theta, ln theta, log10 theta)
+// the edges are F^-1(F(lo) + k w) for k = 0 .. n-1, then hi exactly, with w
+// = (F(hi) - F(lo)) / n_bins, or the given width and n = ceil((F(hi) -
+// F(lo)) / width) (the last bin narrower when the range is not a whole
+// number of widths).  Equal widths in ln and in log10 give the same edges
+// (up to rounding): the two presets differ in the units of the width.
+extern "C" int pc_bin_edges(int32_t preset, double lo_deg, double hi_deg, int32_t n_bins, double width,
+                            int32_t max_edges, double *edges, int32_t *n_edges) {
+    pc::clear_error();
+    if (!n_edges) return pc::fail(PC_ERR_INVALID, "n_edges is NULL");
+    if (preset < PC_BINS_EVEN || preset > PC_BINS_LOG10) return pc::fail(PC_ERR_INVALID, "unknown bin preset");
+    if (!std::isfinite(lo_deg) || !std::isfinite(hi_deg) || !(lo_deg < hi_deg) || lo_deg < 0.0 || hi_deg > 180.0)
+        return pc::fail(PC_ERR_INVALID, "need 0 <= lo < hi <= 180 degrees");
+    if (preset != PC_BINS_EVEN && !(lo_deg > 0.0))
+        return pc::fail(PC_ERR_INVALID, "logarithmic bins need lo > 0");
+    auto F = [&](double x) { return preset == PC_BINS_EVEN ? x : preset == PC_BINS_LN ? std::log(x) : std::log10(x); };
+    auto Finv = [&](double y) {
+        return preset == PC_BINS_EVEN ? y : preset == PC_BINS_LN ? std::exp(y) : std::pow(10.0, y);
+    };
+    const double f0 = F(lo_deg), f1 = F(hi_deg), span = f1 - f0;
+    double w = 0.0;
+    int64_t n = 0;
+    if (n_bins > 0) {
+        n = n_bins;
+        w = span / static_cast<double>(n);
+    } else {
+        if (!(width > 0.0) || !std::isfinite(width)) return pc::fail(PC_ERR_INVALID, "need n_bins > 0 or width > 0");
+        const double q = span / width;
+        n = static_cast<int64_t>(std::ceil(q * (1.0 - 1e-12)));
+        if (n < 1) n = 1;
+        if (q > 1e7) return pc::fail(PC_ERR_INVALID, "more than 1023 bins");
+        w = width;
+    }
+    if (n + 1 > pc::kMaxEdges) return pc::fail(PC_ERR_INVALID, "more than 1023 bins");
+    std::vector<double> e(static_cast<size_t>(n) + 1);
+    e[0] = lo_deg;
+    for (int64_t k = 1; k < n; ++k) e[static_cast<size_t>(k)] = Finv(f0 + static_cast<double>(k) * w);
+    e[static_cast<size_t>(n)] = hi_deg;
+    std::string err;
+    if (!pc::validate_edges(e.data(), static_cast<int>(e.size()), err))
+        return pc::fail(PC_ERR_INVALID, "preset gives unusable edges: " + err);
+    *n_edges = static_cast<int32_t>(e.size());
+    if (edges && max_edges >= static_cast<int32_t>(e.size())) memcpy(edges, e.data(), sizeof(double) * e.size());
+    else if (edges) return pc::fail(PC_ERR_INVALID, "edges buffer holds fewer than n_edges values");
+    return PC_OK;
+}

@@ -422,3 +422,33 @@ def test_aperture_filter_table_matches_the_definition():
     # away from the steep part the error is a few binary32 ulps of Q
     flat = (x > 0.1) & (x < 0.85)
     assert np.all(err[flat] <= 8 * 2.0 ** -24 * np.maximum(ref[flat], 1e-3))
+
+
+def test_bin_presets():
+    """The paper's presets (Sec. 2.1): limits and evenly spaced, natural-log or
+    log10 bins, by count or by width in the preset's scale."""
+    e = pc.pc_bin_edges(pc.PC_BINS_LN, 0.01, 20.0, n_bins=40)
+    assert e.size == 41 and e[0] == 0.01 and e[-1] == 20.0
+    assert np.allclose(e, synth.log_edges(0.01, 20.0, 40), rtol=1e-14, atol=0)
+    assert np.all(np.diff(np.log(e)) > 0) and np.allclose(np.diff(np.log(e)), np.log(2000.0) / 40, rtol=1e-9)
+    # equal steps in log10 theta give the same edges as in ln theta
+    assert np.allclose(pc.pc_bin_edges(pc.PC_BINS_LOG10, 0.01, 20.0, n_bins=40), e, rtol=1e-14, atol=0)
+    # by width: a decade split in 0.1-decade bins; ln widths; even widths, last bin narrower
+    d = pc.pc_bin_edges(pc.PC_BINS_LOG10, 0.1, 10.0, width=0.1)
+    assert d.size == 21 and np.allclose(np.log10(d), np.linspace(-1, 1, 21), atol=1e-14)
+    assert pc.pc_bin_edges(pc.PC_BINS_LN, 0.1, 10.0, width=np.log(10.0) / 10).size == 21
+    lin = pc.pc_bin_edges(pc.PC_BINS_EVEN, 0.0, 30.0, width=0.6)
+    assert lin.size == 51 and np.allclose(lin, synth.linear_edges(0.0, 30.0, 50), rtol=0, atol=1e-12)
+    odd = pc.pc_bin_edges(pc.PC_BINS_EVEN, 0.0, 1.0, width=0.3)
+    assert odd.tolist() == [0.0, 0.3, 0.6, 0.8999999999999999, 1.0] or odd.tolist() == [0.0, 0.3, 0.6, 0.9, 1.0]
+    # the edges are usable as they are
+    assert pc.pc_chord2_edges(e).size == 41
+    for bad in [dict(preset=pc.PC_BINS_LN, lo_deg=0.0, hi_deg=1.0, n_bins=4),
+                dict(preset=pc.PC_BINS_EVEN, lo_deg=2.0, hi_deg=1.0, n_bins=4),
+                dict(preset=pc.PC_BINS_EVEN, lo_deg=0.0, hi_deg=181.0, n_bins=4),
+                dict(preset=pc.PC_BINS_EVEN, lo_deg=0.0, hi_deg=10.0, n_bins=2000),
+                dict(preset=pc.PC_BINS_EVEN, lo_deg=0.0, hi_deg=10.0),
+                dict(preset=7, lo_deg=0.0, hi_deg=10.0, n_bins=4)]:
+        with pytest.raises(pc.PcError) as ex:
+            pc.pc_bin_edges(**bad)
+        assert ex.value.code == pc.PC_ERR_INVALID
