@@ -696,10 +696,10 @@ void Server::worker(int k) {
         std::string err;
         std::vector<int> rcs(batch.size(), launch_parts(batch, st, &err));
         std::vector<std::string> errs(batch.size(), err);
-        if (rcs[0] == PC_ERR_NOMEM && batch.size() > 1) {
+        const bool split_up = rcs[0] == PC_ERR_NOMEM && batch.size() > 1;
+        if (split_up) {
             // the device had less memory than admission saw: the requests
             // run one launch each rather than fail together
-            ++n_split_batches;
             for (size_t q = 0; q < batch.size(); ++q) {
                 errs[q].clear();
                 rcs[q] = launch_parts({batch[q]}, st, &errs[q]);
@@ -709,6 +709,7 @@ void Server::worker(int k) {
         {
             std::lock_guard<std::mutex> lk(mu);
             for (size_t q = 0; q < batch.size(); ++q) finish_part(*batch[q], rcs[q], errs[q]);
+            if (split_up) ++n_split_batches;
             reserved -= bytes;
             --running_batches;
             ++n_batches;
