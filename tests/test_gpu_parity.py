@@ -548,8 +548,18 @@ def test_128_point_tiles_match_the_oracle(mode):
         for g, w in zip(got, want):
             assert g.tolist() == w.tolist()
         if mode == pc.PC_MIXED:
+            assert pc.pc_debug_last_pruning()["split_items"] > 0
+        # two compact clusters 15 deg apart with sparse edges: tile pairs
+        # across them meet one or two edges (few-edge and Gram-form units)
+        rng = np.random.default_rng(34)
+        n = 1280
+        F = (np.concatenate([100 + 0.5 * rng.standard_normal(n), 100 + 0.5 * rng.standard_normal(n)]),
+             np.concatenate([0.5 * rng.standard_normal(n), 15 + 0.5 * rng.standard_normal(n)]))
+        ef = np.array([0.01, 1.0, 5.0, 12.0, 15.0, 30.0])
+        assert pc.pc_count_ex(dev(F), ef, mode=mode).tolist() == oracle.count(F, ef).tolist()
+        if mode == pc.PC_MIXED:
             st = pc.pc_debug_last_pruning()
-            assert st["split_items"] > 0 and st["few_items"] > 0
+            assert st["few_items"] > 0 and st["gram_items"] > 0
         rng = np.random.default_rng(55)
         patch = synth.centred_patch(12.0)
         e2 = synth.log_edges(0.05, 8.0, 12)
