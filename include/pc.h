@@ -312,9 +312,18 @@ int pc_guard_band(const double *theta_edges_deg, int32_t n_edges, float *lo, flo
  * of "hbm_budget_bytes" (the key still wins).
  * Admission (policy 0) is first come, first served: requests enter in submission order
  * while max_inflight, the free device memory minus the budget and the bytes
- * held by running batches (128 bytes per point + 1 MiB each), and
- * max_batch_pairs per launch allow.  A request that could not fit even on an
- * empty device fails with PC_ERR_NOMEM.
+ * held by running batches, and max_batch_pairs per launch allow.  A request
+ * (or its next part) reserves the device work area its launch needs as the
+ * batch runner plans it on the host -- converted and ordered copies, sort
+ * scratch, 16 bytes per tile pair of survivor lists, results -- plus 1 MiB
+ * for tables and descriptors.  A request that could not fit even on an empty
+ * device fails with PC_ERR_NOMEM; a launch of several requests that still
+ * runs out of device memory is retried one request per launch.
+ *   "slice_pairs"       requests of more pairs than this (DD + DR + RR) run
+ *                       as row-range parts of about this many pairs, one per
+ *                       launch, between other requests (default 5e11; 0:
+ *                       whole requests).  Counts add up exactly over the
+ *                       parts (the paper's submatrices, Sec. 2.1).
  */
 int pc_server_create(const char *json_cfg, void **server);
 
