@@ -140,6 +140,31 @@ typedef struct {
 int pc_count_batch(const pc_job *jobs, int32_t n_jobs, int32_t mode, void *stream);
 
 /*
+ * pc_count_batch_static -- pc_count_batch without any device allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * kernels and counts as pc_count_batch.  Every device buffer of the call --
+ * converted and spatially ordered catalogue copies, sort scratch, survivor
+ * lists, descriptors, edge-set tables, results -- is placed in one fixed
+ * device array of PC_STATIC_SCRATCH_BYTES bytes that the library holds on each
+ * GPU it has run this call on, from the first such call until the process
+ * ends.  Host catalogues are copied into that array as well.
+ *   Limit: a batch whose work area exceeds PC_STATIC_SCRATCH_BYTES returns
+ *   PC_ERR_INVALID with the needed size in pc_last_error(), before anything
+ *   is launched (roughly: about 200 bytes per point of every distinct
+ *   catalogue plus 16 bytes per pair of 256-point tiles; e.g. DD, DR and RR
+ *   of 2 x 300,000 points fit).
+ *   Sharing: all calls on one GPU use that GPU's array, which keeps the last
+ *   call's contents (each call clears what it needs cleared).  Calls from one
+ *   process are serialised by a per-device lock; calls of different processes,
+ *   or graph replays of a captured call, that overlap on one GPU race on the
+ *   array and must be ordered by the caller.
+ *   PC_TUNED is honoured; the counting kernel is not timed by HIP events here.
+ */
+#define PC_STATIC_SCRATCH_BYTES (256ull * 1024ull * 1024ull)
+int pc_count_batch_static(const pc_job *jobs, int32_t n_jobs, int32_t mode, void *stream);
+
+/*
  * pc_bin_edges -- theta edges from the paper's binning presets (Sec. 2.1: the
  * histogram's low and high limits and one of three preset bin widths),
  * host only; the counting calls take the edges it writes.

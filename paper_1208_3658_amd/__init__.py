@@ -71,6 +71,7 @@ _SIGNATURES = {
     "pc_count": ([_PCAT, _PCAT, _vp, _i32, _i32, _vp, _vp], ctypes.c_int),
     "pc_count_ex": ([_PCAT, _PCAT, _vp, _i32, _i32, _i32, _i64, _i64, _vp, _vp], ctypes.c_int),
     "pc_count_batch": ([ctypes.POINTER(pc_job), _i32, _i32, _vp], ctypes.c_int),
+    "pc_count_batch_static": ([ctypes.POINTER(pc_job), _i32, _i32, _vp], ctypes.c_int),
     "pc_wtheta": ([_vp, _vp, _vp, _i32, _i64, _i64, _vp], ctypes.c_int),
     "pc_bin_edges": ([_i32, ctypes.c_double, ctypes.c_double, _i32, ctypes.c_double, _i32, _vp,
                       ctypes.POINTER(_i32)], ctypes.c_int),
@@ -294,6 +295,19 @@ def pc_count_batch(jobs, mode: int = PC_MIXED, stream=None):
                         1 if auto else 0, int(r0), int(r1), out.ctypes.data)
         outs.append(out)
     _check(lib().pc_count_batch(arr, len(jobs), int(mode), _stream(stream)))
+    return outs
+
+
+PC_STATIC_SCRATCH_BYTES = 256 * 1024 * 1024
+
+
+def pc_count_batch_static(jobs, mode: int = PC_MIXED, stream=None):
+    """pc_count_batch in the library's fixed device work area of
+    PC_STATIC_SCRATCH_BYTES (no device allocation by the library; calls on
+    one GPU share that area).  Same jobs, same counts."""
+    keep = []
+    arr, outs = _job_array(jobs, keep)
+    _check(lib().pc_count_batch_static(arr, len(jobs), int(mode), _stream(stream)))
     return outs
 
 

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpc.so")
 SOURCES = ["pc_kernels.hip", "pc_prep.hip", "pc_api.cpp", "pc_tables.cpp", "pc_estimator.cpp", "pc_serve.cpp",
-           "pc_tune.cpp", "pc_aperture.hip", "pc_kernels_t128.hip", "pc_prep_t128.hip"]
+           "pc_tune.cpp", "pc_aperture.hip", "pc_kernels_t128.hip", "pc_prep_t128.hip", "pc_static.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
