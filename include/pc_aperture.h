@@ -21,13 +21,15 @@
  * theta_max and the grid (arcmin in the paper's workload); n_gal is the
  * galaxy number density per unit area of that unit.
  *
- * Precision.  The aperture cut is a decision and is taken exactly as the
- * binary64 definition takes it: dx = x_i - x_p, dy = y_i - y_p and
+ * Precision.  The aperture cut is a decision and gives exactly the result
+ * of the binary64 definition: dx = x_i - x_p, dy = y_i - y_p and
  * |d|^2 = dx*dx + dy*dy in binary64 without fused multiply-add, grid point
  * (ix, iy) at (x0 + ix*dx_grid, y0 + iy*dy_grid) likewise, galaxy in iff
- * 0 < |d|^2 < theta_max^2 (binary64).  n_in is therefore exact.  The filter
- * and the tangential term are evaluated in binary32 from dx, dy rounded to
- * binary32 and summed in binary32 over at most 64 galaxies, then in
+ * 0 < |d|^2 < theta_max^2 (binary64).  The library decides it from a
+ * binary32 |d|^2 wherever a proven error bound allows and from the binary64
+ * definition otherwise, so n_in is exact.  The filter and the tangential term
+ * are evaluated in binary32 from offsets to a reference point of the point's
+ * block of the grid and summed in binary32 over at most 64 galaxies, then in
  * binary64: map and snr agree with the binary64 definition to within
  * 1e-4 * sum_i Q(x_i)|eps_i| / n_gal (map) and the corresponding bound on
  * snr; the exact form of the bound is in the library's design notes.
@@ -83,8 +85,9 @@ typedef struct {
  *
  * Blocks until the outputs are written.  Errors: PC_ERR_INVALID for a NULL
  * or malformed argument, a non-finite coordinate or ellipticity (device
- * catalogues are checked on the device before any output is written), or
- * sizes out of range; PC_ERR_NOMEM when the work space (about 80 bytes per
+ * catalogues are checked on the device before any output is written), sizes
+ * out of range, or a grid whose extent plus 2 theta_max reaches 1e15 units
+ * along either axis; PC_ERR_NOMEM when the work space (about 80 bytes per
  * galaxy plus 4-8 bytes per cell of the search lattice, plus 20 bytes per
  * grid point for host outputs) cannot be allocated; PC_ERR_DEVICE for HIP
  * failures.  Outputs are untouched on error.
@@ -111,6 +114,16 @@ int pc_debug_last_aperture(double *kernel_ms, uint64_t *pairs_tested, uint64_t *
  * NULL arrays with n > 0 or n < 0.
  */
 int pc_debug_ap_filter(const double *x, int64_t n, double *q);
+
+/*
+ * pc_debug_ap_points_per_lane -- points = 1 or 2: the calling thread's later
+ * pc_aperture_mass calls give each GPU lane points x points grid points (a
+ * wave a block of 8 x 8 or 16 x 16 points); 0 restores the choice the call
+ * makes itself (2 when a 16 x 16 block spans at most a quarter of theta_max).
+ * Same results within the stated tolerance, n_in identical.  For testing both
+ * kernel instances on one input.  PC_ERR_INVALID for other values.
+ */
+int pc_debug_ap_points_per_lane(int32_t points);
 
 #ifdef __cplusplus
 }

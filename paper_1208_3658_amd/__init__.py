@@ -62,6 +62,7 @@ _SIGNATURES = {
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p],
                          ctypes.c_int),
     "pc_debug_ap_filter": ([_vp, _i64, _vp], ctypes.c_int),
+    "pc_debug_ap_points_per_lane": ([_i32], ctypes.c_int),
     "pc_debug_last_aperture": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "pc_debug_admission_plan": ([_vp, _vp, _vp, _i32, _u64, _u64, _u64, _i32, ctypes.c_char_p, _vp],
@@ -522,6 +523,12 @@ def pc_debug_ap_filter(x) -> np.ndarray:
     q = np.empty(x.size, dtype=np.float64)
     _check(lib().pc_debug_ap_filter(x.ctypes.data, x.size, q.ctypes.data))
     return q
+
+
+def pc_debug_ap_points_per_lane(points: int):
+    """Force 1 or 2 grid points per lane along each axis in this thread's
+    aperture-mass calls (0: the call's own choice)."""
+    _check(lib().pc_debug_ap_points_per_lane(int(points)))
 
 
 def pc_debug_last_aperture() -> dict:

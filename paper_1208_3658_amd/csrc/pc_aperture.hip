@@ -44,21 +44,21 @@ size_t scan_sums_words(int64_t m);
 
 namespace {
 
-constexpr int kApSide = 8;             // grid points per wave along each axis
 constexpr int kApWaves = 4;            // waves per workgroup: 2 x 2 blocks sharing one filter table
-constexpr int kApGroupSide = 2 * kApSide;
 constexpr int kQCells = 1024;          // filter table cells over x in [0, 1]
 constexpr int kApFlush = 64;           // galaxies summed in binary32 before the binary64 add
 constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 constexpr int64_t kMaxCells = int64_t(1) << 22;
+constexpr double kMaxExtent = 1e15;     // lattice extent limit (binary32 offsets stay finite)
+thread_local int t_ap_force_p = 0;      // points per lane forced for testing (0: chosen per launch)
 
 // One galaxy as the map kernel reads it (32 bytes, one scalar load).
 struct alignas(32) ApGal {
     double x, y;  // position
     float a;      // -e1
-    float b;      // -2 e2
+    float a2;     // 2 e1
+    float b2;     // -2 e2
     float ee;     // e1^2 + e2^2 (binary64, rounded once)
-    float pad;
 };
 
 // Square search lattice: cell (cx, cy) covers [ox + cx s, ox + (cx+1) s) x ...
@@ -80,6 +80,10 @@ struct ApParams {
     double reach;     // theta with a relative margin for the cell search
     float k_s;        // table position s = r k_s = kQCells x, x = r / theta
     float s_max;      // largest binary32 below kQCells (r rounded up to theta)
+    float r2f;        // theta^2 rounded to binary32: the provisional cut
+    float r2f_below;  // the largest binary32 below r2f
+    float band;       // |f2 - r2f| <= band: the binary32 |d|^2 cannot decide the cut
+    float near0;      // f2 <= near0: a galaxy near the point, decided and weighted in binary64
     double n_gal;
     double *map;
     double *snr;
@@ -149,9 +153,9 @@ __global__ void __launch_bounds__(256) k_ap_place(const double *__restrict__ X, 
     g.x = X[i];
     g.y = Y[i];
     g.a = static_cast<float>(-e1);
-    g.b = static_cast<float>(-2.0 * e2);
+    g.a2 = static_cast<float>(2.0 * e1);
+    g.b2 = static_cast<float>(-2.0 * e2);
     g.ee = static_cast<float>(e1 * e1 + e2 * e2);
-    g.pad = 0.0f;
     gal[lo + rank] = g;
 }
 
@@ -163,9 +167,9 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
-// Filter constants held in VGPRs (an instruction reads at most one SGPR).
+// Constants held in VGPRs (an instruction reads at most one SGPR).
 struct ApConsts {
-    float k_s, s_max;
+    float k_s, s_max, r2f, r2f_below, band, near0;
     uint32_t tab;  // LDS byte address of the filter table
 };
 
@@ -180,67 +184,85 @@ __device__ __forceinline__ float q_table(float s, uint32_t tab) {
     return fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
 }
 
-// One (grid point, galaxy) pair: the exact cut, then Eq. 4 from the table and
-// the tangential ellipticity, accumulated into the binary32 partial sums.
-__device__ __forceinline__ void ap_pair(const ApGal &G, double xg, double yg, double r2, const ApConsts &K,
-                                        uint32_t &cnt, float &a1, float &a2) {
-    const double ddx = G.x - xg;
-    const double ddy = G.y - yg;
-    const double d2 = ddx * ddx + ddy * ddy;
-    if (d2 < r2 && d2 > 0.0) {
-        cnt += 1u;
-        const float fx = static_cast<float>(ddx), fy = static_cast<float>(ddy);
-        // |d|^2 > 0 can still round below the smallest normal binary32 value;
-        // raised to it, r stays finite (the direction of such a pair, within
-        // 1e-19 of the point, is then not resolved in binary32)
-        const float f2 = fmaxf(static_cast<float>(d2), FLT_MIN);
-        const float rinv = __builtin_amdgcn_rsqf(f2);
-        const float r = f2 * rinv;
-        const float q = q_table(fminf(r * K.k_s, K.s_max), K.tab);
-        // cos 2phi and sin 2phi from the unit direction
-        const float ux = fx * rinv, uy = fy * rinv;
-        const float c2 = fmaf(-uy, uy, ux * ux);
-        const float s2 = ux * uy;
-        const float et = fmaf(G.a, c2, G.b * s2);
-        a1 = fmaf(q, et, a1);
-        a2 = fmaf(q * q, G.ee, a2);
-    }
-}
-
-// One wave per 8 x 8 block of grid points, four waves (2 x 2 blocks) per
-// workgroup sharing the filter table in LDS.  Groups are dealt to the eight
-// XCDs in contiguous strips (the hardware assigns workgroup b to XCD b mod 8),
-// so neighbouring blocks, which read mostly the same galaxies, share an L2.
-__global__ void __launch_bounds__(64 * kApWaves) k_ap_map(const ApParams p) {
+// One wave owns a block of (8P) x (8P) grid points: lane (lx, ly) = (lane % 8,
+// lane / 8) holds the P x P points (lx + 8a, ly + 8b), so every galaxy read
+// (wave-uniform, scalar loads) is used for P^2 independent pairs per lane.
+// Four waves (2 x 2 blocks) per workgroup share the filter table in LDS.
+// Groups are dealt to the eight XCDs in contiguous strips (the hardware
+// assigns workgroup b to XCD b mod 8), so neighbouring blocks, which read
+// mostly the same galaxies, share an L2.
+//
+// Per pair, in binary32: the galaxy and the point relative to a reference
+// point of the block (the galaxy's offset is formed once per galaxy in
+// binary64 and rounded), dx, dy and f2 = dx^2 + dy^2.  The cut is decided
+// from f2 against theta^2 wherever a proven bound on |f2 - |d|^2| (host code
+// below, `cut_bands`) allows it; pairs with f2 within `band` of theta^2 are
+// decided by the binary64 definition, so the set of galaxies in each aperture
+// is exact.  A galaxy very near its point (f2 <= near0) is decided by the
+// binary64 definition too and, when inside, weighted from its binary64 offset:
+// the binary32 offsets, good to a few units in the last place of the block's
+// size, would not resolve its direction.  For the other pairs inside: x =
+// |d| / theta_max from one reciprocal square root, the filter from the table,
+// and
+//   eps_t = -(e1 cos 2phi + e2 sin 2phi) = -e1 + (2 / f2) (e1 dy^2 - e2 dx dy)
+// (cos 2phi = 1 - 2 dy^2 / f2, sin 2phi = 2 dx dy / f2); the products
+// Q eps_t and Q^2 |eps|^2 are summed in binary32 over at most 64 galaxies and
+// then in binary64.
+template <int P>
+__global__ void __launch_bounds__(64 * kApWaves) __attribute__((amdgpu_waves_per_eu(P == 2 ? 4 : 7)))
+k_ap_map(const ApParams p) {
+    constexpr int BS = 8 * P;   // block side in points
+    constexpr int K = P * P;    // points per lane
     __shared__ float4 qtab[kQCells];
     const int lane = static_cast<int>(threadIdx.x) & 63;
-    const int wave = static_cast<int>(threadIdx.x) >> 6;
+    // wave-uniform (a scalar register): the block, its galaxy ranges and the
+    // galaxy loop are the same for every lane of the wave
+    const int wave = static_cast<int>(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
     const int b = static_cast<int>(blockIdx.x);
     const int tile = (b & 7) * p.per_xcd + (b >> 3);
     if (tile >= p.n_tiles) return;  // the whole workgroup: before any barrier
     for (int k = static_cast<int>(threadIdx.x); k < kQCells; k += 64 * kApWaves) qtab[k] = p.qtab[k];
     __syncthreads();
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-    const int ix0 = tx * kApGroupSide + (wave & 1) * kApSide, iy0 = ty * kApGroupSide + (wave >> 1) * kApSide;
+    const int ix0 = tx * 2 * BS + (wave & 1) * BS, iy0 = ty * 2 * BS + (wave >> 1) * BS;
     // a block of the group past the grid's edge has no points
     if (ix0 >= p.nx || iy0 >= p.ny) return;
-    const int ix1 = min(ix0 + kApSide - 1, p.nx - 1), iy1 = min(iy0 + kApSide - 1, p.ny - 1);
-    const int ixl = ix0 + (lane & (kApSide - 1)), iyl = iy0 + lane / kApSide;
-    const bool valid = ixl <= ix1 && iyl <= iy1;
-    const int ix = min(ixl, ix1), iy = min(iyl, iy1);  // lanes past the grid edge repeat a point
-    const double xg = p.x0 + static_cast<double>(ix) * p.gdx;
-    const double yg = p.y0 + static_cast<double>(iy) * p.gdy;
+    const int ix1 = min(ix0 + BS - 1, p.nx - 1), iy1 = min(iy0 + BS - 1, p.ny - 1);
+    // the block's reference point: its centre (any binary64 value serves)
+    const double xb = p.x0 + (static_cast<double>(ix0) + 0.5 * (BS - 1)) * p.gdx;
+    const double yb = p.y0 + (static_cast<double>(iy0) + 0.5 * (BS - 1)) * p.gdy;
+    int ixk[K], iyk[K];
+    bool valid[K];
+    float Xg[K], Yg[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int ixl = ix0 + (lane & 7) + 8 * (k % P), iyl = iy0 + (lane >> 3) + 8 * (k / P);
+        valid[k] = ixl <= ix1 && iyl <= iy1;
+        ixk[k] = min(ixl, ix1);  // lanes past the grid edge repeat a point
+        iyk[k] = min(iyl, iy1);
+        // the grid point as the definition forms it (product, then sum)
+        const double xg = p.x0 + static_cast<double>(ixk[k]) * p.gdx;
+        const double yg = p.y0 + static_cast<double>(iyk[k]) * p.gdy;
+        Xg[k] = static_cast<float>(xg - xb);
+        Yg[k] = static_cast<float>(yg - yb);
+    }
     const double gxl = p.x0 + static_cast<double>(ix0) * p.gdx, gxh = p.x0 + static_cast<double>(ix1) * p.gdx;
     const double gyl = p.y0 + static_cast<double>(iy0) * p.gdy, gyh = p.y0 + static_cast<double>(iy1) * p.gdy;
     const Lattice L = p.lat;
-    ApConsts K{p.k_s, p.s_max,
+    ApConsts C{p.k_s, p.s_max, p.r2f, p.r2f_below, p.band, p.near0,
                static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
                    (__attribute__((address_space(3))) const float4 *)(qtab)))};
-    asm("" : "+v"(K.k_s), "+v"(K.s_max), "+v"(K.tab));
+    asm("" : "+v"(C.k_s), "+v"(C.s_max), "+v"(C.r2f), "+v"(C.r2f_below), "+v"(C.band), "+v"(C.near0), "+v"(C.tab));
     const double slack = L.s * 1e-9;  // covers rounding of the cell coordinates
 
-    double S1 = 0.0, S2 = 0.0;
-    uint32_t cnt = 0;
+    double S1[K], S2[K];
+    uint32_t cnt[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        S1[k] = 0.0;
+        S2[k] = 0.0;
+        cnt[k] = 0u;
+    }
     uint64_t tested = 0;
     const int cy0 = cell_index(gyl - p.reach - slack, L.oy, L.inv_s, L.ncy);
     const int cy1 = cell_index(gyh + p.reach + slack, L.oy, L.inv_s, L.ncy);
@@ -260,23 +282,116 @@ __global__ void __launch_bounds__(64 * kApWaves) k_ap_map(const ApParams p) {
         tested += g_end - g_begin;
         for (uint32_t c0 = g_begin; c0 < g_end; c0 += kApFlush) {
             const uint32_t c1 = min(c0 + static_cast<uint32_t>(kApFlush), g_end);
-            float a1 = 0.0f, a2 = 0.0f;
-            for (uint32_t g = c0; g < c1; ++g) ap_pair(p.gal[g], xg, yg, p.r2, K, cnt, a1, a2);
-            S1 += static_cast<double>(a1);
-            S2 += static_cast<double>(a2);
+            float a1[K], a2[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                a1[k] = 0.0f;
+                a2[k] = 0.0f;
+            }
+            // galaxies go through scalar registers, each loaded one galaxy
+            // ahead of its use
+            ApGal Gn = p.gal[c0];
+            for (uint32_t g = c0; g < c1; ++g) {
+                const ApGal G = Gn;
+                Gn = p.gal[min(g + 1u, c1 - 1u)];
+                const float X = static_cast<float>(G.x - xb), Y = static_cast<float>(G.y - yb);
+                float fdx[K], fdy[K], py[K], f2[K];
+                float near = FLT_MAX, low = FLT_MAX;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    fdx[k] = X - Xg[k];
+                    fdy[k] = Y - Yg[k];
+                    py[k] = fdy[k] * fdy[k];
+                    f2[k] = fmaf(fdx[k], fdx[k], py[k]);
+                    near = fminf(near, fabsf(f2[k] - C.r2f));
+                    low = fminf(low, f2[k]);
+                }
+                if (__builtin_expect(__builtin_amdgcn_ballot_w64(near <= C.band || low <= C.near0) != 0, 0)) {
+                    // rare: a pair of the wave that f2 cannot decide is
+                    // decided by the binary64 definition (0 < dx*dx + dy*dy <
+                    // theta^2, no fused multiply-add, grid point formed as
+                    // above) and its f2 moved to the matching side of r2f (by
+                    // at most `band`); a galaxy near its point, if inside, is
+                    // weighted here from its binary64 offset and left out of
+                    // the binary32 step below
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const double xg = p.x0 + static_cast<double>(ixk[k]) * p.gdx;
+                        const double yg = p.y0 + static_cast<double>(iyk[k]) * p.gdy;
+                        const double ddx = G.x - xg, ddy = G.y - yg;
+                        const double d2 = ddx * ddx + ddy * ddy;
+                        const bool inside = d2 < p.r2 && d2 > 0.0;
+                        const bool near_point = f2[k] <= C.near0;
+                        if (near_point && inside) {
+                            const double c2 = (ddx * ddx - ddy * ddy) / d2, s2 = (ddx * ddy) / d2;
+                            const float et = static_cast<float>(static_cast<double>(G.a) * c2 +
+                                                                static_cast<double>(G.b2) * s2);
+                            const float qn = q_table(fminf(static_cast<float>(sqrt(d2) * p.k_s), C.s_max), C.tab);
+                            a1[k] = fmaf(qn, et, a1[k]);
+                            a2[k] = fmaf(qn * qn, G.ee, a2[k]);
+                            cnt[k] += 1u;
+                        }
+                        const bool undecided = fabsf(f2[k] - C.r2f) <= C.band || near_point;
+                        const float moved = (inside && !near_point) ? fminf(f2[k], C.r2f_below) : fmaxf(f2[k], C.r2f);
+                        f2[k] = undecided ? moved : f2[k];
+                    }
+                }
+                // f2 raised to `near0` keeps every value below finite (a pair
+                // so raised is never inside here: see above)
+                float rinv[K], q[K];
+                uint32_t addr[K];
+                bool in[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    in[k] = f2[k] < C.r2f;
+                    cnt[k] += in[k] ? 1u : 0u;
+                    const float f2c = __builtin_amdgcn_fmed3f(f2[k], C.near0, FLT_MAX);
+                    rinv[k] = __builtin_amdgcn_rsqf(f2c);
+                    const float sk = fminf((f2c * rinv[k]) * C.k_s, C.s_max);
+                    addr[k] = C.tab + (static_cast<uint32_t>(sk) << 4);
+                    q[k] = __builtin_amdgcn_fractf(sk);  // position in the cell, for now
+                }
+                typedef float f32x4 __attribute__((ext_vector_type(4)));
+                using lds_f4 = __attribute__((address_space(3))) const f32x4;
+                f32x4 cq[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) cq[k] = *(lds_f4 *)(uintptr_t)(addr[k]);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const float t = q[k];
+                    float qk = fmaf(fmaf(fmaf(cq[k].w, t, cq[k].z), t, cq[k].y), t, cq[k].x);
+                    qk = in[k] ? qk : 0.0f;
+                    const float rr = rinv[k] * rinv[k];
+                    const float inner = fmaf(G.a2, py[k], G.b2 * (fdx[k] * fdy[k]));
+                    const float et = fmaf(rr, inner, G.a);
+                    a1[k] = fmaf(qk, et, a1[k]);
+                    a2[k] = fmaf(qk * qk, G.ee, a2[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                S1[k] += static_cast<double>(a1[k]);
+                S2[k] += static_cast<double>(a2[k]);
+            }
         }
     }
-    if (valid) {
-        const int64_t o = static_cast<int64_t>(iy) * p.nx + ix;
-        p.map[o] = S1 / p.n_gal;
-        if (p.snr) p.snr[o] = S2 > 0.0 ? (1.4142135623730951 * S1) / sqrt(S2) : __builtin_nan("");
-        if (p.n_in) p.n_in[o] = cnt;
+    uint32_t in_lane = 0, lanes = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (valid[k]) {
+            const int64_t o = static_cast<int64_t>(iyk[k]) * p.nx + ixk[k];
+            p.map[o] = S1[k] / p.n_gal;
+            if (p.snr) p.snr[o] = S2[k] > 0.0 ? (1.4142135623730951 * S1[k]) / sqrt(S2[k]) : __builtin_nan("");
+            if (p.n_in) p.n_in[o] = cnt[k];
+            in_lane += cnt[k];
+            lanes += 1u;
+        }
     }
     if (p.stats) {
-        const uint32_t in_wave = wave_sum_u32(valid ? cnt : 0u);
-        const uint32_t lanes = wave_sum_u32(valid ? 1u : 0u);
+        const uint32_t in_wave = wave_sum_u32(in_lane);
+        const uint32_t pts = wave_sum_u32(lanes);
         if (lane == 0) {
-            atomicAdd(p.stats + 0, static_cast<unsigned long long>(tested) * lanes);
+            atomicAdd(p.stats + 0, static_cast<unsigned long long>(tested) * pts);
             atomicAdd(p.stats + 1, static_cast<unsigned long long>(in_wave));
         }
     }
@@ -394,6 +509,11 @@ int check_args(const pc_shear_catalog *cat, const pc_grid *grid, double theta_ma
 int make_lattice(const pc_grid *g, double theta, Lattice *L) {
     const double span_x = (g->nx - 1) * g->dx + 2.0 * theta;
     const double span_y = (g->ny - 1) * g->dy + 2.0 * theta;
+    // every galaxy the map kernel looks at lies in the lattice, so its
+    // binary32 offsets from a block (at most the lattice's extent) stay
+    // finite, and so do their squares
+    if (!(span_x < kMaxExtent && span_y < kMaxExtent))
+        return fail(PC_ERR_INVALID, "grid extent plus twice theta_max must be below 1e15 units");
     double s = theta / 16.0;
     for (int it = 0; it < 200; ++it) {
         const double cx = std::ceil(span_x / s) + 3.0, cy = std::ceil(span_y / s) + 3.0;
@@ -411,10 +531,83 @@ int make_lattice(const pc_grid *g, double theta, Lattice *L) {
     return fail(PC_ERR_INVALID, "grid extent too large for the search lattice");
 }
 
+// Grid points per lane along each axis (blocks of 8P x 8P points per wave):
+// 2 when the 16 x 16 block is small beside the filter disc (a quarter of its
+// radius), so that the extra galaxies visited by the larger block stay few;
+// else 1.
+int points_per_lane(const pc_grid *g, double theta) {
+    if (t_ap_force_p == 1 || t_ap_force_p == 2) return t_ap_force_p;
+    return 16.0 * std::max(g->dx, g->dy) <= 0.25 * theta ? 2 : 1;
+}
+
+// The binary32 cut and its guard bands.  Notation: u = 2^-24, v = 2^-53;
+// (xb, yb) a block's reference point, every point of the block within hx
+// (hy) of it; D = |d| exactly, DX = x_i - x_p exactly.  The kernel forms
+//   X = RN32(RN64(x_i - xb)), Xg = RN32(RN64(x_p - xb)), fdx = RN32(X - Xg)
+// (likewise in y), py = RN32(fdy^2), f2 = RN32(fdx^2 + py) (one fused
+// multiply-add).  |x_i - xb| <= D + hx, so |X - Xg - DX| <= u1 (D + 2 hx)
+// with u1 = u + 2v, and
+//   |fdx - DX| <= ex = c1 D + cx,  c1 = u1 (1 + u) + u,  cx = 2 u1 (1 + u) hx,
+//   |f2 - D^2| <= B(D) = 2 D (ex + ey) + ex^2 + ey^2 + w (D + ex + ey)^2,
+// w = u (2 + u): a quadratic a D^2 + b D + c with non-negative coefficients.
+// The binary64 definition d2 = RN64(RN64(ddx^2) + RN64(ddy^2)), ddx =
+// RN64(DX), is within 4.0001 v D^2 of D^2, and r2f = RN32(r2) within u r2 of
+// r2 = RN64(theta^2).  Then
+//   * d2 < r2 gives D < theta (1 + 3v) and f2 <= D^2 + B(D) < r2f + G with
+//     G = (u + 8v) r2 + B(theta (1 + 1e-6));
+//   * d2 >= r2 gives D >= theta0 = theta (1 - 3v) and f2 >= D^2 - B(D); when
+//     D^2 - B(D) is increasing from theta0 on (2 (1 - a) theta0 >= b), f2 >
+//     r2f - G;
+//   * d2 = 0 needs ddx = ddy = 0 up to underflow, D below 1e-161, and then f2
+//     <= B(D), about c;
+//   * the offset (fdx, fdy) is within e(D) = sqrt(ex^2 + ey^2) <= e0 + sqrt(2)
+//     c1 D of (DX, DY), e0 = sqrt(cx^2 + cy^2), so its direction is within
+//     about e(D) / D radians: at most 2^-17 + 2 c1 once D >= Dn = 2^17 e0, and
+//     cos 2phi, sin 2phi within twice that, a relative 3e-5 of |eps| in eps_t.
+// So with band >= G, |f2 - r2f| > band decides the cut as the definition
+// does; near0 >= Dn^2 + B(Dn) (and >= 2c) catches every pair with D <= Dn,
+// among them every pair with d2 = 0.  Both are doubled, raised by 2^-100
+// (absolute: it also covers binary32 results below the normal range) and
+// rounded up to binary32.  hx includes the binary64 rounding of the grid
+// points and of the reference point.  Where the increasing condition fails
+// (grid spacing beyond ~1e6 theta), band is made large enough that every pair
+// with f2 below r2f + band is decided in binary64.
+void cut_bands(const pc_grid *g, double theta, double r2, int P, float *r2f, float *band, float *near0) {
+    const double u = std::ldexp(1.0, -24), v = std::ldexp(1.0, -53), u1 = u + 2.0 * v, w = u * (2.0 + u);
+    const double ext_x = std::fabs(g->x0) + (g->nx + 8.0 * P) * g->dx;
+    const double ext_y = std::fabs(g->y0) + (g->ny + 8.0 * P) * g->dy;
+    const double hx = 4.0 * P * g->dx + 8.0 * v * ext_x, hy = 4.0 * P * g->dy + 8.0 * v * ext_y;
+    const double c1 = u1 * (1.0 + u) + u, cx = 2.0 * u1 * (1.0 + u) * hx, cy = 2.0 * u1 * (1.0 + u) * hy;
+    const double qa = 4.0 * c1 + 2.0 * c1 * c1 + w * (1.0 + 2.0 * c1) * (1.0 + 2.0 * c1);
+    const double qb = 2.0 * (cx + cy) * (1.0 + c1 + w * (1.0 + 2.0 * c1));
+    const double qc = cx * cx + cy * cy + w * (cx + cy) * (cx + cy);
+    auto B = [&](double D) { return (qa * D + qb) * D + qc; };
+    const double floor_abs = std::ldexp(1.0, -100);
+    const double theta0 = theta * (1.0 - 3.0 * v);
+    double G = (u + 8.0 * v) * r2 + B(theta * (1.0 + 1e-6));
+    if (!(2.0 * (1.0 - qa) * theta0 >= qb)) G = std::max(G, 4.0 * r2);
+    auto up = [](double x) {
+        float f = static_cast<float>(x);
+        if (static_cast<double>(f) < x) f = std::nextafter(f, FLT_MAX);
+        return f;
+    };
+    *r2f = static_cast<float>(r2);
+    *band = up(2.0 * G + floor_abs);
+    const double dn = std::ldexp(std::sqrt(cx * cx + cy * cy), 17);
+    *near0 = up(2.0 * std::max(dn * dn + B(dn), B(1e-150)) + floor_abs);
+}
+
 }  // namespace
 }  // namespace pc
 
 using namespace pc;
+
+extern "C" int pc_debug_ap_points_per_lane(int32_t points) {
+    clear_error();
+    if (points < 0 || points > 2) return fail(PC_ERR_INVALID, "points per lane must be 0 (automatic), 1 or 2");
+    t_ap_force_p = points;
+    return PC_OK;
+}
 
 extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid, double theta_max, double n_gal,
                                 double *map, double *snr, uint32_t *n_in, int32_t out_on_device, void *stream) {
@@ -520,8 +713,10 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     p.gdy = grid->dy;
     p.nx = grid->nx;
     p.ny = grid->ny;
-    p.tiles_x = (grid->nx + kApGroupSide - 1) / kApGroupSide;
-    const int tiles_y = (grid->ny + kApGroupSide - 1) / kApGroupSide;
+    const int P = points_per_lane(grid, theta_max);
+    const int group_side = 16 * P;  // 2 x 2 blocks of 8P x 8P points
+    p.tiles_x = (grid->nx + group_side - 1) / group_side;
+    const int tiles_y = (grid->ny + group_side - 1) / group_side;
     p.n_tiles = p.tiles_x * tiles_y;
     p.per_xcd = (p.n_tiles + 7) / 8;
     p.theta = theta_max;
@@ -529,6 +724,8 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     p.reach = theta_max * (1.0 + 1e-9);
     p.k_s = static_cast<float>(static_cast<double>(kQCells) / theta_max);
     p.s_max = std::nextafter(static_cast<float>(kQCells), 0.0f);
+    cut_bands(grid, theta_max, p.r2, P, &p.r2f, &p.band, &p.near0);
+    p.r2f_below = std::nextafter(p.r2f, 0.0f);
     p.qtab = qtab;
     p.n_gal = n_gal;
     p.map = d_map;
@@ -543,7 +740,10 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
         AP_HIP(hipEventCreate(&ev.b), "hipEventCreate");
         AP_HIP(hipEventRecord(ev.a, st), "hipEventRecord");
     }
-    k_ap_map<<<dim3(static_cast<uint32_t>(8 * p.per_xcd)), dim3(64 * kApWaves), 0, st>>>(p);
+    if (P == 2)
+        k_ap_map<2><<<dim3(static_cast<uint32_t>(8 * p.per_xcd)), dim3(64 * kApWaves), 0, st>>>(p);
+    else
+        k_ap_map<1><<<dim3(static_cast<uint32_t>(8 * p.per_xcd)), dim3(64 * kApWaves), 0, st>>>(p);
     AP_HIP(hipGetLastError(), "k_ap_map");
     if (timing) AP_HIP(hipEventRecord(ev.b, st), "hipEventRecord");
 

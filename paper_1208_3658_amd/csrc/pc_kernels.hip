@@ -452,25 +452,59 @@ __device__ __forceinline__ void tile32(unsigned char *lds, const float4 *__restr
 
 struct FewCtx {
     float lo[kFewMax], hi[kFewMax];  // bands of edges k0 .. k0+M-1
+    uint32_t w[kFewMax];             // bits of RN(hi - lo) per band
     uint32_t k0;
 };
 
-// n += (c > hi); band |= (c >= lo) & !(c > hi), band a lane mask; lo and hi
-// are wave-uniform (scalar registers: one scalar operand per compare).  Three
-// vector instructions (two compares, an add with carry-in) and two scalar
-// ones; written out because the compiler otherwise recomputes !(c > hi) as a
-// third compare.  Compares with a NaN are false: a NaN chord counts nowhere.
-__device__ __forceinline__ void few_count(float c, float lo, float hi, uint32_t &n, uint64_t &band) {
-    uint64_t gt, ge;
+// The M bands of an item, wave-uniform, and the width bits w.
+__device__ __forceinline__ void few_band(FewCtx &f, int q, float2 v) {
+    f.lo[q] = uniform_f(v.x);
+    f.hi[q] = uniform_f(v.y);
+    f.w[q] = uniform(__float_as_uint(v.y - v.x));
+}
+
+// Two chords against one band, in plain arithmetic (no compare, no scalar
+// instruction).  d = RN(hi - c) has the sign of hi - c, so its sign bit is
+// (c > hi): added to n, the lane's count of chords above the band.  A chord
+// inside the band (lo <= c <= hi) has 0 <= hi - c <= hi - lo, hence, rounding
+// being monotone, 0 <= d <= RN(hi - lo): the bits of d, read as an unsigned
+// integer (a negative d has the sign bit set), are at most w.  mn keeps the
+// minimum of those bits over a step; a step whose minimum is at most w in some
+// lane is re-checked (a superset of its in-band chords).  Chords that must
+// count nowhere (masked pairs) are -infinity: d = +infinity adds nothing and
+// is never at most w.  Six vector instructions for two chords; written out so
+// that the compiler keeps the two differences short-lived.
+__device__ __forceinline__ void few_tally2(float c1, float c2, float hi, uint32_t &n, uint32_t &mn) {
+    uint32_t d1, d2, s1, s2;
     asm volatile(
-        "v_cmp_gt_f32_e64 %[gt], %[c], %[hi]\n\t"
-        "v_cmp_ge_f32_e64 %[ge], %[c], %[lo]\n\t"
-        "s_andn2_b64 %[ge], %[ge], %[gt]\n\t"
-        "s_or_b64 %[band], %[band], %[ge]\n\t"
-        "v_addc_co_u32_e64 %[n], %[gt], 0, %[n], %[gt]"
-        : [n] "+v"(n), [band] "+s"(band), [gt] "=&s"(gt), [ge] "=&s"(ge)
-        : [c] "v"(c), [lo] "s"(lo), [hi] "s"(hi)
-        : "scc");
+        "v_sub_f32 %[d1], %[hi], %[c1]\n\t"
+        "v_sub_f32 %[d2], %[hi], %[c2]\n\t"
+        "v_lshrrev_b32 %[s1], 31, %[d1]\n\t"
+        "v_lshrrev_b32 %[s2], 31, %[d2]\n\t"
+        "v_add3_u32 %[n], %[n], %[s1], %[s2]\n\t"
+        "v_min3_u32 %[mn], %[mn], %[d1], %[d2]"
+        : [n] "+v"(n), [mn] "+v"(mn), [d1] "=&v"(d1), [d2] "=&v"(d2), [s1] "=&v"(s1), [s2] "=&v"(s2)
+        : [c1] "v"(c1), [c2] "v"(c2), [hi] "s"(hi));
+}
+
+template <int M>
+__device__ __forceinline__ void few_tally(float c1, float c2, const FewCtx &f, uint32_t (&ngt)[M], uint32_t (&mn)[M]) {
+#pragma unroll
+    for (int t = 0; t < M; ++t) few_tally2(c1, c2, f.hi[t], ngt[t], mn[t]);
+}
+
+template <int M>
+__device__ __forceinline__ void few_step_start(uint32_t (&mn)[M]) {
+#pragma unroll
+    for (int t = 0; t < M; ++t) mn[t] = 0xFFFFFFFFu;
+}
+
+template <int M>
+__device__ __forceinline__ bool few_step_band(const uint32_t (&mn)[M], const FewCtx &f) {
+    bool b = false;
+#pragma unroll
+    for (int t = 0; t < M; ++t) b |= mn[t] <= f.w[t];
+    return __builtin_amdgcn_ballot_w64(b) != 0;
 }
 
 // Add a lane's few-edge register counts to its histogram column: rows k0 ..
@@ -521,22 +555,27 @@ __device__ __forceinline__ void step32_few(unsigned char *lds, const float4 (&b)
                                            int64_t ibeg, int32_t i_lim, int32_t j_rel, bool diag,
                                            const TileCtx &k, const FewCtx &f, uint32_t (&ngt)[M]) {
     const int32_t lane = static_cast<int32_t>(threadIdx.x);
-    uint64_t band = 0;
+    uint32_t mn[M];
+    few_step_start<M>(mn);
+    static_assert(kR % 2 == 0, "chords are tallied in pairs");
 #pragma unroll
     for (int q = 0; q < NJ; ++q)
 #pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            float c = chord2_32(ax[r], ay[r], az[r], b[q]);
-            if (MASKED) {
-                // a masked-out pair becomes NaN, which no compare counts
-                const int32_t ir = r * kWave + lane;
-                const bool ok = ir < i_lim && (!diag || ir < j_rel + jj + q);
-                c = ok ? c : __builtin_nanf("");
-            }
+        for (int r = 0; r < kR; r += 2) {
+            float c[2];
 #pragma unroll
-            for (int t = 0; t < M; ++t) few_count(c, f.lo[t], f.hi[t], ngt[t], band);
+            for (int h = 0; h < 2; ++h) {
+                c[h] = chord2_32(ax[r + h], ay[r + h], az[r + h], b[q]);
+                if (MASKED) {
+                    // a masked-out pair becomes -infinity, which counts nowhere
+                    const int32_t ir = (r + h) * kWave + lane;
+                    const bool ok = ir < i_lim && (!diag || ir < j_rel + jj + q);
+                    c[h] = ok ? c[h] : -__builtin_inff();
+                }
+            }
+            few_tally<M>(c[0], c[1], f, ngt, mn);
         }
-    if (__builtin_expect(band != 0, 0)) {
+    if (__builtin_expect(few_step_band<M>(mn, f), 0)) {
 #pragma unroll
         for (int q = 0; q < NJ; ++q)
 #pragma unroll
@@ -610,7 +649,7 @@ __device__ __forceinline__ void tile32_few(unsigned char *lds, const float4 *__r
 // fused multiply-adds, four roundings, against six instructions for the
 // difference form; the matrix-core band bounds its error (same centring
 // condition, at most eight roundings).  i slots past the end of the range
-// get |a'|^2 = NaN, so all their chords are NaN and count nowhere.
+// get |a'|^2 = -infinity, so all their chords are -infinity and count nowhere.
 template <int M, int NJ>
 __device__ __forceinline__ void step32_gram(unsigned char *lds, const float4 (&b)[NJ],
                                             const double4 *__restrict__ J64t, int32_t jj, const float (&ax)[kR],
@@ -618,17 +657,20 @@ __device__ __forceinline__ void step32_gram(unsigned char *lds, const float4 (&b
                                             const double4 *__restrict__ I64, int64_t ibeg, const TileCtx &k,
                                             const FewCtx &f, uint32_t (&ngt)[M]) {
     const int32_t lane = static_cast<int32_t>(threadIdx.x);
-    uint64_t band = 0;
+    uint32_t mn[M];
+    few_step_start<M>(mn);
 #pragma unroll
     for (int q = 0; q < NJ; ++q)
 #pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            const float c = __builtin_fmaf(ax[r], b[q].x, __builtin_fmaf(ay[r], b[q].y,
-                                           __builtin_fmaf(az[r], b[q].z, na[r] + b[q].w)));
+        for (int r = 0; r < kR; r += 2) {
+            float c[2];
 #pragma unroll
-            for (int t = 0; t < M; ++t) few_count(c, f.lo[t], f.hi[t], ngt[t], band);
+            for (int h = 0; h < 2; ++h)
+                c[h] = __builtin_fmaf(ax[r + h], b[q].x, __builtin_fmaf(ay[r + h], b[q].y,
+                                      __builtin_fmaf(az[r + h], b[q].z, na[r + h] + b[q].w)));
+            few_tally<M>(c[0], c[1], f, ngt, mn);
         }
-    if (__builtin_expect(band != 0, 0)) {
+    if (__builtin_expect(few_step_band<M>(mn, f), 0)) {
 #pragma unroll
         for (int q = 0; q < NJ; ++q)
 #pragma unroll
@@ -642,7 +684,7 @@ __device__ __forceinline__ void step32_gram(unsigned char *lds, const float4 (&b
 }
 
 // The lane's i-points centred on the j-tile's centre o, in binary32, with
-// |a'|^2; slots past a ragged end get NaN so their pairs count nowhere.
+// |a'|^2; slots past a ragged end get -infinity so their pairs count nowhere.
 struct GramI {
     float ax[kR], ay[kR], az[kR], na[kR];
     uint32_t valid;
@@ -661,7 +703,7 @@ __device__ __forceinline__ void centre_i_gram(GramI &g, const double4 (&pts)[kR]
         g.ay[r] = static_cast<float>(p.y - oy);
         g.az[r] = static_cast<float>(p.z - oz);
         const float n2 = __builtin_fmaf(g.az[r], g.az[r], __builtin_fmaf(g.ay[r], g.ay[r], g.ax[r] * g.ax[r]));
-        g.na[r] = ok ? n2 : __builtin_nanf("");
+        g.na[r] = ok ? n2 : -__builtin_inff();
         g.valid += ok ? 1u : 0u;
     }
 }
@@ -724,12 +766,11 @@ __device__ __forceinline__ void bin_mfma_few(unsigned char *lds, const f32x4 (&D
         c[4 * m + 2] = D[m].z;
         c[4 * m + 3] = D[m].w;
     }
-    uint64_t band = 0;
+    uint32_t mn[M];
+    few_step_start<M>(mn);
 #pragma unroll
-    for (int v = 0; v < 4 * MB; ++v)
-#pragma unroll
-        for (int t = 0; t < M; ++t) few_count(c[v], f.lo[t], f.hi[t], ngt[t], band);
-    if (__builtin_expect(band != 0, 0)) {
+    for (int v = 0; v < 4 * MB; v += 2) few_tally<M>(c[v], c[v + 1], f, ngt, mn);
+    if (__builtin_expect(few_step_band<M>(mn, f), 0)) {
 #pragma unroll
         for (int v = 0; v < 4 * MB; ++v) {
             // an opaque copy: the compares are redone here rather than their
@@ -1096,9 +1137,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
 #pragma unroll
             for (int q = 0; q < kFewMax; ++q) {
                 const uint32_t e = min(few_k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
-                const float2 v = ld_const_f2(band_g + 2u * e);
-                f.lo[q] = uniform_f(v.x);
-                f.hi[q] = uniform_f(v.y);
+                few_band(f, q, ld_const_f2(band_g + 2u * e));
             }
             const double4 o = ld_const(centre_j ? sd.jb + u : sd.ib + t);
             const double4 *I64t = uniform_ptr(sd.i64 + ibeg);
@@ -1115,13 +1154,11 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
 #pragma unroll
                 for (int q = 0; q < kFewMax; ++q) {
                     const uint32_t e = min(few_k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
-                    const float2 v = ld_const_f2(bd + 2u * e);
-                    f.lo[q] = uniform_f(v.x);
-                    f.hi[q] = uniform_f(v.y);
+                    few_band(f, q, ld_const_f2(bd + 2u * e));
                 }
             }
             if (use_gram) {
-                // not a diagonal tile; i slots past a ragged end are NaN
+                // not a diagonal tile; i slots past a ragged end are -infinity
                 const double4 o = ld_const(sd.jb + u);
                 GramI g;
                 if (!PC_EARLY_GRAM) load_gi();
@@ -1176,14 +1213,12 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
 #pragma unroll
                     for (int q = 0; q < kFewMax; ++q) {
                         const uint32_t e = min(k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
-                        const float2 v = ld_const_f2(bd + 2u * e);
-                        f.lo[q] = uniform_f(v.x);
-                        f.hi[q] = uniform_f(v.y);
+                        few_band(f, q, ld_const_f2(bd + 2u * e));
                     }
                 }
             };
             if (use_gram) {
-                // not a diagonal tile; i slots past a ragged end are NaN
+                // not a diagonal tile; i slots past a ragged end are -infinity
                 const double4 o = ld_const(sd.jb + u);
                 GramI g;
                 if (!PC_EARLY_GRAM) load_gi();

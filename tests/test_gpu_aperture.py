@@ -1,7 +1,8 @@
 """Parity of the GPU aperture-mass map (Sec. 3, Eq. 3-5) with the binary64
-oracle.  The aperture membership n_in is bit-exact (the cut is taken in
-binary64 exactly as the definition states it); map and SNR agree within the
-bound derived from the binary32 filter arithmetic:
+oracle.  The aperture membership n_in is bit-exact (the cut gives the binary64
+definition's result: decided from a binary32 |d|^2 outside a proven band,
+in binary64 inside it); map and SNR agree within the bound derived from the
+binary32 filter arithmetic:
   |map - map_ref| <= 1e-4 * sum_i Q_i |eps_i| / n_gal,
   |snr - snr_ref| <= 1e-4 * (sqrt(2) * sum_i Q_i |eps_i| / sqrt(S2) + |snr_ref|),
 with S2 = sum_i Q_i^2 |eps_i|^2 from the oracle (derivation in the design
@@ -42,14 +43,53 @@ def _small(n=20000, density=35.0, config=11):
     return synth.shear_catalog(n, density=density, config=config)
 
 
+@pytest.fixture(params=[1, 2], ids=["8x8_blocks", "16x16_blocks"])
+def points_per_lane(request):
+    """Both kernel instances (1 or 2 x 2 grid points per lane) on the same
+    inputs."""
+    pc.pc_debug_ap_points_per_lane(request.param)
+    yield request.param
+    pc.pc_debug_ap_points_per_lane(0)
+
+
 @pytest.mark.parametrize("theta", [0.3, 2.0, 7.5])
-def test_small_grid_matches_oracle(theta):
+def test_small_grid_matches_oracle(theta, points_per_lane):
     cat, side = _small()
-    grid = (0.17, -0.6, side / 37.0, side / 29.0, 37, 29)  # ragged 8x8 blocks, points off the field
+    grid = (0.17, -0.6, side / 37.0, side / 29.0, 37, 29)  # ragged blocks, points off the field
     ref = oracle.aperture_grid(cat, grid, theta, 35.0)
     gpu = pc.pc_aperture_mass(cat, grid, theta, 35.0)
     worst = _check(gpu, ref, 35.0, f"theta={theta}")
     print(f"theta={theta}: worst map error {worst:.3g} of tolerance, mean n_in {ref['n_in'].mean():.1f}")
+
+
+def test_cut_decided_exactly_at_theta_and_on_points(points_per_lane):
+    """Galaxies placed on grid points, at exactly theta_max from grid points
+    along the axes and diagonals, and one binary64 ulp inside and outside of
+    that: the binary32 |d|^2 cannot decide these, so the binary64 definition
+    must, and n_in must equal the oracle's everywhere."""
+    theta = 1.5
+    grid = (0.3, -0.2, 0.125, 0.1, 40, 36)
+    rng = np.random.default_rng(21)
+    ix, iy = rng.integers(0, 40, 300), rng.integers(0, 36, 300)
+    px, py = grid[0] + ix * grid[2], grid[1] + iy * grid[3]
+    ang = rng.choice([0.0, 0.5 * np.pi, np.pi, 1.5 * np.pi, 0.25 * np.pi, 1.1], 300)
+    gx, gy = px + theta * np.cos(ang), py + theta * np.sin(ang)
+    inward = np.nextafter(gx, px)
+    outward = np.nextafter(gx, 2 * gx - px)
+    x = np.concatenate([px, gx, inward, outward, rng.uniform(-2, 7, 3000)])
+    y = np.concatenate([py, gy, gy, gy, rng.uniform(-2, 6, 3000)])
+    e = rng.normal(0.0, 0.3, (2, x.size))
+    cat = (x, y, e[0], e[1])
+    gpu = pc.pc_aperture_mass(cat, grid, theta, 30.0)
+    ref = oracle.aperture_grid(cat, grid, theta, 30.0)
+    _check(gpu, ref, 30.0, f"cut P={points_per_lane}")
+
+
+def test_grid_extent_limit():
+    cat, side = _small(1000, config=18)
+    with pytest.raises(pc.PcError) as ei:
+        pc.pc_aperture_mass(cat, (0.0, 0.0, 1e14, 1.0, 12, 3), 2.0, 35.0)
+    assert ei.value.code == pc.PC_ERR_INVALID
 
 
 def test_device_inputs_and_outputs_match_host_path():
@@ -82,7 +122,7 @@ def test_reproducible_bits():
         assert np.array_equal(a[k], b[k], equal_nan=True)
 
 
-def test_rings_and_boundaries():
+def test_rings_and_boundaries(points_per_lane):
     # tangential ring: SNR = sqrt(2K); cross ring: map 0; galaxies exactly at
     # theta_max and exactly on the point are out; one just inside is in
     k, r, theta, g = 24, 1.1, 2.0, 0.2
@@ -129,7 +169,7 @@ def test_device_catalogue_with_nan_is_rejected():
     assert torch.all(out["map"] == 7.0).item()
 
 
-def test_clustered_positions():
+def test_clustered_positions(points_per_lane):
     # many galaxies in few cells (the rank placement is quadratic per cell)
     rng = np.random.default_rng(16)
     n = 40000
@@ -173,7 +213,7 @@ def test_paper_workload_sampled(grid_n, theta):
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_seeded_random_maps(seed):
+def test_seeded_random_maps(seed, points_per_lane):
     # random catalogue size and density, filter radius, grid shape, spacing
     # and offset (grids partly off the field), against the oracle
     rng = np.random.default_rng(2000 + seed)
