@@ -119,7 +119,8 @@ int pc_debug_ap_filter(const double *x, int64_t n, double *q);
  * pc_debug_ap_points_per_lane -- points = 1 or 2: the calling thread's later
  * pc_aperture_mass calls give each GPU lane points x points grid points (a
  * wave a block of 8 x 8 or 16 x 16 points); 0 restores the choice the call
- * makes itself (2 when a 16 x 16 block spans at most a quarter of theta_max).
+ * makes itself (2 when a 16 x 16 block spans at most a quarter of theta_max
+ * and the grid has at least 16 such blocks per compute unit).
  * Same results within the stated tolerance, n_in identical.  For testing both
  * kernel instances on one input.  PC_ERR_INVALID for other values.
  */

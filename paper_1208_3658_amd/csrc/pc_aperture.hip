@@ -81,9 +81,10 @@ struct ApParams {
     float k_s;        // table position s = r k_s = kQCells x, x = r / theta
     float s_max;      // largest binary32 below kQCells (r rounded up to theta)
     float r2f;        // theta^2 rounded to binary32: the provisional cut
-    float r2f_below;  // the largest binary32 below r2f
     float band;       // |f2 - r2f| <= band: the binary32 |d|^2 cannot decide the cut
     float near0;      // f2 <= near0: a galaxy near the point, decided and weighted in binary64
+    float nbig;       // -1 / band: clamp(fma(f2 - r2f, nbig, 1/2)) is 1 inside, 0 outside
+    float f2_in, f2_out;  // r2f -+ 2 band: where a pair decided in binary64 is moved
     double n_gal;
     double *map;
     double *snr;
@@ -169,9 +170,24 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 
 // Constants held in VGPRs (an instruction reads at most one SGPR).
 struct ApConsts {
-    float k_s, s_max, r2f, r2f_below, band, near0;
+    float k_s, s_max, r2f, band, near0, nbig, f2_in, f2_out;
     uint32_t tab;  // LDS byte address of the filter table
 };
+
+// clamp(e * m + 1/2) to [0, 1] in one fused multiply-add (its clamp bit).
+__device__ __forceinline__ float fma_clamp01(float e, float m) {
+    float r;
+    asm("v_fma_f32 %0, %1, %2, 0.5 clamp" : "=v"(r) : "v"(e), "v"(m));
+    return r;
+}
+
+// max(a, b) of two finite values, one instruction (fmaxf would first quiet
+// signalling NaNs, which cannot occur here).
+__device__ __forceinline__ float max_f32(float a, float b) {
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 
 // The filter Q(x) of Eq. 4 at table position s = kQCells x (s <= s_max):
 // cell i = floor(s), t = s - i, Q = c0 + t (c1 + t (c2 + t c3)).
@@ -249,10 +265,10 @@ k_ap_map(const ApParams p) {
     const double gxl = p.x0 + static_cast<double>(ix0) * p.gdx, gxh = p.x0 + static_cast<double>(ix1) * p.gdx;
     const double gyl = p.y0 + static_cast<double>(iy0) * p.gdy, gyh = p.y0 + static_cast<double>(iy1) * p.gdy;
     const Lattice L = p.lat;
-    ApConsts C{p.k_s, p.s_max, p.r2f, p.r2f_below, p.band, p.near0,
+    ApConsts C{p.k_s, p.s_max, p.r2f, p.band, p.near0, p.nbig, p.f2_in, p.f2_out,
                static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
                    (__attribute__((address_space(3))) const float4 *)(qtab)))};
-    asm("" : "+v"(C.k_s), "+v"(C.s_max), "+v"(C.r2f), "+v"(C.r2f_below), "+v"(C.band), "+v"(C.near0), "+v"(C.tab));
+    asm("" : "+v"(C.k_s), "+v"(C.s_max), "+v"(C.r2f), "+v"(C.band), "+v"(C.near0), "+v"(C.nbig), "+v"(C.f2_in), "+v"(C.f2_out));
     const double slack = L.s * 1e-9;  // covers rounding of the cell coordinates
 
     double S1[K], S2[K];
@@ -282,11 +298,12 @@ k_ap_map(const ApParams p) {
         tested += g_end - g_begin;
         for (uint32_t c0 = g_begin; c0 < g_end; c0 += kApFlush) {
             const uint32_t c1 = min(c0 + static_cast<uint32_t>(kApFlush), g_end);
-            float a1[K], a2[K];
+            float a1[K], a2[K], cntf[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 a1[k] = 0.0f;
                 a2[k] = 0.0f;
+                cntf[k] = 0.0f;
             }
             // galaxies go through scalar registers, each loaded one galaxy
             // ahead of its use
@@ -332,20 +349,21 @@ k_ap_map(const ApParams p) {
                             cnt[k] += 1u;
                         }
                         const bool undecided = fabsf(f2[k] - C.r2f) <= C.band || near_point;
-                        const float moved = (inside && !near_point) ? fminf(f2[k], C.r2f_below) : fmaxf(f2[k], C.r2f);
+                        const float moved = (inside && !near_point) ? C.f2_in : C.f2_out;
                         f2[k] = undecided ? moved : f2[k];
                     }
                 }
-                // f2 raised to `near0` keeps every value below finite (a pair
-                // so raised is never inside here: see above)
-                float rinv[K], q[K];
+                // inside: w = 1, outside: w = 0, exactly (|f2 - r2f| > band
+                // here, or f2 was moved to 2 band from r2f); plain
+                // arithmetic, no compare.  f2 raised to `near0` keeps every
+                // value below finite (a pair so raised is never inside here).
+                float rinv[K], q[K], wt[K];
                 uint32_t addr[K];
-                bool in[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    in[k] = f2[k] < C.r2f;
-                    cnt[k] += in[k] ? 1u : 0u;
-                    const float f2c = __builtin_amdgcn_fmed3f(f2[k], C.near0, FLT_MAX);
+                    wt[k] = fma_clamp01(f2[k] - C.r2f, C.nbig);
+                    cntf[k] += wt[k];
+                    const float f2c = max_f32(f2[k], C.near0);
                     rinv[k] = __builtin_amdgcn_rsqf(f2c);
                     const float sk = fminf((f2c * rinv[k]) * C.k_s, C.s_max);
                     addr[k] = C.tab + (static_cast<uint32_t>(sk) << 4);
@@ -360,7 +378,7 @@ k_ap_map(const ApParams p) {
                 for (int k = 0; k < K; ++k) {
                     const float t = q[k];
                     float qk = fmaf(fmaf(fmaf(cq[k].w, t, cq[k].z), t, cq[k].y), t, cq[k].x);
-                    qk = in[k] ? qk : 0.0f;
+                    qk *= wt[k];
                     const float rr = rinv[k] * rinv[k];
                     const float inner = fmaf(G.a2, py[k], G.b2 * (fdx[k] * fdy[k]));
                     const float et = fmaf(rr, inner, G.a);
@@ -372,6 +390,7 @@ k_ap_map(const ApParams p) {
             for (int k = 0; k < K; ++k) {
                 S1[k] += static_cast<double>(a1[k]);
                 S2[k] += static_cast<double>(a2[k]);
+                cnt[k] += static_cast<uint32_t>(cntf[k]);  // at most 64, exact
             }
         }
     }
@@ -533,11 +552,13 @@ int make_lattice(const pc_grid *g, double theta, Lattice *L) {
 
 // Grid points per lane along each axis (blocks of 8P x 8P points per wave):
 // 2 when the 16 x 16 block is small beside the filter disc (a quarter of its
-// radius), so that the extra galaxies visited by the larger block stay few;
-// else 1.
-int points_per_lane(const pc_grid *g, double theta) {
+// radius), so that the extra galaxies visited by the larger block stay few,
+// and the grid gives at least 16 such blocks per CU (four waves per SIMD, the
+// instance's occupancy); else 1.
+int points_per_lane(const pc_grid *g, double theta, int cus) {
     if (t_ap_force_p == 1 || t_ap_force_p == 2) return t_ap_force_p;
-    return 16.0 * std::max(g->dx, g->dy) <= 0.25 * theta ? 2 : 1;
+    const double blocks16 = (static_cast<double>(g->nx) * g->ny) / 256.0;
+    return 16.0 * std::max(g->dx, g->dy) <= 0.25 * theta && blocks16 >= 16.0 * cus ? 2 : 1;
 }
 
 // The binary32 cut and its guard bands.  Notation: u = 2^-24, v = 2^-53;
@@ -713,7 +734,7 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     p.gdy = grid->dy;
     p.nx = grid->nx;
     p.ny = grid->ny;
-    const int P = points_per_lane(grid, theta_max);
+    const int P = points_per_lane(grid, theta_max, di->cus);
     const int group_side = 16 * P;  // 2 x 2 blocks of 8P x 8P points
     p.tiles_x = (grid->nx + group_side - 1) / group_side;
     const int tiles_y = (grid->ny + group_side - 1) / group_side;
@@ -725,7 +746,9 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     p.k_s = static_cast<float>(static_cast<double>(kQCells) / theta_max);
     p.s_max = std::nextafter(static_cast<float>(kQCells), 0.0f);
     cut_bands(grid, theta_max, p.r2, P, &p.r2f, &p.band, &p.near0);
-    p.r2f_below = std::nextafter(p.r2f, 0.0f);
+    p.nbig = -1.0f / p.band;
+    p.f2_in = p.r2f - 2.0f * p.band;
+    p.f2_out = p.r2f + 2.0f * p.band;
     p.qtab = qtab;
     p.n_gal = n_gal;
     p.map = d_map;

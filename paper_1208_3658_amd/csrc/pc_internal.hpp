@@ -47,15 +47,17 @@ constexpr uint32_t kLdsTarget = 16 * 1024;  // per-wave histogram bytes aimed fo
 inline uint32_t row_bytes_for(int cols) { return static_cast<uint32_t>(cols) * 4u; }
 
 // Cell lookup entry of the mixed (binary32) kernel.  For a squared chord c in
-// the cell: c > hi -> histogram row offset off_hi, else off_lo; lo <= c <= hi
-// -> re-check in binary64.  Offsets are byte offsets of histogram rows.  A
-// finite hi only occurs in a cell that one band meets, where off_hi = off_lo
-// + one row, so the kernel reads the first 12 bytes alone and adds the row
-// when c > hi.
+// the cell: row offset off_lo, plus one row when c > hi; lo <= c <= hi ->
+// re-check in binary64.  Offsets are byte offsets of histogram rows.  A
+// finite hi only occurs in a cell that one band meets (the next row is then
+// that band's edge's).  wbits = the bits of RN32(hi - lo) in a one-band cell
+// (a chord in the band has 0 <= RN32(hi - c) <= RN32(hi - lo)), 0 in a cell
+// without a band (lo = hi = +inf: RN32(hi - c) = +inf is never in), all ones
+// in a cell that several bands meet (lo = -inf, hi = +inf: always re-checked).
 struct LutEntry32 {
     uint32_t off_lo;
     float lo, hi;
-    uint32_t off_hi;
+    uint32_t wbits;
 };
 
 // Cell lookup entry of the binary64 kernel: c >= e -> off_hi, else off_lo.

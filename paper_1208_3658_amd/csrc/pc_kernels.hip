@@ -203,6 +203,13 @@ __device__ __forceinline__ uint4 lds_read4(uint32_t addr) {
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// max(a - b, 0) for unsigned a, b: one subtract with its clamp bit.
+__device__ __forceinline__ uint32_t sub_sat(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_sub_u32_e64 %0, %1, %2 clamp" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t umed3(uint32_t x, uint32_t lo, uint32_t hi) {
     return min(max(x, lo), hi);
 }
@@ -307,7 +314,7 @@ __device__ __forceinline__ float chord2_32(float ax, float ay, float az, float4 
 }
 
 struct TileCtx {
-    uint32_t shift, lut_base, lane_off, trash_off, row_bytes;
+    uint32_t shift, lut_base, lane_off, trash_off, row_bytes, row_shift;
     float klo, khi;  // key clamp as floats
     int32_t n_edges;
     const double *e64;
@@ -348,32 +355,36 @@ __device__ __forceinline__ void step32(unsigned char *lds, const float4 (&b)[NJ]
             c2[q][r] = chord2_32(ax[r], ay[r], az[r], b[q]);
             a[q][r] = cell_addr(key32(c2[q][r], k.klo, k.khi), k.shift, k.lut_base);
         }
-    uint3 e[NJ][kR];
+    uint4 e[NJ][kR];
 #pragma unroll
     for (int q = 0; q < NJ; ++q)
 #pragma unroll
-        for (int r = 0; r < kR; ++r) e[q][r] = lds_read3(a[q][r]);
-    bool any_band = false;
+        for (int r = 0; r < kR; ++r) e[q][r] = lds_read4(a[q][r]);
+    // As in the few-edge paths, without compares: d = RN(hi - c) has the sign
+    // of hi - c, so its sign bit adds the cell's next row when c > hi; a chord
+    // in the cell's band has 0 <= d <= RN(hi - lo), whose bits the entry holds
+    // (all ones where several bands meet, 0 where none does), so the step's
+    // minimum of max(bits(d) - wbits, 0) is 0 when some chord may be in a band.
+    uint32_t mn = 0xFFFFFFFFu;
 #pragma unroll
     for (int q = 0; q < NJ; ++q)
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
-            const bool gt = c2[q][r] > __uint_as_float(e[q][r].z);
-            const bool band = !gt & (c2[q][r] >= __uint_as_float(e[q][r].y));
-            uint32_t off = e[q][r].x + (gt ? k.row_bytes : 0u) + k.lane_off;
+            const uint32_t bd = __float_as_uint(__uint_as_float(e[q][r].z) - c2[q][r]);
+            uint32_t off = e[q][r].x + ((bd >> 31) << k.row_shift) + k.lane_off;
+            uint32_t t = sub_sat(bd, e[q][r].w);
             if (MASKED) {
                 // i slot valid, and on a diagonal tile i < j (positions
                 // relative to the tile start: i = r*64 + lane, j = j_rel + jj + q)
                 const int32_t ir = r * kWave + lane;
                 const bool ok = ir < i_lim && (!diag || ir < j_rel + jj + q);
                 off = ok ? off : k.trash_off;
-                any_band |= ok & band;
-            } else {
-                any_band |= band;
+                t = ok ? t : 1u;
             }
+            mn = min(mn, t);
             lds_add(lds, off, 1u);
         }
-    if (__builtin_expect(any_band, 0)) {
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(mn == 0u) != 0, 0)) {
         // rare: a binary32 chord is within the error band of an edge;
         // recompute such pairs in binary64 exactly as the reference does and
         // move their count from the provisional row to the exact one
@@ -1114,6 +1125,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
         k.lane_off = lane_off;
         k.trash_off = trash_off;
         k.row_bytes = row_bytes;
+        k.row_shift = static_cast<uint32_t>(__builtin_ctz(row_bytes));
         k.klo = __uint_as_float(clo);
         k.khi = __uint_as_float(chi);
         k.n_edges = n_edges;

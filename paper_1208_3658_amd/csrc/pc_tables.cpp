@@ -197,15 +197,15 @@ void build_lut32(const std::vector<float> &lo, const std::vector<float> &hi, uin
         LutEntry32 e;
         e.off_lo = k_base * row_bytes;
         if (n_in == 0) {
-            e.off_hi = e.off_lo;
+            e.wbits = 0u;
             e.lo = inf;
             e.hi = inf;
         } else if (n_in == 1) {
-            e.off_hi = (k_base + 1) * row_bytes;
             e.lo = lo[k_in];
             e.hi = hi[k_in];
+            e.wbits = f2u(e.hi - e.lo);  // binary32 subtraction, as the kernel's
         } else {
-            e.off_hi = e.off_lo;
+            e.wbits = 0xFFFFFFFFu;
             e.lo = -inf;
             e.hi = inf;
             ++out.multi;

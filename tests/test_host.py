@@ -142,11 +142,22 @@ def _emulate_kernel(theta, A, B=None):
         E = ent[cell]
         lo = E[:, 1].view(np.float32)
         hi = E[:, 2].view(np.float32)
-        # as the kernel does it: off_lo, plus one row when c > hi
-        row = (E[:, 0] + np.where(c32 > hi, info["row_bytes"], 0)) // info["row_bytes"]
+        # as the kernel does it: d = RN32(hi - c); off_lo, plus one row when
+        # the sign bit of d is set; a chord is flagged for the re-check when
+        # max(bits(d) - wbits, 0) = 0, and the re-check moves the flagged
+        # chords that lie in the band (lo <= c <= hi) to their binary64 row
+        with np.errstate(invalid="ignore", over="ignore"):
+            d = (hi - c32).astype(np.float32)
+        bd = d.view(np.uint32)
+        row = (E[:, 0] + (bd >> 31) * info["row_bytes"]) // info["row_bytes"]
+        flagged = bd <= E[:, 3]
         band = (c32 >= lo) & ~(c32 > hi)
+        assert np.all(flagged[band]), "an in-band chord was not flagged"
+        assert np.array_equal(row[~band], np.where(c32 > hi, E[:, 0] + info["row_bytes"], E[:, 0])[~band]
+                              // info["row_bytes"])
         row = row.astype(np.int64)
-        row[band] = np.searchsorted(e64, c64[band], side="right")
+        fix = flagged & band
+        row[fix] = np.searchsorted(e64, c64[fix], side="right")
         counts.append(np.bincount(row, minlength=theta.size + 1).astype(np.uint64))
     return counts
 
@@ -276,14 +287,21 @@ def test_few_edge_binning_reproduces_the_oracle(name, gram):
 
 
 @pytest.mark.parametrize("name", sorted(EDGE_SETS))
-def test_cell_entries_finite_hi_means_next_row(name):
-    """The kernel reads (off_lo, lo, hi) only and adds one row when c > hi:
-    valid because a finite hi occurs only in one-band cells."""
+def test_cell_entries_hold_band_width_bits(name):
+    """A cell entry is (off_lo, lo, hi, wbits): a finite hi only in one-band
+    cells, with wbits the bits of RN32(hi - lo); no band: lo = hi = +inf,
+    wbits 0; several bands: lo = -inf, hi = +inf, wbits all ones."""
     info, ent = pc.pc_debug_lut32(EDGE_SETS[name])
+    lo = ent[:, 1].view(np.float32)
     hi = ent[:, 2].view(np.float32)
     fin = np.isfinite(hi)
-    assert np.all(ent[fin, 3] == ent[fin, 0] + info["row_bytes"])
+    assert np.array_equal(ent[fin, 3], (hi[fin] - lo[fin]).astype(np.float32).view(np.uint32))
     assert np.all(hi[~fin] == np.inf)
+    none = ~fin & (lo == np.inf)
+    multi = ~fin & (lo == -np.inf)
+    assert np.all(none | multi | fin)
+    assert np.all(ent[none, 3] == 0) and np.all(ent[multi, 3] == 0xFFFFFFFF)
+    assert int(np.sum(multi)) == info["multi"]
 
 
 def test_wtheta_matches_oracle_bitwise():
