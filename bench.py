@@ -257,18 +257,26 @@ def cpu_baseline(c, target_s: float):
     return out
 
 
-def serve_oracle_check(reqs, cats, randoms, results, budget_s: float):
-    """Served answers against the CPU oracle: DD and DR of whole requests,
-    smallest first, until about budget_s seconds of oracle time are spent.
+def serve_oracle_check(pc, reqs, cats, randoms, results, budget_s: float, seed: int = 77):
+    """Served answers against the CPU oracle, two ways.
+    * whole requests: DD and DR of the smallest requests, smallest first,
+      until about half of budget_s seconds of oracle time are spent;
+    * every request: its served DD, DR and RR equal one direct launch of the
+      same jobs (pc_count_batch on the same catalogues and edges), and a
+      seeded window of 32 data rows of that request's DD and DR, counted by
+      the library (pc_count_ex row range) and by the oracle, agree: the
+      oracle pins a sample of every request's counts, the direct launch ties
+      them to the served answer.
     (RR of a 10^6-point pool catalogue is 5e11 pairs per edge set, minutes of
-    oracle time each: it is compared with the tests' oracle-pinned batch
-    counts instead, not here.)"""
+    oracle time each: RR is tied to the direct launch only; the tests pin the
+    library's RR against the oracle.)"""
+    import numpy as np
     import oracle
     order = sorted(range(len(reqs)), key=lambda k: (cats[k][0].size, k))
     t0 = time.perf_counter()
     checked, same, n_max, pairs = 0, True, 0, 0
     for k in order:
-        if time.perf_counter() - t0 > budget_s:
+        if time.perf_counter() - t0 > 0.5 * budget_s:
             break
         r, cat, res = reqs[k], cats[k], results[k]
         R = randoms[r["patch"]]
@@ -278,9 +286,33 @@ def serve_oracle_check(reqs, cats, randoms, results, budget_s: float):
         checked += 1
         n_max = max(n_max, int(cat[0].size))
         pairs += int(dd.sum()) + int(dr.sum())
+    whole_s = time.perf_counter() - t0
+    rng = np.random.default_rng(seed)
+    t1 = time.perf_counter()
+    direct_same, rows_same, row_pairs = True, True, 0
+    for k, (r, cat, res) in enumerate(zip(reqs, cats, results)):
+        R = randoms[r["patch"]]
+        dd, dr, rr = pc.pc_count_batch([{"A": cat, "edges": r["edges"]},
+                                        {"A": cat, "B": R, "edges": r["edges"], "auto": False},
+                                        {"A": R, "edges": r["edges"]}])
+        direct_same &= (res["DD"].tolist() == dd.tolist() and res["DR"].tolist() == dr.tolist()
+                        and res["RR"].tolist() == rr.tolist())
+        n = int(cat[0].size)
+        a = int(rng.integers(0, max(n - 32, 0) + 1))
+        b = min(a + 32, n)
+        g_dd = pc.pc_count_ex(cat, r["edges"], rows=(a, b))
+        g_dr = pc.pc_count_ex(cat, r["edges"], B=R, auto=False, rows=(a, b))
+        o_dd = oracle.count(cat, r["edges"], rows=(a, b))
+        o_dr = oracle.count(cat, r["edges"], B=R, auto=False, rows=(a, b))
+        rows_same &= g_dd.tolist() == o_dd.tolist() and g_dr.tolist() == o_dr.tolist()
+        row_pairs += int(o_dd.sum()) + int(o_dr.sum())
     return {"requests": checked, "of": len(reqs), "n_max": n_max, "pairs": pairs, "identical_dd_dr": bool(same),
-            "oracle_s": time.perf_counter() - t0, "threads": oracle.num_threads(),
-            "sample": "the smallest requests (whole DD and DR) within the oracle time budget"}
+            "oracle_s": whole_s, "threads": oracle.num_threads(),
+            "sample": "the smallest requests (whole DD and DR) within half the oracle time budget",
+            "every_request": {"requests": len(reqs), "served_equal_direct_launch_dd_dr_rr": bool(direct_same),
+                              "row_window": 32, "row_window_pairs": row_pairs,
+                              "rows_identical_to_oracle_dd_dr": bool(rows_same),
+                              "seconds": time.perf_counter() - t1}}
 
 
 def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: bool = True, server_cfg=None,
@@ -335,7 +367,7 @@ def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: 
         if abs(load - 0.7) < 1e-9:
             out.update({"rate_hz": rate, **mixed})
             if oracle_seconds > 0:
-                out["oracle_check"] = serve_oracle_check(reqs, cats, randoms, res_m, oracle_seconds)
+                out["oracle_check"] = serve_oracle_check(pc, reqs, cats, randoms, res_m, oracle_seconds)
             if fp64_compare:
                 single64, res_f = run(arrivals, {"streams": 1, "max_inflight": 64, "max_batch_pairs": 1,
                                                  "mode": pc.PC_FP64_PLAIN})
@@ -504,7 +536,7 @@ def main():
     fp64_run = (mode & 0xFF) == pc.PC_FP64_PLAIN
     peak = PEAK_FP64_VECTOR_TFLOPS if fp64_run else PEAK_FP32_VECTOR_TFLOPS
     # the same rate counting, per pair, only the comparisons its path needs
-    # (few-edge pairs compare with the m <= 2 edges left in their interval)
+    # (few-edge pairs compare with the m <= 3 edges left in their interval)
     by = paths["by_edges"]
     assert sum(by) == prn["pairs_computed"], (by, prn["pairs_computed"])
     work_method = sum(by[m] * work_per_pair_method(n_bins, m) for m in range(4))

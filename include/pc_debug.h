@@ -93,7 +93,7 @@ int pc_debug_last_launch(double *kernel_ms, uint64_t *items, int32_t *grid, uint
  * the j-tile's four sub-blocks of 64 points are looked at one by one, some
  * binned whole, the others visited with their own edges (split_items counts
  * those items).  few_items counts the work units (items, or open sub-blocks
- * of split items) with at most 2 edges inside their chord interval (binned by
+ * of split items) with at most 3 edges inside their chord interval (binned by
  * comparing with those edges alone), gram_items those whose vector-path
  * chords are formed in tile-centred Gram form.  Any pointer may be NULL.
  */

@@ -96,7 +96,7 @@ struct TableDesc {
 constexpr int kItemBits = 40;
 constexpr int kFewMax = 3;  // at most 3: m has two bits
 #ifndef PC_FEWCUT
-#define PC_FEWCUT 2         // items with at most this many edges use few-edge binning (<= kFewMax)
+#define PC_FEWCUT 3         // items with at most this many edges use few-edge binning (<= kFewMax)
 #endif
 constexpr uint64_t kItemMask = (1ull << kItemBits) - 1;
 constexpr int kSplitBit = 53;

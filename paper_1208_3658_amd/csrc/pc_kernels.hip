@@ -467,11 +467,15 @@ struct FewCtx {
     uint32_t k0;
 };
 
-// The M bands of an item, wave-uniform, and the width bits w.
+// The M bands of an item, wave-uniform, and the width bits w.  An edge at 0
+// has the band (-inf, -inf): every chord lies above it.  Its hi is taken as
+// -FLT_MAX, which orders every chord the same way, so that hi - c is never
+// -inf - (-inf) for a chord marked -infinity (see few_tally2).
 __device__ __forceinline__ void few_band(FewCtx &f, int q, float2 v) {
+    const float hi = fmaxf(v.y, -__FLT_MAX__);
     f.lo[q] = uniform_f(v.x);
-    f.hi[q] = uniform_f(v.y);
-    f.w[q] = uniform(__float_as_uint(v.y - v.x));
+    f.hi[q] = uniform_f(hi);
+    f.w[q] = uniform(__float_as_uint(hi - v.x));
 }
 
 // Two chords against one band, in plain arithmetic (no compare, no scalar
@@ -550,12 +554,15 @@ __device__ __forceinline__ void few_recheck(unsigned char *lds, float c, const d
     }
 }
 
+// A chord inside one of the item's bands.  -infinity marks a pair that
+// counts nowhere (a Gram-form i slot past a ragged end), which a band with
+// lo = -infinity (an edge at or near 0) would otherwise take in.
 template <int M>
 __device__ __forceinline__ bool few_in_band(float c, const FewCtx &f) {
     bool band = false;
 #pragma unroll
     for (int t = 0; t < M; ++t) band |= !(c > f.hi[t]) & (c >= f.lo[t]);
-    return band;
+    return band & (c > -__builtin_inff());
 }
 
 template <bool MASKED, int M, int NJ>

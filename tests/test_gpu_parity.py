@@ -303,6 +303,26 @@ def test_matrix_core_path_far_clusters_and_edge_pairs(mode):
             assert st["mfma_items"] == 0 and stc["mfma_items"] == 0
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_edge_at_zero_with_ragged_gram_items(mode):
+    """An edge at 0 (its band is (-inf, -inf): every chord lies above it) in
+    few-edge items whose i-tile is ragged: the i slots past the end count
+    nowhere (marked -infinity in the Gram form) and must never be taken for
+    in-band chords or counted above the zero edge."""
+    rng = np.random.default_rng(41)
+    for n_a, n_b in [(300, 700), (45, 513), (257, 256)]:
+        A = (100 + 0.4 * rng.standard_normal(n_a), 0.4 * rng.standard_normal(n_a))
+        B = (100 + 0.4 * rng.standard_normal(n_b), 15 + 0.4 * rng.standard_normal(n_b))
+        for e in (np.array([0.0, 14.0, 16.0]), np.array([0.0, 1e-9, 13.0, 15.0, 17.0]),
+                  synth.linear_edges(0.0, 90.0, 9)):
+            got = pc.pc_count_ex(dev(A), e, B=dev(B), auto=False, mode=mode)
+            assert got.tolist() == oracle.count(A, e, B=B, auto=False).tolist(), (n_a, n_b, e.size)
+            if mode == pc.PC_MIXED and e.size == 3:
+                assert pc.pc_debug_last_pruning()["gram_items"] > 0
+            AB = (np.concatenate([A[0], B[0]]), np.concatenate([A[1], B[1]]))
+            assert pc.pc_count_ex(dev(AB), e, mode=mode).tolist() == oracle.count(AB, e).tolist(), (n_a, n_b)
+
+
 @pytest.mark.parametrize("mode", [pc.PC_MIXED, pc.PC_MIXED | pc.PC_MATRIX_CORES])
 def test_split_items_match_oracle(mode):
     """Clustered points on a 10-degree patch with 30 log bins: most surviving
