@@ -59,29 +59,38 @@ def cpu_model() -> str:
     return ""
 
 
-def code_fingerprint(path: str) -> str:
-    """SHA-256 of a source file's code: comments removed and whitespace
-    collapsed, so that editing a comment does not retire a profile record."""
+def code_fingerprint(paths) -> str:
+    """SHA-256 of the code of one source file, or of several in order (a
+    kernel and the local headers its device code uses): comments removed and
+    whitespace collapsed, so that editing a comment does not retire a profile
+    record."""
     import hashlib
     import re
-    with open(path) as f:
-        text = f.read()
-    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", " ", text)
-    text = " ".join(text.split())
-    return hashlib.sha256(text.encode()).hexdigest()
+    parts = []
+    for path in ([paths] if isinstance(paths, str) else paths):
+        with open(path) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        parts.append(" ".join(text.split()))
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()
 
 
-def recorded_traffic(record: str, source: str):
+# the sources whose code a traffic record was taken on, per kernel
+K_COUNT_SOURCES = ("pc_kernels.hip", "pc_internal.hpp", "pc_math.h")
+K_AP_MAP_SOURCES = ("pc_aperture.hip",)
+
+
+def recorded_traffic(record: str, sources):
     """HBM bytes per launch from a committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     record, if it was taken on the kernel code as it is now; else None."""
     rec = os.path.join(ROOT, "profiles", record)
-    src = os.path.join(ROOT, "paper_1208_3658_amd", "csrc", source)
+    srcs = [os.path.join(ROOT, "paper_1208_3658_amd", "csrc", x) for x in sources]
     if not os.path.exists(rec):
         return None
     with open(rec) as f:
         r = json.load(f)
-    return r["traffic_bytes_per_launch"] if r.get("kernel_code_sha256") == code_fingerprint(src) else None
+    return r["traffic_bytes_per_launch"] if r.get("kernel_code_sha256") == code_fingerprint(srcs) else None
 
 
 # Aperture mass (Sec. 3): algorithmic flops per galaxy-point pair inside the
@@ -167,7 +176,7 @@ def aperture_main(args):
                    "pairs_in_aperture": pairs},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": recorded_traffic("k_ap_map_shear1M_grid2048_theta32_traffic.json", "pc_aperture.hip"),
+                     "traffic": recorded_traffic("k_ap_map_shear1M_grid2048_theta32_traffic.json", K_AP_MAP_SOURCES),
                      "kernel_ms": kern_s * 1e3,
                      "work_per_pair": AP_FLOPS_PER_PAIR, "pairs_tested": info["pairs_tested"],
                      "cell_side_arcmin": info["cell_side"]},
@@ -262,11 +271,11 @@ def serve_oracle_check(pc, reqs, cats, randoms, results, budget_s: float, seed: 
     * whole requests: DD and DR of the smallest requests, smallest first,
       until about half of budget_s seconds of oracle time are spent;
     * every request: its served DD, DR and RR equal one direct launch of the
-      same jobs (pc_count_batch on the same catalogues and edges), and a
-      seeded window of 32 data rows of that request's DD and DR, counted by
-      the library (pc_count_ex row range) and by the oracle, agree: the
-      oracle pins a sample of every request's counts, the direct launch ties
-      them to the served answer.
+      same jobs (pc_count_batch on the same catalogues and edges), and windows
+      of 8 data rows of that request's DR (seeded) and DD (near the end of
+      the catalogue), counted by the library (pc_count_ex row range) and by
+      the oracle, agree: the oracle pins a sample of every request's counts,
+      the direct launch ties them to the served answer.
     (RR of a 10^6-point pool catalogue is 5e11 pairs per edge set, minutes of
     oracle time each: RR is tied to the direct launch only; the tests pin the
     library's RR against the oracle.)"""
@@ -287,30 +296,56 @@ def serve_oracle_check(pc, reqs, cats, randoms, results, budget_s: float, seed: 
         n_max = max(n_max, int(cat[0].size))
         pairs += int(dd.sum()) + int(dr.sum())
     whole_s = time.perf_counter() - t0
+    import torch
+
+    def dev(cat):
+        return tuple(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in cat)
+
     rng = np.random.default_rng(seed)
     t1 = time.perf_counter()
+    r_dev = [dev(R) for R in randoms]                       # the pool catalogues, once
+    r_xyz = [oracle.unit_vectors(*R) for R in randoms]
+
+    def oracle_rows(cat, e, p, dr_rows, dd_rows):
+        # DR: data rows dr_rows against all randoms; DD: pairs i < j with i
+        # in dd_rows, from the catalogue's tail (the oracle converts only that)
+        c2 = oracle.chord2_edges(e)
+        (a, b), (t0_, t1_) = dr_rows, dd_rows
+        o_dr = oracle.count_xyz(oracle.unit_vectors(cat[0][a:b], cat[1][a:b]), c2, r_xyz[p], auto=False)
+        o_dd = oracle.count_xyz(oracle.unit_vectors(cat[0][t0_:], cat[1][t0_:]), c2, rows=(0, t1_ - t0_))
+        return o_dd, o_dr
+
+    from concurrent.futures import ThreadPoolExecutor
     direct_same, rows_same, row_pairs = True, True, 0
-    for k, (r, cat, res) in enumerate(zip(reqs, cats, results)):
-        R = randoms[r["patch"]]
-        dd, dr, rr = pc.pc_count_batch([{"A": cat, "edges": r["edges"]},
-                                        {"A": cat, "B": R, "edges": r["edges"], "auto": False},
-                                        {"A": R, "edges": r["edges"]}])
-        direct_same &= (res["DD"].tolist() == dd.tolist() and res["DR"].tolist() == dr.tolist()
-                        and res["RR"].tolist() == rr.tolist())
-        n = int(cat[0].size)
-        a = int(rng.integers(0, max(n - 32, 0) + 1))
-        b = min(a + 32, n)
-        g_dd = pc.pc_count_ex(cat, r["edges"], rows=(a, b))
-        g_dr = pc.pc_count_ex(cat, r["edges"], B=R, auto=False, rows=(a, b))
-        o_dd = oracle.count(cat, r["edges"], rows=(a, b))
-        o_dr = oracle.count(cat, r["edges"], B=R, auto=False, rows=(a, b))
-        rows_same &= g_dd.tolist() == o_dd.tolist() and g_dr.tolist() == o_dr.tolist()
-        row_pairs += int(o_dd.sum()) + int(o_dr.sum())
+    pending = []
+    with ThreadPoolExecutor(max_workers=8) as pool:
+        for k, (r, cat, res) in enumerate(zip(reqs, cats, results)):
+            p, e = r["patch"], r["edges"]
+            d_cat = dev(cat)
+            dd, dr, rr = pc.pc_count_batch([{"A": d_cat, "edges": e},
+                                            {"A": d_cat, "B": r_dev[p], "edges": e, "auto": False},
+                                            {"A": r_dev[p], "edges": e}])
+            direct_same &= (res["DD"].tolist() == dd.tolist() and res["DR"].tolist() == dr.tolist()
+                            and res["RR"].tolist() == rr.tolist())
+            # a seeded window of W data rows for DR; for DD the W rows that
+            # start 2048 rows before the catalogue's end
+            n, W = int(cat[0].size), 8
+            a = int(rng.integers(0, max(n - W, 0) + 1))
+            dr_rows = (a, min(a + W, n))
+            t0_ = max(n - 2048 - W, 0)
+            dd_rows = (t0_, min(t0_ + W, n))
+            g_dr = pc.pc_count_ex(d_cat, e, B=r_dev[p], auto=False, rows=dr_rows)
+            g_dd = pc.pc_count_ex(d_cat, e, rows=dd_rows)
+            pending.append((g_dd, g_dr, pool.submit(oracle_rows, cat, e, p, dr_rows, dd_rows)))
+        for g_dd, g_dr, fut in pending:
+            o_dd, o_dr = fut.result()
+            rows_same &= g_dd.tolist() == o_dd.tolist() and g_dr.tolist() == o_dr.tolist()
+            row_pairs += int(o_dd.sum()) + int(o_dr.sum())
     return {"requests": checked, "of": len(reqs), "n_max": n_max, "pairs": pairs, "identical_dd_dr": bool(same),
             "oracle_s": whole_s, "threads": oracle.num_threads(),
             "sample": "the smallest requests (whole DD and DR) within half the oracle time budget",
             "every_request": {"requests": len(reqs), "served_equal_direct_launch_dd_dr_rr": bool(direct_same),
-                              "row_window": 32, "row_window_pairs": row_pairs,
+                              "row_window": 8, "row_window_pairs": row_pairs,
                               "rows_identical_to_oracle_dd_dr": bool(rows_same),
                               "seconds": time.perf_counter() - t1}}
 
@@ -347,11 +382,23 @@ def serve_run(pc, n_req: int, seed_config: int = 5, loads=(0.7,), fp64_compare: 
         res = [srv.poll(j) for j in ids]
         st = srv.stats()
         srv.close()
-        lat = np.sort(np.array([x["latency_s"] for x in res]))
+        lat_raw = np.array([x["latency_s"] for x in res])
+        lat = np.sort(lat_raw)
+        # where the tail lives: latencies of the requests grouped by their
+        # DD + DR pairs (quantiles of request size)
+        size = np.array([r["n"] * (r["n"] - 1) / 2 + r["n"] * randoms[r["patch"]][0].size for r in reqs])
+        by_size, order = [], np.argsort(size, kind="stable")
+        for q0, q1 in ((0.0, 0.5), (0.5, 0.9), (0.9, 0.99), (0.99, 1.0)):
+            sel = order[int(round(q0 * len(order))):int(round(q1 * len(order)))]
+            if sel.size:
+                ls = lat_raw[sel]
+                by_size.append({"size_quantiles": [q0, q1], "requests": int(sel.size),
+                                "max_pairs": float(size[sel].max()), "p50_s": float(np.percentile(ls, 50)),
+                                "p99_s": float(np.percentile(ls, 99)), "max_s": float(ls.max())})
         return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                 "gpairs_s": st["pairs"] / wall / 1e9, "wall_s": wall, "batches": st["batches"],
                 "rr_cached": st["rr_cached"], "parts_requeued": st.get("parts_requeued", 0),
-                "slice_pairs": st.get("slice_pairs")}, res
+                "slice_pairs": st.get("slice_pairs"), "latency_by_size": by_size}, res
 
     mixed_cfg = {"streams": 2, "max_inflight": 64, **(server_cfg or {})}
     closed, _ = run(np.zeros(n_req), mixed_cfg)
@@ -552,7 +599,7 @@ def main():
                    + ("+tuned" if mode & pc.PC_TUNED else "")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": recorded_traffic("k_count_mixed_1M_traffic.json", "pc_kernels.hip")
+                     "traffic": recorded_traffic("k_count_mixed_1M_traffic.json", K_COUNT_SOURCES)
                      if args.workload == "1m" and args.mode == "mixed" else None,
                      "frac_method": achieved_method / peak, "achieved_method": achieved_method,
                      "work_per_pair_method": work_method / max(prn["pairs_computed"], 1),

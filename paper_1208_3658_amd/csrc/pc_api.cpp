@@ -24,6 +24,8 @@ namespace pc {
 hipError_t launch_convert(const double *ra, const double *dec, int64_t n, double4 *a64, float4 *a32,
                           int *err, hipStream_t st);
 hipError_t launch_zero(unsigned long long *p, int64_t n, hipStream_t st);
+hipError_t launch_add_copies(unsigned long long *dst, const unsigned long long *src, int64_t n, int32_t n_copies,
+                             hipStream_t st);
 size_t sort_scratch_words(int64_t n);
 
 // the per-tile-size steps (pc_kernels.hip, pc_prep.hip; one instance per size)
@@ -575,9 +577,10 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
         }
     }
     // results block, read back with one copy: meta[kMetaWords] | each job's counts | conversion flags
-    // (meta[0..6]: pruning figures, meta[7]: re-check tally, meta[8..15]: the
-    // counting kernel's work queue, meta[16..21]: computed pairs by path)
-    constexpr size_t kMetaWords = 24;
+    // (meta[0]: survivors, meta[7]: re-check tally, meta[8..15]: the counting
+    // kernel's work queue, from meta[kPruneStatBase]: the prune pass's
+    // statistics in kPruneStripes copies)
+    constexpr size_t kMetaWords = kPruneStatBase + kPruneStripes * kPruneStripeWords;
     size_t res_words = kMetaWords;
     for (size_t q = 0; q < jobs.size(); ++q) res_words += static_cast<size_t>(jobs[q].n_edges + 1);
     const size_t err_words = (std::max<size_t>(srcs.size(), 1) + 1) / 2;
@@ -591,6 +594,10 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
     }
     const size_t o_err = o_res + sizeof(unsigned long long) * res_words;
     const size_t o_meta = o_res;
+    // the prune pass's copies of every job's counters (zeroed with the results)
+    const size_t count_words = res_words - kMetaWords;
+    const size_t o_pcopies = ar.take(sizeof(unsigned long long) * kPruneStripes * count_words);
+    const size_t zero_words = (o_pcopies - o_res) / sizeof(unsigned long long) + kPruneStripes * count_words;
     const size_t o_scratch = ar.take(sizeof(uint32_t) * (max_sort_n > 0 ? sort_scratch_words(max_sort_n) : 1));
 
     // ---- segments
@@ -673,7 +680,7 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
     }
 
     // ---- convert the sources (validity flags read back at the end)
-    PC_HIP(launch_zero(reinterpret_cast<unsigned long long *>(W + o_res), static_cast<int64_t>(res_words + err_words), st),
+    PC_HIP(launch_zero(reinterpret_cast<unsigned long long *>(W + o_res), static_cast<int64_t>(zero_words), st),
            "zero results");
     std::vector<const double4 *> src_a64(srcs.size(), nullptr);
     for (size_t k = 0; k < srcs.size(); ++k) {
@@ -748,6 +755,9 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
         sd.jg = vp[vj].g32s;
         sd.jb_sub = vp[vj].sub_bounds;
         sd.counts = reinterpret_cast<unsigned long long *>(W + plan[static_cast<size_t>(sd.job)].o_counts);
+        sd.pcounts = reinterpret_cast<unsigned long long *>(W + o_pcopies + plan[static_cast<size_t>(sd.job)].o_counts -
+                                                            o_res - sizeof(unsigned long long) * kMetaWords);
+        sd.pstride = static_cast<int64_t>(count_words);
     }
     std::vector<TableDesc> tds;
     uint32_t hist_max = 0, lut_max = 0;
@@ -780,10 +790,15 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
     uint64_t *sub_words = reinterpret_cast<uint64_t *>(W + o_sub);
     int grid = 0;
     if (items > 0) {
-        if (prune)
+        if (prune) {
             PC_HIP(T.launch_prune(d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune_rows, surv,
                                 split ? sub_words : nullptr, meta, mc ? 1 : 0, split ? 1 : 0, st),
                    "prune");
+            PC_HIP(launch_add_copies(reinterpret_cast<unsigned long long *>(W + o_res) + kMetaWords,
+                                     reinterpret_cast<const unsigned long long *>(W + o_pcopies),
+                                     static_cast<int64_t>(count_words), kPruneStripes, st),
+                   "add prune counts");
+        }
         int per_cu = 0;
         PC_HIP(T.count_occupancy(fp64, mc, lds_bytes, &per_cu), "occupancy");
         per_cu = std::max(per_cu, 1);
@@ -818,6 +833,9 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
         memcpy(jobs[q].counts, hres.data() + (plan[q].o_counts - o_res) / sizeof(unsigned long long),
                sizeof(uint64_t) * static_cast<size_t>(jobs[q].n_edges + 1));
     const unsigned long long *hmeta = hres.data();
+    uint64_t ps[kPruneStats] = {};  // the prune pass's statistics, stripes added up
+    for (int c = 0; c < kPruneStripes; ++c)
+        for (int k = 1; k < kPruneStats; ++k) ps[k] += hmeta[kPruneStatBase + c * kPruneStripeWords + k];
 
     uint64_t total_pairs = 0;
     for (const SegDesc &sd : segs) {
@@ -832,14 +850,14 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
     t_last.kernel_ms = -1.0;
     t_last.survivors = prune ? hmeta[0] : items;
     t_last.pairs_total = total_pairs;
-    t_last.pairs_computed = prune ? hmeta[1] : total_pairs;
-    t_last.mfma_items = prune ? hmeta[3] : 0;
-    t_last.few_items = prune ? hmeta[4] : 0;
-    t_last.gram_items = prune ? hmeta[5] : 0;
-    t_last.split_items = prune ? hmeta[6] : 0;
+    t_last.pairs_computed = prune ? ps[1] : total_pairs;
+    t_last.mfma_items = prune ? ps[2] : 0;
+    t_last.few_items = prune ? ps[3] : 0;
+    t_last.gram_items = prune ? ps[4] : 0;
+    t_last.split_items = prune ? ps[5] : 0;
     t_last.rechecked = hmeta[7];
-    for (int m = 0; m < 4; ++m) t_last.pairs_by_m[m] = prune ? hmeta[16 + m] : 0;
-    t_last.pairs_gram = prune ? hmeta[20] : 0;
+    for (int m = 0; m < 4; ++m) t_last.pairs_by_m[m] = prune ? ps[6 + m] : 0;
+    t_last.pairs_gram = prune ? ps[10] : 0;
     if (!prune || fp64) {
         // every computed pair through the cell table (the binary64 kernel
         // ignores the few-edge tags)
@@ -847,7 +865,7 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
         for (int m = 1; m < 4; ++m) t_last.pairs_by_m[m] = 0;
         t_last.pairs_gram = 0;
     }
-    t_last.pairs_mfma = prune ? hmeta[21] : 0;
+    t_last.pairs_mfma = prune ? ps[11] : 0;
     t_last.workspace_bytes = ar.size;
     if (t_timing && !ext && items > 0) {
         float ms = 0.0f;

@@ -34,6 +34,16 @@ constexpr int kWave = 64;                 // gfx950 wavefront
 constexpr int kR = PC_R;                  // i-points held per lane
 constexpr int kTile = kWave * kR;         // points per tile, both axes (square tiles)
 constexpr int kMaxEdges = 1024;       // theta edges per table
+// The prune pass's statistics (12 words) are added into kPruneStripes copies
+// of kPruneStripeWords words at word kPruneStatBase of the launch's results
+// block, a copy per group of workgroups; the host adds the copies up.  Its
+// whole-tile-pair counts go to kPruneStripes copies of the jobs' counters in
+// the same way, which one small kernel adds into the counters.  Device-wide
+// atomics on one address serialise, and every workgroup has some to add.
+constexpr int kPruneStats = 12;
+constexpr int kPruneStripes = 16;
+constexpr int kPruneStripeWords = 16;
+constexpr int kPruneStatBase = 32;
 constexpr int kJPad = 16;               // readable points past the end of an ordered binary32 copy
 constexpr int kMaxLutCells = 1024;        // per table, 16 bytes each
 constexpr uint32_t kLdsTarget = 16 * 1024;  // per-wave histogram bytes aimed for at most
@@ -140,6 +150,10 @@ struct SegDesc {
     int64_t prow0;          // first row of the segment in the prune pass's row space
     int32_t tri, tab, job, pad;
     unsigned long long *counts;  // the job's n_edges+1 device counters
+    // the prune pass's copies of the job's counters: copy c at pcounts + c *
+    // pstride, c < kPruneStripes (added into counts after the pass)
+    unsigned long long *pcounts;
+    int64_t pstride;
 };
 
 // Host-side form of an edge set.

@@ -187,6 +187,25 @@ hipError_t launch_zero_u32(uint32_t *p, int64_t m, hipStream_t st) {
     return hipGetLastError();
 }
 
+// dst[w] += sum over s < n_copies of src[s * n + w], w < n (one thread per word)
+__global__ void __launch_bounds__(256) k_add_copies(unsigned long long *__restrict__ dst,
+                                                    const unsigned long long *__restrict__ src, int64_t n,
+                                                    int32_t n_copies) {
+    const int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (w >= n) return;
+    unsigned long long v = 0;
+    for (int32_t s = 0; s < n_copies; ++s) v += src[static_cast<int64_t>(s) * n + w];
+    dst[w] += v;
+}
+
+hipError_t launch_add_copies(unsigned long long *dst, const unsigned long long *src, int64_t n, int32_t n_copies,
+                             hipStream_t st) {
+    if (n <= 0 || n_copies <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    k_add_copies<<<dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, st>>>(dst, src, n, n_copies);
+    return hipGetLastError();
+}
+
 // In-place exclusive prefix sum of a[0, m); sums: scan_sums_words(m) words.
 hipError_t launch_exclusive_scan(uint32_t *a, int64_t m, uint32_t *sums, hipStream_t st) {
     if (m <= 0) return hipSuccess;
@@ -368,8 +387,16 @@ __device__ __forceinline__ void chord_interval(const double4 &bi, const double4 
     c_hi = hi * hi * (1.0 + 1e-12) + 1e-300;
 }
 
+// far_l: a chord length past the last edge, sqrt(e[n_edges - 1]) * (1 +
+// 1e-12) in binary64.  A tile pair whose squared centre distance d2 exceeds
+// (far_l + r_I + r_J)^2 (1 + 1e-12) has every chord past the last edge: the
+// computed d2 is at most 5 ulp above the true squared distance D^2 and the
+// bound at most 4 ulp below its value, so D - r_I - r_J > far_l (1 + 0.49e-12);
+// every pair is at least that far apart, and its binary64 squared chord
+// (5 ulp) stays above e[n_edges - 1].
 template <typename P>
-__device__ __forceinline__ PruneOut prune_item(const SegDesc &sd, int64_t t, int64_t u, P e, int32_t n_edges,
+__device__ __forceinline__ PruneOut prune_item(const SegDesc &sd, int64_t t, int64_t u, const double4 &bi,
+                                               const double4 &bj, P e, int32_t n_edges, double far_l,
                                                int32_t mfma_ok, int32_t split_ok) {
     PruneOut o;
     o.sub = 0;
@@ -377,10 +404,26 @@ __device__ __forceinline__ PruneOut prune_item(const SegDesc &sd, int64_t t, int
     const int64_t nj = min<int64_t>(kTile, sd.nj - u * kTile);
     const bool diag = sd.tri && t == u;
     o.pairs = diag ? static_cast<uint64_t>(ni * (ni - 1) / 2) : static_cast<uint64_t>(ni * nj);
-    const double4 bi = sd.ib[t];
-    const double4 bj = sd.jb[u];
+    {
+        // past the last edge without the square root (most tile pairs of a
+        // wide field)
+        const double dx = bi.x - bj.x, dy = bi.y - bj.y, dz = bi.z - bj.z;
+        const double reach = far_l + (bi.w + bj.w);
+        if (dx * dx + dy * dy + dz * dz > reach * reach * (1.0 + 1e-12)) {
+            o.bin = n_edges;
+            o.tags = 0;
+            return o;
+        }
+    }
     double lo, c_lo, c_hi;
     chord_interval(bi, bj, lo, c_lo, c_hi);
+    if (c_lo > e[n_edges - 1]) {
+        // the whole interval lies past the last edge (most tile pairs of a
+        // wide field): the bin above it, without the two searches
+        o.bin = n_edges;
+        o.tags = 0;
+        return o;
+    }
     const uint32_t k_lo = count_le(e, n_edges, c_lo);
     const uint32_t k_hi = count_le(e, n_edges, c_hi);
     if (k_lo == k_hi) {
@@ -463,6 +506,24 @@ __device__ __forceinline__ bool row_item(const SegDesc &sd, int64_t r, int64_t c
     return c < sd.tiles_j;
 }
 
+constexpr int kPruneThreads = 256;     // threads per prune workgroup
+constexpr int kPruneMaskSteps = 128;  // steps of 256 columns whose survivor ballots are kept (4 KB)
+
+// Column c of prune row r with the bounds of its two tiles; a column past the
+// row's end (valid false) loads the bounds of tile 0, which every segment has.
+struct PruneCol {
+    int64_t t, u;
+    uint64_t q;
+    bool valid;
+    double4 bi, bj;
+};
+
+__device__ __forceinline__ void load_col(const SegDesc &sd, int64_t r, int64_t c, PruneCol &k) {
+    k.valid = row_item(sd, r, c, k.t, k.u, k.q);
+    k.bi = sd.ib[k.valid ? k.t : 0];
+    k.bj = sd.jb[k.valid ? k.u : 0];
+}
+
 // One workgroup per row of tile pairs (one i-tile, or the two i-tiles of a
 // folded triangle row), threads across its columns: (t, u) and the item
 // number come without divisions, and the edges of the row's table sit in LDS.
@@ -471,29 +532,32 @@ __device__ __forceinline__ bool row_item(const SegDesc &sd, int64_t r, int64_t c
 // atomic and writes them in a second pass (the decision is recomputed), and
 // flushes its histogram and statistics with one atomic per non-zero entry --
 // global atomics on a few shared counters would otherwise serialise the pass.
-__global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs, int32_t n_segs,
+__global__ void __launch_bounds__(kPruneThreads) k_prune(const SegDesc *__restrict__ segs, int32_t n_segs,
                                                const TableDesc *__restrict__ tabs,
                                                uint64_t *__restrict__ survivors, uint64_t *__restrict__ sub_out,
                                                unsigned long long *__restrict__ meta, int32_t mfma_ok,
                                                int32_t split_ok) {
-    // meta[0] = survivors, meta[1] = pairs left for the counting kernel,
-    // meta[2] = pairs binned whole, meta[3] = survivors marked for the matrix
-    // cores; work units (a survivor, or an open sub-block of a split one):
-    // meta[4] with at most PC_FEWCUT edges in their chord interval, meta[5]
-    // with vector-path chords in Gram form; meta[6] = split survivors.
-    // Pairs left for the counting kernel by the path it takes them through
-    // (the same decisions as k_count): meta[16 + m] = pairs binned against m
-    // edges one by one (m = 1..3), meta[16] = pairs binned through the cell
-    // table; meta[20] = pairs whose chords the vector path forms in Gram form,
-    // meta[21] = pairs on the matrix cores.
+    // meta[0] = survivors (the slot counter).  Statistics, summed over the
+    // kPruneStripes stripes at meta[kPruneStatBase + stripe * kPruneStripeWords
+    // + k] (k as in s_stat): k = 1 pairs left for the counting kernel, 2
+    // survivors marked for the matrix cores; work units (a survivor, or an
+    // open sub-block of a split one): 3 with at most PC_FEWCUT edges in their
+    // chord interval, 4 with vector-path chords in Gram form; 5 split
+    // survivors; pairs left for the counting kernel by the path it takes them
+    // through (the same decisions as k_count): 6 + m binned against m edges
+    // one by one (m = 1..3), 6 through the cell table; 10 pairs whose chords
+    // the vector path forms in Gram form, 11 pairs on the matrix cores.
     __shared__ double e_lds[kMaxEdges];
     __shared__ unsigned long long h_lds[kMaxEdges + 1];
     // survivors, pairs, matrix-core, few-edge, Gram, split; pairs by m (4),
     // Gram-form pairs, matrix-core pairs
-    constexpr int kStats = 12;
+    static_assert(kPruneStats <= kPruneStripeWords, "statistics per stripe");
+    constexpr int kStats = kPruneStats;
     __shared__ unsigned long long s_stat[kStats];
-    __shared__ unsigned long long s_base, s_whole;
+    __shared__ unsigned long long s_base;
     __shared__ unsigned int s_cursor;
+    // survivor ballots of the first kPruneMaskSteps steps of each wave
+    __shared__ uint64_t s_mask[kPruneMaskSteps][kPruneThreads / kWave];
     const int64_t row_g = blockIdx.x;
     int s = 0;  // last segment with prow0 <= row_g
     {
@@ -513,33 +577,42 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
     for (int32_t k = tid; k < n_edges; k += blockDim.x) e_lds[k] = td.e64[k];
     for (int32_t k = tid; k <= n_edges; k += blockDim.x) h_lds[k] = 0ull;
     if (tid < kStats) s_stat[tid] = 0ull;
-    if (tid == 0) {
-        s_whole = 0ull;
-        s_cursor = 0u;
-    }
+    if (tid == 0) s_cursor = 0u;
     __syncthreads();
     const int64_t r = row_g - sd.prow0;
     const int64_t cols = sd.tri ? sd.tiles_i + 1 : sd.tiles_j;
+    const double far_l = sqrt(e_lds[n_edges - 1]) * (1.0 + 1e-12);
     constexpr unsigned long long kSubPairs = static_cast<unsigned long long>(kTile) * kSub;
 
-    // pass 1: histogram of whole tile pairs and sub-blocks, statistics of survivors
-    for (int64_t c0 = 0; c0 < cols; c0 += blockDim.x) {
-        int64_t t, u;
-        uint64_t q;
-        const bool valid = row_item(sd, r, c0 + tid, t, u, q);
+    // pass 1: histogram of whole tile pairs and sub-blocks, statistics of
+    // survivors.  Whole tile pairs past the last edge (most of them in a wide
+    // field) and the statistics add up in registers over the row and are
+    // reduced once at its end; other whole tile pairs go to the LDS histogram.
+    unsigned long long above = 0;
+    // survivors, pairs left, matrix-core items, few-edge work units, Gram
+    // work units, split items; pairs by the counting kernel's path: by edges
+    // compared one by one (index m, 0 = cell table), Gram-form chords, matrix
+    // cores (the layout of s_stat)
+    unsigned long long st[kStats];
+#pragma unroll
+    for (int k = 0; k < kStats; ++k) st[k] = 0ull;
+    // the next column's tiles load while this one is judged; each wave keeps
+    // the ballot of its survivors per step for the second pass
+    PruneCol cur, nxt;
+    load_col(sd, r, tid, cur);
+    nxt = cur;
+    const int wave = tid / kWave;
+    for (int64_t c0 = 0, it = 0; c0 < cols; c0 += kPruneThreads, ++it) {
+        if (c0 + kPruneThreads < cols) load_col(sd, r, c0 + kPruneThreads + tid, nxt);
         bool survive = false;
-        unsigned long long pairs = 0, few_u = 0, gram_u = 0;
-        // pairs by the counting kernel's path: by edges compared one by one
-        // (index m, 0 = cell table), Gram-form chords, matrix cores
-        unsigned long long by_m[4] = {0, 0, 0, 0}, gram_p = 0, mfma_p = 0;
-        uint64_t tags = 0, sub = 0;
-        if (valid) {
-            const PruneOut o = prune_item(sd, t, u, e_lds, n_edges, mfma_ok, split_ok);
-            if (o.bin >= 0) {
+        if (cur.valid) {
+            const PruneOut o = prune_item(sd, cur.t, cur.u, cur.bi, cur.bj, e_lds, n_edges, far_l, mfma_ok, split_ok);
+            survive = o.bin < 0;
+            if (o.bin == n_edges) {
+                above += o.pairs;
+            } else if (o.bin >= 0) {
                 atomicAdd(&h_lds[o.bin], static_cast<unsigned long long>(o.pairs));
             } else if (o.sub) {
-                sub = o.sub;
-                tags = o.tags;
                 // the kernel forms a split item's chords in Gram form when
                 // every open sub-block allows it
                 bool gram_all = true;
@@ -548,6 +621,7 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                     const uint32_t f = static_cast<uint32_t>(o.sub >> (16 * k)) & 0xFFFFu;
                     if (!(f & kSubWhole) && !(f & kSubGram)) gram_all = false;
                 }
+                unsigned long long left = 0;
 #pragma unroll
                 for (int k = 0; k < kSubs; ++k) {
                     const uint32_t f = static_cast<uint32_t>(o.sub >> (16 * k)) & 0xFFFFu;
@@ -555,55 +629,46 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
                         atomicAdd(&h_lds[f & 2047u], kSubPairs);
                     } else {
                         const uint32_t m = (f >> 11) & 3u;
-                        pairs += kSubPairs;
-                        few_u += m != 0u ? 1ull : 0ull;
-                        gram_u += (f & kSubGram) != 0u ? 1ull : 0ull;
-                        by_m[m] += kSubPairs;
-                        gram_p += gram_all ? kSubPairs : 0ull;
+                        left += kSubPairs;
+                        st[3] += m != 0u ? 1ull : 0ull;
+                        st[4] += (f & kSubGram) != 0u ? 1ull : 0ull;
+                        st[6 + m] += kSubPairs;
+                        st[10] += gram_all ? kSubPairs : 0ull;
                     }
                 }
-                survive = pairs != 0;
+                st[0] += left != 0 ? 1ull : 0ull;
+                st[1] += left;
+                st[5] += left != 0 ? 1ull : 0ull;
+                survive = left != 0;
             } else {
-                survive = true;
-                pairs = o.pairs;
-                tags = o.tags;
-                const uint32_t m = static_cast<uint32_t>((tags >> (kItemBits + 11)) & 3u);
-                const bool mc = (tags >> 63) != 0;
-                few_u = m != 0u ? 1ull : 0ull;
-                gram_u = ((tags >> 61) & 1u) != 0 ? 1ull : 0ull;
-                by_m[m] = pairs;
-                gram_p = (!mc && gram_u && m != 0u) ? pairs : 0ull;
-                mfma_p = mc ? pairs : 0ull;
+                const uint32_t m = static_cast<uint32_t>((o.tags >> (kItemBits + 11)) & 3u);
+                const bool mc = (o.tags >> 63) != 0;
+                const bool gram = ((o.tags >> 61) & 1u) != 0;
+                st[0] += 1ull;
+                st[1] += o.pairs;
+                st[2] += mc ? 1ull : 0ull;
+                st[3] += m != 0u ? 1ull : 0ull;
+                st[4] += gram ? 1ull : 0ull;
+                st[6 + m] += o.pairs;
+                st[10] += (!mc && gram && m != 0u) ? o.pairs : 0ull;
+                st[11] += mc ? o.pairs : 0ull;
             }
         }
         const uint64_t sm = __ballot(survive);
-        if (sm) {
+        if (it < kPruneMaskSteps && lane == 0) s_mask[it][wave] = sm;
+        cur = nxt;
+    }
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                pairs += __shfl_xor(pairs, o, kWave);
-                few_u += __shfl_xor(few_u, o, kWave);
-                gram_u += __shfl_xor(gram_u, o, kWave);
+    for (int o = 32; o > 0; o >>= 1) {
+        above += __shfl_xor(above, o, kWave);
 #pragma unroll
-                for (int m = 0; m < 4; ++m) by_m[m] += __shfl_xor(by_m[m], o, kWave);
-                gram_p += __shfl_xor(gram_p, o, kWave);
-                mfma_p += __shfl_xor(mfma_p, o, kWave);
-            }
-            const uint64_t mm = __ballot(survive && (tags >> 63) != 0);
-            const uint64_t ms = __ballot(survive && sub != 0);
-            if (lane == 0) {
-                atomicAdd(&s_stat[0], static_cast<unsigned long long>(__popcll(sm)));
-                atomicAdd(&s_stat[1], pairs);
-                atomicAdd(&s_stat[2], static_cast<unsigned long long>(__popcll(mm)));
-                atomicAdd(&s_stat[3], few_u);
-                atomicAdd(&s_stat[4], gram_u);
-                atomicAdd(&s_stat[5], static_cast<unsigned long long>(__popcll(ms)));
+        for (int k = 0; k < kStats; ++k) st[k] += __shfl_xor(st[k], o, kWave);
+    }
+    if (lane == 0) {
+        if (above) atomicAdd(&h_lds[n_edges], above);
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    if (by_m[m]) atomicAdd(&s_stat[6 + m], by_m[m]);
-                if (gram_p) atomicAdd(&s_stat[10], gram_p);
-                if (mfma_p) atomicAdd(&s_stat[11], mfma_p);
-            }
-        }
+        for (int k = 0; k < kStats; ++k)
+            if (st[k]) atomicAdd(&s_stat[k], st[k]);
     }
     __syncthreads();
     if (tid == 0) s_base = s_stat[0] ? atomicAdd(meta + 0, s_stat[0]) : 0ull;
@@ -611,17 +676,24 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
 
     // pass 2: the survivors, written into the workgroup's reserved slots
     if (s_stat[0]) {
-        for (int64_t c0 = 0; c0 < cols; c0 += blockDim.x) {
-            int64_t t, u;
-            uint64_t q;
-            const bool valid = row_item(sd, r, c0 + tid, t, u, q);
+        const int wave = tid / kWave;
+        for (int64_t c0 = 0, it = 0; c0 < cols; c0 += kPruneThreads, ++it) {
+            // steps whose ballot the first pass kept: only their survivors
+            // are judged again
+            const uint64_t kept = it < kPruneMaskSteps ? s_mask[it][wave] : ~0ull;
+            if (kept == 0) continue;
             bool survive = false;
-            uint64_t tags = 0, sub = 0;
-            if (valid) {
-                const PruneOut o = prune_item(sd, t, u, e_lds, n_edges, mfma_ok, split_ok);
-                survive = o.bin < 0 && (o.sub == 0 || open_subs(o.sub) != 0);
-                tags = o.tags;
-                sub = o.sub;
+            uint64_t tags = 0, sub = 0, q = 0;
+            if ((kept >> lane) & 1u) {
+                PruneCol k;
+                load_col(sd, r, c0 + tid, k);
+                if (k.valid) {
+                    const PruneOut o = prune_item(sd, k.t, k.u, k.bi, k.bj, e_lds, n_edges, far_l, mfma_ok, split_ok);
+                    survive = o.bin < 0 && (o.sub == 0 || open_subs(o.sub) != 0);
+                    tags = o.tags;
+                    sub = o.sub;
+                    q = k.q;
+                }
             }
             const uint64_t sm = __ballot(survive);
             if (sm) {
@@ -639,32 +711,15 @@ __global__ void __launch_bounds__(256) k_prune(const SegDesc *__restrict__ segs,
         }
     }
 
-    // flush: one atomic per non-zero bin and per statistic
-    unsigned long long whole = 0;
+    // flush: one atomic per non-zero bin and per statistic, into one of
+    // kPruneStripes copies (by workgroup) of the counters and statistics
+    unsigned long long *pc = sd.pcounts + static_cast<int64_t>(blockIdx.x % kPruneStripes) * sd.pstride;
     for (int32_t k = tid; k <= n_edges; k += blockDim.x) {
         const unsigned long long v = h_lds[k];
-        if (v) {
-            atomicAdd(sd.counts + k, v);
-            whole += v;
-        }
+        if (v) atomicAdd(pc + k, v);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) whole += __shfl_xor(whole, o, kWave);
-    if (lane == 0 && whole) atomicAdd(&s_whole, whole);
-    __syncthreads();
-    if (tid == 0) {
-        if (s_whole) atomicAdd(meta + 2, s_whole);
-        if (s_stat[0]) {
-            atomicAdd(meta + 1, s_stat[1]);
-            if (s_stat[2]) atomicAdd(meta + 3, s_stat[2]);
-            if (s_stat[3]) atomicAdd(meta + 4, s_stat[3]);
-            if (s_stat[4]) atomicAdd(meta + 5, s_stat[4]);
-            if (s_stat[5]) atomicAdd(meta + 6, s_stat[5]);
-#pragma unroll
-            for (int k = 6; k < kStats; ++k)
-                if (s_stat[k]) atomicAdd(meta + 10 + k, s_stat[k]);
-        }
-    }
+    if (tid > 0 && tid < kStats && s_stat[0] && s_stat[tid])
+        atomicAdd(meta + kPruneStatBase + (blockIdx.x % kPruneStripes) * kPruneStripeWords + tid, s_stat[tid]);
 }
 
 // Spatially ordered copy of src[base, base+n) into a64s/a32s, and the tile
@@ -686,7 +741,7 @@ hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *ta
                         int32_t split_ok, hipStream_t st) {
     if (total_rows <= 0) return hipSuccess;
     if (total_rows > 0x7FFFFFFF) return hipErrorInvalidValue;
-    k_prune<<<dim3(static_cast<uint32_t>(total_rows)), dim3(256), 0, st>>>(segs, n_segs, tabs, survivors, sub, meta,
+    k_prune<<<dim3(static_cast<uint32_t>(total_rows)), dim3(kPruneThreads), 0, st>>>(segs, n_segs, tabs, survivors, sub, meta,
                                                                           mfma_ok, split_ok);
     return hipGetLastError();
 }
