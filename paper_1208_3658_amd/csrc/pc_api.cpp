@@ -577,10 +577,11 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
         }
     }
     // results block, read back with one copy: meta[kMetaWords] | each job's counts | conversion flags
-    // (meta[0]: survivors, meta[7]: re-check tally, meta[8..15]: the counting
-    // kernel's work queue, from meta[kPruneStatBase]: the prune pass's
-    // statistics in kPruneStripes copies)
-    constexpr size_t kMetaWords = kPruneStatBase + kPruneStripes * kPruneStripeWords;
+    // (meta[0]: survivors, meta[7]: re-check tally, from meta[kPruneStatBase]:
+    // the prune pass's statistics in kPruneStripes copies, from
+    // meta[kQueueBase]: the counting kernel's work queue, 8 counters
+    // kQueueStride words apart)
+    constexpr size_t kMetaWords = kQueueBase + 8 * kQueueStride;
     size_t res_words = kMetaWords;
     for (size_t q = 0; q < jobs.size(); ++q) res_words += static_cast<size_t>(jobs[q].n_edges + 1);
     const size_t err_words = (std::max<size_t>(srcs.size(), 1) + 1) / 2;
@@ -815,7 +816,7 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
             PC_HIP(hipEventRecord(t_ev0, st), "hipEventRecord");
         }
         PC_HIP(T.launch_count(fp64, mc, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
-                            prune ? meta : nullptr, split ? sub_words : nullptr, items, lut_off, stage_off, meta + 8,
+                            prune ? meta : nullptr, split ? sub_words : nullptr, items, lut_off, stage_off, meta + kQueueBase,
                             meta + 7, lt.chunk, lds_bytes, grid, t_flush_cap, st),
                "count kernel");
         if (timed) PC_HIP(hipEventRecord(t_ev1, st), "hipEventRecord");

@@ -44,6 +44,10 @@ constexpr int kPruneStats = 12;
 constexpr int kPruneStripes = 16;
 constexpr int kPruneStripeWords = 16;
 constexpr int kPruneStatBase = 32;
+// The counting kernel's work queue: eight counters (one per XCD slice), each
+// in its own cache line, after the prune statistics.
+constexpr int kQueueStride = 16;
+constexpr int kQueueBase = kPruneStatBase + kPruneStripes * kPruneStripeWords;
 constexpr int kJPad = 16;               // readable points past the end of an ordered binary32 copy
 constexpr int kMaxLutCells = 1024;        // per table, 16 bytes each
 constexpr uint32_t kLdsTarget = 16 * 1024;  // per-wave histogram bytes aimed for at most

@@ -94,7 +94,7 @@ struct KParams {
     int32_t n_segs;
     uint32_t lut_lds_off;   // byte offset of the cell table in LDS (after the histogram)
     uint32_t stage_lds_off; // byte offset of the matrix-core path's A-operand block (16 x 64 floats)
-    unsigned long long *queue;  // 8 zeroed chunk counters, one per slice of the items
+    unsigned long long *queue;  // 8 zeroed chunk counters kQueueStride words apart, one per slice of the items
     unsigned long long *rechecked;  // zeroed; pairs re-checked in binary64 are added here
     uint32_t chunk;             // items taken from the queue at a time
     uint64_t flush_cap;         // > 0: flush the histogram at least every flush_cap items (testing)
@@ -1004,7 +1004,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 const uint32_t x = (x0 + xs) & 7u;
                 const uint64_t s0 = total * x / 8u, s1 = total * (x + 1u) / 8u;
                 unsigned long long c = 0;
-                if (lane == 0) c = atomicAdd(p.queue + x, static_cast<unsigned long long>(kChunk));
+                if (lane == 0) c = atomicAdd(p.queue + x * kQueueStride, static_cast<unsigned long long>(kChunk));
                 c = uniform_u64(c);
                 if (s0 + c < s1) {
                     wi = s0 + c;
