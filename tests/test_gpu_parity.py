@@ -255,6 +255,32 @@ def test_whole_tile_pair_binning_matches_every_pair(mode):
         oracle.count(A, e, rows=(650, 2900)).tolist()
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_tile_pairs_around_the_last_edge(mode):
+    """Clusters whose separations sit just below, at and just above the last
+    edge (20 deg): the prune pass bins a tile pair past the last edge from
+    its squared centre distance, without the square root; tile pairs on
+    either side of that bound must give the oracle's counts, pruned or not."""
+    rng = np.random.default_rng(33)
+    parts = [(0.3 * rng.standard_normal(2000), 0.3 * rng.standard_normal(2000))]
+    for k, d in enumerate([19.0, 19.8, 19.95, 20.0, 20.05, 20.2, 21.0, 23.0]):
+        # clusters on a small circle around (0, 0), each at distance ~d
+        pa = 2 * np.pi * k / 8
+        ra0, dec0 = d * np.cos(pa), d * np.sin(pa)
+        parts.append((ra0 + 0.3 * rng.standard_normal(700), dec0 + 0.3 * rng.standard_normal(700)))
+    A = (np.concatenate([p[0] for p in parts[:1]]), np.concatenate([p[1] for p in parts[:1]]))
+    B = (np.concatenate([p[0] for p in parts[1:]]) % 360.0, np.concatenate([p[1] for p in parts[1:]]))
+    A = (A[0] % 360.0, A[1])
+    AB = (np.concatenate([A[0], B[0]]), np.concatenate([A[1], B[1]]))
+    e = synth.log_edges(0.1, 20.0, 12)
+    want_cross = oracle.count(A, e, B=B, auto=False)
+    want_auto = oracle.count(AB, e)
+    assert want_cross[-1] > 0 and want_cross[-2] > 0  # pairs on both sides of the last edge
+    for extra in (0, pc.PC_NO_PRUNE):
+        assert pc.pc_count_ex(dev(A), e, B=dev(B), auto=False, mode=mode | extra).tolist() == want_cross.tolist()
+        assert pc.pc_count_ex(dev(AB), e, mode=mode | extra).tolist() == want_auto.tolist()
+
+
 def test_pruning_skips_most_pairs_on_the_1m_shape():
     c = synth.config_1m(n_parents=5_000, n_random=100_000)
     D, R, e = dev(c["D"]), dev(c["R"]), c["edges"]
