@@ -42,6 +42,19 @@ int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, int64_t *info
 int pc_debug_guard_band_gram(const double *theta_edges_deg, int32_t n_edges, float *lo, float *hi);
 
 /*
+ * pc_debug_fused_band -- the thresholds of the vector few-edge paths (h, w:
+ * host arrays of n_edges floats, written).  Those paths form d = h - c for
+ * the smallest edge of a work item in one chain of binary32 roundings (gram !=
+ * 0: tile-centred Gram chords; 0: differences of binary32 unit vectors), and
+ * for its other edges d_t = RN32(d + RN32(h_t - h)) (at most three edges, so
+ * the reference is at most two edges down); then d_t < 0 proves the binary64
+ * chord is at or above edge t, d_t > w_t proves it below, and 0 <= d_t <= w_t
+ * sends the pair to the binary64 re-check.  An edge at 0 gets h = -FLT_MAX,
+ * w = 0.  Returns PC_OK or PC_ERR_INVALID (bad edges).
+ */
+int pc_debug_fused_band(const double *theta_edges_deg, int32_t n_edges, int32_t gram, float *h, float *w);
+
+/*
  * pc_debug_set_timing -- on != 0: the calling thread's later counting calls
  * record HIP events around the counting kernel on the call's stream.
  */

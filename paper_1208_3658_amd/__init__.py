@@ -98,6 +98,7 @@ _SIGNATURES = {
     "pc_debug_last_launch": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "pc_debug_last_pruning": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "pc_debug_guard_band_gram": ([_vp, _i32, _vp, _vp], ctypes.c_int),
+    "pc_debug_fused_band": ([_vp, _i32, _i32, _vp, _vp], ctypes.c_int),
     "pc_server_create": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
     "pc_server_set_random": ([_vp, _i32, _PCAT], ctypes.c_int),
     "pc_server_submit": ([_vp, _PCAT, _i32, _vp, _i32, ctypes.POINTER(_u64)], ctypes.c_int),
@@ -401,6 +402,16 @@ def pc_guard_band(theta_edges, gram: bool = False):
     f = lib().pc_debug_guard_band_gram if gram else lib().pc_guard_band
     _check(f(tp, t.size, lo.ctypes.data, hi.ctypes.data))
     return lo, hi
+
+
+def pc_debug_fused_band(theta_edges, gram: bool = False):
+    """Per-edge thresholds (h, w) of the vector few-edge paths' fused
+    differences d = h - c; gram=True: tile-centred Gram chords."""
+    t, tp = _edges(theta_edges)
+    h = np.empty(t.size, dtype=np.float32)
+    w = np.empty(t.size, dtype=np.float32)
+    _check(lib().pc_debug_fused_band(tp, t.size, 1 if gram else 0, h.ctypes.data, w.ctypes.data))
+    return h, w
 
 
 def pc_debug_lut32(theta_edges):

@@ -168,12 +168,14 @@ DevTable::~DevTable() {
 }
 
 void table_blob(const HostTable &h, TableBlob *out) {
-    // one device block: e64 | band | band_g | lut32 | lut64
+    // one device block: e64 | band | band_g | fband | fband_g | lut32 | lut64
     const size_t b_e = sizeof(double) * h.e64.size();
     const size_t b_b = 2 * sizeof(float) * h.e64.size();
     out->o_band = (b_e + 255) & ~size_t(255);
     out->o_band_g = (out->o_band + b_b + 255) & ~size_t(255);
-    out->o_lut32 = (out->o_band_g + b_b + 255) & ~size_t(255);
+    out->o_fband = (out->o_band_g + b_b + 255) & ~size_t(255);
+    out->o_fband_g = (out->o_fband + b_b + 255) & ~size_t(255);
+    out->o_lut32 = (out->o_fband_g + b_b + 255) & ~size_t(255);
     const size_t b_l32 = sizeof(LutEntry32) * h.lut32.entries.size();
     out->o_lut64 = (out->o_lut32 + b_l32 + 255) & ~size_t(255);
     const size_t b_l64 = sizeof(LutEntry64) * h.lut64.size();
@@ -184,6 +186,9 @@ void table_blob(const HostTable &h, TableBlob *out) {
         const float bb[4] = {h.lo[k], h.hi[k], h.lo_g[k], h.hi_g[k]};
         memcpy(blob.data() + out->o_band + 8 * k, bb, 8);
         memcpy(blob.data() + out->o_band_g + 8 * k, bb + 2, 8);
+        const float fb[4] = {h.fh[k], h.fw[k], h.fh_g[k], h.fw_g[k]};
+        memcpy(blob.data() + out->o_fband + 8 * k, fb, 8);
+        memcpy(blob.data() + out->o_fband_g + 8 * k, fb + 2, 8);
     }
     if (b_l32) memcpy(blob.data() + out->o_lut32, h.lut32.entries.data(), b_l32);
     if (b_l64) memcpy(blob.data() + out->o_lut64, h.lut64.data(), b_l64);
@@ -193,6 +198,8 @@ void table_place(DevTable *t, const TableBlob &b, unsigned char *base) {
     t->d_e64 = reinterpret_cast<const double *>(base);
     t->d_band = reinterpret_cast<const float *>(base + b.o_band);
     t->d_band_g = reinterpret_cast<const float *>(base + b.o_band_g);
+    t->d_fband = reinterpret_cast<const float *>(base + b.o_fband);
+    t->d_fband_g = reinterpret_cast<const float *>(base + b.o_fband_g);
     t->d_lut32 = base + b.o_lut32;
     t->d_lut64 = base + b.o_lut64;
 }
@@ -271,6 +278,8 @@ TableDesc table_desc(const DevTable &t, bool fp64) {
         d.search = 0;
         d.band = t.d_band;
         d.band_g = t.d_band_g;
+        d.fband = t.d_fband;
+        d.fband_g = t.d_fband_g;
     }
     return d;
 }
@@ -1134,6 +1143,18 @@ extern "C" int pc_debug_lut32(const double *theta_edges_deg, int32_t n_edges, in
     info[7] = 0;
     if (entries && static_cast<int64_t>(L.entries.size()) <= max_cells)
         memcpy(entries, L.entries.data(), sizeof(LutEntry32) * L.entries.size());
+    return PC_OK;
+}
+
+extern "C" int pc_debug_fused_band(const double *theta_edges_deg, int32_t n_edges, int32_t gram, float *h,
+                                   float *w) {
+    clear_error();
+    if (!theta_edges_deg || !h || !w) return fail(PC_ERR_INVALID, "NULL argument");
+    HostTable t;
+    std::string err;
+    if (!build_table(theta_edges_deg, n_edges, t, err)) return fail(PC_ERR_INVALID, err);
+    memcpy(h, (gram ? t.fh_g : t.fh).data(), sizeof(float) * static_cast<size_t>(n_edges));
+    memcpy(w, (gram ? t.fw_g : t.fw).data(), sizeof(float) * static_cast<size_t>(n_edges));
     return PC_OK;
 }
 

@@ -92,9 +92,10 @@ struct TableDesc {
     int32_t n_edges;
     int32_t search;         // fp64 only: 1 = no exact cell table, binary search per pair
     int32_t cols;           // histogram lane columns (power of two <= 64)
-    // guard bands as (lo, hi) binary32 pairs per edge, plain and matrix-core
+    // guard bands as (lo, hi) binary32 pairs per edge, plain and matrix-core,
+    // and the vector few-edge paths' fused (h, W) pairs, plain and Gram
     // (mixed only; device)
-    const float *band, *band_g;
+    const float *band, *band_g, *fband, *fband_g;
 };
 
 // A survivor work item (one tile pair left after whole-tile-pair binning), as
@@ -172,6 +173,9 @@ struct HostTable {
     // mixed kernel: direct chords (binary32 unit vectors) and tile-centred
     // chords formed by the matrix cores, each with its own guard band
     std::vector<float> lo_g, hi_g;
+    // vector few-edge paths: thresholds h and flag widths W of the fused
+    // differences d = h - c (fused_bands), direct and tile-centred chords
+    std::vector<float> fh, fw, fh_g, fw_g;
     Lut32 lut32;
     // fp64 kernel
     uint32_t clamp_lo64 = 0, clamp_hi64 = 0, shift64 = 0;
@@ -195,5 +199,12 @@ void guard_band(double e, float *lo, float *hi);
 // matrix cores (coordinates centred on the tile of smaller bounding radius r,
 // every pair of the tile pair at chord >= 2 r).
 void guard_band_gram(double e, float *lo, float *hi);
+
+// Thresholds h and flag widths W of the vector few-edge paths, which form d =
+// h - c for the item's smallest edge in one chain of roundings and the other
+// edges' d from it (gram: tile-centred Gram chords, else differences of
+// binary32 unit vectors): d < 0 => c64 >= e; d > W => c64 < e; an edge at 0
+// gets h = -FLT_MAX, W = 0.
+void fused_bands(const std::vector<double> &e64, bool gram, std::vector<float> &h, std::vector<float> &w);
 
 }  // namespace pc

@@ -462,8 +462,10 @@ __device__ __forceinline__ void tile32(unsigned char *lds, const float4 *__restr
 // the exact row, -1 on the provisional one) goes to the histogram directly.
 
 struct FewCtx {
-    float lo[kFewMax], hi[kFewMax];  // bands of edges k0 .. k0+M-1
-    uint32_t w[kFewMax];             // bits of RN(hi - lo) per band
+    float lo[kFewMax], hi[kFewMax];  // bands of edges k0 .. k0+M-1 (matrix-core path), or
+                                     // hi: the vector paths' thresholds h
+    uint32_t w[kFewMax];             // bits of RN(hi - lo) per band, or of the flag width W
+    float del[kFewMax];              // vector paths: RN(h_t - h_0), t >= 1
     uint32_t k0;
 };
 
@@ -476,6 +478,95 @@ __device__ __forceinline__ void few_band(FewCtx &f, int q, float2 v) {
     f.lo[q] = uniform_f(v.x);
     f.hi[q] = uniform_f(hi);
     f.w[q] = uniform(__float_as_uint(hi - v.x));
+}
+
+// The vector few-edge paths (thresholds from fused_bands): chords are never
+// rounded themselves.  For the item's smallest edge the path forms d_0 = h_0 -
+// c in one chain of binary32 roundings, and for edge t >= 1 d_t = RN(d_0 +
+// del_t), del_t = RN(h_t - h_0): d_t < 0 proves the binary64 chord at or above
+// edge t, d_t > W_t proves it below, and 0 <= d_t <= W_t sends the chord to
+// the binary64 re-check.  A pair that counts nowhere has d = +infinity.  The
+// prune pass never puts an edge at 0 into a few-edge item.
+__device__ __forceinline__ void few_band_fused(FewCtx &f, int q, float2 v) {
+    f.hi[q] = uniform_f(v.x);
+    f.w[q] = uniform(__float_as_uint(v.y));
+}
+
+__device__ __forceinline__ void few_fused_ref(FewCtx &f) {
+#pragma unroll
+    for (int q = 1; q < kFewMax; ++q) f.del[q] = uniform_f(f.hi[q] - f.hi[0]);
+}
+
+// Two chords' d against the smallest edge: the sign bits are added to n, the
+// bits of d (unsigned) to the step's minimum mn.  Four vector instructions.
+__device__ __forceinline__ void tally_d2(float d1, float d2, uint32_t &n, uint32_t &mn) {
+    uint32_t s1, s2;
+    asm volatile(
+        "v_lshrrev_b32 %[s1], 31, %[d1]\n\t"
+        "v_lshrrev_b32 %[s2], 31, %[d2]\n\t"
+        "v_add3_u32 %[n], %[n], %[s1], %[s2]\n\t"
+        "v_min3_u32 %[mn], %[mn], %[d1], %[d2]"
+        : [n] "+v"(n), [mn] "+v"(mn), [s1] "=&v"(s1), [s2] "=&v"(s2)
+        : [d1] "v"(d1), [d2] "v"(d2));
+}
+
+// The same for a higher edge of the item: d = RN(d_0 + del).  Six vector
+// instructions, as many as one subtract per chord and edge needs.
+__device__ __forceinline__ void tally_add2(float d1, float d2, float del, uint32_t &n, uint32_t &mn) {
+    uint32_t e1, e2, s1, s2;
+    asm volatile(
+        "v_add_f32 %[e1], %[del], %[d1]\n\t"
+        "v_add_f32 %[e2], %[del], %[d2]\n\t"
+        "v_lshrrev_b32 %[s1], 31, %[e1]\n\t"
+        "v_lshrrev_b32 %[s2], 31, %[e2]\n\t"
+        "v_add3_u32 %[n], %[n], %[s1], %[s2]\n\t"
+        "v_min3_u32 %[mn], %[mn], %[e1], %[e2]"
+        : [n] "+v"(n), [mn] "+v"(mn), [e1] "=&v"(e1), [e2] "=&v"(e2), [s1] "=&v"(s1), [s2] "=&v"(s2)
+        : [d1] "v"(d1), [d2] "v"(d2), [del] "s"(del));
+}
+
+template <int M>
+__device__ __forceinline__ void few_tally_fused(float d1, float d2, const FewCtx &f, uint32_t (&ngt)[M],
+                                                uint32_t (&mn)[M]) {
+    tally_d2(d1, d2, ngt[0], mn[0]);
+#pragma unroll
+    for (int t = 1; t < M; ++t) tally_add2(d1, d2, f.del[t], ngt[t], mn[t]);
+}
+
+// A pair whose d_0 a flagged step recomputes: true if some d_t lies in its
+// flag window; prov = k0 + #{t : d_t < 0}, the row the step counted it in.
+template <int M>
+__device__ __forceinline__ bool few_in_window(float d0, const FewCtx &f, uint32_t &prov) {
+    bool in = false;
+    prov = f.k0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        const uint32_t b = __float_as_uint(t == 0 ? d0 : d0 + f.del[t]);
+        prov += b >> 31;
+        in |= b <= f.w[t];
+    }
+    return in;
+}
+
+// binary64 re-check of one flagged pair counted in row prov
+__device__ __forceinline__ void few_recheck_row(unsigned char *lds, uint32_t prov, const double4 &a64,
+                                                const double4 &b64, const TileCtx &k) {
+    const double c64 = chord2_64(a64.x, a64.y, a64.z, b64.x, b64.y, b64.z);
+    const uint32_t exact = bin_search(k.e64, k.n_edges, c64);
+    lds_add(lds, k.trash_off + k.row_bytes, 1u);  // re-check tally row
+    if (exact != prov) {
+        lds_add(lds, exact * k.row_bytes + k.lane_off, 1u);
+        lds_add(lds, prov * k.row_bytes + k.lane_off, 0xFFFFFFFFu);
+    }
+}
+
+// d_0 of a pair in the difference form: d_0 = RN(-s_z^2 + RN(-s_y^2 +
+// RN(h_0 - s_x^2))) with s = RN(a - b) per component
+__device__ __forceinline__ float fused_d_diff(float ax, float ay, float az, float4 b, float h0) {
+    const float dx = ax - b.x;
+    const float dy = ay - b.y;
+    const float dz = az - b.z;
+    return __builtin_fmaf(-dz, dz, __builtin_fmaf(-dy, dy, __builtin_fmaf(-dx, dx, h0)));
 }
 
 // Two chords against one band, in plain arithmetic (no compare, no scalar
@@ -580,32 +671,33 @@ __device__ __forceinline__ void step32_few(unsigned char *lds, const float4 (&b)
     for (int q = 0; q < NJ; ++q)
 #pragma unroll
         for (int r = 0; r < kR; r += 2) {
-            float c[2];
+            float d[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                c[h] = chord2_32(ax[r + h], ay[r + h], az[r + h], b[q]);
+                d[h] = fused_d_diff(ax[r + h], ay[r + h], az[r + h], b[q], f.hi[0]);
                 if (MASKED) {
-                    // a masked-out pair becomes -infinity, which counts nowhere
+                    // a masked-out pair gets d = +infinity, which counts nowhere
                     const int32_t ir = (r + h) * kWave + lane;
                     const bool ok = ir < i_lim && (!diag || ir < j_rel + jj + q);
-                    c[h] = ok ? c[h] : -__builtin_inff();
+                    d[h] = ok ? d[h] : __builtin_inff();
                 }
             }
-            few_tally<M>(c[0], c[1], f, ngt, mn);
+            few_tally_fused<M>(d[0], d[1], f, ngt, mn);
         }
     if (__builtin_expect(few_step_band<M>(mn, f), 0)) {
 #pragma unroll
         for (int q = 0; q < NJ; ++q)
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
-                float c = chord2_32(ax[r], ay[r], az[r], b[q]);
-                asm volatile("" : "+v"(c));
-                bool band = few_in_band<M>(c, f);
+                float d = fused_d_diff(ax[r], ay[r], az[r], b[q], f.hi[0]);
+                asm volatile("" : "+v"(d));
+                uint32_t prov;
+                bool in = few_in_window<M>(d, f, prov);
                 if (MASKED) {
                     const int32_t ir = r * kWave + lane;
-                    band &= ir < i_lim && (!diag || ir < j_rel + jj + q);
+                    in &= ir < i_lim && (!diag || ir < j_rel + jj + q);
                 }
-                if (band) few_recheck<M>(lds, c, I64[ibeg + r * kWave + lane], J64t[jj + q], f, k);
+                if (in) few_recheck_row(lds, prov, I64[ibeg + r * kWave + lane], J64t[jj + q], k);
             }
     }
 }
@@ -662,16 +754,17 @@ __device__ __forceinline__ void tile32_few(unsigned char *lds, const float4 *__r
 // bound: chords in Gram form centred on the j-tile's centre o, on the vector
 // ALU.  The j side comes precomputed per point as (-2 b'_x, -2 b'_y, -2 b'_z,
 // |b'|^2) with b' = RN32(b - o); the lane's i-points are centred here, a' =
-// RN32(a - o), with |a'|^2 in binary32.  A chord is then
-// a'_x B_x + (a'_y B_y + (a'_z B_z + (|a'|^2 + |b'|^2))): one add and three
-// fused multiply-adds, four roundings, against six instructions for the
-// difference form; the matrix-core band bounds its error (same centring
-// condition, at most eight roundings).  i slots past the end of the range
-// get |a'|^2 = -infinity, so all their chords are -infinity and count nowhere.
+// RN32(a - o), kept negated, with |a'|^2 in binary32 and, per run of edges,
+// S = RN(h_0 - |a'|^2).  Then d_0 = h_0 - |a' - b'|^2 comes as
+// (-a'_x) B_x + ((-a'_y) B_y + ((-a'_z) B_z + (S - |b'|^2))): one subtract and
+// three fused multiply-adds, against six instructions for the difference
+// form; fused_bands bounds its error (same centring condition).  i slots past
+// the end of the range get |a'|^2 = -infinity, so S and every d are
+// +infinity and count nowhere.
 template <int M, int NJ>
 __device__ __forceinline__ void step32_gram(unsigned char *lds, const float4 (&b)[NJ],
-                                            const double4 *__restrict__ J64t, int32_t jj, const float (&ax)[kR],
-                                            const float (&ay)[kR], const float (&az)[kR], const float (&na)[kR],
+                                            const double4 *__restrict__ J64t, int32_t jj, const float (&nx)[kR],
+                                            const float (&ny)[kR], const float (&nz)[kR], const float (&S)[kR],
                                             const double4 *__restrict__ I64, int64_t ibeg, const TileCtx &k,
                                             const FewCtx &f, uint32_t (&ngt)[M]) {
     const int32_t lane = static_cast<int32_t>(threadIdx.x);
@@ -681,30 +774,32 @@ __device__ __forceinline__ void step32_gram(unsigned char *lds, const float4 (&b
     for (int q = 0; q < NJ; ++q)
 #pragma unroll
         for (int r = 0; r < kR; r += 2) {
-            float c[2];
+            float d[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h)
-                c[h] = __builtin_fmaf(ax[r + h], b[q].x, __builtin_fmaf(ay[r + h], b[q].y,
-                                      __builtin_fmaf(az[r + h], b[q].z, na[r + h] + b[q].w)));
-            few_tally<M>(c[0], c[1], f, ngt, mn);
+                d[h] = __builtin_fmaf(nx[r + h], b[q].x, __builtin_fmaf(ny[r + h], b[q].y,
+                                      __builtin_fmaf(nz[r + h], b[q].z, S[r + h] - b[q].w)));
+            few_tally_fused<M>(d[0], d[1], f, ngt, mn);
         }
     if (__builtin_expect(few_step_band<M>(mn, f), 0)) {
 #pragma unroll
         for (int q = 0; q < NJ; ++q)
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
-                float c = __builtin_fmaf(ax[r], b[q].x, __builtin_fmaf(ay[r], b[q].y,
-                                         __builtin_fmaf(az[r], b[q].z, na[r] + b[q].w)));
-                asm volatile("" : "+v"(c));
-                if (few_in_band<M>(c, f)) few_recheck<M>(lds, c, I64[ibeg + r * kWave + lane], J64t[jj + q], f, k);
+                float d = __builtin_fmaf(nx[r], b[q].x, __builtin_fmaf(ny[r], b[q].y,
+                                         __builtin_fmaf(nz[r], b[q].z, S[r] - b[q].w)));
+                asm volatile("" : "+v"(d));
+                uint32_t prov;
+                if (few_in_window<M>(d, f, prov)) few_recheck_row(lds, prov, I64[ibeg + r * kWave + lane], J64t[jj + q], k);
             }
     }
 }
 
-// The lane's i-points centred on the j-tile's centre o, in binary32, with
-// |a'|^2; slots past a ragged end get -infinity so their pairs count nowhere.
+// The lane's i-points centred on the j-tile's centre o, in binary32 and
+// negated, with |a'|^2; slots past a ragged end get -infinity so their pairs
+// count nowhere.
 struct GramI {
-    float ax[kR], ay[kR], az[kR], na[kR];
+    float nx[kR], ny[kR], nz[kR], na[kR];
     uint32_t valid;
 };
 
@@ -717,10 +812,13 @@ __device__ __forceinline__ void centre_i_gram(GramI &g, const double4 (&pts)[kR]
         const int32_t ir = r * kWave + lane;
         const bool ok = ir < i_lim;
         const double4 p = pts[r];
-        g.ax[r] = static_cast<float>(p.x - ox);
-        g.ay[r] = static_cast<float>(p.y - oy);
-        g.az[r] = static_cast<float>(p.z - oz);
-        const float n2 = __builtin_fmaf(g.az[r], g.az[r], __builtin_fmaf(g.ay[r], g.ay[r], g.ax[r] * g.ax[r]));
+        const float x = static_cast<float>(p.x - ox);
+        const float y = static_cast<float>(p.y - oy);
+        const float z = static_cast<float>(p.z - oz);
+        g.nx[r] = -x;
+        g.ny[r] = -y;
+        g.nz[r] = -z;
+        const float n2 = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
         g.na[r] = ok ? n2 : -__builtin_inff();
         g.valid += ok ? 1u : 0u;
     }
@@ -734,6 +832,10 @@ __device__ __forceinline__ void tile32_gram(unsigned char *lds, const float4 *__
     uint32_t ngt[M];
 #pragma unroll
     for (int t = 0; t < M; ++t) ngt[t] = 0u;
+    // S = RN(h_0 - |a'|^2) per slot, for this run's edges
+    float S[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) S[r] = f.hi[0] - g.na[r];
     constexpr int NJ = PC_JUNROLL;
     int32_t jj = 0;
     // two j buffers in turn: the next step's points load while this step runs
@@ -741,18 +843,18 @@ __device__ __forceinline__ void tile32_gram(unsigned char *lds, const float4 *__
     load_j<NJ>(Jg, b0);
     for (; jj + 2 * NJ <= jn; jj += 2 * NJ) {
         load_j<NJ>(Jg + jj + NJ, b1);
-        step32_gram<M, NJ>(lds, b0, J64t, jj, g.ax, g.ay, g.az, g.na, I64, ibeg, k, f, ngt);
+        step32_gram<M, NJ>(lds, b0, J64t, jj, g.nx, g.ny, g.nz, S, I64, ibeg, k, f, ngt);
         load_j<NJ>(Jg + jj + 2 * NJ, b0);
-        step32_gram<M, NJ>(lds, b1, J64t, jj + NJ, g.ax, g.ay, g.az, g.na, I64, ibeg, k, f, ngt);
+        step32_gram<M, NJ>(lds, b1, J64t, jj + NJ, g.nx, g.ny, g.nz, S, I64, ibeg, k, f, ngt);
     }
     if (jj + NJ <= jn) {
-        step32_gram<M, NJ>(lds, b0, J64t, jj, g.ax, g.ay, g.az, g.na, I64, ibeg, k, f, ngt);
+        step32_gram<M, NJ>(lds, b0, J64t, jj, g.nx, g.ny, g.nz, S, I64, ibeg, k, f, ngt);
         jj += NJ;
     }
     for (; jj < jn; ++jj) {
         float4 bt[1];
         load_j<1>(Jg + jj, bt);
-        step32_gram<M, 1>(lds, bt, J64t, jj, g.ax, g.ay, g.az, g.na, I64, ibeg, k, f, ngt);
+        step32_gram<M, 1>(lds, bt, J64t, jj, g.nx, g.ny, g.nz, S, I64, ibeg, k, f, ngt);
     }
     few_flush<M>(lds, ngt, g.valid * static_cast<uint32_t>(jn), f, k);
 }
@@ -994,7 +1096,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     uint32_t row_bytes = 0, lane_off = 0, clo = 0, chi = 0, shift = 0, lut_base = 0, trash_off = 0;
     bool search = false;
     const double *e64 = nullptr;
-    const float *band = nullptr, *band_g = nullptr;
+    const float *band_g = nullptr, *fband = nullptr, *fband_g = nullptr;
     uint64_t flush_every = 1;
 
     for (;; ++wi) {
@@ -1046,8 +1148,9 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
             if (sd.tab != cur_tab) {
                 const TableDesc td = ld_const_struct(p.tabs + sd.tab);
                 n_edges = td.n_edges;
-                band = td.band;
                 band_g = td.band_g;
+                fband = td.fband;
+                fband_g = td.fband_g;
                 clo = td.clamp_lo;
                 chi = td.clamp_hi;
                 shift = td.shift;
@@ -1169,12 +1272,13 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
             FewCtx f;
             f.k0 = uniform(few_k0);
             if (few_m) {
-                const float *bd = gram_j ? band_g : band;
+                const float *bd = gram_j ? fband_g : fband;
 #pragma unroll
                 for (int q = 0; q < kFewMax; ++q) {
                     const uint32_t e = min(few_k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
-                    few_band(f, q, ld_const_f2(bd + 2u * e));
+                    few_band_fused(f, q, ld_const_f2(bd + 2u * e));
                 }
+                few_fused_ref(f);
             }
             if (use_gram) {
                 // not a diagonal tile; i slots past a ragged end are -infinity
@@ -1232,8 +1336,9 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
 #pragma unroll
                     for (int q = 0; q < kFewMax; ++q) {
                         const uint32_t e = min(k0 + static_cast<uint32_t>(q), static_cast<uint32_t>(n_edges - 1));
-                        few_band(f, q, ld_const_f2(bd + 2u * e));
+                        few_band_fused(f, q, ld_const_f2(bd + 2u * e));
                     }
+                    few_fused_ref(f);
                 }
             };
             if (use_gram) {
@@ -1247,7 +1352,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 int32_t nj;
                 for (int part = 0; next_run(part, m, k0, jb, nj);) {
                     FewCtx f;
-                    bands(f, m, k0, band_g);
+                    bands(f, m, k0, fband_g);
                     const float4 *Jg = uniform_ptr(sd.jg + jb);
                     const double4 *J64p = uniform_ptr(sd.j64 + jb);
                     if (m == 1) tile32_gram<1>(lds, Jg, J64p, nj, g, sd.i64, ibeg, k, f);
@@ -1260,7 +1365,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 int32_t nj;
                 for (int part = 0; next_run(part, m, k0, jb, nj);) {
                     FewCtx f;
-                    bands(f, m, k0, band);
+                    bands(f, m, k0, fband);
                     const float4 *Jt = uniform_ptr(sd.j32 + jb);
                     const double4 *J64p = uniform_ptr(sd.j64 + jb);
                     if (m == 1) tile32_few<false, 1>(lds, Jt, J64p, nj, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, false, k, f);

@@ -383,7 +383,9 @@ __device__ __forceinline__ void chord_interval(const double4 &bi, const double4 
     const double rs = (bi.w + bj.w) * (1.0 + 0x1p-45);
     lo = fmax(0.0, d * (1.0 - 0x1p-45) - rs - 0x1p-50);
     const double hi = d * (1.0 + 0x1p-45) + rs + 0x1p-50;
-    c_lo = lo * lo * (1.0 - 1e-12) - 1e-300;
+    // (a squared chord is never negative, so an edge at 0 always lies at or
+    // below the interval: few-edge items never hold it)
+    c_lo = fmax(lo * lo * (1.0 - 1e-12) - 1e-300, 0.0);
     c_hi = hi * hi * (1.0 + 1e-12) + 1e-300;
 }
 

@@ -131,6 +131,103 @@ double err_gram(double c) {
 
 void guard_band_gram(double e, float *lo, float *hi) { band_from(e, err_gram, lo, hi); }
 
+// ---- fused few-edge thresholds ---------------------------------------------
+//
+// The vector few-edge paths never round the chord itself: with the item's
+// smallest edge as reference (threshold h_ref), they form d_ref = h_ref - c in
+// one chain of roundings, and for the item's other edges d_t = RN(d_ref +
+// D_t), D_t = RN32(h_t - h_ref) >= 0; the sign bit of d_t is (chord above edge
+// t), and 0 <= d_t <= W_t flags the chord for the binary64 re-check.  (The
+// prune pass never puts an edge at 0 in a few-edge item: every chord is at or
+// above it.)
+//   * difference form: d_ref = RN(-s_z^2 + RN(-s_y^2 + RN(h - s_x^2))), three
+//     fused multiply-adds on the binary32 differences s (|s - d| <= D as for
+//     guard_band); q = |s|^2 exactly has |q - c| <= D (2 sqrt c + D); each
+//     partial result is h less a partial sum of squares, at most max(h, q) in
+//     magnitude, so the three roundings add <= g3 max(h, q);
+//   * Gram form (tile-centred, as guard_band_gram, r <= sqrt(c)/2): na =
+//     RN(|a'|^2), bw = RN(|b'|^2) (g3 each), S = RN(h - na), T = RN(S - bw),
+//     then three fused multiply-adds of 2 a'_k b'_k: five roundings on values
+//     of at most max(h, (|a'| + |b'|)^2 (1 + g3));
+//   * an edge that is not the reference adds the rounding of D_t (<= u h_t)
+//     and of the sum (<= u |d_t| <= u max(h_t, c) to first order).
+// The reference is at or below edge t, so H >= h_t >= h_ref bounds every
+// threshold in the chain, and E_t(c) (the chain's bound at H plus g2 (H +
+// max(H, c))) bounds |d_t - (h_t - c)|; it grows with c, and E_t'(c) < 1.
+// H starts at 2 e+ and is then lowered to the threshold h_t found with it
+// (a smaller H gives a smaller h_t, so H >= h_t still holds).  Then, with e+
+// and e- as in band_from:
+//   h_t = RU32(e+ + K E_t(e+)):  d_t < 0 means c > h_t - E_t(c), so c > e+
+//        (otherwise c <= e+ and h_t - E_t(c) >= e+), hence c64 >= e;
+//   W_t = RU32(h_t - e- + K E_t(e-)):  a chord with c >= e- has d_t <= h_t - c
+//        + E_t(c) <= h_t - e- + E_t(e-) <= W_t, so d_t > W_t means c < e-,
+//        hence c64 < e.
+// An edge at 0 needs no band: h = -FLT_MAX (every d is negative: above it)
+// and W = 0 (a d of +0 cannot occur there).
+namespace {
+
+double err_diff_fused(double c, double H) {
+    const double r = std::sqrt(c);
+    const double D = delta0() + kU * r;
+    const double g3 = 3.0 * kU / (1.0 - 3.0 * kU);
+    return D * (2.0 * r + D) + g3 * std::max(H, (r + D) * (r + D)) + 8.0 * kTau;
+}
+
+double err_gram_fused(double c, double H) {
+    const double sc = std::sqrt(c);
+    const double r = 0.5 * sc;
+    const double al = kU * r * (1.0 + 0x1p-52) + 1.7320508075688772 * kTau;
+    const double be = kU * (sc + r) * (1.0 + 0x1p-52) + 1.7320508075688772 * kTau;
+    const double na = r + al, nb = sc + r + be;
+    const double g3 = 3.0 * kU / (1.0 - 3.0 * kU);
+    const double g5 = 5.0 * kU / (1.0 - 5.0 * kU);
+    return 2.0 * sc * (al + be) + (al + be) * (al + be) + g3 * (na * na + nb * nb) +
+           g5 * std::max(H, (na + nb) * (na + nb) * (1.0 + g3)) + 20.0 * kTau;
+}
+
+}  // namespace
+
+void fused_bands(const std::vector<double> &e64, bool gram, std::vector<float> &h, std::vector<float> &w) {
+    const size_t n = e64.size();
+    h.assign(n, -std::numeric_limits<float>::max());
+    w.assign(n, 0.0f);
+    const double g5 = 5.0 * kV / (1.0 - 5.0 * kV);
+    const double g2 = 2.0 * kU / (1.0 - 2.0 * kU);
+    auto eplus = [&](double e) { return (e + 5.0 * 0x1p-1074) / (1.0 - g5) * (1.0 + 8.0 * kV); };
+    auto eminus = [&](double e) { return (e - 5.0 * 0x1p-1074) / (1.0 + g5) * (1.0 - 8.0 * kV); };
+    // H bounds the edge's own threshold, hence the reference's (at most two
+    // edges down); thresholds come out within a few hundred ulp of e+, and the
+    // loop widens H should one not fit under it
+    std::vector<double> H(n);
+    for (size_t k = 0; k < n; ++k) H[k] = 2.0 * eplus(e64[k]);
+    for (int pass = 0; pass < 8; ++pass) {
+        for (size_t k = 0; k < n; ++k) {
+            const double e = e64[k];
+            if (e <= 0.0) continue;
+            auto E = [&](double c) {
+                const double base = gram ? err_gram_fused(c, H[k]) : err_diff_fused(c, H[k]);
+                return base + g2 * (H[k] + std::max(H[k], c)) + 2.0 * kTau;
+            };
+            const double ep = eplus(e), em = eminus(e);
+            const float hk = round_up32(ep + kK * E(ep));
+            h[k] = hk;
+            w[k] = round_up32((static_cast<double>(hk) - em + kK * E(std::max(em, 0.0))) * (1.0 + 4.0 * kV));
+        }
+        // first pass: lower H to the thresholds found; later passes: done
+        // once every threshold fits under its H
+        bool fits = pass > 0;
+        for (size_t k = 0; k < n; ++k) {
+            if (h[k] > H[k]) {
+                H[k] = 2.0 * h[k];
+                fits = false;
+            } else if (pass == 0 && e64[k] > 0.0) {
+                H[k] = h[k];
+            }
+        }
+        if (fits) return;
+    }
+}
+
 namespace {
 
 // ---- binary32 cell table ------------------------------------------------
@@ -317,6 +414,8 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
         guard_band(t.e64[k], &t.lo[k], &t.hi[k]);
         guard_band_gram(t.e64[k], &t.lo_g[k], &t.hi_g[k]);
     }
+    fused_bands(t.e64, false, t.fh, t.fw);
+    fused_bands(t.e64, true, t.fh_g, t.fw_g);
     // widest histogram (up to the kernel's preferred width) that keeps the
     // per-wave histogram within the LDS target; narrower histograms let more
     // waves share a CU

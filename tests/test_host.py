@@ -286,6 +286,138 @@ def test_few_edge_binning_reproduces_the_oracle(name, gram):
     assert checked > 0
 
 
+def _f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32)
+
+
+def _fma32(a, b, c):
+    """binary32 fused multiply-add, emulated: the product of two binary32
+    values is exact in binary64; the sum is rounded to binary64, then to
+    binary32 (a double rounding, far below the thresholds' margins)."""
+    return _f32(np.asarray(a, np.float64) * np.asarray(b, np.float64) + np.asarray(c, np.float64))
+
+
+def _fused_d_variants(a64, b64, h_ref, gram, rng):
+    """d = h_ref - c as the vector few-edge paths form it, in one chain of
+    binary32 roundings: differences of the binary32 unit vectors and three
+    fused multiply-adds (x, y, z and z, y, x), or tile-centred Gram chords
+    (centre within half the chord of either point): na, bw by fused
+    multiply-adds, S = h - na, T = S - bw, then the products 2 a'_k b'_k."""
+    out = []
+    if not gram:
+        s = _f32(a64.astype(np.float32) - b64.astype(np.float32))
+        for order in ((0, 1, 2), (2, 1, 0)):
+            d = _f32(h_ref)
+            for k in order:
+                d = _fma32(-s[:, k], s[:, k], d)
+            out.append(d)
+        return out
+    sc = np.sqrt(_c64(a64, b64))
+    w = rng.normal(size=a64.shape)
+    w /= np.linalg.norm(w, axis=1)[:, None]
+    r = (0.5 * sc * rng.uniform(0.0, 0.999, sc.size))[:, None]
+    for near in (a64, b64):
+        o = near + r * w
+        A = (a64 - o).astype(np.float32)
+        B = (b64 - o).astype(np.float32)
+        na = _fma32(A[:, 2], A[:, 2], _fma32(A[:, 1], A[:, 1], _f32(A[:, 0].astype(np.float64) ** 2)))
+        bw = _fma32(B[:, 2], B[:, 2], _fma32(B[:, 1], B[:, 1], _f32(B[:, 0].astype(np.float64) ** 2)))
+        T = _f32(_f32(np.float64(h_ref) - na) - bw.astype(np.float64))
+        d = T
+        for k in (2, 1, 0):
+            d = _fma32(-A[:, k], -2.0 * B[:, k], d)
+        out.append(d)
+    return out
+
+
+def _fused_d_edge(d_ref, h, k, ref):
+    """d of edge k from the reference edge's d: RN32(d_ref + RN32(h_k - h_ref))."""
+    if k == ref:
+        return d_ref
+    delta = _f32(np.float64(h[k]) - np.float64(h[ref]))
+    return _f32(d_ref.astype(np.float64) + np.float64(delta))
+
+
+@pytest.mark.parametrize("gram", [False, True])
+@pytest.mark.parametrize("name", sorted(EDGE_SETS))
+def test_fused_thresholds_separate_binary32_from_binary64_decisions(name, gram):
+    """The vector few-edge paths' fused differences d = h - c (for the
+    reference edge, and for an edge one or two above it through RN32(h_k -
+    h_ref)): d < 0 only for chords at or above the edge in binary64, d > w
+    only for chords below it."""
+    theta = EDGE_SETS[name]
+    e = oracle.chord2_edges(theta)
+    h, w = pc.pc_debug_fused_band(theta, gram=gram)
+    ra1, dec1, ra2, dec2 = _pairs_near_edges(theta, per_edge=200, seed=13)
+    a = oracle.unit_vectors(ra1, dec1)
+    b = oracle.unit_vectors(ra2, dec2)
+    c64 = _c64(a, b)
+    rng = np.random.default_rng(17)
+    near = np.searchsorted(e, c64)  # pairs are generated around each edge
+    checked = 0
+    for k in range(e.size):
+        if e[k] <= 0:
+            assert h[k] == -np.finfo(np.float32).max and w[k] == 0.0
+            continue
+        sel = (near == k) | (near == k + 1)
+        if not np.any(sel):
+            continue
+        for ref in range(max(k - 2, 0), k + 1):
+            if e[ref] <= 0:
+                continue  # an edge at 0 is never in a few-edge item
+            for d_ref in _fused_d_variants(a[sel], b[sel], h[ref], gram, rng):
+                d = _fused_d_edge(d_ref, h, k, ref)
+                assert np.all(c64[sel][d < 0] >= e[k]), (name, gram, k, ref)
+                assert np.all(c64[sel][d > w[k]] < e[k]), (name, gram, k, ref)
+                checked += int(sel.sum())
+    assert checked > 0
+    # the flag window is as narrow as the guard band of the same chords
+    lo, hi = pc.pc_guard_band(theta, gram=gram)
+    fin = np.isfinite(lo) & (e > 0)
+    assert np.all(w[fin] <= 2.0 * (hi[fin].astype(np.float64) - lo[fin]))
+
+
+@pytest.mark.parametrize("gram", [False, True])
+@pytest.mark.parametrize("name", ["log_40", "paper_254", "linear_zero_180", "tiny"])
+def test_fused_few_edge_binning_reproduces_the_oracle(name, gram):
+    """Few-edge binning as the vector paths do it: for an interval of m <= 3
+    consecutive edges holding the exact chord, the row is k0 + #{t : d_t < 0}
+    with d_t from the smallest edge's fused difference, and a chord with 0 <=
+    d_t <= w_t for some t takes its binary64 row.  (An edge at 0 is never in
+    such an interval: every chord lies above it.)"""
+    theta = EDGE_SETS[name]
+    e64 = oracle.chord2_edges(theta)
+    h, w = pc.pc_debug_fused_band(theta, gram=gram)
+    wb = w.view(np.uint32)
+    ra1, dec1, ra2, dec2 = _pairs_near_edges(theta, per_edge=160, seed=23)
+    a = oracle.unit_vectors(ra1, dec1)
+    b = oracle.unit_vectors(ra2, dec2)
+    c64 = _c64(a, b)
+    want = np.searchsorted(e64, c64, side="right")
+    rng = np.random.default_rng(29)
+    checked = 0
+    for m in (1, 2, 3):
+        for shift in range(m + 1):
+            k0 = want - shift
+            ok = (k0 >= 0) & (k0 + m <= e64.size)
+            ok &= e64[np.clip(k0, 0, e64.size - 1)] > 0
+            for k in np.unique(k0[ok]):
+                sel = ok & (k0 == k)
+                ref = int(k)
+                for d_ref in _fused_d_variants(a[sel], b[sel], h[ref], gram, rng):
+                    row = np.full(d_ref.size, int(k), dtype=np.int64)
+                    flag = np.zeros(d_ref.size, dtype=bool)
+                    for t in range(int(k), int(k) + m):
+                        d = _fused_d_edge(d_ref, h, t, ref)
+                        bits = d.view(np.uint32)
+                        row += bits >> 31
+                        flag |= bits <= wb[t]
+                    row[flag] = np.searchsorted(e64, c64[sel][flag], side="right")
+                    assert np.array_equal(row, want[sel]), (name, gram, m, int(k))
+                    checked += int(sel.sum())
+    assert checked > 0
+
+
 @pytest.mark.parametrize("name", sorted(EDGE_SETS))
 def test_cell_entries_hold_band_width_bits(name):
     """A cell entry is (off_lo, lo, hi, wbits): a finite hi only in one-band
