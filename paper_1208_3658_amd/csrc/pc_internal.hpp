@@ -92,9 +92,10 @@ struct TableDesc {
     int32_t n_edges;
     int32_t search;         // fp64 only: 1 = no exact cell table, binary search per pair
     int32_t cols;           // histogram lane columns (power of two <= 64)
-    // guard bands as (lo, hi) binary32 pairs per edge, plain and matrix-core,
-    // and the vector few-edge paths' fused (h, W) pairs, plain and Gram
-    // (mixed only; device)
+    // guard bands as (lo, hi) binary32 pairs per edge, plain (kept for
+    // inspection; the cell tables hold its values and no kernel reads it) and
+    // matrix-core, and the vector few-edge paths' fused (h, W) pairs, plain
+    // and Gram (mixed only; device)
     const float *band, *band_g, *fband, *fband_g;
 };
 
