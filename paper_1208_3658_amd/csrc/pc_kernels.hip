@@ -454,12 +454,13 @@ __device__ __forceinline__ void tile32(unsigned char *lds, const float4 *__restr
 //
 // When the whole chord interval of a tile pair contains only M <= kFewMax
 // edges (k0 .. k0+M-1; the prune pass proved every exact chord to lie above
-// edge k0-1 and below edge k0+M), a chord's row is k0 + #{k < M : c > hi_k}
-// and only those M bands need checking.  Each lane counts, per k, its chords
-// above band k in a register over the whole item and adds the counts to its
-// histogram column at the end: no cell table read and no histogram atomic per
-// pair.  In-band chords are re-checked in binary64; their correction (+1 on
-// the exact row, -1 on the provisional one) goes to the histogram directly.
+// edge k0-1 and below edge k0+M), a chord's row is k0 + #{k < M : chord above
+// edge k0+k}, and only those M edges need checking.  Each lane counts, per k,
+// its chords above edge k in a register over the whole item and adds the
+// counts to its histogram column at the end: no cell table read and no
+// histogram atomic per pair.  Chords that binary32 cannot place are
+// re-checked in binary64; their correction (+1 on the exact row, -1 on the
+// provisional one) goes to the histogram directly.
 
 struct FewCtx {
     float lo[kFewMax], hi[kFewMax];  // bands of edges k0 .. k0+M-1 (matrix-core path), or
