@@ -189,7 +189,8 @@ bool validate_edges(const double *theta_deg, int n_edges, std::string &err);
 
 // Validates theta edges; fills e64, the guard bands and both cell tables.
 // cols32 > 0 fixes the mixed kernel's histogram lane columns (a power of two
-// in [8, 64]); 0 picks the widest up to PC_COLS32 within the LDS target.
+// in [4, 64]); 0 picks the widest up to PC_COLS32 whose histogram and cell
+// table fit the LDS target together.
 bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string &err, int cols32 = 0);
 
 // The guard band of one squared-chord edge e (binary64): binary32 lo, hi with

@@ -416,22 +416,29 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
     }
     fused_bands(t.e64, false, t.fh, t.fw);
     fused_bands(t.e64, true, t.fh_g, t.fw_g);
-    // widest histogram (up to the kernel's preferred width) that keeps the
-    // per-wave histogram within the LDS target; narrower histograms let more
-    // waves share a CU
-    auto pick = [&](int widest) {
-        for (int c = widest; c > 8; c >>= 1)
-            if (static_cast<uint64_t>(n_edges + 3) * row_bytes_for(c) <= kLdsTarget) return c;
-        return 8;
+    // widest histogram (up to the kernel's preferred width, at least `narrowest`
+    // columns) that keeps the per-wave histogram, plus `extra` bytes of table,
+    // within the LDS target; narrower histograms let more waves share a CU
+    auto pick = [&](int widest, int narrowest, uint64_t extra) {
+        for (int c = widest; c > narrowest; c >>= 1)
+            if (static_cast<uint64_t>(n_edges + 3) * row_bytes_for(c) + extra <= kLdsTarget) return c;
+        return narrowest;
     };
-    if (cols32 != 0 && (cols32 < 8 || cols32 > 64 || (cols32 & (cols32 - 1)) != 0)) {
-        err = "histogram columns must be a power of two in [8, 64]";
+    if (cols32 != 0 && (cols32 < 4 || cols32 > 64 || (cols32 & (cols32 - 1)) != 0)) {
+        err = "histogram columns must be a power of two in [4, 64]";
         return false;
     }
-    t.cols32 = cols32 ? cols32 : pick(PC_COLS32);
-    t.cols64 = pick(PC_COLS64);
-    t.row_bytes32 = row_bytes_for(t.cols32);
+    t.cols64 = pick(PC_COLS64, 8, 0);
     t.row_bytes64 = row_bytes_for(t.cols64);
+    if (cols32) {
+        t.cols32 = cols32;
+    } else {
+        // the mixed kernel's cell table shares the wave's LDS with its
+        // histogram (the table's size does not depend on the columns)
+        build_lut32(t.lo, t.hi, row_bytes_for(PC_COLS32), t.lut32);
+        t.cols32 = pick(PC_COLS32, 4, sizeof(LutEntry32) * t.lut32.entries.size());
+    }
+    t.row_bytes32 = row_bytes_for(t.cols32);
     build_lut32(t.lo, t.hi, t.row_bytes32, t.lut32);
     build_lut64(t);
     return true;

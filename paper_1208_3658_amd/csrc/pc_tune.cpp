@@ -158,7 +158,7 @@ int parse_file(const char *path, std::map<TuneKey, TuneEntry> *out) {
         if (ok && field(line, "launch_ms", &v)) e.launch_ms = atof(v.c_str());
         // entries written before the tile size was tuned mean 256-point tiles
         if (ok && field(line, "tile", &v)) ok = to_int(v, &e.tune.tile) && (e.tune.tile == 128 || e.tune.tile == 256);
-        const bool cols_ok = e.tune.cols == 0 || (e.tune.cols >= 8 && e.tune.cols <= 64 &&
+        const bool cols_ok = e.tune.cols == 0 || (e.tune.cols >= 4 && e.tune.cols <= 64 &&
                                                   (e.tune.cols & (e.tune.cols - 1)) == 0);
         if (!ok || !cols_ok || e.tune.chunk < 1 || e.tune.chunk > 64 || (mc != 0 && mc != 1) ||
             (mc && e.tune.tile != 256))
@@ -282,7 +282,7 @@ extern "C" int pc_autotune(const pc_job *jobs, int32_t n_jobs, int32_t mode, con
     }
     std::vector<LaunchTune> cands;
     for (int mc = 0; mc <= ((mixed && prune && tile == 256) ? 1 : 0); ++mc)
-        for (int cols : {8, 16, 32})
+        for (int cols : {4, 8, 16, 32})
             for (int chunk : {2, 4, 8}) {
                 if (!mixed && cols != 8) continue;  // the binary64 kernel's columns are fixed
                 LaunchTune t;

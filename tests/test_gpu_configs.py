@@ -98,8 +98,8 @@ def test_autotune_chooses_a_configuration_and_tuned_runs_are_exact(tmp_path):
     cache = tmp_path / "tune.jsonl"
     counts, cfg = pc.pc_autotune(jobs, cache_path=cache)
     # tile size first (two candidates), then columns x chunk (x matrix cores at 256-point tiles)
-    assert cfg["tile"] in (128, 256) and cfg["cols"] in (8, 16, 32) and cfg["chunk"] in (2, 4, 8)
-    assert cfg["candidates"] == (20 if cfg["tile"] == 256 else 11)
+    assert cfg["tile"] in (128, 256) and cfg["cols"] in (4, 8, 16, 32) and cfg["chunk"] in (2, 4, 8)
+    assert cfg["candidates"] == (26 if cfg["tile"] == 256 else 14)
     assert cfg["kernel_ms"] > 0 and cfg["launch_ms"] > 0
     want = [oracle.count(c["D"], e), oracle.count(c["D"], e, B=c["R"], auto=False), oracle.count(c["R"], e)]
     for got, w in zip(counts, want):
