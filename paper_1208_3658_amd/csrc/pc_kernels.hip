@@ -1051,16 +1051,20 @@ __device__ __forceinline__ void tile64(unsigned char *lds, const double4 *__rest
 
 // Waves per SIMD asked of the register allocator.  The counting loops wait
 // on scalar loads of j-points, LDS and the i-point loads of each item, and
-// more resident waves hide that: on the 1M workload the mixed instance takes
-// 52.8, 51.3 and 50.7 ms at 6, 7 and 8 waves per SIMD.  At 8 (64 VGPRs) the
-// allocator spills to scratch, mostly around the rarely taken binary64
-// re-check branches.  The binary64 instance keeps 7, the matrix-core one 3.
+// more resident waves hide that, while fewer leave more registers and fewer
+// spills to scratch (mostly around the rarely taken binary64 re-check
+// branches).  The 256-point instance (4 i-points per lane, a Gram run's S
+// per slot) is built for 6 (80 VGPRs, 96 bytes of scratch per lane): on the
+// 1M workload it takes 43.6, 43.9, 45.9 and 47.2 ms at 6, 5, 7 and 8 waves per
+// SIMD on one box.  The 128-point instance keeps 8 (64 VGPRs): on the
+// batched workload 730 ms, against 765 ms for the best launch at 6.  The
+// binary64 instance keeps 7, the matrix-core one 3.
 #ifdef PC_WAVES_PER_EU
 #define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PC_WAVES_PER_EU)))
 #elif defined(PC_NO_OCCUPANCY_HINT)
 #define PC_OCCUPANCY
 #else
-#define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MC ? 3 : (FP64 ? 7 : 8))))
+#define PC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MC ? 3 : (FP64 ? 7 : (kR == 4 ? 6 : 8)))))
 #endif
 
 // MC: tile pairs marked by the prune pass go through the matrix cores (a
