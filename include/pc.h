@@ -230,7 +230,8 @@ int pc_estimator(int32_t kind, const uint64_t *DD, const uint64_t *DR, const uin
  * same counts, and remember the fastest for batches of this shape (device,
  * ceil(log2(max n_edges)), floor(log2(pairs))); later calls with PC_TUNED use
  * it.  First the tile size -- the size of the submatrices the pair matrix is
- * cut into (Sec. 2.1): 128 or 256 points -- on the whole launch's time; then,
+ * cut into (Sec. 2.1): 128 or 256 points -- on the whole launch's time (each
+ * size launched once untimed, then timed twice, its faster run kept); then,
  * at that size, histogram lane columns {4, 8, 16, 32}, work items taken from the
  * queue at a time {2, 4, 8} and matrix cores off/on (PC_MIXED with 256-point
  * tiles only) on the counting kernel's time.  Each job's counts are written
