@@ -45,7 +45,7 @@ size_t scan_sums_words(int64_t m);
 namespace {
 
 constexpr int kApWaves = 4;            // waves per workgroup: 2 x 2 blocks sharing one filter table
-constexpr int kQCells = 1024;          // filter table cells over x in [0, 1]
+constexpr int kQCells = 1024;          // filter table cells over x in [0, 1], and one at x = 1
 constexpr int kApFlush = 64;           // galaxies summed in binary32 before the binary64 add
 constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 constexpr int64_t kMaxCells = int64_t(1) << 22;
@@ -71,15 +71,14 @@ struct Lattice {
 struct ApParams {
     const ApGal *gal;
     const uint32_t *start;  // ncx * ncy + 1 cell starts
-    const float4 *qtab;     // kQCells cubics (c0, c1, c2, c3): Q = c0 + t (c1 + t (c2 + t c3))
+    const float4 *qtab;     // kQCells + 1 cubics (c0, c1, c2, c3): Q = c0 + t (c1 + t (c2 + t c3))
     Lattice lat;
     double x0, y0, gdx, gdy;
     int32_t nx, ny, tiles_x, n_tiles, per_xcd;  // tiles: groups of 2 x 2 blocks
     double theta;     // filter radius
     double r2;        // theta^2 (binary64), the cut
     double reach;     // theta with a relative margin for the cell search
-    float k_s;        // table position s = r k_s = kQCells x, x = r / theta
-    float s_max;      // largest binary32 below kQCells (r rounded up to theta)
+    float k_x;        // x = r k_x = r / theta, clamped to [0, 1]; table position s = kQCells x
     float r2f;        // theta^2 rounded to binary32: the provisional cut
     float band;       // |f2 - r2f| <= band: the binary32 |d|^2 cannot decide the cut
     float near0;      // f2 <= near0: a galaxy near the point, decided and weighted in binary64
@@ -170,7 +169,7 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 
 // Constants held in VGPRs (an instruction reads at most one SGPR).
 struct ApConsts {
-    float k_s, s_max, r2f, band, near0, nbig, f2_in, f2_out;
+    float k_x, r2f, band, near0, nbig, f2_in, f2_out;
     uint32_t tab;  // LDS byte address of the filter table
 };
 
@@ -189,8 +188,19 @@ __device__ __forceinline__ float max_f32(float a, float b) {
     return r;
 }
 
-// The filter Q(x) of Eq. 4 at table position s = kQCells x (s <= s_max):
-// cell i = floor(s), t = s - i, Q = c0 + t (c1 + t (c2 + t c3)).
+// The table position of a separation r: x = RN(r k_x) clamped to [0, 1] by
+// the multiply's clamp bit (a full-rate instruction, where a min is not),
+// then s = kQCells x, exact.  For x below 1 this is RN(r kQCells / theta)
+// rounded once, as kQCells is a power of two.
+__device__ __forceinline__ float table_pos(float r, float k_x) {
+    float x;
+    asm("v_mul_f32_e64 %0, %1, %2 clamp" : "=v"(x) : "v"(r), "v"(k_x));
+    return x * static_cast<float>(kQCells);
+}
+
+// The filter Q(x) of Eq. 4 at table position s = kQCells x (0 <= s <=
+// kQCells): cell i = floor(s), t = s - i, Q = c0 + t (c1 + t (c2 + t c3));
+// s = kQCells reads the last cell, the constant Q(1).
 __device__ __forceinline__ float q_table(float s, uint32_t tab) {
     const uint32_t i = static_cast<uint32_t>(s);
     const float t = __builtin_amdgcn_fractf(s);
@@ -224,12 +234,20 @@ __device__ __forceinline__ float q_table(float s, uint32_t tab) {
 // (cos 2phi = 1 - 2 dy^2 / f2, sin 2phi = 2 dx dy / f2); the products
 // Q eps_t and Q^2 |eps|^2 are summed in binary32 over at most 64 galaxies and
 // then in binary64.
-template <int P>
+//
+// RAISE: f2 is raised to near0 before the reciprocal square root.  Every f2
+// that reaches the binary32 step is positive and normal when r2f - 2 band is
+// (a pair left there has f2 > near0 >= 2^-100, a pair moved there r2f +- 2
+// band), and the host then takes the instance without it; with the band
+// widened to decide every pair in binary64 (grid spacing far beyond theta)
+// r2f - 2 band is negative, and the raise keeps the weights of such moved
+// pairs finite.
+template <int P, bool RAISE>
 __global__ void __launch_bounds__(64 * kApWaves) __attribute__((amdgpu_waves_per_eu(P == 2 ? 4 : 7)))
 k_ap_map(const ApParams p) {
     constexpr int BS = 8 * P;   // block side in points
     constexpr int K = P * P;    // points per lane
-    __shared__ float4 qtab[kQCells];
+    __shared__ float4 qtab[kQCells + 1];
     const int lane = static_cast<int>(threadIdx.x) & 63;
     // wave-uniform (a scalar register): the block, its galaxy ranges and the
     // galaxy loop are the same for every lane of the wave
@@ -237,7 +255,7 @@ k_ap_map(const ApParams p) {
     const int b = static_cast<int>(blockIdx.x);
     const int tile = (b & 7) * p.per_xcd + (b >> 3);
     if (tile >= p.n_tiles) return;  // the whole workgroup: before any barrier
-    for (int k = static_cast<int>(threadIdx.x); k < kQCells; k += 64 * kApWaves) qtab[k] = p.qtab[k];
+    for (int k = static_cast<int>(threadIdx.x); k <= kQCells; k += 64 * kApWaves) qtab[k] = p.qtab[k];
     __syncthreads();
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
     const int ix0 = tx * 2 * BS + (wave & 1) * BS, iy0 = ty * 2 * BS + (wave >> 1) * BS;
@@ -265,10 +283,10 @@ k_ap_map(const ApParams p) {
     const double gxl = p.x0 + static_cast<double>(ix0) * p.gdx, gxh = p.x0 + static_cast<double>(ix1) * p.gdx;
     const double gyl = p.y0 + static_cast<double>(iy0) * p.gdy, gyh = p.y0 + static_cast<double>(iy1) * p.gdy;
     const Lattice L = p.lat;
-    ApConsts C{p.k_s, p.s_max, p.r2f, p.band, p.near0, p.nbig, p.f2_in, p.f2_out,
+    ApConsts C{p.k_x, p.r2f, p.band, p.near0, p.nbig, p.f2_in, p.f2_out,
                static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
                    (__attribute__((address_space(3))) const float4 *)(qtab)))};
-    asm("" : "+v"(C.k_s), "+v"(C.s_max), "+v"(C.r2f), "+v"(C.band), "+v"(C.near0), "+v"(C.nbig), "+v"(C.f2_in), "+v"(C.f2_out));
+    asm("" : "+v"(C.k_x), "+v"(C.r2f), "+v"(C.band), "+v"(C.near0), "+v"(C.nbig), "+v"(C.f2_in), "+v"(C.f2_out));
     const double slack = L.s * 1e-9;  // covers rounding of the cell coordinates
 
     double S1[K], S2[K];
@@ -343,7 +361,7 @@ k_ap_map(const ApParams p) {
                             const double c2 = (ddx * ddx - ddy * ddy) / d2, s2 = (ddx * ddy) / d2;
                             const float et = static_cast<float>(static_cast<double>(G.a) * c2 +
                                                                 static_cast<double>(G.b2) * s2);
-                            const float qn = q_table(fminf(static_cast<float>(sqrt(d2) * p.k_s), C.s_max), C.tab);
+                            const float qn = q_table(table_pos(static_cast<float>(sqrt(d2)), C.k_x), C.tab);
                             a1[k] = fmaf(qn, et, a1[k]);
                             a2[k] = fmaf(qn * qn, G.ee, a2[k]);
                             cnt[k] += 1u;
@@ -355,17 +373,17 @@ k_ap_map(const ApParams p) {
                 }
                 // inside: w = 1, outside: w = 0, exactly (|f2 - r2f| > band
                 // here, or f2 was moved to 2 band from r2f); plain
-                // arithmetic, no compare.  f2 raised to `near0` keeps every
-                // value below finite (a pair so raised is never inside here).
+                // arithmetic, no compare.  Every value below is finite: f2 is
+                // positive and normal (see RAISE).
                 float rinv[K], q[K], wt[K];
                 uint32_t addr[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     wt[k] = fma_clamp01(f2[k] - C.r2f, C.nbig);
                     cntf[k] += wt[k];
-                    const float f2c = max_f32(f2[k], C.near0);
+                    const float f2c = RAISE ? max_f32(f2[k], C.near0) : f2[k];
                     rinv[k] = __builtin_amdgcn_rsqf(f2c);
-                    const float sk = fminf((f2c * rinv[k]) * C.k_s, C.s_max);
+                    const float sk = table_pos(f2c * rinv[k], C.k_x);
                     addr[k] = C.tab + (static_cast<uint32_t>(sk) << 4);
                     q[k] = __builtin_amdgcn_fractf(sk);  // position in the cell, for now
                 }
@@ -464,11 +482,12 @@ double q_filter(double x) {
     return th / (1.0 + std::exp(6.0 - 150.0 * x) + std::exp(-47.0 + 50.0 * x));
 }
 
-// The filter table: cell k covers x in [k, k+1] / kQCells; its cubic in
-// t = kQCells x - k interpolates Q at the four Chebyshev points of [0, 1]
-// (solved in binary64, coefficients rounded to binary32 once).  Built once.
+// The filter table: cell k < kQCells covers x in [k, k+1] / kQCells; its
+// cubic in t = kQCells x - k interpolates Q at the four Chebyshev points of
+// [0, 1] (solved in binary64, coefficients rounded to binary32 once).  Cell
+// kQCells holds the constant Q(1), for x = 1 (t = 0).  Built once.
 const float4 *filter_table() {
-    static float4 tab[kQCells];
+    static float4 tab[kQCells + 1];
     static std::once_flag once;
     std::call_once(once, [] {
         const double kPi = 3.14159265358979323846;
@@ -495,6 +514,7 @@ const float4 *filter_table() {
             tab[k] = make_float4(static_cast<float>(A[0][4] / A[0][0]), static_cast<float>(A[1][4] / A[1][1]),
                                  static_cast<float>(A[2][4] / A[2][2]), static_cast<float>(A[3][4] / A[3][3]));
         }
+        tab[kQCells] = make_float4(static_cast<float>(q_filter(1.0)), 0.0f, 0.0f, 0.0f);
     });
     return tab;
 }
@@ -662,7 +682,7 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     const size_t o_sums = take(&size, sizeof(uint32_t) * scan_sums_words(n_cells + 1));
     const size_t o_flag = take(&size, 4 * sizeof(uint32_t));
     const size_t o_stats = take(&size, 2 * sizeof(unsigned long long));
-    const size_t o_qtab = take(&size, sizeof(float4) * kQCells);
+    const size_t o_qtab = take(&size, sizeof(float4) * (kQCells + 1));
     const size_t o_out = host_out ? take(&size, (2 * sizeof(double) + sizeof(uint32_t)) * static_cast<size_t>(m)) : 0;
     DevMem ws;
     ws.st = st;
@@ -692,7 +712,7 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     uint32_t *flag = reinterpret_cast<uint32_t *>(base + o_flag);
     unsigned long long *stats = reinterpret_cast<unsigned long long *>(base + o_stats);
     float4 *qtab = reinterpret_cast<float4 *>(base + o_qtab);
-    AP_HIP(hipMemcpyAsync(qtab, filter_table(), sizeof(float4) * kQCells, hipMemcpyHostToDevice, st),
+    AP_HIP(hipMemcpyAsync(qtab, filter_table(), sizeof(float4) * (kQCells + 1), hipMemcpyHostToDevice, st),
            "H2D filter table");
 
     // order the galaxies by cell
@@ -743,8 +763,9 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
     p.theta = theta_max;
     p.r2 = theta_max * theta_max;
     p.reach = theta_max * (1.0 + 1e-9);
-    p.k_s = static_cast<float>(static_cast<double>(kQCells) / theta_max);
-    p.s_max = std::nextafter(static_cast<float>(kQCells), 0.0f);
+    // RN32(kQCells / theta) / kQCells: exact (a power of two, no subnormal
+    // for theta below the extent limit)
+    p.k_x = static_cast<float>(static_cast<double>(kQCells) / theta_max) / static_cast<float>(kQCells);
     cut_bands(grid, theta_max, p.r2, P, &p.r2f, &p.band, &p.near0);
     p.nbig = -1.0f / p.band;
     p.f2_in = p.r2f - 2.0f * p.band;
@@ -763,10 +784,18 @@ extern "C" int pc_aperture_mass(const pc_shear_catalog *cat, const pc_grid *grid
         AP_HIP(hipEventCreate(&ev.b), "hipEventCreate");
         AP_HIP(hipEventRecord(ev.a, st), "hipEventRecord");
     }
-    if (P == 2)
-        k_ap_map<2><<<dim3(static_cast<uint32_t>(8 * p.per_xcd)), dim3(64 * kApWaves), 0, st>>>(p);
+    // f2 needs no raise when every value it can take in the binary32 step is
+    // positive and normal (see k_ap_map)
+    const bool raise = !(p.f2_in >= FLT_MIN);
+    const dim3 grid_dim(static_cast<uint32_t>(8 * p.per_xcd)), block_dim(64 * kApWaves);
+    if (P == 2 && !raise)
+        k_ap_map<2, false><<<grid_dim, block_dim, 0, st>>>(p);
+    else if (P == 2)
+        k_ap_map<2, true><<<grid_dim, block_dim, 0, st>>>(p);
+    else if (!raise)
+        k_ap_map<1, false><<<grid_dim, block_dim, 0, st>>>(p);
     else
-        k_ap_map<1><<<dim3(static_cast<uint32_t>(8 * p.per_xcd)), dim3(64 * kApWaves), 0, st>>>(p);
+        k_ap_map<1, true><<<grid_dim, block_dim, 0, st>>>(p);
     AP_HIP(hipGetLastError(), "k_ap_map");
     if (timing) AP_HIP(hipEventRecord(ev.b, st), "hipEventRecord");
 
@@ -811,11 +840,12 @@ extern "C" int pc_debug_ap_filter(const double *x, int64_t n, double *q) {
     clear_error();
     if (n < 0 || (n > 0 && (!x || !q))) return fail(PC_ERR_INVALID, "NULL argument or n < 0");
     const float4 *tab = filter_table();
-    const float s_max = std::nextafter(static_cast<float>(kQCells), 0.0f);
     for (int64_t k = 0; k < n; ++k) {
-        // the kernel's steps in binary32: s = x kQCells clamped below kQCells,
-        // cell floor(s), t = s - floor(s), Horner with fused multiply-adds
-        const float sv = std::fmin(static_cast<float>(x[k]) * static_cast<float>(kQCells), s_max);
+        // the kernel's steps in binary32: x clamped to [0, 1], s = kQCells x,
+        // cell floor(s) (kQCells at x = 1), t = s - floor(s), Horner with
+        // fused multiply-adds
+        const float xf = std::fmin(std::fmax(static_cast<float>(x[k]), 0.0f), 1.0f);
+        const float sv = xf * static_cast<float>(kQCells);
         const uint32_t i = static_cast<uint32_t>(sv);
         const float t = sv - std::floor(sv);
         const float4 c = tab[i];

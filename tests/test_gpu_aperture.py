@@ -85,6 +85,31 @@ def test_cut_decided_exactly_at_theta_and_on_points(points_per_lane):
     _check(gpu, ref, 30.0, f"cut P={points_per_lane}")
 
 
+def test_grid_spacing_far_beyond_theta(points_per_lane):
+    """Grid spacing 10^7 theta_max: the binary32 offsets cannot resolve the
+    aperture, the guard band is widened so that every pair is decided (and
+    every pair inside weighted) in binary64, and r2f - 2 band is negative, so
+    the kernel instance that raises f2 before its reciprocal square root
+    runs.  Galaxies on grid points, at fractions of theta from them and well
+    outside, plus a uniform background: n_in bit-exact, map and SNR within
+    the tolerance."""
+    theta = 1e-4
+    grid = (-3.0e3, 2.0e3, 1.0e3, 7.5e2, 9, 7)
+    rng = np.random.default_rng(31)
+    k = rng.integers(0, 9 * 7, 240)
+    px, py = grid[0] + (k % 9) * grid[2], grid[1] + (k // 9) * grid[3]
+    frac = rng.choice([0.0, 0.2, 0.7, 0.999, 1.3, 3.0], k.size)
+    ang = rng.uniform(0.0, 2.0 * np.pi, k.size)
+    x = np.concatenate([px + frac * theta * np.cos(ang), rng.uniform(-3.5e3, 6.5e3, 2000)])
+    y = np.concatenate([py + frac * theta * np.sin(ang), rng.uniform(1.5e3, 7.0e3, 2000)])
+    e = rng.normal(0.0, 0.3, (2, x.size))
+    cat = (x, y, e[0], e[1])
+    gpu = pc.pc_aperture_mass(cat, grid, theta, 30.0)
+    ref = oracle.aperture_grid(cat, grid, theta, 30.0)
+    assert ref["n_in"].sum() > 60
+    _check(gpu, ref, 30.0, f"wide spacing P={points_per_lane}")
+
+
 def test_grid_extent_limit():
     cat, side = _small(1000, config=18)
     with pytest.raises(pc.PcError) as ei:
