@@ -72,6 +72,16 @@ int pc_debug_set_timing(int32_t on);
 int pc_debug_set_flush_every(uint64_t items);
 
 /*
+ * pc_debug_set_compact_table -- the calling thread's later mixed-precision
+ * counting launches (not the matrix-core one) hold the binary32 cell table in
+ * its 8-byte form: mode 0 (default) when that lets more waves share a CU than
+ * the 16-byte form, 1 whenever every table of the launch has it (row offsets
+ * within 14 bits), -1 never.  Counts are unchanged (the same cells and
+ * re-check decisions, Sec. 2.1 binning); PC_ERR_INVALID for another mode.
+ */
+int pc_debug_set_compact_table(int32_t mode);
+
+/*
  * pc_debug_set_tile -- tile = 128 or 256: the calling thread's later counting
  * launches (except pc_autotune's own candidates) cut the pair matrix into
  * tiles of that many points whatever the tuner chose; 0 restores the default

@@ -90,6 +90,7 @@ _SIGNATURES = {
     "pc_debug_lut32": ([_vp, _i32, _vp, _vp, _i64], ctypes.c_int),
     "pc_debug_set_timing": ([_i32], ctypes.c_int),
     "pc_debug_set_flush_every": ([_u64], ctypes.c_int),
+    "pc_debug_set_compact_table": ([_i32], ctypes.c_int),
     "pc_debug_fail_allocations": ([_i32], ctypes.c_int),
     "pc_debug_set_tile": ([_i32], ctypes.c_int),
     "pc_debug_server_hold": ([_vp, _i32], ctypes.c_int),
@@ -433,6 +434,13 @@ def pc_debug_set_flush_every(items: int):
     """items > 0: flush the counting kernel's LDS histograms at least every
     `items` work items on this thread (testing); 0: default."""
     _check(lib().pc_debug_set_flush_every(int(items)))
+
+
+def pc_debug_set_compact_table(mode: int):
+    """Cell table form of this thread's later mixed counting launches: 0 the
+    8-byte form when it raises the waves per CU (default), 1 whenever built,
+    -1 never (testing)."""
+    _check(lib().pc_debug_set_compact_table(int(mode)))
 
 
 def pc_debug_set_tile(tile: int):

@@ -30,7 +30,8 @@ size_t sort_scratch_words(int64_t n);
 
 // the per-tile-size steps (pc_kernels.hip, pc_prep.hip; one instance per size)
 #define PC_TILE_STEPS                                                                                              \
-    hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,        \
+    hipError_t launch_count(bool fp64, bool mc, bool compact, const SegDesc *segs, int32_t n_segs,                 \
+                            const TableDesc *tabs,                                                                 \
                             const uint64_t *items, const unsigned long long *n_items, const uint64_t *sub,         \
                             uint64_t total_items, uint32_t lut_lds_off, uint32_t stage_lds_off,                    \
                             unsigned long long *queue, unsigned long long *rechecked, int chunk,                   \
@@ -40,7 +41,7 @@ size_t sort_scratch_words(int64_t n);
     hipError_t launch_prune(const SegDesc *segs, int32_t n_segs, const TableDesc *tabs, int64_t total_rows,        \
                             uint64_t *survivors, uint64_t *sub, unsigned long long *meta, int32_t mfma_ok,         \
                             int32_t split_ok, hipStream_t st);                                                     \
-    hipError_t count_occupancy(bool fp64, bool mc, uint32_t lds_bytes, int *blocks_per_cu);                        \
+    hipError_t count_occupancy(bool fp64, bool mc, bool compact, uint32_t lds_bytes, int *blocks_per_cu);          \
     hipError_t set_max_lds(uint32_t bytes);
 namespace t256 { PC_TILE_STEPS }
 namespace t128 { PC_TILE_STEPS }
@@ -168,7 +169,7 @@ DevTable::~DevTable() {
 }
 
 void table_blob(const HostTable &h, TableBlob *out) {
-    // one device block: e64 | band | band_g | fband | fband_g | lut32 | lut64
+    // one device block: e64 | band | band_g | fband | fband_g | lut32 | lutc | lut64
     const size_t b_e = sizeof(double) * h.e64.size();
     const size_t b_b = 2 * sizeof(float) * h.e64.size();
     out->o_band = (b_e + 255) & ~size_t(255);
@@ -177,7 +178,9 @@ void table_blob(const HostTable &h, TableBlob *out) {
     out->o_fband_g = (out->o_fband + b_b + 255) & ~size_t(255);
     out->o_lut32 = (out->o_fband_g + b_b + 255) & ~size_t(255);
     const size_t b_l32 = sizeof(LutEntry32) * h.lut32.entries.size();
-    out->o_lut64 = (out->o_lut32 + b_l32 + 255) & ~size_t(255);
+    out->o_lutc = (out->o_lut32 + b_l32 + 255) & ~size_t(255);
+    const size_t b_lc = sizeof(LutEntryC) * h.lut32.compact.size();
+    out->o_lut64 = (out->o_lutc + b_lc + 255) & ~size_t(255);
     const size_t b_l64 = sizeof(LutEntry64) * h.lut64.size();
     std::vector<unsigned char> &blob = out->bytes;
     blob.assign(out->o_lut64 + b_l64 + 256, 0);
@@ -191,6 +194,7 @@ void table_blob(const HostTable &h, TableBlob *out) {
         memcpy(blob.data() + out->o_fband_g + 8 * k, fb + 2, 8);
     }
     if (b_l32) memcpy(blob.data() + out->o_lut32, h.lut32.entries.data(), b_l32);
+    if (b_lc) memcpy(blob.data() + out->o_lutc, h.lut32.compact.data(), b_lc);
     if (b_l64) memcpy(blob.data() + out->o_lut64, h.lut64.data(), b_l64);
 }
 
@@ -201,6 +205,7 @@ void table_place(DevTable *t, const TableBlob &b, unsigned char *base) {
     t->d_fband = reinterpret_cast<const float *>(base + b.o_fband);
     t->d_fband_g = reinterpret_cast<const float *>(base + b.o_fband_g);
     t->d_lut32 = base + b.o_lut32;
+    t->d_lutc = t->host.lut32.compact.empty() ? nullptr : base + b.o_lutc;
     t->d_lut64 = base + b.o_lut64;
 }
 
@@ -270,6 +275,7 @@ TableDesc table_desc(const DevTable &t, bool fp64) {
     } else {
         d.cols = h.cols32;
         d.lut = t.d_lut32;
+        d.lutc = t.d_lutc;
         d.clamp_lo = h.lut32.clamp_lo;
         d.clamp_hi = h.lut32.clamp_hi;
         d.shift = h.lut32.shift;
@@ -284,16 +290,16 @@ TableDesc table_desc(const DevTable &t, bool fp64) {
     return d;
 }
 
-// LDS bytes a table needs: histogram rows, then the cell table (or edges),
-// then (mixed) the matrix-core path's cell table
-static void table_lds(const DevTable &t, bool fp64, uint32_t *hist, uint32_t *lut) {
+// LDS bytes a table needs: histogram rows, then the cell table (or edges;
+// compact: the 8-byte cells)
+static void table_lds(const DevTable &t, bool fp64, bool compact, uint32_t *hist, uint32_t *lut) {
     const HostTable &h = t.host;
     *hist = static_cast<uint32_t>(h.e64.size() + 3) * (fp64 ? h.row_bytes64 : h.row_bytes32);
     if (fp64) {
         *lut = h.search64 ? static_cast<uint32_t>(8 * h.e64.size())
                           : static_cast<uint32_t>(16 * h.lut64.size());
     } else {
-        *lut = static_cast<uint32_t>(16 * h.lut32.entries.size());
+        *lut = static_cast<uint32_t>((compact ? 8 : 16) * h.lut32.entries.size());
     }
 }
 
@@ -362,6 +368,8 @@ void set_thread_timing(bool on) { t_timing = on; }
 static thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
 // per-thread cap on the counting kernel's histogram flush interval (testing)
 static thread_local uint64_t t_flush_cap = 0;
+// compact cell tables: 0 when they raise the waves per CU, 1 whenever built, -1 never
+static thread_local int t_compact_mode = 0;
 // per-thread tile size for launches without explicit parameters (testing; 0: as chosen)
 static thread_local int t_force_tile = 0;
 static thread_local BatchStats t_last;
@@ -770,18 +778,48 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
         sd.pstride = static_cast<int64_t>(count_words);
     }
     std::vector<TableDesc> tds;
-    uint32_t hist_max = 0, lut_max = 0;
+    bool compact_ok = !fp64 && !mc;
     for (auto &t : tabs) {
         tds.push_back(table_desc(*t, fp64));
-        uint32_t h, l;
-        table_lds(*t, fp64, &h, &l);
-        hist_max = std::max(hist_max, h);
-        lut_max = std::max(lut_max, l);
+        compact_ok = compact_ok && t->d_lutc != nullptr;
     }
     // LDS: histogram | cell table (or edges) | matrix-core A operands
-    const uint32_t lut_off = (hist_max + 15u) & ~15u;
-    const uint32_t stage_off = lut_off + ((std::max<uint32_t>(lut_max, 16u) + 15u) & ~15u);
-    const uint32_t lds_bytes = stage_off + (mc ? 16u * kWave * 4u : 0u);
+    auto layout = [&](bool compact, uint32_t *lut_off, uint32_t *stage_off, uint32_t *lds) {
+        uint32_t hist_max = 0, lut_max = 0;
+        for (auto &t : tabs) {
+            uint32_t h, l;
+            table_lds(*t, fp64, compact, &h, &l);
+            hist_max = std::max(hist_max, h);
+            lut_max = std::max(lut_max, l);
+        }
+        *lut_off = (hist_max + 15u) & ~15u;
+        *stage_off = *lut_off + ((std::max<uint32_t>(lut_max, 16u) + 15u) & ~15u);
+        *lds = *stage_off + (mc ? 16u * kWave * 4u : 0u);
+    };
+    uint32_t lut_off = 0, stage_off = 0, lds_bytes = 0;
+    layout(false, &lut_off, &stage_off, &lds_bytes);
+    // the compact cell table costs one instruction per cell-table chord; it
+    // is taken when its smaller LDS footprint lets more waves share a CU
+    bool compact = false;
+    if (compact_ok && t_compact_mode >= 0 && items > 0) {
+        uint32_t lo_c = 0, so_c = 0, lds_c = 0;
+        layout(true, &lo_c, &so_c, &lds_c);
+        bool take = t_compact_mode > 0;
+        if (!take && lds_bytes <= di->lds_per_block) {
+            int full = 0, small = 0;
+            PC_HIP(T.count_occupancy(false, false, false, lds_bytes, &full), "occupancy");
+            PC_HIP(T.count_occupancy(false, false, true, lds_c, &small), "occupancy");
+            take = small > full;
+        } else if (!take) {
+            take = true;  // only the compact table fits
+        }
+        if (take) {
+            compact = true;
+            lut_off = lo_c;
+            stage_off = so_c;
+            lds_bytes = lds_c;
+        }
+    }
     if (lds_bytes > di->lds_per_block)
         return fail(PC_ERR_INVALID, "edge set needs " + std::to_string(lds_bytes) +
                                         " bytes of LDS per wave; the device allows " +
@@ -810,7 +848,7 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
                    "add prune counts");
         }
         int per_cu = 0;
-        PC_HIP(T.count_occupancy(fp64, mc, lds_bytes, &per_cu), "occupancy");
+        PC_HIP(T.count_occupancy(fp64, mc, compact, lds_bytes, &per_cu), "occupancy");
         per_cu = std::max(per_cu, 1);
         int64_t g = static_cast<int64_t>(di->cus) * per_cu;
         g = std::min<int64_t>(g, static_cast<int64_t>(items));
@@ -824,7 +862,7 @@ int run_batch_opts(const std::vector<BatchJob> &jobs, int mode_flags, hipStream_
             }
             PC_HIP(hipEventRecord(t_ev0, st), "hipEventRecord");
         }
-        PC_HIP(T.launch_count(fp64, mc, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
+        PC_HIP(T.launch_count(fp64, mc, compact, d_segs, static_cast<int32_t>(segs.size()), d_tabs, prune ? surv : nullptr,
                             prune ? meta : nullptr, split ? sub_words : nullptr, items, lut_off, stage_off, meta + kQueueBase,
                             meta + 7, lt.chunk, lds_bytes, grid, t_flush_cap, st),
                "count kernel");
@@ -1186,6 +1224,13 @@ extern "C" int pc_debug_set_tile(int32_t tile) {
 extern "C" int pc_debug_set_flush_every(uint64_t items) {
     clear_error();
     t_flush_cap = items;
+    return PC_OK;
+}
+
+extern "C" int pc_debug_set_compact_table(int32_t mode) {
+    clear_error();
+    if (mode < -1 || mode > 1) return fail(PC_ERR_INVALID, "mode must be -1, 0 or 1");
+    t_compact_mode = mode;
     return PC_OK;
 }
 

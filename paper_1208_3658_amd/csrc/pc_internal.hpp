@@ -74,6 +74,17 @@ struct LutEntry32 {
     uint32_t wbits;
 };
 
+// The same cell in 8 bytes, for launches whose LDS would otherwise limit
+// the waves per CU: bits(hi), and wc = wbits rounded up to a multiple of
+// kCtOffMask + 1 (all ones stay all ones) with off_lo in the low bits.  wc >=
+// wbits, so the flag test against it takes every chord the full entry's
+// does; the kernel re-checks every flagged chord (provisional row off_lo), so
+// lo is not needed.  Only built when every off_lo is at most kCtOffMask.
+constexpr uint32_t kCtOffMask = 0x3FFFu;
+struct LutEntryC {
+    uint32_t hi_bits, wc;
+};
+
 // Cell lookup entry of the binary64 kernel: c >= e -> off_hi, else off_lo.
 struct LutEntry64 {
     uint32_t off_lo, off_hi;
@@ -83,6 +94,7 @@ struct LutEntry64 {
 // One edge set as the kernels see it.
 struct TableDesc {
     const void *lut;        // LutEntry32[] (mixed) or LutEntry64[] (fp64); device
+    const void *lutc;       // LutEntryC[] (mixed, when built) or null; device
     const double *e64;      // n_edges binary64 squared-chord edges; device
     uint32_t clamp_lo;      // cell key clamp (binary32 bits, or high word of binary64)
     uint32_t clamp_hi;
@@ -137,6 +149,7 @@ constexpr uint32_t kSubGram = 1u << 14;
 struct Lut32 {
     uint32_t clamp_lo = 0, clamp_hi = 0, shift = 0;
     std::vector<LutEntry32> entries;
+    std::vector<LutEntryC> compact;  // the same cells, 8 bytes each; empty when off_lo does not fit
     int multi = 0;  // cells that always re-check (bands closer than the cell width)
 };
 

@@ -293,11 +293,19 @@ __device__ __forceinline__ const T *uniform_ptr(const T *p) {
     return reinterpret_cast<const T *>(lo | (hi << 32));
 }
 
-// LDS byte address of the cell-table entry for key: ((key >> shift) << 4) + base
+// LDS byte address of the cell-table entry for key: ((key >> shift) << 4) +
+// base, or << 3 for the compact 8-byte entries
+template <int ES = 4>
 __device__ __forceinline__ uint32_t cell_addr(uint32_t key, uint32_t shift, uint32_t base) {
     uint32_t r;
-    asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(r) : "v"(key >> shift), "v"(base));
+    asm("v_lshl_add_u32 %0, %1, %3, %2" : "=v"(r) : "v"(key >> shift), "v"(base), "i"(ES));
     return r;
+}
+
+__device__ __forceinline__ uint2 lds_read2(uint32_t addr) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 v = *(__attribute__((address_space(3))) const u32x2 *)(uintptr_t)(addr);
+    return make_uint2(v.x, v.y);
 }
 
 // Cell key of a binary32 squared chord: its bits, clamped to the table range
@@ -338,7 +346,13 @@ __device__ __forceinline__ void load_j(const float4 *__restrict__ J, float4 (&b)
 // NJ consecutive j-points against the lane's kR i-points: all chords first,
 // then all cell-table reads, then all histogram adds, so the LDS latency of
 // NJ * kR lookups overlaps.  Slot r of lane l holds i = ibeg + r*64 + l.
-template <bool MASKED, int NJ>
+//
+// CT: the compact cell table, 8 bytes per entry (bits(hi), wc), wc = the
+// width bits rounded up to a multiple of kCtOffMask + 1 with off_lo in its low
+// bits: the flag test against wc is a superset of the one against the width
+// bits, and the re-check takes every flagged chord (its provisional row is
+// off_lo), so no lo is needed.
+template <bool MASKED, int NJ, bool CT = false>
 __device__ __forceinline__ void step32(unsigned char *lds, const float4 (&b)[NJ],
                                        const double4 *__restrict__ J64t, int32_t jj,
                                        const float (&ax)[kR], const float (&ay)[kR],
@@ -353,13 +367,20 @@ __device__ __forceinline__ void step32(unsigned char *lds, const float4 (&b)[NJ]
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
             c2[q][r] = chord2_32(ax[r], ay[r], az[r], b[q]);
-            a[q][r] = cell_addr(key32(c2[q][r], k.klo, k.khi), k.shift, k.lut_base);
+            a[q][r] = cell_addr<CT ? 3 : 4>(key32(c2[q][r], k.klo, k.khi), k.shift, k.lut_base);
         }
     uint4 e[NJ][kR];
 #pragma unroll
     for (int q = 0; q < NJ; ++q)
 #pragma unroll
-        for (int r = 0; r < kR; ++r) e[q][r] = lds_read4(a[q][r]);
+        for (int r = 0; r < kR; ++r) {
+            if (CT) {
+                const uint2 v = lds_read2(a[q][r]);
+                e[q][r] = make_uint4(v.y & kCtOffMask, 0u, v.x, v.y);
+            } else {
+                e[q][r] = lds_read4(a[q][r]);
+            }
+        }
     // As in the few-edge paths, without compares: d = RN(hi - c) has the sign
     // of hi - c, so its sign bit adds the cell's next row when c > hi; a chord
     // in the cell's band has 0 <= d <= RN(hi - lo), whose bits the entry holds
@@ -394,8 +415,16 @@ __device__ __forceinline__ void step32(unsigned char *lds, const float4 (&b)[NJ]
             for (int r = 0; r < kR; ++r) {
                 float c = chord2_32(ax[r], ay[r], az[r], b[q]);
                 asm volatile("" : "+v"(c));
-                const uint3 en = lds_read3(cell_addr(key32(c, k.klo, k.khi), k.shift, k.lut_base));
-                bool band = !(c > __uint_as_float(en.z)) && (c >= __uint_as_float(en.y));
+                uint3 en;
+                bool band;
+                if (CT) {
+                    const uint2 v = lds_read2(cell_addr<3>(key32(c, k.klo, k.khi), k.shift, k.lut_base));
+                    en = make_uint3(v.y & kCtOffMask, 0u, v.x);
+                    band = __float_as_uint(__uint_as_float(v.x) - c) <= v.y;
+                } else {
+                    en = lds_read3(cell_addr(key32(c, k.klo, k.khi), k.shift, k.lut_base));
+                    band = !(c > __uint_as_float(en.z)) && (c >= __uint_as_float(en.y));
+                }
                 if (MASKED) {
                     const int32_t ir = r * kWave + lane;
                     band &= ir < i_lim && (!diag || ir < j_rel + jj + q);
@@ -421,7 +450,7 @@ __device__ __forceinline__ void step32(unsigned char *lds, const float4 (&b)[NJ]
 // MASKED: some i slots are past the end of the range (i_lim < kTile), or this
 // is a diagonal tile (only i < j counts); masked-out pairs go to the discard
 // row.  j_rel = first j of the tile minus first i of the tile.
-template <bool MASKED>
+template <bool MASKED, bool CT = false>
 __device__ __forceinline__ void tile32(unsigned char *lds, const float4 *__restrict__ Jt,
                                        const double4 *__restrict__ J64t, int32_t jn,
                                        const float (&ax)[kR], const float (&ay)[kR],
@@ -435,18 +464,18 @@ __device__ __forceinline__ void tile32(unsigned char *lds, const float4 *__restr
     load_j<NJ>(Jt, b0);
     for (; jj + 2 * NJ <= jn; jj += 2 * NJ) {
         load_j<NJ>(Jt + jj + NJ, b1);
-        step32<MASKED, NJ>(lds, b0, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+        step32<MASKED, NJ, CT>(lds, b0, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
         load_j<NJ>(Jt + jj + 2 * NJ, b0);
-        step32<MASKED, NJ>(lds, b1, J64t, jj + NJ, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+        step32<MASKED, NJ, CT>(lds, b1, J64t, jj + NJ, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
     }
     if (jj + NJ <= jn) {
-        step32<MASKED, NJ>(lds, b0, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+        step32<MASKED, NJ, CT>(lds, b0, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
         jj += NJ;
     }
     for (; jj < jn; ++jj) {
         float4 bt[1];
         load_j<1>(Jt + jj, bt);
-        step32<MASKED, 1>(lds, bt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
+        step32<MASKED, 1, CT>(lds, bt, J64t, jj, ax, ay, az, I64, ibeg, i_lim, j_rel, diag, k);
     }
 }
 
@@ -1070,7 +1099,8 @@ __device__ __forceinline__ void tile64(unsigned char *lds, const double4 *__rest
 // MC: tile pairs marked by the prune pass go through the matrix cores (a
 // separate instance, so the binary32-only instance keeps its lower register
 // count and occupancy).
-template <bool FP64, bool MC>
+// CT: the cell table in its compact form (mixed kernel only; see step32).
+template <bool FP64, bool MC, bool CT = false>
 __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t lds0 = lds_addr(lds);
@@ -1167,11 +1197,16 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                 row_bytes = static_cast<uint32_t>(cols) * 4u;
                 lane_off = lds0 + (lane & static_cast<uint32_t>(cols - 1)) * 4u;
                 trash_off = static_cast<uint32_t>(n_edges + 1) * row_bytes + lane_off;
-                lut_base = (FP64 && search) ? lds0 + p.lut_lds_off : lds0 + p.lut_lds_off - (td.key0 << 4);
+                lut_base = (FP64 && search) ? lds0 + p.lut_lds_off
+                                            : lds0 + p.lut_lds_off - (td.key0 << (CT ? 3 : 4));
                 // copy the cell table (or, for a search table, the edges) into LDS
                 if (FP64 && search) {
                     double *dst = reinterpret_cast<double *>(lds + p.lut_lds_off);
                     for (int32_t k = lane; k < n_edges; k += kWave) dst[k] = td.e64[k];
+                } else if (CT) {
+                    const uint2 *src = reinterpret_cast<const uint2 *>(td.lutc);
+                    uint2 *dst = reinterpret_cast<uint2 *>(lds + p.lut_lds_off);
+                    for (int32_t k = lane; k < td.n_cells; k += kWave) dst[k] = src[k];
                 } else {
                     const uint4 *src = reinterpret_cast<const uint4 *>(td.lut);
                     uint4 *dst = reinterpret_cast<uint4 *>(lds + p.lut_lds_off);
@@ -1301,12 +1336,12 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                     if (few_m == 1) tile32_few<true, 1>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
                     else if (few_m == 2) tile32_few<true, 2>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
                     else if (few_m == 3) tile32_few<true, 3>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
-                    else tile32<true>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
+                    else tile32<true, CT>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
                 } else {
                     if (few_m == 1) tile32_few<false, 1>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
                     else if (few_m == 2) tile32_few<false, 2>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
                     else if (few_m == 3) tile32_few<false, 3>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k, f);
-                    else tile32<false>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
+                    else tile32<false, CT>(lds, Jt, J64t, jn, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, diag, k);
                 }
             }
         } else {
@@ -1376,7 +1411,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
                     if (m == 1) tile32_few<false, 1>(lds, Jt, J64p, nj, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, false, k, f);
                     else if (m == 2) tile32_few<false, 2>(lds, Jt, J64p, nj, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, false, k, f);
                     else if (m == 3) tile32_few<false, 3>(lds, Jt, J64p, nj, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, false, k, f);
-                    else tile32<false>(lds, Jt, J64p, nj, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, false, k);
+                    else tile32<false, CT>(lds, Jt, J64p, nj, fx, fy, fz, sd.i64, ibeg, i_lim, j_rel, false, k);
                 }
             }
         }
@@ -1384,7 +1419,7 @@ __global__ void __launch_bounds__(kWave) PC_OCCUPANCY k_count(KParams p) {
     if (cur_job >= 0) flush_hist(lds, n_edges + 1, cols, clear_words, cur_counts, p.rechecked);
 }
 
-hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
+hipError_t launch_count(bool fp64, bool mc, bool compact, const SegDesc *segs, int32_t n_segs, const TableDesc *tabs,
                         const uint64_t *items, const unsigned long long *n_items, const uint64_t *sub,
                         uint64_t total_items, uint32_t lut_lds_off, uint32_t stage_lds_off,
                         unsigned long long *queue, unsigned long long *rechecked, int chunk, uint32_t lds_bytes,
@@ -1407,23 +1442,29 @@ hipError_t launch_count(bool fp64, bool mc, const SegDesc *segs, int32_t n_segs,
         k_count<true, false><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
     else if (mc)
         k_count<false, kMatrixCores><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
+    else if (compact)
+        k_count<false, false, true><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
     else
         k_count<false, false><<<dim3(grid), dim3(kWave), lds_bytes, st>>>(p);
     return hipGetLastError();
 }
 
-hipError_t count_occupancy(bool fp64, bool mc, uint32_t lds_bytes, int *blocks_per_cu) {
+hipError_t count_occupancy(bool fp64, bool mc, bool compact, uint32_t lds_bytes, int *blocks_per_cu) {
     if (fp64)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<true, false>, kWave, lds_bytes);
     if (mc)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<false, kMatrixCores>, kWave,
                                                              lds_bytes);
+    if (compact)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<false, false, true>, kWave,
+                                                             lds_bytes);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_count<false, false>, kWave, lds_bytes);
 }
 
 hipError_t set_max_lds(uint32_t bytes) {
-    const void *fs[3] = {reinterpret_cast<const void *>(k_count<true, false>),
+    const void *fs[4] = {reinterpret_cast<const void *>(k_count<true, false>),
                          reinterpret_cast<const void *>(k_count<false, false>),
+                         reinterpret_cast<const void *>(k_count<false, false, true>),
                          reinterpret_cast<const void *>(k_count<false, kMatrixCores>)};
     for (const void *f : fs) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

@@ -42,6 +42,7 @@ struct DevTable {
     const float *d_fband = nullptr;   // (h, W) per edge, the vector few-edge paths' fused thresholds
     const float *d_fband_g = nullptr; // the same for tile-centred Gram chords
     const void *d_lut32 = nullptr;
+    const void *d_lutc = nullptr;
     const void *d_lut64 = nullptr;
     ~DevTable();
 };
@@ -49,10 +50,10 @@ struct DevTable {
 int get_table(const double *theta, int32_t n_edges, std::shared_ptr<DevTable> *out, int cols = 0);
 
 // A table's device image: e64 | band | band_g | fband | fband_g | lut32 |
-// lut64 at the offsets below (256-byte aligned), built on the host.
+// lutc | lut64 at the offsets below (256-byte aligned), built on the host.
 struct TableBlob {
     std::vector<unsigned char> bytes;
-    size_t o_band = 0, o_band_g = 0, o_fband = 0, o_fband_g = 0, o_lut32 = 0, o_lut64 = 0;
+    size_t o_band = 0, o_band_g = 0, o_fband = 0, o_fband_g = 0, o_lut32 = 0, o_lutc = 0, o_lut64 = 0;
 };
 void table_blob(const HostTable &h, TableBlob *out);
 // points t's device pointers into a copy of the blob at `base` (t does not own it)

@@ -440,6 +440,19 @@ bool build_table(const double *theta_deg, int n_edges, HostTable &t, std::string
     }
     t.row_bytes32 = row_bytes_for(t.cols32);
     build_lut32(t.lo, t.hi, t.row_bytes32, t.lut32);
+    // the 8-byte form of the same cells, when every row offset fits in the
+    // low bits of the rounded-up width
+    t.lut32.compact.clear();
+    bool fits = true;
+    for (const LutEntry32 &e : t.lut32.entries) fits = fits && e.off_lo <= kCtOffMask;
+    if (fits) {
+        t.lut32.compact.reserve(t.lut32.entries.size());
+        for (const LutEntry32 &e : t.lut32.entries) {
+            const uint64_t up = (static_cast<uint64_t>(e.wbits) + kCtOffMask) & ~static_cast<uint64_t>(kCtOffMask);
+            const uint32_t w = up > 0xFFFFFFFFull ? ~kCtOffMask : static_cast<uint32_t>(up);
+            t.lut32.compact.push_back({f2u(e.hi), w | e.off_lo});
+        }
+    }
     build_lut64(t);
     return true;
 }

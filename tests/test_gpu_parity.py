@@ -624,3 +624,50 @@ def test_128_point_tiles_match_the_oracle(mode):
             pc.pc_catalog_release(h)
     finally:
         pc.pc_debug_set_tile(0)
+
+
+@pytest.mark.parametrize("tile", [256, 128])
+def test_compact_cell_table_matches_oracle(tile):
+    """The 8-byte cell table (bits(hi) and the width bits rounded up, with the
+    row offset in their low bits; every flagged chord re-checked in binary64)
+    forced on: the small configuration's DD, DR and RR, pairs within a few
+    ulps of the edges, the paper's 254 log bins, and ragged sizes equal the
+    oracle, with less LDS per wave than the 16-byte table.  With 254 bins the
+    default launch takes it by itself (more waves per CU)."""
+    try:
+        pc.pc_debug_set_tile(tile)
+        c = synth.config_small(scale=0.3)
+        D, R, e = c["D"], c["R"], c["edges"]
+        jobs = [{"A": dev(D), "edges": e}, {"A": dev(D), "B": dev(R), "edges": e, "auto": False},
+                {"A": dev(R), "edges": e}]
+        want = [oracle.count(D, e), oracle.count(D, e, B=R, auto=False), oracle.count(R, e)]
+        pc.pc_debug_set_compact_table(-1)
+        pc.pc_count_batch(jobs)
+        full = pc.pc_debug_last_launch()["lds_bytes"]
+        pc.pc_debug_set_compact_table(1)
+        got = pc.pc_count_batch(jobs)
+        for g, w in zip(got, want):
+            assert g.tolist() == w.tolist()
+        assert pc.pc_debug_last_launch()["lds_bytes"] < full
+        for theta in [synth.log_edges(0.01, 20.0, 40), synth.linear_edges(0.0, 60.0, 30)]:
+            A = _near_edge_catalogue(theta)
+            assert pc.pc_count_ex(dev(A), theta).tolist() == oracle.count(A, theta).tolist()
+            assert pc.pc_debug_last_rechecks() > 0
+        rng = np.random.default_rng(71)
+        ep = synth.log_edges(0.001, 90.0, 254)
+        A = synth.uniform_patch(2500, synth.centred_patch(30.0), rng)
+        B = synth.uniform_patch(1700, synth.centred_patch(30.0), rng)
+        assert pc.pc_count_ex(dev(A), ep).tolist() == oracle.count(A, ep).tolist()
+        assert pc.pc_count_ex(dev(A), ep, B=dev(B), auto=False).tolist() == oracle.count(A, ep, B=B, auto=False).tolist()
+        compact = pc.pc_debug_last_launch()["lds_bytes"]
+        pc.pc_debug_set_compact_table(0)
+        assert pc.pc_count_ex(dev(A), ep, B=dev(B), auto=False).tolist() == oracle.count(A, ep, B=B, auto=False).tolist()
+        assert pc.pc_debug_last_launch()["lds_bytes"] == compact
+        pc.pc_debug_set_compact_table(1)
+        e2 = synth.log_edges(0.05, 8.0, 12)
+        for n in (1, 2, 127, 129, 255, 257, 1000):
+            A = synth.uniform_patch(n, synth.centred_patch(12.0), rng)
+            assert pc.pc_count_ex(dev(A), e2).tolist() == oracle.count(A, e2).tolist(), n
+    finally:
+        pc.pc_debug_set_compact_table(0)
+        pc.pc_debug_set_tile(0)
