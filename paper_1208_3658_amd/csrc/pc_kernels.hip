@@ -12,8 +12,9 @@
 //     tile only i < j: every unordered pair exactly once, no self-pairs
 //     (Sec. 2, n(n-1)/2 pairs); cross pairs use every tile pair (n_A n_B);
 //   * each workgroup is a single wave that owns its LDS: a private cell
-//     table for the current edge set and a histogram of `cols` lane columns
-//     (8 to 64: only the 64 / cols lanes of one wave that share a column can
+//     table for the current edge set (16-byte entries, or 8-byte ones when
+//     that lets more waves share a CU) and a histogram of `cols` lane columns
+//     (4 to 32: only the 64 / cols lanes of one wave that share a column can
 //     meet on a word, never lanes of other waves, so the paper's same-bin
 //     atomic contention across threads, Sec. 2.1, is bounded), flushed into
 //     64-bit global counters when the job changes and at the end; the
